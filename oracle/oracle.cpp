@@ -1,0 +1,849 @@
+// CPU FP64 oracle of the angular-momentum-conserving Cartesian FMM
+// (Marcello 2017).  TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke
+// check and the CPU-baseline leg of the benchmark, never by the GPU solver.
+//
+// Plain, slow and written to be checked against the paper by eye:
+//   * full 3-index / 4-index tensor loops, no symmetry packing;
+//   * moments summed directly over each cell's particles (eq. 1, quad, the
+//     octupole definition), not shifted from children;
+//   * the far field of every accepted pair evaluated at each particle of
+//     both cells with eqs. 2-4 as printed (no local-expansion push-down);
+//   * the near field by direct mutual summation over particle pairs.
+// Built with -O2 -ffp-contract=off so that every product and sum rounds on
+// its own, in the order written here.
+//
+// Where the paper is silent the readings are (each is also listed in the
+// design notes of the repository):
+//   R := Z_A - Z_B for the pair (field cell A, source cell B): with the printed
+//        D tensors this is the sign that makes eqs. 2-4 attractive and
+//        consistent with the Taylor expansion of G(X - Y);
+//   eq. 7 uses the appendix prefactor 1/(n!(P-n)!) = 1/6 at P = 3, with the
+//        sign of eq. 7 (A gets +F_c/M_A, B gets -F_c/M_B);
+//   dipole terms are dropped (they vanish about the centre of mass);
+//   the correction is a force only; potentials exclude it;
+//   tree: Morton keys on a 21-bit grid over the bounding cube, split iff
+//        count > n_crit and level < max_level, children in octant order;
+//   centres of mass are summed leaf-sequentially in key order and parents over
+//        their children in octant order;
+//   the walk follows a symmetric dual recursion (below).
+#include "oracle.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <utility>
+#include <vector>
+
+namespace {
+
+constexpr int kMaxLevel = 21;  // key resolution: 21 bits per dimension
+
+struct Cell {
+  int32_t level;
+  int64_t begin, count;
+  int32_t parent, child0, nchild;
+  uint64_t prefix;  // key >> 3*(21-level)
+};
+
+struct Moments {
+  double M = 0.0;
+  double S[3] = {0.0, 0.0, 0.0};  // sum of mu * X, used for Z
+  double Z[3] = {0.0, 0.0, 0.0};
+  double Rmax = 0.0;
+  double M2[3][3] = {};     // sum mu x_i x_j about Z
+  double M3[3][3][3] = {};  // sum mu x_i x_j x_k about Z
+};
+
+}  // namespace
+
+struct orc_tree {
+  int64_t n = 0;
+  int32_t n_crit = 25;
+  int32_t max_level = kMaxLevel;
+  double lo[3] = {0, 0, 0};
+  double side = 1.0, scale = 1.0;
+  std::vector<double> x, y, z, m;  // sorted copies
+  std::vector<int64_t> perm;       // sorted index -> caller index
+  std::vector<uint64_t> keys;      // sorted keys
+  std::vector<Cell> cells;         // (level, begin) order
+  std::vector<Moments> mom;
+  bool have_moments = false;
+  bool have_lists = false;
+  double theta = 0.5;
+  std::vector<std::pair<int32_t, int32_t>> m2l, p2p;
+  int64_t coincident = 0;
+};
+
+namespace {
+
+inline bool is_leaf(const Cell& c) { return c.nchild == 0; }
+
+double kdelta(int a, int b) { return a == b ? 1.0 : 0.0; }
+
+// ---------------------------------------------------------------- keys ---
+// Root cube: lo_d = min over particles of X_d; side = largest extent (1 if the
+// points coincide).  Each coordinate is quantised to 21 bits and the three
+// integers are interleaved, x in the most significant bit of every triple.
+uint64_t morton_key(const double X[3], const double lo[3], double scale) {
+  const uint64_t qmax = (uint64_t(1) << kMaxLevel) - 1;
+  uint64_t q[3];
+  for (int d = 0; d < 3; ++d) {
+    double v = (X[d] - lo[d]) * scale;
+    double f = std::floor(v);
+    uint64_t qi = f <= 0.0 ? 0 : (uint64_t)f;
+    q[d] = qi > qmax ? qmax : qi;
+  }
+  uint64_t key = 0;
+  for (int b = 0; b < kMaxLevel; ++b) {
+    key |= ((q[0] >> b) & 1) << (3 * b + 2);
+    key |= ((q[1] >> b) & 1) << (3 * b + 1);
+    key |= ((q[2] >> b) & 1) << (3 * b + 0);
+  }
+  return key;
+}
+
+// ------------------------------------------------------- Green's function ---
+// g(R) = -1/R and its derivatives, Sec. 2.  D..D_ijk as printed; D_ijkl is the
+// fourth derivative (derived by differentiating D_ijk once more); D'_ijkl is
+// the tensor of eq. 8.
+struct Greens {
+  double D0;
+  double D1[3];
+  double D2[3][3];
+  double D3[3][3][3];
+  double D4[3][3][3][3];
+  double D4p[3][3][3][3];
+};
+
+void greens(const double R[3], Greens& g, bool want4) {
+  double R2 = (R[0] * R[0] + R[1] * R[1]) + R[2] * R[2];
+  double Rn = std::sqrt(R2);
+  double inv = 1.0 / Rn;
+  double inv3 = inv * inv * inv;
+  double inv5 = inv3 * inv * inv;
+  double inv7 = inv5 * inv * inv;
+  double inv9 = inv7 * inv * inv;
+  g.D0 = -inv;
+  for (int i = 0; i < 3; ++i) g.D1[i] = R[i] * inv3;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) g.D2[i][j] = -(3.0 * R[i] * R[j] - kdelta(i, j) * R2) * inv5;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k)
+        g.D3[i][j][k] = (15.0 * R[i] * R[j] * R[k] -
+                         3.0 * (kdelta(i, j) * R[k] + kdelta(j, k) * R[i] + kdelta(k, i) * R[j]) * R2) *
+                        inv7;
+  if (!want4) return;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l) {
+          double t4 = -105.0 * R[i] * R[j] * R[k] * R[l] * inv9;
+          double t2 = 15.0 *
+                      (kdelta(i, j) * R[k] * R[l] + kdelta(i, k) * R[j] * R[l] +
+                       kdelta(i, l) * R[j] * R[k] + kdelta(j, k) * R[i] * R[l] +
+                       kdelta(j, l) * R[i] * R[k] + kdelta(k, l) * R[i] * R[j]) *
+                      inv7;
+          double t0 = -3.0 *
+                      (kdelta(i, j) * kdelta(k, l) + kdelta(i, k) * kdelta(j, l) +
+                       kdelta(i, l) * kdelta(j, k)) *
+                      inv5;
+          g.D4[i][j][k][l] = t4 + t2 + t0;
+          // eq. 8: only the delta_i. terms of the fourth derivative are kept
+          double p2 = 15.0 *
+                      (kdelta(i, j) * R[k] * R[l] + kdelta(i, k) * R[j] * R[l] +
+                       kdelta(i, l) * R[j] * R[k]) *
+                      inv7;
+          g.D4p[i][j][k][l] = p2 + t0;
+        }
+}
+
+// --------------------------------------------------------------- moments ---
+// M2_ij = sum mu x_i x_j and M3_ijk = sum mu x_i x_j x_k with x = X - Z, summed
+// over the particles [b, b+cnt) of the sorted arrays (eq. quad and the
+// octupole definition).  Rmax^2 is the largest squared distance to Z.
+void moments_about(const orc_tree& t, int64_t b, int64_t cnt, Moments& mo) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      mo.M2[i][j] = 0.0;
+      for (int k = 0; k < 3; ++k) mo.M3[i][j][k] = 0.0;
+    }
+  double r2max = 0.0;
+  for (int64_t p = b; p < b + cnt; ++p) {
+    double xv[3] = {t.x[p] - mo.Z[0], t.y[p] - mo.Z[1], t.z[p] - mo.Z[2]};
+    double mu = t.m[p];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        mo.M2[i][j] += mu * xv[i] * xv[j];
+        for (int k = 0; k < 3; ++k) mo.M3[i][j][k] += mu * xv[i] * xv[j] * xv[k];
+      }
+    double r2 = (xv[0] * xv[0] + xv[1] * xv[1]) + xv[2] * xv[2];
+    if (r2 > r2max) r2max = r2;
+  }
+  mo.Rmax = std::sqrt(r2max);
+}
+
+// ------------------------------------------------------------- far field ---
+// One accepted pair, R = Z_A - Z_B.  Eq. 3 (field in A) and eq. 4 (field in B)
+// with dipole terms dropped; eq. 2 for the potential in A and its mirror image
+// for B (the expansion of G(Y - X) about -R, octupole constant dropped).
+struct PairTerms {
+  Greens g;
+  double Fc[3];  // correction force of the variant (zero for UC)
+};
+
+void pair_terms(const Moments& A, const Moments& B, int variant, PairTerms& pt) {
+  double R[3] = {A.Z[0] - B.Z[0], A.Z[1] - B.Z[1], A.Z[2] - B.Z[2]};
+  greens(R, pt.g, variant != ORC_UC);
+  for (int i = 0; i < 3; ++i) pt.Fc[i] = 0.0;
+  if (variant == ORC_UC) return;
+  // eq. 7 / eq. 8: F_c,i = -(1/6) (M_A,jkl M_B - M_A M_B,jkl) D_ijkl
+  for (int i = 0; i < 3; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l) {
+          double Q = A.M3[j][k][l] * B.M - A.M * B.M3[j][k][l];
+          double D = variant == ORC_TC ? pt.g.D4[i][j][k][l] : pt.g.D4p[i][j][k][l];
+          s += Q * D;
+        }
+    pt.Fc[i] = -(1.0 / 6.0) * s;
+  }
+}
+
+// eq. 3: acceleration at x (relative to Z_A) caused by B
+void eq3_accel(const Greens& g, const Moments& B, const double x[3], double out[3]) {
+  for (int i = 0; i < 3; ++i) {
+    double c0 = B.M * g.D1[i];
+    double q = 0.0;
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k) q += B.M2[j][k] * g.D3[i][j][k];
+    c0 += 0.5 * q;
+    double c1 = 0.0;
+    for (int j = 0; j < 3; ++j) c1 += x[j] * (B.M * g.D2[i][j]);
+    double c2 = 0.0;
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k) c2 += x[j] * x[k] * B.M * g.D3[i][j][k];
+    out[i] = -(c0 + c1 + 0.5 * c2);
+  }
+}
+
+// eq. 4: acceleration at y (relative to Z_B) caused by A, same D(R)
+void eq4_accel(const Greens& g, const Moments& A, const double y[3], double out[3]) {
+  for (int i = 0; i < 3; ++i) {
+    double c0 = -A.M * g.D1[i];
+    double q = 0.0;
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k) q += A.M2[j][k] * g.D3[i][j][k];
+    c0 -= 0.5 * q;
+    double c1 = 0.0;
+    for (int j = 0; j < 3; ++j) c1 += y[j] * (A.M * g.D2[i][j]);
+    double c2 = 0.0;
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k) c2 += y[j] * y[k] * A.M * g.D3[i][j][k];
+    out[i] = -(c0 + c1 - 0.5 * c2);
+  }
+}
+
+// eq. 2: potential at x (relative to Z_A) caused by B
+double eq2_pot_A(const Greens& g, const Moments& B, const double x[3]) {
+  double q = 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) q += B.M2[i][j] * g.D2[i][j];
+  double p = B.M * g.D0 + 0.5 * q;
+  for (int i = 0; i < 3; ++i) {
+    double qi = 0.0;
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k) qi += B.M2[j][k] * g.D3[i][j][k];
+    p += x[i] * (B.M * g.D1[i] + 0.5 * qi);
+  }
+  double s2 = 0.0, s3 = 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      s2 += x[i] * x[j] * B.M * g.D2[i][j];
+      for (int k = 0; k < 3; ++k) s3 += x[i] * x[j] * x[k] * B.M * g.D3[i][j][k];
+    }
+  return p + 0.5 * s2 + (1.0 / 6.0) * s3;
+}
+
+// potential at y (relative to Z_B) caused by A: the expansion of eq. 2 with the
+// roles of the cells exchanged, written with the same D(R), so odd orders flip
+double eq2_pot_B(const Greens& g, const Moments& A, const double y[3]) {
+  double q = 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) q += A.M2[i][j] * g.D2[i][j];
+  double p = A.M * g.D0 + 0.5 * q;
+  for (int i = 0; i < 3; ++i) {
+    double qi = 0.0;
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k) qi += A.M2[j][k] * g.D3[i][j][k];
+    p -= y[i] * (A.M * g.D1[i] + 0.5 * qi);
+  }
+  double s2 = 0.0, s3 = 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      s2 += y[i] * y[j] * A.M * g.D2[i][j];
+      for (int k = 0; k < 3; ++k) s3 += y[i] * y[j] * y[k] * A.M * g.D3[i][j][k];
+    }
+  return p + 0.5 * s2 - (1.0 / 6.0) * s3;
+}
+
+// ------------------------------------------------------------------ walk ---
+// Symmetric dual recursion.  A pair is accepted when |Z_A - Z_B| >= (R_A +
+// R_B)/theta (and the centres differ); two leaves that fail become a near-field
+// pair; otherwise the larger cell (by R_max, ties to the lower index; the
+// non-leaf when one is a leaf) is replaced by its children.  A cell with itself
+// recurses into its children's self pairs and all child pairs.
+bool accept(const orc_tree& t, int32_t a, int32_t b) {
+  const Moments& A = t.mom[a];
+  const Moments& B = t.mom[b];
+  double dx = A.Z[0] - B.Z[0];
+  double dy = A.Z[1] - B.Z[1];
+  double dz = A.Z[2] - B.Z[2];
+  double d = std::sqrt((dx * dx + dy * dy) + dz * dz);
+  double rhs = (A.Rmax + B.Rmax) / t.theta;
+  return d > 0.0 && d >= rhs;
+}
+
+void walk_pair(orc_tree& t, int32_t a, int32_t b) {
+  if (accept(t, a, b)) {
+    t.m2l.emplace_back(std::min(a, b), std::max(a, b));
+    return;
+  }
+  const Cell& A = t.cells[a];
+  const Cell& B = t.cells[b];
+  if (is_leaf(A) && is_leaf(B)) {
+    t.p2p.emplace_back(std::min(a, b), std::max(a, b));
+    return;
+  }
+  double ra = t.mom[a].Rmax, rb = t.mom[b].Rmax;
+  bool split_a;
+  if (is_leaf(A))
+    split_a = false;
+  else if (is_leaf(B))
+    split_a = true;
+  else
+    split_a = ra > rb || (ra == rb && a < b);
+  if (split_a) {
+    for (int32_t c = A.child0; c < A.child0 + A.nchild; ++c) walk_pair(t, c, b);
+  } else {
+    for (int32_t c = B.child0; c < B.child0 + B.nchild; ++c) walk_pair(t, a, c);
+  }
+}
+
+void walk_self(orc_tree& t, int32_t c) {
+  const Cell& C = t.cells[c];
+  if (is_leaf(C)) {
+    t.p2p.emplace_back(c, c);
+    return;
+  }
+  for (int32_t a = C.child0; a < C.child0 + C.nchild; ++a) walk_self(t, a);
+  for (int32_t a = C.child0; a < C.child0 + C.nchild; ++a)
+    for (int32_t b = a + 1; b < C.child0 + C.nchild; ++b) walk_pair(t, a, b);
+}
+
+bool finite_inputs(int64_t n, const double* x, const double* y, const double* z, const double* m,
+                   int32_t* status) {
+  for (int64_t i = 0; i < n; ++i) {
+    if (!std::isfinite(x[i]) || !std::isfinite(y[i]) || !std::isfinite(z[i]) ||
+        !std::isfinite(m[i])) {
+      *status = ORC_E_NONFINITE;
+      return false;
+    }
+    if (!(m[i] > 0.0)) {
+      *status = ORC_E_INVALID;
+      return false;
+    }
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+orc_tree* orc_build_tree(int64_t n, const double* x, const double* y, const double* z,
+                         const double* m, int32_t n_crit, int32_t max_level, int32_t* status) {
+  int32_t st_dummy;
+  if (!status) status = &st_dummy;
+  *status = ORC_OK;
+  if (n < 1 || n_crit < 1 || max_level < 0 || max_level > kMaxLevel) {
+    *status = ORC_E_INVALID;
+    return nullptr;
+  }
+  if (!finite_inputs(n, x, y, z, m, status)) return nullptr;
+  orc_tree* t = new orc_tree();
+  t->n = n;
+  t->n_crit = n_crit;
+  t->max_level = max_level;
+  // root cube
+  double hi[3];
+  t->lo[0] = hi[0] = x[0];
+  t->lo[1] = hi[1] = y[0];
+  t->lo[2] = hi[2] = z[0];
+  for (int64_t i = 1; i < n; ++i) {
+    t->lo[0] = std::min(t->lo[0], x[i]);
+    hi[0] = std::max(hi[0], x[i]);
+    t->lo[1] = std::min(t->lo[1], y[i]);
+    hi[1] = std::max(hi[1], y[i]);
+    t->lo[2] = std::min(t->lo[2], z[i]);
+    hi[2] = std::max(hi[2], z[i]);
+  }
+  double side = 0.0;
+  for (int d = 0; d < 3; ++d) side = std::max(side, hi[d] - t->lo[d]);
+  if (side == 0.0) side = 1.0;
+  t->side = side;
+  t->scale = double(uint64_t(1) << kMaxLevel) / side;
+  // keys, then a stable sort: equal keys keep caller order
+  std::vector<uint64_t> key(n);
+  for (int64_t i = 0; i < n; ++i) {
+    double X[3] = {x[i], y[i], z[i]};
+    key[i] = morton_key(X, t->lo, t->scale);
+  }
+  t->perm.resize(n);
+  std::iota(t->perm.begin(), t->perm.end(), int64_t(0));
+  std::stable_sort(t->perm.begin(), t->perm.end(),
+                   [&](int64_t a, int64_t b) { return key[a] < key[b]; });
+  t->keys.resize(n);
+  t->x.resize(n);
+  t->y.resize(n);
+  t->z.resize(n);
+  t->m.resize(n);
+  for (int64_t s = 0; s < n; ++s) {
+    int64_t i = t->perm[s];
+    t->keys[s] = key[i];
+    t->x[s] = x[i];
+    t->y[s] = y[i];
+    t->z[s] = z[i];
+    t->m[s] = m[i];
+  }
+  // octree, one level at a time: a cell with more than n_crit particles below
+  // the finest level is split into its non-empty octants, in octant order
+  Cell root{0, 0, n, -1, -1, 0, 0};
+  t->cells.push_back(root);
+  size_t level_begin = 0;
+  for (int lev = 0;; ++lev) {
+    size_t level_end = t->cells.size();
+    if (level_begin == level_end) break;
+    for (size_t c = level_begin; c < level_end; ++c) {
+      Cell cur = t->cells[c];
+      if (!(cur.count > n_crit && lev < max_level)) continue;
+      int shift = 3 * (kMaxLevel - (lev + 1));
+      int32_t first_child = (int32_t)t->cells.size();
+      int32_t nch = 0;
+      for (uint64_t oct = 0; oct < 8; ++oct) {
+        int64_t b = -1, cnt = 0;
+        for (int64_t p = cur.begin; p < cur.begin + cur.count; ++p) {
+          if (((t->keys[p] >> shift) & 7) == oct) {
+            if (b < 0) b = p;
+            ++cnt;
+          }
+        }
+        if (cnt == 0) continue;
+        Cell ch{lev + 1, b, cnt, (int32_t)c, -1, 0, (cur.prefix << 3) | oct};
+        t->cells.push_back(ch);
+        ++nch;
+      }
+      t->cells[c].child0 = first_child;
+      t->cells[c].nchild = nch;
+    }
+    level_begin = level_end;
+  }
+  return t;
+}
+
+void orc_free(orc_tree* t) { delete t; }
+
+int64_t orc_num_cells(const orc_tree* t) { return (int64_t)t->cells.size(); }
+
+int32_t orc_depth(const orc_tree* t) {
+  int32_t d = 0;
+  for (const Cell& c : t->cells) d = std::max(d, c.level);
+  return d;
+}
+
+void orc_get_cube(const orc_tree* t, double* lo3, double* side, double* scale) {
+  for (int d = 0; d < 3; ++d) lo3[d] = t->lo[d];
+  *side = t->side;
+  *scale = t->scale;
+}
+
+void orc_get_keys(const orc_tree* t, uint64_t* keys, int64_t* perm) {
+  for (int64_t s = 0; s < t->n; ++s) {
+    if (keys) keys[s] = t->keys[s];
+    if (perm) perm[s] = t->perm[s];
+  }
+}
+
+void orc_get_cells(const orc_tree* t, int32_t* level, int64_t* begin, int64_t* count,
+                   int32_t* parent, int32_t* child0, int32_t* nchild) {
+  for (size_t c = 0; c < t->cells.size(); ++c) {
+    const Cell& C = t->cells[c];
+    if (level) level[c] = C.level;
+    if (begin) begin[c] = C.begin;
+    if (count) count[c] = C.count;
+    if (parent) parent[c] = C.parent;
+    if (child0) child0[c] = C.nchild ? C.child0 : -1;
+    if (nchild) nchild[c] = C.nchild;
+  }
+}
+
+int32_t orc_compute_moments(orc_tree* t) {
+  size_t nc = t->cells.size();
+  t->mom.assign(nc, Moments());
+  // mass and first moment: leaves sequentially over their particles, parents
+  // over their children in octant order (deepest cells first)
+  for (size_t ci = nc; ci-- > 0;) {
+    const Cell& C = t->cells[ci];
+    Moments& mo = t->mom[ci];
+    if (is_leaf(C)) {
+      for (int64_t p = C.begin; p < C.begin + C.count; ++p) {
+        mo.M += t->m[p];
+        mo.S[0] += t->m[p] * t->x[p];
+        mo.S[1] += t->m[p] * t->y[p];
+        mo.S[2] += t->m[p] * t->z[p];
+      }
+    } else {
+      for (int32_t c = C.child0; c < C.child0 + C.nchild; ++c) {
+        mo.M += t->mom[c].M;
+        for (int d = 0; d < 3; ++d) mo.S[d] += t->mom[c].S[d];
+      }
+    }
+    for (int d = 0; d < 3; ++d) mo.Z[d] = mo.S[d] / mo.M;
+  }
+  // higher moments and R_max directly from the particles of each cell
+  for (size_t ci = 0; ci < nc; ++ci)
+    moments_about(*t, t->cells[ci].begin, t->cells[ci].count, t->mom[ci]);
+  t->have_moments = true;
+  t->have_lists = false;
+  return ORC_OK;
+}
+
+void orc_get_moments(const orc_tree* t, double* out) {
+  for (size_t c = 0; c < t->mom.size(); ++c) {
+    const Moments& mo = t->mom[c];
+    double* o = out + 21 * c;
+    o[0] = mo.M;
+    o[1] = mo.Z[0];
+    o[2] = mo.Z[1];
+    o[3] = mo.Z[2];
+    o[4] = mo.Rmax;
+    int q = 5;
+    for (int i = 0; i < 3; ++i)
+      for (int j = i; j < 3; ++j) o[q++] = mo.M2[i][j];
+    for (int i = 0; i < 3; ++i)
+      for (int j = i; j < 3; ++j)
+        for (int k = j; k < 3; ++k) o[q++] = mo.M3[i][j][k];
+  }
+}
+
+int32_t orc_walk(orc_tree* t, double theta) {
+  if (!(theta > 0.0 && theta <= 1.0)) return ORC_E_INVALID;
+  if (!t->have_moments) return ORC_E_STATE;
+  t->theta = theta;
+  t->m2l.clear();
+  t->p2p.clear();
+  walk_self(*t, 0);
+  std::sort(t->m2l.begin(), t->m2l.end());
+  std::sort(t->p2p.begin(), t->p2p.end());
+  t->have_lists = true;
+  return ORC_OK;
+}
+
+int64_t orc_num_m2l(const orc_tree* t) { return (int64_t)t->m2l.size(); }
+int64_t orc_num_p2p(const orc_tree* t) { return (int64_t)t->p2p.size(); }
+
+void orc_get_lists(const orc_tree* t, int32_t* m2l_ab, int32_t* p2p_ab) {
+  for (size_t i = 0; i < t->m2l.size(); ++i) {
+    m2l_ab[2 * i] = t->m2l[i].first;
+    m2l_ab[2 * i + 1] = t->m2l[i].second;
+  }
+  for (size_t i = 0; i < t->p2p.size(); ++i) {
+    p2p_ab[2 * i] = t->p2p[i].first;
+    p2p_ab[2 * i + 1] = t->p2p[i].second;
+  }
+}
+
+int32_t orc_evaluate(orc_tree* t, int32_t variant, double G, double* ax, double* ay, double* az,
+                     double* pot) {
+  if (!t->have_lists) return ORC_E_STATE;
+  if (variant < ORC_UC || variant > ORC_TCO) return ORC_E_INVALID;
+  int64_t n = t->n;
+  std::vector<double> gx(n, 0.0), gy(n, 0.0), gz(n, 0.0), ph(n, 0.0);
+  // far field: every accepted pair, at every particle of both cells
+  for (const auto& pr : t->m2l) {
+    const Cell& CA = t->cells[pr.first];
+    const Cell& CB = t->cells[pr.second];
+    const Moments& A = t->mom[pr.first];
+    const Moments& B = t->mom[pr.second];
+    PairTerms pt;
+    pair_terms(A, B, variant, pt);
+    for (int64_t p = CA.begin; p < CA.begin + CA.count; ++p) {
+      double xv[3] = {t->x[p] - A.Z[0], t->y[p] - A.Z[1], t->z[p] - A.Z[2]};
+      double g[3];
+      eq3_accel(pt.g, B, xv, g);
+      gx[p] += g[0] + pt.Fc[0] / A.M;
+      gy[p] += g[1] + pt.Fc[1] / A.M;
+      gz[p] += g[2] + pt.Fc[2] / A.M;
+      ph[p] += eq2_pot_A(pt.g, B, xv);
+    }
+    for (int64_t p = CB.begin; p < CB.begin + CB.count; ++p) {
+      double yv[3] = {t->x[p] - B.Z[0], t->y[p] - B.Z[1], t->z[p] - B.Z[2]};
+      double g[3];
+      eq4_accel(pt.g, A, yv, g);
+      gx[p] += g[0] - pt.Fc[0] / B.M;
+      gy[p] += g[1] - pt.Fc[1] / B.M;
+      gz[p] += g[2] - pt.Fc[2] / B.M;
+      ph[p] += eq2_pot_B(pt.g, A, yv);
+    }
+  }
+  // near field: every particle pair of every non-accepted leaf pair, once
+  t->coincident = 0;
+  for (const auto& pr : t->p2p) {
+    const Cell& CA = t->cells[pr.first];
+    const Cell& CB = t->cells[pr.second];
+    bool self = pr.first == pr.second;
+    for (int64_t i = CA.begin; i < CA.begin + CA.count; ++i) {
+      int64_t jb = self ? i + 1 : CB.begin;
+      for (int64_t j = jb; j < CB.begin + CB.count; ++j) {
+        double dx = t->x[j] - t->x[i];
+        double dy = t->y[j] - t->y[i];
+        double dz = t->z[j] - t->z[i];
+        double r2 = (dx * dx + dy * dy) + dz * dz;
+        if (r2 == 0.0) {
+          ++t->coincident;
+          continue;
+        }
+        double r = std::sqrt(r2);
+        double r3 = r2 * r;
+        // acceleration on i towards j and on j towards i
+        gx[i] += t->m[j] * dx / r3;
+        gy[i] += t->m[j] * dy / r3;
+        gz[i] += t->m[j] * dz / r3;
+        gx[j] -= t->m[i] * dx / r3;
+        gy[j] -= t->m[i] * dy / r3;
+        gz[j] -= t->m[i] * dz / r3;
+        ph[i] -= t->m[j] / r;
+        ph[j] -= t->m[i] / r;
+      }
+    }
+  }
+  for (int64_t s = 0; s < n; ++s) {
+    int64_t i = t->perm[s];
+    ax[i] = G * gx[s];
+    ay[i] = G * gy[s];
+    az[i] = G * gz[s];
+    if (pot) pot[i] = G * ph[s];
+  }
+  return ORC_OK;
+}
+
+int32_t orc_evaluate_sample(orc_tree* t, int32_t variant, double G, int64_t ns, const int64_t* idx,
+                            double* ax, double* ay, double* az, double* pot) {
+  if (!t->have_lists) return ORC_E_STATE;
+  if (variant < ORC_UC || variant > ORC_TCO) return ORC_E_INVALID;
+  int64_t n = t->n;
+  // caller index -> sorted position, cell -> partners of each list
+  std::vector<int64_t> pos(n);
+  for (int64_t s = 0; s < n; ++s) pos[t->perm[s]] = s;
+  size_t nc = t->cells.size();
+  std::vector<std::vector<int32_t>> far(nc), near(nc);
+  for (const auto& pr : t->m2l) {
+    far[pr.first].push_back(pr.second);
+    far[pr.second].push_back(pr.first);
+  }
+  for (const auto& pr : t->p2p) {
+    near[pr.first].push_back(pr.second);
+    if (pr.first != pr.second) near[pr.second].push_back(pr.first);
+  }
+  for (int64_t q = 0; q < ns; ++q) {
+    if (idx[q] < 0 || idx[q] >= n) return ORC_E_INVALID;
+    int64_t p = pos[idx[q]];
+    double g[3] = {0.0, 0.0, 0.0}, ph = 0.0;
+    // the leaf holding p, then every ancestor up to the root
+    int32_t c = 0;
+    std::vector<int32_t> chain{0};
+    while (t->cells[c].nchild) {
+      const Cell& C = t->cells[c];
+      int32_t next = -1;
+      for (int32_t k = C.child0; k < C.child0 + C.nchild; ++k)
+        if (p >= t->cells[k].begin && p < t->cells[k].begin + t->cells[k].count) next = k;
+      c = next;
+      chain.push_back(c);
+    }
+    for (int32_t cell : chain) {
+      for (int32_t other : far[cell]) {
+        // the pair is stored once as (lower, higher); the lower index is the
+        // field cell of eq. 3 and the higher that of eq. 4
+        int32_t a = std::min(cell, other), b = std::max(cell, other);
+        PairTerms pt;
+        pair_terms(t->mom[a], t->mom[b], variant, pt);
+        const Moments& own = t->mom[cell];
+        double xv[3] = {t->x[p] - own.Z[0], t->y[p] - own.Z[1], t->z[p] - own.Z[2]};
+        double gg[3];
+        if (cell == a) {
+          eq3_accel(pt.g, t->mom[b], xv, gg);
+          for (int d = 0; d < 3; ++d) g[d] += gg[d] + pt.Fc[d] / own.M;
+          ph += eq2_pot_A(pt.g, t->mom[b], xv);
+        } else {
+          eq4_accel(pt.g, t->mom[a], xv, gg);
+          for (int d = 0; d < 3; ++d) g[d] += gg[d] - pt.Fc[d] / own.M;
+          ph += eq2_pot_B(pt.g, t->mom[a], xv);
+        }
+      }
+    }
+    int32_t leaf = chain.back();
+    for (int32_t other : near[leaf]) {
+      const Cell& O = t->cells[other];
+      for (int64_t j = O.begin; j < O.begin + O.count; ++j) {
+        double dx = t->x[j] - t->x[p];
+        double dy = t->y[j] - t->y[p];
+        double dz = t->z[j] - t->z[p];
+        double r2 = (dx * dx + dy * dy) + dz * dz;
+        if (r2 == 0.0) continue;
+        double r = std::sqrt(r2);
+        double r3 = r2 * r;
+        g[0] += t->m[j] * dx / r3;
+        g[1] += t->m[j] * dy / r3;
+        g[2] += t->m[j] * dz / r3;
+        ph -= t->m[j] / r;
+      }
+    }
+    ax[q] = G * g[0];
+    ay[q] = G * g[1];
+    az[q] = G * g[2];
+    if (pot) pot[q] = G * ph;
+  }
+  return ORC_OK;
+}
+
+int64_t orc_num_coincident(const orc_tree* t) { return t->coincident; }
+
+int32_t orc_solve(int64_t n, const double* x, const double* y, const double* z, const double* m,
+                  double theta, int32_t n_crit, int32_t variant, double G, double* ax, double* ay,
+                  double* az, double* pot) {
+  if (!(theta > 0.0 && theta <= 1.0)) return ORC_E_INVALID;
+  int32_t st = ORC_OK;
+  orc_tree* t = orc_build_tree(n, x, y, z, m, n_crit, kMaxLevel, &st);
+  if (!t) return st;
+  orc_compute_moments(t);
+  st = orc_walk(t, theta);
+  if (st == ORC_OK) st = orc_evaluate(t, variant, G, ax, ay, az, pot);
+  orc_free(t);
+  return st;
+}
+
+int32_t orc_direct(int64_t n, const double* x, const double* y, const double* z, const double* m,
+                   int64_t ntarget, const int64_t* targets, double G, double* ax, double* ay,
+                   double* az, double* pot, double* gabs) {
+  if (n < 1 || ntarget < 0) return ORC_E_INVALID;
+  for (int64_t q = 0; q < ntarget; ++q) {
+    int64_t i = targets ? targets[q] : q;
+    if (i < 0 || i >= n) return ORC_E_INVALID;
+    double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0, sa = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+      double dx = x[j] - x[i];
+      double dy = y[j] - y[i];
+      double dz = z[j] - z[i];
+      double r2 = (dx * dx + dy * dy) + dz * dz;
+      if (r2 == 0.0) continue;
+      double r = std::sqrt(r2);
+      double r3 = r2 * r;
+      sx += m[j] * dx / r3;
+      sy += m[j] * dy / r3;
+      sz += m[j] * dz / r3;
+      sp -= m[j] / r;
+      sa += m[j] / r2;
+    }
+    ax[q] = G * sx;
+    ay[q] = G * sy;
+    az[q] = G * sz;
+    if (pot) pot[q] = G * sp;
+    if (gabs) gabs[q] = G * sa;
+  }
+  return ORC_OK;
+}
+
+void orc_greens(const double* R3, double* D0, double* D1, double* D2, double* D3, double* D4,
+                double* D4p) {
+  Greens g;
+  greens(R3, g, true);
+  *D0 = g.D0;
+  std::memcpy(D1, g.D1, sizeof(g.D1));
+  std::memcpy(D2, g.D2, sizeof(g.D2));
+  std::memcpy(D3, g.D3, sizeof(g.D3));
+  std::memcpy(D4, g.D4, sizeof(g.D4));
+  std::memcpy(D4p, g.D4p, sizeof(g.D4p));
+}
+
+void orc_cluster_moments(int64_t n, const double* x, const double* y, const double* z,
+                         const double* m, double* out21) {
+  int32_t st;
+  orc_tree* t = orc_build_tree(n, x, y, z, m, (int32_t)n, 0, &st);  // one leaf
+  if (!t) return;
+  // keep caller order inside the single leaf so the sums run in caller order
+  for (int64_t i = 0; i < n; ++i) {
+    t->x[i] = x[i];
+    t->y[i] = y[i];
+    t->z[i] = z[i];
+    t->m[i] = m[i];
+    t->perm[i] = i;
+  }
+  orc_compute_moments(t);
+  orc_get_moments(t, out21);
+  orc_free(t);
+}
+
+void orc_pair_far(int64_t nA, const double* xa, const double* ya, const double* za,
+                  const double* ma, int64_t nB, const double* xb, const double* yb,
+                  const double* zb, const double* mb, int32_t variant, double* gA, double* phiA,
+                  double* gB, double* phiB) {
+  // moments of each cluster as one cell, particles in caller order
+  auto cluster = [](int64_t n, const double* x, const double* y, const double* z,
+                    const double* m) {
+    orc_tree* t = new orc_tree();
+    t->n = n;
+    t->x.assign(x, x + n);
+    t->y.assign(y, y + n);
+    t->z.assign(z, z + n);
+    t->m.assign(m, m + n);
+    Cell c{0, 0, n, -1, -1, 0, 0};
+    t->cells.push_back(c);
+    Moments mo;
+    for (int64_t p = 0; p < n; ++p) {
+      mo.M += m[p];
+      mo.S[0] += m[p] * x[p];
+      mo.S[1] += m[p] * y[p];
+      mo.S[2] += m[p] * z[p];
+    }
+    for (int d = 0; d < 3; ++d) mo.Z[d] = mo.S[d] / mo.M;
+    moments_about(*t, 0, n, mo);
+    t->mom.push_back(mo);
+    return t;
+  };
+  orc_tree* ta = cluster(nA, xa, ya, za, ma);
+  orc_tree* tb = cluster(nB, xb, yb, zb, mb);
+  const Moments& A = ta->mom[0];
+  const Moments& B = tb->mom[0];
+  PairTerms pt;
+  pair_terms(A, B, variant, pt);
+  for (int64_t p = 0; p < nA; ++p) {
+    double xv[3] = {xa[p] - A.Z[0], ya[p] - A.Z[1], za[p] - A.Z[2]};
+    double g[3];
+    eq3_accel(pt.g, B, xv, g);
+    for (int d = 0; d < 3; ++d) gA[3 * p + d] = g[d] + pt.Fc[d] / A.M;
+    if (phiA) phiA[p] = eq2_pot_A(pt.g, B, xv);
+  }
+  for (int64_t p = 0; p < nB; ++p) {
+    double yv[3] = {xb[p] - B.Z[0], yb[p] - B.Z[1], zb[p] - B.Z[2]};
+    double g[3];
+    eq4_accel(pt.g, A, yv, g);
+    for (int d = 0; d < 3; ++d) gB[3 * p + d] = g[d] - pt.Fc[d] / B.M;
+    if (phiB) phiB[p] = eq2_pot_B(pt.g, A, yv);
+  }
+  delete ta;
+  delete tb;
+}
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+/*
+ * CPU FP64 oracle for the angular-momentum-conserving Cartesian FMM
+ * (Marcello 2017, "A Very Fast And Angular Momentum Conserving Tree Code").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, plain reference that
+ * the GPU library is judged against.  Only the test-suite, the smoke check and
+ * the CPU-baseline leg of the benchmark may load it; the GPU solver never
+ * calls, links or includes anything from here, and nothing here is shared
+ * with it.
+ *
+ * Every routine follows the paper's definitions directly (full index loops,
+ * no symmetry packing, no blocking):
+ *   - octree with at most n_crit particles per leaf          (Sec. 2)
+ *   - centre of mass Z and R_max of every cell               (Sec. 2, opening criterion)
+ *   - moments M, M_ij, M_ijk about Z                          (Sec. 2, eqs. 1, quad, octupole def.)
+ *   - Green's function derivatives D .. D_ijk (printed), D_ijkl (fourth
+ *     derivative, Sec. 2 eq. 7 text; closed form derived), D'_ijkl (eq. 8)
+ *   - far field of an accepted pair, eqs. 2-4, evaluated at every particle
+ *   - torque correction F_c, eq. 7 with the prefactor of the appendix (1/6)
+ *   - direct near field between particles of non-accepted leaf pairs
+ *
+ * All arrays are host memory owned by the caller.  Functions return 0 on
+ * success and a negative code on invalid input (see ORC_E_*).
+ */
+#ifndef AMFMM_ORACLE_H
+#define AMFMM_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_OK 0
+#define ORC_E_INVALID (-1)
+#define ORC_E_NONFINITE (-2)
+#define ORC_E_STATE (-5)
+
+/* variants of Sec. 3: UC = uncorrected, TC = eq. 7, TCO = eq. 8 */
+#define ORC_UC 0
+#define ORC_TC 1
+#define ORC_TCO 2
+
+typedef struct orc_tree orc_tree;
+
+/* Steps: bounding cube + Morton keys, stable sort, octree (Sec. 2).
+ * n >= 1, all inputs finite, m > 0.  max_level <= 21.  Returns NULL and sets
+ * *status on invalid input. */
+orc_tree* orc_build_tree(int64_t n, const double* x, const double* y, const double* z,
+                         const double* m, int32_t n_crit, int32_t max_level, int32_t* status);
+void orc_free(orc_tree* t);
+
+int64_t orc_num_cells(const orc_tree* t);
+int32_t orc_depth(const orc_tree* t); /* deepest level present */
+/* bounding cube: lo[3], side, scale */
+void orc_get_cube(const orc_tree* t, double* lo3, double* side, double* scale);
+/* sorted keys and permutation: perm[s] = caller index of the s-th sorted particle */
+void orc_get_keys(const orc_tree* t, uint64_t* keys, int64_t* perm);
+/* cells in (level, first particle) order */
+void orc_get_cells(const orc_tree* t, int32_t* level, int64_t* begin, int64_t* count,
+                   int32_t* parent, int32_t* child0, int32_t* nchild);
+
+/* Upward pass: M, Z, R_max, M_ij, M_ijk of every cell. */
+int32_t orc_compute_moments(orc_tree* t);
+/* per cell 21 doubles: M, Zx,Zy,Zz, Rmax, M_xx,M_xy,M_xz,M_yy,M_yz,M_zz,
+ * M_xxx,M_xxy,M_xxz,M_xyy,M_xyz,M_xzz,M_yyy,M_yyz,M_yzz,M_zzz */
+void orc_get_moments(const orc_tree* t, double* out21);
+
+/* Dual tree walk under the opening criterion (Sec. 2).  theta in (0,1]. */
+int32_t orc_walk(orc_tree* t, double theta);
+int64_t orc_num_m2l(const orc_tree* t);
+int64_t orc_num_p2p(const orc_tree* t);
+/* unordered pairs {a,b}: m2l with a<b, p2p with a<=b, each list sorted */
+void orc_get_lists(const orc_tree* t, int32_t* m2l_ab, int32_t* p2p_ab);
+
+/* Evaluation: far field (eqs. 2-4) + correction of the variant + near field.
+ * Outputs in caller order, scaled by G.  pot may be NULL. */
+int32_t orc_evaluate(orc_tree* t, int32_t variant, double G, double* ax, double* ay, double* az,
+                     double* pot);
+/* The same evaluation at a sample of particles only (caller indices idx[0..ns)),
+ * for checks at sizes where evaluating every particle is too slow.  Needs the
+ * walk.  Outputs are per sample entry. */
+int32_t orc_evaluate_sample(orc_tree* t, int32_t variant, double G, int64_t ns, const int64_t* idx,
+                            double* ax, double* ay, double* az, double* pot);
+/* number of particle pairs skipped because they coincide (r == 0, i != j) */
+int64_t orc_num_coincident(const orc_tree* t);
+
+/* Whole solve in one call (build, moments, walk, evaluate). */
+int32_t orc_solve(int64_t n, const double* x, const double* y, const double* z, const double* m,
+                  double theta, int32_t n_crit, int32_t variant, double G, double* ax, double* ay,
+                  double* az, double* pot);
+
+/* Direct summation (the exact result the method approximates).  For each
+ * target index t (all particles when targets == NULL, ntarget = n) returns the
+ * acceleration, the potential and gabs = sum_j m_j / r^2 (the magnitude scale
+ * of the sum).  Coincident pairs are skipped. */
+int32_t orc_direct(int64_t n, const double* x, const double* y, const double* z, const double* m,
+                   int64_t ntarget, const int64_t* targets, double G, double* ax, double* ay,
+                   double* az, double* pot, double* gabs);
+
+/* Building blocks exposed for the pins. */
+/* full tensors: D0[1], D1[3], D2[9], D3[27], D4[81], D4p[81] at R (Sec. 2) */
+void orc_greens(const double* R3, double* D0, double* D1, double* D2, double* D3, double* D4,
+                double* D4p);
+/* Moments of one cluster (as one cell): out21 as in orc_get_moments. */
+void orc_cluster_moments(int64_t n, const double* x, const double* y, const double* z,
+                         const double* m, double* out21);
+/* One accepted pair (cluster A = field of eq. 3, cluster B = field of eq. 4),
+ * evaluated at every particle of both, with the correction of the variant.
+ * Outputs are accelerations (3 per particle, interleaved xyz) and potentials. */
+void orc_pair_far(int64_t nA, const double* xa, const double* ya, const double* za,
+                  const double* ma, int64_t nB, const double* xb, const double* yb,
+                  const double* zb, const double* mb, int32_t variant, double* gA, double* phiA,
+                  double* gB, double* phiB);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,60 @@
+"""The pins must catch plausible mistakes in the oracle.
+
+Each case plants one mistake in a copy of the oracle's source (CPU only),
+builds it, and runs the oracle's pin suite against that copy, which must then
+fail.  The mistakes cover every step: keys, tree, moments, walk, the Green's
+function derivatives, eqs. 2-4, the correction of eq. 7 (prefactor and sign)
+and the near field.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "oracle.cpp")
+
+PINS = ["tests/test_oracle_greens.py", "tests/test_oracle_tree.py", "tests/test_oracle_moments.py",
+        "tests/test_oracle_pair.py", "tests/test_oracle_solve.py"]
+
+MUTATIONS = {
+    "correction_prefactor_half": ("pt.Fc[i] = -(1.0 / 6.0) * s;", "pt.Fc[i] = -(0.5) * s;"),
+    "correction_sign": ("pt.Fc[i] = -(1.0 / 6.0) * s;", "pt.Fc[i] = (1.0 / 6.0) * s;"),
+    "separation_sign": ("double R[3] = {A.Z[0] - B.Z[0], A.Z[1] - B.Z[1], A.Z[2] - B.Z[2]};",
+                        "double R[3] = {B.Z[0] - A.Z[0], B.Z[1] - A.Z[1], B.Z[2] - A.Z[2]};"),
+    "eq3_quadrupole_half_dropped": ("    c0 += 0.5 * q;", "    c0 += q;"),
+    "eq4_cubic_sign": ("out[i] = -(c0 + c1 - 0.5 * c2);", "out[i] = -(c0 + c1 + 0.5 * c2);"),
+    "d3_coefficient": ("(15.0 * R[i] * R[j] * R[k] -", "(5.0 * R[i] * R[j] * R[k] -"),
+    "d4_coefficient": ("double t4 = -105.0 *", "double t4 = -15.0 *"),
+    "d4prime_extra_term": ("g.D4p[i][j][k][l] = p2 + t0;", "g.D4p[i][j][k][l] = p2 + t0 + t4;"),
+    "quadrupole_without_mass": ("mo.M2[i][j] += mu * xv[i] * xv[j];", "mo.M2[i][j] += xv[i] * xv[j];"),
+    "octupole_transposed": ("mo.M3[i][j][k] += mu * xv[i] * xv[j] * xv[k];",
+                            "mo.M3[i][j][k] += mu * xv[i] * xv[j] * xv[j];"),
+    "criterion_one_radius": ("double rhs = (A.Rmax + B.Rmax) / t.theta;", "double rhs = (A.Rmax) / t.theta;"),
+    "key_bits_swapped": ("key |= ((q[0] >> b) & 1) << (3 * b + 2);", "key |= ((q[0] >> b) & 1) << (3 * b + 1);"),
+    "split_at_ncrit": ("if (!(cur.count > n_crit && lev < max_level)) continue;",
+                       "if (!(cur.count >= n_crit && lev < max_level)) continue;"),
+    "near_field_no_reaction": ("gx[j] -= t->m[i] * dx / r3;", "gx[j] -= 0.0 * dx / r3;"),
+    "potential_quadratic_half": ("return p + 0.5 * s2 + (1.0 / 6.0) * s3;", "return p + s2 + (1.0 / 6.0) * s3;"),
+    "self_walk_skips_pairs": ("for (int32_t b = a + 1; b < C.child0 + C.nchild; ++b) walk_pair(t, a, b);",
+                              "for (int32_t b = a + 2; b < C.child0 + C.nchild; ++b) walk_pair(t, a, b);"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistake_is_caught(name, tmp_path):
+    old, new = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor not unique/present: {old}"
+    mut = tmp_path / "oracle_mut.cpp"
+    mut.write_text(src.replace(old, new))
+    inc = os.path.join(ROOT, "oracle")
+    so = tmp_path / "liboracle_mut.so"
+    subprocess.run(["g++", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-std=c++17",
+                    "-I", inc, str(mut), "-o", str(so)], check=True)
+    env = dict(os.environ, AMFMM_ORACLE_LIB=str(so))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        "-m", "not gpu"] + PINS, cwd=ROOT, env=env, capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode != 0, f"planted mistake {name} passed every pin:\n{r.stdout[-2000:]}"
