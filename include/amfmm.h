@@ -1,0 +1,145 @@
+/*
+ * amfmm: angular-momentum-conserving Cartesian fast multipole gravity solver
+ * for AMD Instinct MI355X (gfx950), after Marcello 2017, "A Very Fast And
+ * Angular Momentum Conserving Tree Code" (a modification of Dehnen's symmetric
+ * Cartesian FMM).
+ *
+ * C ABI of libamfmm_hip.so.  Every array argument named as a device pointer is
+ * memory on the current HIP device, owned by the caller; the library never
+ * frees it and never keeps it beyond the call.  All work is enqueued on the
+ * stream given to amfmm_create; calls return after enqueueing, except where a
+ * size must be read back (validation, tree levels, walk levels), which
+ * synchronises that stream.  A context is not thread-safe: use one per stream.
+ * Functions return AMFMM_OK (0) or a negative amfmm_status; nothing throws
+ * across this boundary, and amfmm_last_error() describes the last failure.
+ */
+#ifndef AMFMM_H
+#define AMFMM_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AMFMM_OK = 0,
+  AMFMM_E_INVALID = -1,   /* bad size, theta outside (0,1], m <= 0, bad option */
+  AMFMM_E_NONFINITE = -2, /* a NaN or infinite position or mass */
+  AMFMM_E_OOM = -3,       /* device allocation failed or exceeds the context cap */
+  AMFMM_E_HIP = -4,       /* a HIP runtime call failed */
+  AMFMM_E_STATE = -5      /* call order violated (e.g. moments before a tree) */
+} amfmm_status;
+
+/* Variants of Sec. 3: UC = the uncorrected method, TC = torque correction of
+ * eq. 7, TCO = the alternative correction of eq. 8. */
+typedef enum { AMFMM_UC = 0, AMFMM_TC = 1, AMFMM_TCO = 2 } amfmm_variant;
+
+/* Arithmetic of the near field and of the far-field coefficients.
+ * FP64: everything in double precision.
+ * MIXED: pair terms in FP32 on offsets taken relative to cell centres (the
+ * centre-to-centre vector formed in FP64), summed per particle into FP64 with
+ * compensated (two-sum) accumulation; centres of mass, the moment reduction
+ * and the correction of eq. 7/8 stay in FP64. */
+typedef enum { AMFMM_FP64 = 0, AMFMM_MIXED = 1 } amfmm_precision;
+
+/* Accept/open decision of the walk: the geometric opening criterion of Sec. 2,
+ * or the learned error estimate (falls back to the geometric rule when no
+ * network is loaded). */
+typedef enum { AMFMM_GEOMETRIC = 0, AMFMM_LEARNED = 1 } amfmm_criterion;
+
+typedef struct {
+  int32_t n_crit;     /* most particles in a leaf; the paper runs 25 (Sec. 2) */
+  int32_t variant;    /* amfmm_variant */
+  int32_t precision;  /* amfmm_precision */
+  int32_t criterion;  /* amfmm_criterion */
+  double G;           /* gravitational constant applied to all outputs */
+  double learned_tol; /* learned criterion: accept when the predicted pair error <= tol */
+  double theta_max;   /* learned criterion: pairs with (R_A+R_B)/d > theta_max always open */
+  int64_t max_bytes;  /* cap on device scratch owned by the context (0 = no cap) */
+} amfmm_options;
+
+typedef struct amfmm_ctx amfmm_ctx;
+
+/* Fills *opt with n_crit = 25, TC, FP64, geometric, G = 1, learned_tol = 1e-4,
+ * theta_max = 1, max_bytes = 0. */
+int amfmm_default_options(amfmm_options* opt);
+
+/* Creates a context bound to hip_stream (a hipStream_t; NULL = null stream)
+ * on the current device.  The context owns all scratch. */
+int amfmm_create(const amfmm_options* opt, void* hip_stream, amfmm_ctx** out);
+int amfmm_destroy(amfmm_ctx* ctx);
+/* Rebinds the context to another stream of the same device. */
+int amfmm_set_stream(amfmm_ctx* ctx, void* hip_stream);
+
+/* Sec. 2, the octree: bounding cube, 63-bit Morton keys (21 bits per
+ * coordinate), stable radix sort by key, and cells that split while they hold
+ * more than n_crit particles (below level 21).  x,y,z,m: device pointers to n
+ * doubles each (SoA, any order); 1 <= n < 2^31, all finite, m > 0.  Inputs are
+ * copied into sorted order; the caller's arrays are only read. */
+int amfmm_build_tree(amfmm_ctx* ctx, int64_t n, const double* x, const double* y, const double* z,
+                     const double* m);
+
+/* Sec. 2, upward pass: mass M (eq. 1), centre of mass Z, quadrupole M_ij (eq.
+ * quad) and octupole M_ijk about Z, and R_max (largest particle distance to Z)
+ * of every cell.  Needs amfmm_build_tree, else AMFMM_E_STATE. */
+int amfmm_compute_moments(amfmm_ctx* ctx);
+
+/* Sec. 2, interaction selection: a symmetric dual walk accepting cell pairs
+ * with |Z_A - Z_B| >= (R_A,max + R_B,max)/theta (far field), leaf pairs that
+ * fail go to direct summation.  theta in (0,1].  Needs moments. */
+int amfmm_walk(amfmm_ctx* ctx, double theta);
+
+/* Far field (eqs. 2-4 with the correction of the variant, eq. 7 or 8) pushed
+ * down to the particles, plus the direct near field.  Writes accelerations
+ * (device pointers ax, ay, az; n doubles each, caller order) and potentials
+ * (pot, may be NULL), scaled by G.  The potential excludes the self term and
+ * the correction (a force only).  Needs the walk. */
+int amfmm_evaluate(amfmm_ctx* ctx, double* ax, double* ay, double* az, double* pot);
+
+/* The whole solve: build_tree + compute_moments + walk + evaluate. */
+int amfmm_solve_gravity(amfmm_ctx* ctx, int64_t n, const double* x, const double* y,
+                        const double* z, const double* m, double theta, double* ax, double* ay,
+                        double* az, double* pot);
+
+/* Direct summation at ntarget particles (device int64 indices; NULL = all n
+ * particles in order): the exact sum that the method approximates (Sec. 3,
+ * g_PP).  Coincident particles are skipped.  Outputs are device arrays of
+ * ntarget doubles (pot and gabs may be NULL; gabs = G * sum_j m_j / r^2). */
+int amfmm_direct(amfmm_ctx* ctx, int64_t n, const double* x, const double* y, const double* z,
+                 const double* m, int64_t ntarget, const int64_t* targets, double* ax, double* ay,
+                 double* az, double* pot, double* gabs);
+
+/* Sec. 3 net balances of an acceleration field, sqrt(sum_d (sum_n m A_nd)^2 /
+ * sum_d (sum_n m |A_nd|)^2) for A = g (out[0]) and A = X x g (out[1]), summed
+ * on the device with compensated sums.  out: host pointer to 2 doubles;
+ * synchronises the stream. */
+int amfmm_balance(amfmm_ctx* ctx, int64_t n, const double* x, const double* y, const double* z,
+                  const double* m, const double* ax, const double* ay, const double* az,
+                  double* out);
+
+/* ---- introspection (host buffers owned by the caller; synchronising) ---- */
+/* counts[0..5] = cells, depth, far-field pairs, near-field pairs (unordered,
+ * as amfmm_get_lists returns them), leaves, particles */
+int amfmm_get_counts(amfmm_ctx* ctx, int64_t* counts6);
+/* sorted keys (n), permutation perm[s] = caller index of sorted particle s (n),
+ * and per cell (in (level, first particle) order): level, begin, count,
+ * parent, first child (-1 for leaves), child count.  Any pointer may be NULL. */
+int amfmm_get_tree(amfmm_ctx* ctx, uint64_t* keys, int64_t* perm, int32_t* level, int64_t* begin,
+                   int64_t* count, int32_t* parent, int32_t* child0, int32_t* nchild);
+/* 21 doubles per cell: M, Zx, Zy, Zz, R_max, M_xx, M_xy, M_xz, M_yy, M_yz,
+ * M_zz, M_xxx, M_xxy, M_xxz, M_xyy, M_xyz, M_xzz, M_yyy, M_yyz, M_yzz, M_zzz */
+int amfmm_get_moments(amfmm_ctx* ctx, double* out21);
+/* unordered pairs (2 int32 each), sorted: far field {a<b}, near field {a<=b} */
+int amfmm_get_lists(amfmm_ctx* ctx, int32_t* far_ab, int32_t* near_ab);
+/* milliseconds of the phases of the last solve: [0] validate+bbox, [1] keys+sort,
+ * [2] tree levels, [3] moments, [4] walk, [5] far field, [6] push-down,
+ * [7] near field + evaluation at particles, [8] total.  Returns the count written. */
+int amfmm_get_phase_times(amfmm_ctx* ctx, double* ms, int32_t cap);
+
+const char* amfmm_status_string(int status);
+const char* amfmm_last_error(amfmm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

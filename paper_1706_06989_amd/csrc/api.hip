@@ -1,0 +1,403 @@
+// C ABI of libamfmm_hip.so: context, scratch arena, phase sequencing,
+// timing and introspection.  Internal errors are C++ exceptions that never
+// cross the ABI: every entry point turns them into an amfmm_status.
+#include <algorithm>
+#include <cstring>
+#include <utility>
+
+#include "internal.h"
+
+struct amfmm_ctx {
+  amfmm::Ctx c;
+};
+
+namespace amfmm {
+
+static void release(Ctx& c, DevBuf& b) {
+  if (b.p) {
+    (void)hipFree(b.p);
+    c.bytes -= b.cap;
+    b.p = nullptr;
+    b.cap = 0;
+  }
+}
+
+static void* alloc(Ctx& c, size_t bytes) {
+  if (c.opt.max_bytes > 0 && (int64_t)(c.bytes + bytes) > c.opt.max_bytes)
+    throw Error(AMFMM_E_OOM, "device scratch would exceed max_bytes (" + std::to_string(c.bytes + bytes) + " bytes)");
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(AMFMM_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+  }
+  c.bytes += bytes;
+  return p;
+}
+
+void* ensure(Ctx& c, DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  if (b.cap >= bytes) return b.p;
+  release(c, b);
+  size_t want = bytes + bytes / 4;
+  b.p = alloc(c, want);
+  b.cap = want;
+  return b.p;
+}
+
+void* ensure_keep(Ctx& c, DevBuf& b, size_t bytes, size_t keep) {
+  if (bytes == 0) bytes = 8;
+  if (b.cap >= bytes) return b.p;
+  size_t want = bytes + bytes / 4;
+  void* p = alloc(c, want);
+  if (b.p && keep) AMFMM_HIP(hipMemcpyAsync(p, b.p, std::min(keep, b.cap), hipMemcpyDeviceToDevice, c.stream));
+  if (b.p) {
+    AMFMM_HIP(hipStreamSynchronize(c.stream));
+    release(c, b);
+  }
+  b.p = p;
+  b.cap = want;
+  return b.p;
+}
+
+void sync(Ctx& c) { AMFMM_HIP(hipStreamSynchronize(c.stream)); }
+
+static DevBuf* all_bufs(Ctx& c, int i) {
+  DevBuf* v[] = {&c.pos4, &c.keys, &c.perm, &c.keys2, &c.perm2, &c.bbox, &c.scratch, &c.scratch2, &c.hist,
+                 &c.c_begin, &c.c_count, &c.c_parent, &c.c_child0, &c.c_nchild, &c.leaves, &c.geo, &c.mom,
+                 &c.msum, &c.loc, &c.far_start, &c.far_count, &c.far_src, &c.near_start, &c.near_count,
+                 &c.near_src, &c.fx, &c.fy, &c.fx2, &c.fy2, &c.fcnt, &c.grp};
+  const int nv = (int)(sizeof(v) / sizeof(v[0]));
+  return i < nv ? v[i] : nullptr;
+}
+
+static void record(Ctx& c, int i) {
+  if (c.ev_ok) AMFMM_HIP(hipEventRecord(c.ev[i], c.stream));
+}
+
+}  // namespace amfmm
+
+using amfmm::Ctx;
+using amfmm::Error;
+
+template <typename F>
+static int guarded(amfmm_ctx* ctx, F&& f) {
+  if (!ctx) return AMFMM_E_INVALID;
+  try {
+    return f(ctx->c);
+  } catch (const Error& e) {
+    ctx->c.last_error = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    ctx->c.last_error = e.what();
+    return AMFMM_E_HIP;
+  }
+}
+
+template <typename T>
+static std::vector<T> fetch(Ctx& c, const void* dev, size_t count) {
+  std::vector<T> h(count);
+  if (count) AMFMM_HIP(hipMemcpyAsync(h.data(), dev, sizeof(T) * count, hipMemcpyDeviceToHost, c.stream));
+  AMFMM_HIP(hipStreamSynchronize(c.stream));
+  return h;
+}
+
+static int fail(Ctx& c, int code, const char* msg) {
+  c.last_error = msg;
+  return code;
+}
+
+extern "C" {
+
+int amfmm_default_options(amfmm_options* o) {
+  if (!o) return AMFMM_E_INVALID;
+  o->n_crit = 25;
+  o->variant = AMFMM_TC;
+  o->precision = AMFMM_FP64;
+  o->criterion = AMFMM_GEOMETRIC;
+  o->G = 1.0;
+  o->learned_tol = 1e-4;
+  o->theta_max = 1.0;
+  o->max_bytes = 0;
+  return AMFMM_OK;
+}
+
+static int check_options(const amfmm_options* o) {
+  if (o->n_crit < 1 || o->n_crit > 4096) return AMFMM_E_INVALID;
+  if (o->variant < AMFMM_UC || o->variant > AMFMM_TCO) return AMFMM_E_INVALID;
+  if (o->precision != AMFMM_FP64 && o->precision != AMFMM_MIXED) return AMFMM_E_INVALID;
+  if (o->criterion != AMFMM_GEOMETRIC && o->criterion != AMFMM_LEARNED) return AMFMM_E_INVALID;
+  if (!(o->G == o->G) || o->max_bytes < 0) return AMFMM_E_INVALID;
+  return AMFMM_OK;
+}
+
+int amfmm_create(const amfmm_options* opt, void* stream, amfmm_ctx** out) {
+  if (!out) return AMFMM_E_INVALID;
+  *out = nullptr;
+  amfmm_options o;
+  amfmm_default_options(&o);
+  if (opt) o = *opt;
+  if (check_options(&o) != AMFMM_OK) return AMFMM_E_INVALID;
+  amfmm_ctx* ctx = new amfmm_ctx();
+  ctx->c.opt = o;
+  ctx->c.stream = (hipStream_t)stream;
+  if (hipGetDevice(&ctx->c.device) != hipSuccess) {
+    delete ctx;
+    return AMFMM_E_HIP;
+  }
+  bool ok = true;
+  for (auto& e : ctx->c.ev) ok = ok && hipEventCreate(&e) == hipSuccess;
+  ctx->c.ev_ok = ok;
+  *out = ctx;
+  return AMFMM_OK;
+}
+
+int amfmm_destroy(amfmm_ctx* ctx) {
+  if (!ctx) return AMFMM_E_INVALID;
+  Ctx& c = ctx->c;
+  (void)hipStreamSynchronize(c.stream);
+  for (int i = 0; amfmm::all_bufs(c, i); ++i) amfmm::release(c, *amfmm::all_bufs(c, i));
+  for (auto& e : c.ev)
+    if (e) (void)hipEventDestroy(e);
+  delete ctx;
+  return AMFMM_OK;
+}
+
+int amfmm_set_stream(amfmm_ctx* ctx, void* stream) {
+  return guarded(ctx, [&](Ctx& c) -> int {
+    c.stream = (hipStream_t)stream;
+    return AMFMM_OK;
+  });
+}
+
+static int build_tree_impl(Ctx& c, int64_t n, const double* x, const double* y, const double* z,
+                           const double* m) {
+  if (n < 1 || n >= (int64_t)INT32_MAX) return fail(c, AMFMM_E_INVALID, "n must be in [1, 2^31)");
+  if (!x || !y || !z || !m) return fail(c, AMFMM_E_INVALID, "null input pointer");
+  c.have_tree = c.have_moments = c.have_lists = false;
+  amfmm::record(c, 0);
+  int st = amfmm::bbox_validate(c, x, y, z, m, n);
+  if (st == AMFMM_E_NONFINITE) return fail(c, st, "non-finite position or mass");
+  if (st != AMFMM_OK) return fail(c, st, "masses must be positive");
+  amfmm::record(c, 1);
+  amfmm::build_keys_sort(c, x, y, z, m, n);
+  amfmm::record(c, 2);
+  amfmm::build_levels(c);
+  amfmm::record(c, 3);
+  c.have_tree = true;
+  return AMFMM_OK;
+}
+
+int amfmm_build_tree(amfmm_ctx* ctx, int64_t n, const double* x, const double* y, const double* z,
+                     const double* m) {
+  return guarded(ctx, [&](Ctx& c) -> int { return build_tree_impl(c, n, x, y, z, m); });
+}
+
+static int moments_impl(Ctx& c) {
+  if (!c.have_tree) return fail(c, AMFMM_E_STATE, "compute_moments needs build_tree");
+  amfmm::upward_pass(c);
+  amfmm::record(c, 4);
+  return AMFMM_OK;
+}
+
+int amfmm_compute_moments(amfmm_ctx* ctx) {
+  return guarded(ctx, [&](Ctx& c) -> int { return moments_impl(c); });
+}
+
+static int walk_impl(Ctx& c, double theta) {
+  if (!(theta > 0.0 && theta <= 1.0)) return fail(c, AMFMM_E_INVALID, "theta must lie in (0, 1]");
+  if (!c.have_moments) return fail(c, AMFMM_E_STATE, "walk needs compute_moments");
+  amfmm::dual_walk(c, theta);
+  amfmm::record(c, 5);
+  return AMFMM_OK;
+}
+
+int amfmm_walk(amfmm_ctx* ctx, double theta) {
+  return guarded(ctx, [&](Ctx& c) -> int { return walk_impl(c, theta); });
+}
+
+static int evaluate_impl(Ctx& c, double* ax, double* ay, double* az, double* pot) {
+  if (!c.have_lists) return fail(c, AMFMM_E_STATE, "evaluate needs walk");
+  if (!ax || !ay || !az) return fail(c, AMFMM_E_INVALID, "null output pointer");
+  amfmm::far_field(c);
+  amfmm::record(c, 6);
+  amfmm::push_down(c);
+  amfmm::record(c, 7);
+  amfmm::near_field(c, ax, ay, az, pot);
+  amfmm::record(c, 8);
+  return AMFMM_OK;
+}
+
+int amfmm_evaluate(amfmm_ctx* ctx, double* ax, double* ay, double* az, double* pot) {
+  return guarded(ctx, [&](Ctx& c) -> int { return evaluate_impl(c, ax, ay, az, pot); });
+}
+
+int amfmm_solve_gravity(amfmm_ctx* ctx, int64_t n, const double* x, const double* y, const double* z,
+                        const double* m, double theta, double* ax, double* ay, double* az, double* pot) {
+  return guarded(ctx, [&](Ctx& c) -> int {
+    if (!(theta > 0.0 && theta <= 1.0)) return fail(c, AMFMM_E_INVALID, "theta must lie in (0, 1]");
+    if (!ax || !ay || !az) return fail(c, AMFMM_E_INVALID, "null output pointer");
+    int st = build_tree_impl(c, n, x, y, z, m);
+    if (st) return st;
+    if ((st = moments_impl(c))) return st;
+    if ((st = walk_impl(c, theta))) return st;
+    return evaluate_impl(c, ax, ay, az, pot);
+  });
+}
+
+int amfmm_direct(amfmm_ctx* ctx, int64_t n, const double* x, const double* y, const double* z,
+                 const double* m, int64_t ntarget, const int64_t* targets, double* ax, double* ay,
+                 double* az, double* pot, double* gabs) {
+  return guarded(ctx, [&](Ctx& c) -> int {
+    if (n < 1 || ntarget < 0) return fail(c, AMFMM_E_INVALID, "bad sizes");
+    if (!x || !y || !z || !m || !ax || !ay || !az) return fail(c, AMFMM_E_INVALID, "null pointer");
+    if (!targets && ntarget > n) return fail(c, AMFMM_E_INVALID, "ntarget > n without target indices");
+    amfmm::direct_sum(c, n, x, y, z, m, ntarget, targets, ax, ay, az, pot, gabs);
+    return AMFMM_OK;
+  });
+}
+
+int amfmm_balance(amfmm_ctx* ctx, int64_t n, const double* x, const double* y, const double* z,
+                  const double* m, const double* ax, const double* ay, const double* az, double* out) {
+  return guarded(ctx, [&](Ctx& c) -> int {
+    if (n < 1 || !out) return fail(c, AMFMM_E_INVALID, "bad arguments");
+    amfmm::balance(c, n, x, y, z, m, ax, ay, az, out);
+    return AMFMM_OK;
+  });
+}
+
+int amfmm_get_counts(amfmm_ctx* ctx, int64_t* counts) {
+  return guarded(ctx, [&](Ctx& c) -> int {
+    if (!counts) return fail(c, AMFMM_E_INVALID, "null pointer");
+    counts[0] = c.have_tree ? c.ncells : 0;
+    counts[1] = c.have_tree ? c.depth : 0;
+    counts[2] = c.have_lists ? c.n_far / 2 : 0;
+    counts[3] = c.have_lists ? (c.n_near + c.nleaves) / 2 : 0;
+    counts[4] = c.have_tree ? c.nleaves : 0;
+    counts[5] = c.have_tree ? c.n : 0;
+    return AMFMM_OK;
+  });
+}
+
+int amfmm_get_tree(amfmm_ctx* ctx, uint64_t* keys, int64_t* perm, int32_t* level, int64_t* begin,
+                   int64_t* count, int32_t* parent, int32_t* child0, int32_t* nchild) {
+  return guarded(ctx, [&](Ctx& c) -> int {
+    if (!c.have_tree) return fail(c, AMFMM_E_STATE, "no tree");
+    const size_t n = (size_t)c.n, nc = (size_t)c.ncells;
+    if (keys) {
+      auto k = fetch<uint64_t>(c, c.keys.p, n);
+      std::memcpy(keys, k.data(), n * sizeof(uint64_t));
+    }
+    if (perm) {
+      auto p = fetch<int32_t>(c, c.perm.p, n);
+      for (size_t i = 0; i < n; ++i) perm[i] = p[i];
+    }
+    if (level)
+      for (size_t l = 0; l + 1 < c.level_start.size(); ++l)
+        for (int32_t q = c.level_start[l]; q < c.level_start[l + 1]; ++q) level[q] = (int32_t)l;
+    auto cp = [&](const amfmm::DevBuf& b, auto* dst) {
+      if (!dst) return;
+      auto v = fetch<int32_t>(c, b.p, nc);
+      for (size_t i = 0; i < nc; ++i) dst[i] = v[i];
+    };
+    cp(c.c_begin, begin);
+    cp(c.c_count, count);
+    cp(c.c_parent, parent);
+    cp(c.c_child0, child0);
+    cp(c.c_nchild, nchild);
+    return AMFMM_OK;
+  });
+}
+
+int amfmm_get_moments(amfmm_ctx* ctx, double* out21) {
+  return guarded(ctx, [&](Ctx& c) -> int {
+    if (!c.have_moments) return fail(c, AMFMM_E_STATE, "no moments");
+    if (!out21) return fail(c, AMFMM_E_INVALID, "null pointer");
+    const size_t nc = (size_t)c.ncells;
+    auto g = fetch<double>(c, c.geo.p, 4 * nc);
+    auto m = fetch<double>(c, c.mom.p, amfmm::kMom * nc);
+    for (size_t i = 0; i < nc; ++i) {
+      double* o = out21 + 21 * i;
+      o[0] = m[amfmm::kMom * i];
+      o[1] = g[4 * i];
+      o[2] = g[4 * i + 1];
+      o[3] = g[4 * i + 2];
+      o[4] = g[4 * i + 3];
+      for (int q = 0; q < 16; ++q) o[5 + q] = m[amfmm::kMom * i + 1 + q];
+    }
+    return AMFMM_OK;
+  });
+}
+
+int amfmm_get_lists(amfmm_ctx* ctx, int32_t* far_ab, int32_t* near_ab) {
+  return guarded(ctx, [&](Ctx& c) -> int {
+    if (!c.have_lists) return fail(c, AMFMM_E_STATE, "no lists");
+    const size_t nc = (size_t)c.ncells;
+    auto emit = [&](const amfmm::DevBuf& st, const amfmm::DevBuf& cn, const amfmm::DevBuf& src, int64_t total,
+                    bool with_self, int32_t* out) {
+      if (!out) return;
+      auto s = fetch<int64_t>(c, st.p, nc);
+      auto k = fetch<int32_t>(c, cn.p, nc);
+      auto y = fetch<int32_t>(c, src.p, (size_t)total);
+      std::vector<std::pair<int32_t, int32_t>> v;
+      for (size_t x = 0; x < nc; ++x)
+        for (int32_t j = 0; j < k[x]; ++j) {
+          int32_t o = y[(size_t)s[x] + j];
+          if ((int32_t)x < o || (with_self && (int32_t)x == o)) v.emplace_back((int32_t)x, o);
+        }
+      std::sort(v.begin(), v.end());
+      for (size_t i = 0; i < v.size(); ++i) {
+        out[2 * i] = v[i].first;
+        out[2 * i + 1] = v[i].second;
+      }
+    };
+    emit(c.far_start, c.far_count, c.far_src, c.n_far, false, far_ab);
+    emit(c.near_start, c.near_count, c.near_src, c.n_near, true, near_ab);
+    return AMFMM_OK;
+  });
+}
+
+int amfmm_get_phase_times(amfmm_ctx* ctx, double* ms, int32_t cap) {
+  return guarded(ctx, [&](Ctx& c) -> int {
+    if (!ms || cap < 0) return fail(c, AMFMM_E_INVALID, "bad arguments");
+    if (!c.ev_ok) return fail(c, AMFMM_E_HIP, "no timing events");
+    AMFMM_HIP(hipStreamSynchronize(c.stream));
+    double t[9] = {};
+    for (int i = 0; i < 8; ++i) {
+      float v = 0.f;
+      if (hipEventElapsedTime(&v, c.ev[i], c.ev[i + 1]) != hipSuccess) {
+        (void)hipGetLastError();
+        v = 0.f;
+      }
+      t[i] = v;
+    }
+    float all = 0.f;
+    if (hipEventElapsedTime(&all, c.ev[0], c.ev[8]) != hipSuccess) {
+      (void)hipGetLastError();
+      all = 0.f;
+    }
+    t[8] = all;
+    int k = std::min<int32_t>(cap, 9);
+    for (int i = 0; i < k; ++i) ms[i] = t[i];
+    return k;
+  });
+}
+
+const char* amfmm_status_string(int status) {
+  switch (status) {
+    case AMFMM_OK: return "ok";
+    case AMFMM_E_INVALID: return "invalid argument";
+    case AMFMM_E_NONFINITE: return "non-finite input";
+    case AMFMM_E_OOM: return "out of device memory";
+    case AMFMM_E_HIP: return "HIP runtime error";
+    case AMFMM_E_STATE: return "call order violated";
+    default: return "unknown status";
+  }
+}
+
+const char* amfmm_last_error(amfmm_ctx* ctx) {
+  if (!ctx) return "null context";
+  return ctx->c.last_error.c_str();
+}
+
+}  // extern "C"

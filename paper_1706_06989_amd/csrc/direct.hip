@@ -1,0 +1,166 @@
+// Direct summation (the exact g_PP of Sec. 3) at a set of targets, and the
+// net force / torque balance metric of Sec. 3 with compensated sums.
+#include "internal.h"
+
+namespace amfmm {
+namespace {
+
+constexpr int kBS = 256;
+
+__device__ inline double rsqrt_f64(double r2) {
+  double y = __builtin_amdgcn_rsq(r2);
+  const double h = 0.5 * r2;
+  y = y * fma(-h, y * y, 1.5);
+  y = y * fma(-h, y * y, 1.5);
+  return y;
+}
+
+// one thread per target, sources staged through LDS in index order
+__global__ void __launch_bounds__(kBS) k_direct(int64_t n, const double* __restrict__ x, const double* __restrict__ y,
+                                                const double* __restrict__ z, const double* __restrict__ m,
+                                                int64_t nt, const int64_t* __restrict__ tg, double G,
+                                                double* __restrict__ ax, double* __restrict__ ay,
+                                                double* __restrict__ az, double* __restrict__ pot,
+                                                double* __restrict__ gabs) {
+  __shared__ double4 tile[kBS];
+  const int64_t q = (int64_t)blockIdx.x * kBS + threadIdx.x;
+  int64_t i = q < nt ? (tg ? tg[q] : q) : 0;
+  const bool in_range = i >= 0 && i < n;  // bad target indices give NaN outputs
+  const bool valid = q < nt;
+  if (!in_range) i = 0;
+  const double xi = x[i], yi = y[i], zi = z[i];
+  double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0, sa = 0.0;
+  for (int64_t t0 = 0; t0 < n; t0 += kBS) {
+    const int64_t j = t0 + threadIdx.x;
+    tile[threadIdx.x] = j < n ? make_double4(x[j], y[j], z[j], m[j]) : make_double4(0, 0, 0, 0);
+    __syncthreads();
+    const int lim = (int)min<int64_t>(kBS, n - t0);
+    for (int k = 0; k < lim; ++k) {
+      const double4 s = tile[k];
+      const double dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
+      const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+      double w = rsqrt_f64(r2);
+      w = r2 > 0.0 ? w : 0.0;
+      const double mw = s.w * w;
+      const double mw3 = mw * w * w;
+      sx = fma(mw3, dx, sx);
+      sy = fma(mw3, dy, sy);
+      sz = fma(mw3, dz, sz);
+      sp -= mw;
+      sa = fma(mw, w, sa);
+    }
+    __syncthreads();
+  }
+  if (valid && !in_range) sx = sy = sz = sp = sa = __builtin_nan("");
+  if (valid) {
+    ax[q] = G * sx;
+    ay[q] = G * sy;
+    az[q] = G * sz;
+    if (pot) pot[q] = G * sp;
+    if (gabs) gabs[q] = G * sa;
+  }
+}
+
+struct KS {  // compensated running sum (Neumaier)
+  double s = 0.0, c = 0.0;
+  __device__ void add(double v) {
+    double t = s + v;
+    if (fabs(s) >= fabs(v)) c += (s - t) + v;
+    else c += (v - t) + s;
+    s = t;
+  }
+  __device__ void add(const KS& o) {
+    add(o.s);
+    c += o.c;
+  }
+};
+
+constexpr int kNSum = 12;
+
+__global__ void __launch_bounds__(kBS) k_balance_partial(int64_t n, const double* __restrict__ x,
+                                                         const double* __restrict__ y, const double* __restrict__ z,
+                                                         const double* __restrict__ m, const double* __restrict__ gx,
+                                                         const double* __restrict__ gy, const double* __restrict__ gz,
+                                                         double* __restrict__ part) {
+  KS acc[kNSum];
+  for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBS) {
+    const double g[3] = {gx[i], gy[i], gz[i]};
+    const double X[3] = {x[i], y[i], z[i]};
+    const double t[3] = {X[1] * g[2] - X[2] * g[1], X[2] * g[0] - X[0] * g[2], X[0] * g[1] - X[1] * g[0]};
+    const double mi = m[i];
+    for (int d = 0; d < 3; ++d) {
+      acc[d].add(mi * g[d]);
+      acc[3 + d].add(mi * fabs(g[d]));
+      acc[6 + d].add(mi * t[d]);
+      acc[9 + d].add(mi * fabs(t[d]));
+    }
+  }
+  __shared__ double ss[kNSum][kBS], sc[kNSum][kBS];
+  for (int q = 0; q < kNSum; ++q) {
+    ss[q][threadIdx.x] = acc[q].s;
+    sc[q][threadIdx.x] = acc[q].c;
+  }
+  __syncthreads();
+  if (threadIdx.x < kNSum) {
+    KS k;
+    for (int t = 0; t < kBS; ++t) {
+      KS o;
+      o.s = ss[threadIdx.x][t];
+      o.c = sc[threadIdx.x][t];
+      k.add(o);
+    }
+    part[(int64_t)blockIdx.x * 2 * kNSum + 2 * threadIdx.x] = k.s;
+    part[(int64_t)blockIdx.x * 2 * kNSum + 2 * threadIdx.x + 1] = k.c;
+  }
+}
+
+__global__ void k_balance_final(int nb, const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double tot[kNSum];
+  if (threadIdx.x < kNSum) {
+    KS k;
+    for (int b = 0; b < nb; ++b) {
+      KS o;
+      o.s = part[(int64_t)b * 2 * kNSum + 2 * threadIdx.x];
+      o.c = part[(int64_t)b * 2 * kNSum + 2 * threadIdx.x + 1];
+      k.add(o);
+    }
+    tot[threadIdx.x] = k.s + k.c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double num = 0.0, den = 0.0, tnum = 0.0, tden = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      num += tot[d] * tot[d];
+      den += tot[3 + d] * tot[3 + d];
+      tnum += tot[6 + d] * tot[6 + d];
+      tden += tot[9 + d] * tot[9 + d];
+    }
+    out[0] = sqrt(num / den);
+    out[1] = sqrt(tnum / tden);
+  }
+}
+
+}  // namespace
+
+void direct_sum(Ctx& c, int64_t n, const double* x, const double* y, const double* z, const double* m,
+                int64_t ntarget, const int64_t* targets, double* ax, double* ay, double* az, double* pot,
+                double* gabs) {
+  if (ntarget <= 0) return;
+  hipLaunchKernelGGL(k_direct, dim3(blocks_for(ntarget, kBS)), dim3(kBS), 0, c.stream, n, x, y, z, m, ntarget,
+                     targets, c.opt.G, ax, ay, az, pot, gabs);
+  AMFMM_HIP(hipGetLastError());
+}
+
+void balance(Ctx& c, int64_t n, const double* x, const double* y, const double* z, const double* m,
+             const double* ax, const double* ay, const double* az, double* out) {
+  const int nb = (int)std::min<int64_t>(512, (n + kBS - 1) / kBS);
+  double* part = (double*)ensure(c, c.scratch2, sizeof(double) * (2 * kNSum * (size_t)nb + 2));
+  double* res = part + 2 * kNSum * (size_t)nb;
+  hipLaunchKernelGGL(k_balance_partial, dim3(nb), dim3(kBS), 0, c.stream, n, x, y, z, m, ax, ay, az, part);
+  hipLaunchKernelGGL(k_balance_final, dim3(1), dim3(64), 0, c.stream, nb, (const double*)part, res);
+  AMFMM_HIP(hipGetLastError());
+  AMFMM_HIP(hipMemcpyAsync(out, res, sizeof(double) * 2, hipMemcpyDeviceToHost, c.stream));
+  AMFMM_HIP(hipStreamSynchronize(c.stream));
+}
+
+}  // namespace amfmm

@@ -1,0 +1,329 @@
+// Evaluation: far field per target cell, push-down to the leaves, and the
+// near field fused with the evaluation at the particles and the unsort.
+//
+// Far field (eqs. 2-4, dipoles dropped, octupole constant dropped): for the
+// target X and a source Y with R = Z_X - Z_Y, the Taylor coefficients of the
+// potential about Z_X are
+//   C    += M_Y D + 1/2 M_Y,lm D_lm          C_k   += M_Y D_k + 1/2 M_Y,lm D_klm
+//   C_kl += M_Y D_kl                          C_klm += M_Y D_klm
+// (eq. 2 read as a polynomial in x; eq. 4 for the other cell of a pair is the
+// same expression with R -> -R, so directed evaluation per target reproduces
+// the symmetric pair exactly up to summation order).  The correction of eq. 7
+// (prefactor 1/6, see the appendix at P = 3) adds F_c/M_X to X with
+//   F_c,i = -(1/6) Q_jkl D_ijkl,  Q = M_X,jkl M_Y - M_X M_Y,jkl,
+// contracted in closed form: Q_jkl D_ijkl = t4 R_i (Q.RRR) + 3 t3 (Q_ikl R_k
+// R_l + R_i Q_jkk R_j) + 3 t2 Q_ikk with t2 = -3/R^5, t3 = 15/R^7, t4 =
+// -105/R^9.  Eq. 8 keeps only 3 t3 Q_ikl R_k R_l + 3 t2 Q_ikk.
+//
+// One wave per target cell, lanes over its sources, fixed-order butterfly
+// reduction (deterministic).  Near field: one wave per target leaf, lanes =
+// (target, source slice), sources read from the key-sorted double4 array.
+#include "internal.h"
+
+namespace amfmm {
+namespace {
+
+constexpr int kBS = 256;
+constexpr int kWaves = kBS / 64;
+
+// T[p][m]: packed triple index of sorted(pair p, m); pairs xx xy xz yy yz zz
+__constant__ int kT[6][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}, {3, 6, 7}, {4, 7, 8}, {5, 8, 9}};
+
+// 1/sqrt(r2) from the hardware estimate refined by two Newton steps
+__device__ inline double rsqrt_f64(double r2) {
+  double y = __builtin_amdgcn_rsq(r2);
+  const double h = 0.5 * r2;
+  y = y * fma(-h, y * y, 1.5);
+  y = y * fma(-h, y * y, 1.5);
+  return y;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <int VARIANT>
+__global__ void __launch_bounds__(kBS) k_far(int32_t nc, const double4* __restrict__ geo, const double* __restrict__ mom,
+                                             const int64_t* __restrict__ fstart, const int32_t* __restrict__ fcount,
+                                             const int32_t* __restrict__ fsrc, double* __restrict__ loc) {
+  const int lane = threadIdx.x & 63;
+  const int32_t X = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (X >= nc) return;
+  const int32_t cnt = fcount[X];
+  const int64_t st = fstart[X];
+  const double4 gx = geo[X];
+  const double* mx = mom + (int64_t)X * kMom;
+  const double MX = mx[0];
+  double OX[10];
+#pragma unroll
+  for (int u = 0; u < 10; ++u) OX[u] = VARIANT ? mx[7 + u] : 0.0;
+  double acc[23];
+#pragma unroll
+  for (int u = 0; u < 23; ++u) acc[u] = 0.0;
+  for (int32_t j = lane; j < cnt; j += 64) {
+    const int32_t Y = fsrc[st + j];
+    const double4 gy = geo[Y];
+    const double* my = mom + (int64_t)Y * kMom;
+    const double M = my[0];
+    double Q2[6], O3[10];
+#pragma unroll
+    for (int u = 0; u < 6; ++u) Q2[u] = my[1 + u];
+#pragma unroll
+    for (int u = 0; u < 10; ++u) O3[u] = my[7 + u];
+    const double R[3] = {gx.x - gy.x, gx.y - gy.y, gx.z - gy.z};
+    const double r2 = fma(R[0], R[0], fma(R[1], R[1], R[2] * R[2]));
+    const double ri = rsqrt_f64(r2);
+    const double ri2 = ri * ri;
+    const double t1 = ri * ri2;
+    const double t2 = -3.0 * t1 * ri2;
+    const double t3 = -5.0 * t2 * ri2;
+    const double RR[6] = {R[0] * R[0], R[0] * R[1], R[0] * R[2], R[1] * R[1], R[1] * R[2], R[2] * R[2]};
+    // D_kl and D_klm (packed)
+    double D2[6], D3[10];
+#pragma unroll
+    for (int u = 0; u < 6; ++u) D2[u] = t2 * RR[u];
+    D2[0] += t1;
+    D2[3] += t1;
+    D2[5] += t1;
+    D3[0] = fma(t3 * RR[0], R[0], 3.0 * t2 * R[0]);
+    D3[1] = fma(t3 * RR[0], R[1], t2 * R[1]);
+    D3[2] = fma(t3 * RR[0], R[2], t2 * R[2]);
+    D3[3] = fma(t3 * RR[3], R[0], t2 * R[0]);
+    D3[4] = t3 * RR[1] * R[2];
+    D3[5] = fma(t3 * RR[5], R[0], t2 * R[0]);
+    D3[6] = fma(t3 * RR[3], R[1], 3.0 * t2 * R[1]);
+    D3[7] = fma(t3 * RR[3], R[2], t2 * R[2]);
+    D3[8] = fma(t3 * RR[5], R[1], t2 * R[1]);
+    D3[9] = fma(t3 * RR[5], R[2], 3.0 * t2 * R[2]);
+    // contractions of the source quadrupole
+    const double trQ = Q2[0] + Q2[3] + Q2[5];
+    const double QR[3] = {fma(Q2[0], R[0], fma(Q2[1], R[1], Q2[2] * R[2])),
+                          fma(Q2[1], R[0], fma(Q2[3], R[1], Q2[4] * R[2])),
+                          fma(Q2[2], R[0], fma(Q2[4], R[1], Q2[5] * R[2]))};
+    const double RQR = fma(R[0], QR[0], fma(R[1], QR[1], R[2] * QR[2]));
+    // C and C_k
+    acc[0] += fma(-M, ri, 0.5 * fma(t2, RQR, t1 * trQ));
+    const double a1 = fma(M, t1, 0.5 * fma(t3, RQR, t2 * trQ));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc[1 + k] += fma(a1, R[k], t2 * QR[k]);
+#pragma unroll
+    for (int u = 0; u < 6; ++u) acc[4 + u] = fma(M, D2[u], acc[4 + u]);
+#pragma unroll
+    for (int u = 0; u < 10; ++u) acc[10 + u] = fma(M, D3[u], acc[10 + u]);
+    if (VARIANT) {
+      double Q[10];
+#pragma unroll
+      for (int u = 0; u < 10; ++u) Q[u] = fma(OX[u], M, -MX * O3[u]);
+      const double mult[6] = {1.0, 2.0, 2.0, 1.0, 2.0, 1.0};
+      double v[3], w[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int p = 0; p < 6; ++p) s = fma(mult[p] * Q[kT[p][i]], RR[p], s);
+        v[i] = s;
+      }
+      w[0] = Q[0] + Q[3] + Q[5];
+      w[1] = Q[1] + Q[6] + Q[8];
+      w[2] = Q[2] + Q[7] + Q[9];
+      double F[3];
+      if (VARIANT == AMFMM_TC) {
+        const double t4 = -7.0 * t3 * ri2;
+        const double s = fma(R[0], v[0], fma(R[1], v[1], R[2] * v[2]));
+        const double wR = fma(R[0], w[0], fma(R[1], w[1], R[2] * w[2]));
+#pragma unroll
+        for (int i = 0; i < 3; ++i) F[i] = fma(t4 * s, R[i], 3.0 * fma(t3, fma(R[i], wR, v[i]), t2 * w[i]));
+      } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) F[i] = 3.0 * fma(t3, v[i], t2 * w[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) acc[20 + i] += F[i];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 23; ++u) acc[u] = wave_sum(acc[u]);
+  if (lane == 0) {
+    double* o = loc + (int64_t)X * kLoc;
+    const double cf = -1.0 / (6.0 * MX);
+#pragma unroll
+    for (int u = 0; u < 20; ++u) o[u] = acc[u];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) o[20 + i] = VARIANT ? cf * acc[20 + i] : 0.0;
+    o[23] = 0.0;
+  }
+}
+
+// loc[child] += Taylor shift of loc[parent] to the child's centre
+__global__ void __launch_bounds__(kBS) k_l2l(int32_t c0, int32_t nl, const int32_t* __restrict__ par,
+                                             const double4* __restrict__ geo, double* __restrict__ loc) {
+  int32_t i = blockIdx.x * kBS + threadIdx.x;
+  if (i >= nl) return;
+  const int32_t c = c0 + i;
+  const int32_t P = par[c];
+  const double4 gc = geo[c], gp = geo[P];
+  const double d[3] = {gc.x - gp.x, gc.y - gp.y, gc.z - gp.z};
+  const double* L = loc + (int64_t)P * kLoc;
+  double* o = loc + (int64_t)c * kLoc;
+  double C1[3] = {L[1], L[2], L[3]};
+  double C2[6], C3[10];
+#pragma unroll
+  for (int u = 0; u < 6; ++u) C2[u] = L[4 + u];
+#pragma unroll
+  for (int u = 0; u < 10; ++u) C3[u] = L[10 + u];
+  const double dd[6] = {d[0] * d[0], d[0] * d[1], d[0] * d[2], d[1] * d[1], d[1] * d[2], d[2] * d[2]};
+  const double mult[6] = {1.0, 2.0, 2.0, 1.0, 2.0, 1.0};
+  // (C3 dd)_k and (C2 d)_k
+  double C3dd[3], C2d[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double s = 0.0;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) s = fma(mult[p] * C3[kT[p][k]], dd[p], s);
+    C3dd[k] = s;
+  }
+  C2d[0] = fma(C2[0], d[0], fma(C2[1], d[1], C2[2] * d[2]));
+  C2d[1] = fma(C2[1], d[0], fma(C2[3], d[1], C2[4] * d[2]));
+  C2d[2] = fma(C2[2], d[0], fma(C2[4], d[1], C2[5] * d[2]));
+  double c0v = L[0];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) c0v += d[k] * (C1[k] + 0.5 * C2d[k] + (1.0 / 6.0) * C3dd[k]);
+  o[0] += c0v;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) o[1 + k] += C1[k] + C2d[k] + 0.5 * C3dd[k];
+#pragma unroll
+  for (int p = 0; p < 6; ++p) {
+    double s = C2[p];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) s = fma(C3[kT[p][m]], d[m], s);
+    o[4 + p] += s;
+  }
+#pragma unroll
+  for (int u = 0; u < 10; ++u) o[10 + u] += C3[u];
+#pragma unroll
+  for (int i2 = 0; i2 < 3; ++i2) o[20 + i2] += L[20 + i2];
+}
+
+// near field of one leaf per wave, then the far field at each particle from
+// the leaf's coefficients, scaled by G and written in caller order
+__global__ void __launch_bounds__(kBS) k_near(int32_t nleaves, const int32_t* __restrict__ leaves,
+                                              const int32_t* __restrict__ beg, const int32_t* __restrict__ cnt,
+                                              const double4* __restrict__ pos, const double4* __restrict__ geo,
+                                              const double* __restrict__ loc, const int64_t* __restrict__ nstart,
+                                              const int32_t* __restrict__ ncount, const int32_t* __restrict__ nsrc,
+                                              const int32_t* __restrict__ perm, double G, double* __restrict__ ax,
+                                              double* __restrict__ ay, double* __restrict__ az, double* __restrict__ pot) {
+  const int lane = threadIdx.x & 63;
+  const int32_t li = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (li >= nleaves) return;
+  const int32_t X = leaves[li];
+  const int32_t b = beg[X], nt = cnt[X];
+  const int64_t st = nstart[X];
+  const int32_t ns_count = ncount[X];
+  const double4 gx = geo[X];
+  const double* L = loc + (int64_t)X * kLoc;
+  for (int32_t tb = b; tb < b + nt; tb += 64) {
+    const int ntc = min(64, b + nt - tb);
+    const int nsl = 64 / ntc;
+    const int t = lane % ntc, s = lane / ntc;
+    const bool active = s < nsl;
+    const double4 xi = pos[tb + t];
+    double fx = 0.0, fy = 0.0, fz = 0.0, ph = 0.0;
+    if (active) {
+      for (int32_t k = 0; k < ns_count; ++k) {
+        const int32_t Y = nsrc[st + k];
+        const int32_t jb = beg[Y], je = jb + cnt[Y];
+        for (int32_t j = jb + s; j < je; j += nsl) {
+          const double4 q = pos[j];
+          const double dx = q.x - xi.x, dy = q.y - xi.y, dz = q.z - xi.z;
+          const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+          double y = rsqrt_f64(r2);
+          y = r2 > 0.0 ? y : 0.0;
+          const double my = q.w * y;
+          const double my3 = my * y * y;
+          fx = fma(my3, dx, fx);
+          fy = fma(my3, dy, fy);
+          fz = fma(my3, dz, fz);
+          ph -= my;
+        }
+      }
+    }
+    // gather the slices of each target in slice order
+    double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
+    for (int s2 = 0; s2 < nsl; ++s2) {
+      const int src = t + ntc * s2;
+      sx += __shfl(fx, src, 64);
+      sy += __shfl(fy, src, 64);
+      sz += __shfl(fz, src, 64);
+      sp += __shfl(ph, src, 64);
+    }
+    if (s == 0) {
+      // far field at the particle: Taylor polynomial of the leaf's coefficients
+      const double x[3] = {xi.x - gx.x, xi.y - gx.y, xi.z - gx.z};
+      const double xx[6] = {x[0] * x[0], x[0] * x[1], x[0] * x[2], x[1] * x[1], x[1] * x[2], x[2] * x[2]};
+      const double mult[6] = {1.0, 2.0, 2.0, 1.0, 2.0, 1.0};
+      double C3xx[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        double v = 0.0;
+#pragma unroll
+        for (int p = 0; p < 6; ++p) v = fma(mult[p] * L[10 + kT[p][k]], xx[p], v);
+        C3xx[k] = v;
+      }
+      const double C2x[3] = {fma(L[4], x[0], fma(L[5], x[1], L[6] * x[2])),
+                             fma(L[5], x[0], fma(L[7], x[1], L[8] * x[2])),
+                             fma(L[6], x[0], fma(L[8], x[1], L[9] * x[2]))};
+      double g[3], phi = L[0];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        g[k] = L[20 + k] - (L[1 + k] + C2x[k] + 0.5 * C3xx[k]);
+        phi += x[k] * (L[1 + k] + 0.5 * C2x[k] + (1.0 / 6.0) * C3xx[k]);
+      }
+      const int32_t o = perm[tb + t];
+      ax[o] = G * (sx + g[0]);
+      ay[o] = G * (sy + g[1]);
+      az[o] = G * (sz + g[2]);
+      if (pot) pot[o] = G * (sp + phi);
+    }
+  }
+}
+
+}  // namespace
+
+void far_field(Ctx& c) {
+  const int32_t nc = c.ncells;
+  double* loc = (double*)ensure(c, c.loc, sizeof(double) * kLoc * (size_t)nc);
+  dim3 grid(blocks_for(nc, kWaves));
+  auto args = [&](auto kern) {
+    hipLaunchKernelGGL(kern, grid, dim3(kBS), 0, c.stream, nc, (const double4*)c.geo.p, (const double*)c.mom.p,
+                       (const int64_t*)c.far_start.p, (const int32_t*)c.far_count.p, (const int32_t*)c.far_src.p, loc);
+  };
+  switch (c.opt.variant) {
+    case AMFMM_UC: args(k_far<AMFMM_UC>); break;
+    case AMFMM_TC: args(k_far<AMFMM_TC>); break;
+    default: args(k_far<AMFMM_TCO>); break;
+  }
+  AMFMM_HIP(hipGetLastError());
+}
+
+void push_down(Ctx& c) {
+  for (int l = 1; l <= c.depth; ++l) {
+    int32_t c0 = c.level_start[l], nl = c.level_start[l + 1] - c0;
+    hipLaunchKernelGGL(k_l2l, dim3(blocks_for(nl, kBS)), dim3(kBS), 0, c.stream, c0, nl,
+                       as<int32_t>(c.c_parent), (const double4*)c.geo.p, as<double>(c.loc));
+    AMFMM_HIP(hipGetLastError());
+  }
+}
+
+void near_field(Ctx& c, double* ax, double* ay, double* az, double* pot) {
+  hipLaunchKernelGGL(k_near, dim3(blocks_for(c.nleaves, kWaves)), dim3(kBS), 0, c.stream, c.nleaves,
+                     as<int32_t>(c.leaves), as<int32_t>(c.c_begin), as<int32_t>(c.c_count), (const double4*)c.pos4.p,
+                     (const double4*)c.geo.p, (const double*)c.loc.p, (const int64_t*)c.near_start.p,
+                     (const int32_t*)c.near_count.p, (const int32_t*)c.near_src.p, as<int32_t>(c.perm), c.opt.G, ax,
+                     ay, az, pot);
+  AMFMM_HIP(hipGetLastError());
+}
+
+}  // namespace amfmm

@@ -1,0 +1,137 @@
+// Internal declarations of libamfmm_hip.so (host orchestration + kernels).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "amfmm.h"
+
+namespace amfmm {
+
+constexpr int kMaxLevel = 21;  // Morton key resolution per coordinate
+constexpr int kGeo = 4;        // per cell: Zx, Zy, Zz, R_max
+constexpr int kMom = 18;       // per cell: M, M_ij (6), M_ijk (10), pad
+constexpr int kLoc = 24;       // per cell: C (1), C_k (3), C_kl (6), C_klm (10), g_c (3), pad
+
+// index of a symmetric pair / triple inside the packed arrays
+//   pairs   xx xy xz yy yz zz
+//   triples xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define AMFMM_HIP(call)                                                                   \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      throw ::amfmm::Error(AMFMM_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Grow-only device buffer owned by a context.
+struct Arena;
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+struct Ctx {
+  amfmm_options opt;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string last_error;
+  size_t bytes = 0;  // device bytes currently held
+  std::vector<DevBuf*> bufs;
+
+  // particles, sorted by key
+  int64_t n = 0;
+  DevBuf pos4;    // double4 (x, y, z, m)
+  DevBuf keys;    // uint64
+  DevBuf perm;    // int32, sorted -> caller
+  DevBuf keys2;   // sort ping-pong
+  DevBuf perm2;
+  DevBuf bbox;    // 8 doubles: lo[3], hi[3], flags
+  DevBuf scratch; // scan / sort temporaries
+  DevBuf scratch2;
+  DevBuf hist;
+  // cells in (level, begin) order
+  int32_t ncells = 0, depth = 0, nleaves = 0;
+  std::vector<int32_t> level_start;  // host copy, size depth+2
+  DevBuf c_begin, c_count, c_parent, c_child0, c_nchild;  // int32
+  DevBuf leaves;   // int32 ids of leaf cells
+  DevBuf geo;      // double4 per cell
+  DevBuf mom;      // kMom doubles per cell
+  DevBuf msum;     // double4 per cell: sum m*X (x,y,z), unused
+  DevBuf loc;      // kLoc doubles per cell
+  // directed interaction lists grouped by target cell
+  int64_t n_far = 0, n_near = 0;
+  DevBuf far_start, far_count, far_src;     // int32 (start as int64)
+  DevBuf near_start, near_count, near_src;
+  // walk frontier
+  DevBuf fx, fy, fx2, fy2, fcnt, grp;
+  double theta = 0.5;
+  bool have_tree = false, have_moments = false, have_lists = false;
+  // timing
+  hipEvent_t ev[10] = {};
+  bool ev_ok = false;
+  double phase_ms[9] = {};
+  int64_t bytes_cap() const { return opt.max_bytes; }
+};
+
+// allocate (grow-only) a device buffer of at least `bytes`; contents are lost on growth
+void* ensure(Ctx& c, DevBuf& b, size_t bytes);
+// grow keeping the first `keep` bytes
+void* ensure_keep(Ctx& c, DevBuf& b, size_t bytes, size_t keep);
+template <typename T>
+T* as(DevBuf& b) {
+  return static_cast<T*>(b.p);
+}
+void sync(Ctx& c);
+
+// ---- scan.hip ----
+// exclusive prefix sum of n int32 values into out[0..n], out[n] = total
+void scan_i32(Ctx& c, const int32_t* in, int32_t* out, int64_t n);
+// the same for int64 values
+void scan_i64(Ctx& c, const int64_t* in, int64_t* out, int64_t n);
+
+// ---- sort.hip ----
+// stable LSD radix sort of (key, value) pairs by the low `bits` bits of key;
+// results end in keys/vals (the alt buffers are scratch)
+void radix_sort(Ctx& c, uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t* vals_alt,
+                int64_t n, int bits);
+
+// ---- tree.hip ----
+// validate + bounding box; returns 0 or an amfmm_status (reads back flags)
+int bbox_validate(Ctx& c, const double* x, const double* y, const double* z, const double* m,
+                  int64_t n);
+void build_keys_sort(Ctx& c, const double* x, const double* y, const double* z, const double* m,
+                     int64_t n);
+void build_levels(Ctx& c);
+
+// ---- moments.hip ----
+void upward_pass(Ctx& c);
+
+// ---- walk.hip ----
+void dual_walk(Ctx& c, double theta);
+
+// ---- eval.hip ----
+void far_field(Ctx& c);
+void push_down(Ctx& c);
+void near_field(Ctx& c, double* ax, double* ay, double* az, double* pot);
+
+// ---- direct.hip ----
+void direct_sum(Ctx& c, int64_t n, const double* x, const double* y, const double* z,
+                const double* m, int64_t ntarget, const int64_t* targets, double* ax, double* ay,
+                double* az, double* pot, double* gabs);
+void balance(Ctx& c, int64_t n, const double* x, const double* y, const double* z,
+             const double* m, const double* ax, const double* ay, const double* az, double* out);
+
+inline unsigned blocks_for(int64_t n, int threads) {
+  return (unsigned)((n + threads - 1) / threads);
+}
+
+}  // namespace amfmm
