@@ -1,0 +1,154 @@
+"""Benchmark: particles/s of the full gravity solve on one MI355X.
+
+One step = one amfmm_solve_gravity call (validation, bounding cube, keys,
+sort, tree, upward pass, walk, far field, push-down, near field, evaluation at
+the particles, unsort) on inputs already resident in HBM.  Outputs one JSON
+line.  The error of the timed configuration is measured outside the timed
+region against direct summation at a seeded sample of targets.
+
+Workload: 16,777,216-particle Plummer sphere (scale radius 1, mass 1,
+truncated at 20, seed 4, equal masses), G = 1, n_crit = 25, TC variant.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particles/s full force solve, N=16M Plummer, at 1e-4 p99 force error"
+PEAK_FP64_TFLOPS = 78.6  # MI355X vector FP64
+PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (published; packed)
+PEAK_HBM_GBS = 8000.0
+NEAR_FLOPS = 20  # per directed particle interaction (3 sub, 5 r^2, 1 rsqrt, 2 r^-3, 1 mass, 6 acc, 2 pot)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--n", type=int, default=1 << 24)
+    p.add_argument("--theta", type=float, default=0.5)
+    p.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    p.add_argument("--variant", choices=["UC", "TC", "TCO"], default="TC")
+    p.add_argument("--error-sample", type=int, default=4096)
+    p.add_argument("--cpu-n", type=int, default=1 << 16, help="oracle sample size (0 = skip)")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="also run a plain device copy of known size (for HBM counter scaling)")
+    return p.parse_args()
+
+
+def cpu_baseline(n, theta, seed=4):
+    """The CPU oracle as it stands (single thread) on a smaller Plummer sphere
+    of the same generator: particles/s of its full solve."""
+    from oracle import oracle as orc
+    from paper_1706_06989_amd import workloads as W
+
+    x, y, z, m = W.plummer(n, seed=seed)
+    t0 = time.perf_counter()
+    orc.solve(x, y, z, m, theta=theta, variant=orc.TC)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
+            "sample": f"full oracle solve (tree, moments, walk, eqs. 2-4 at every particle, near "
+                      f"field) of a {n}-particle Plummer sphere, same generator, theta={theta}, "
+                      f"TC, single thread, {dt:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are "
+                          "not part of this build (see the sharding notes in DESIGN.md)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1706_06989_amd import amfmm
+    from paper_1706_06989_amd import workloads as W
+
+    variant = {"UC": amfmm.UC, "TC": amfmm.TC, "TCO": amfmm.TCO}[a.variant]
+    prec = amfmm.FP64 if a.precision == "fp64" else amfmm.MIXED
+    x, y, z, m = W.plummer(a.n, seed=4)
+    X, Y, Z, M = (torch.from_numpy(v).to("cuda") for v in (x, y, z, m))
+    del x, y, z, m
+    solver = amfmm.Solver(variant=variant, precision=prec)
+    out = solver._outputs(a.n, True)
+    print(f"# bench: n={a.n} theta={a.theta} {a.precision} {a.variant} warmup={a.warmup} "
+          f"steps={a.steps}", file=sys.stderr, flush=True)
+    for i in range(a.warmup):
+        solver.solve_gravity(X, Y, Z, M, a.theta, out=out)
+        torch.cuda.synchronize()
+        print(f"# warmup {i} done", file=sys.stderr, flush=True)
+    phases = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        solver.solve_gravity(X, Y, Z, M, a.theta, out=out)
+        ph = solver.get_phase_times()  # HIP events on the solver's stream
+        for k, v in ph.items():
+            phases[k] = phases.get(k, 0.0) + v
+        print(f"# step {i}: {ph['total']:.2f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = dt / a.steps * 1e3
+    phases = {k: v / a.steps for k, v in phases.items()}
+    counts = solver.get_counts()
+
+    # accuracy of the timed configuration (outside the timed region)
+    idx = torch.from_numpy(W.sample_targets(a.n, a.error_sample, seed=99)).to("cuda")
+    tx, ty, tz, _, _ = solver.direct(X, Y, Z, M, idx, pot=False, gabs=False)
+    ax, ay, az, _ = out
+    A = torch.stack([ax[idx], ay[idx], az[idx]])
+    T = torch.stack([tx, ty, tz])
+    eps = (torch.linalg.norm(A - T, dim=0) / torch.linalg.norm(T, dim=0)).cpu().numpy()
+    fbal, tbal = solver.balance(X, Y, Z, M, ax, ay, az)
+
+    # roofline of the dominant kernel (near field: one launch per step)
+    near_ms = phases["near+eval"]
+    far_ms = phases["far"]
+    near_tflops = NEAR_FLOPS * counts["near_interactions"] / (near_ms * 1e-3) / 1e12
+    dominant = "near" if near_ms >= far_ms else "far"
+    roof = {"kernel": "k_near (near field + evaluation at particles)", "bound": "alu",
+            "achieved": round(near_tflops, 3),
+            "peak": PEAK_FP64_TFLOPS if a.precision == "fp64" else PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s", "traffic": None,
+            "algorithmic": f"{NEAR_FLOPS} flop x {counts['near_interactions']} interactions",
+            "avg_launch_ms": round(near_ms, 3), "dominant_phase": dominant}
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+
+    cpu = None
+    if a.cpu_n > 0:
+        cpu = cpu_baseline(a.cpu_n, a.theta)
+
+    line = {
+        "metric": METRIC, "value": a.n / (ms * 1e-3), "unit": "particles/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if a.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "plummer16m" if a.n == 1 << 24 else f"plummer{a.n}", "n": a.n,
+                   "theta": a.theta, "variant": a.variant, "precision": a.precision, "n_crit": 25,
+                   "criterion": "geometric",
+                   "p99_rel_force_error": float(np.percentile(eps, 99)),
+                   "mean_rel_force_error": float(eps.mean()),
+                   "max_rel_force_error": float(eps.max()), "error_sample": int(len(eps)),
+                   "meets_1e-4_p99": bool(np.percentile(eps, 99) <= 1e-4),
+                   "force_balance": fbal, "torque_balance": tbal,
+                   "phase_ms": {k: round(v, 3) for k, v in phases.items()}, "counts": counts},
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    if a.copy_calibration:
+        buf = torch.empty(1 << 28, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(buf)
+        for _ in range(3):
+            dst.copy_(buf)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = int(buf.numel())
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -118,9 +118,10 @@ int amfmm_balance(amfmm_ctx* ctx, int64_t n, const double* x, const double* y, c
                   double* out);
 
 /* ---- introspection (host buffers owned by the caller; synchronising) ---- */
-/* counts[0..5] = cells, depth, far-field pairs, near-field pairs (unordered,
- * as amfmm_get_lists returns them), leaves, particles */
-int amfmm_get_counts(amfmm_ctx* ctx, int64_t* counts6);
+/* counts[0..7] = cells, depth, far-field pairs, near-field pairs (unordered,
+ * as amfmm_get_lists returns them), leaves, particles, near-field particle
+ * interactions (directed, i != j), far-field evaluations (directed cell pairs) */
+int amfmm_get_counts(amfmm_ctx* ctx, int64_t* counts8);
 /* sorted keys (n), permutation perm[s] = caller index of sorted particle s (n),
  * and per cell (in (level, first particle) order): level, begin, count,
  * parent, first child (-1 for leaves), child count.  Any pointer may be NULL. */

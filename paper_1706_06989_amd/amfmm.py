@@ -118,11 +118,17 @@ class Solver:
         self._h = h
         self.n = 0
 
-    def __del__(self):
+    def close(self):
         h = getattr(self, "_h", None)
-        if h:
-            lib().amfmm_destroy(h)
-            self._h = None
+        if h and _lib is not None:
+            _lib.amfmm_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def _check(self, st):
         if st < 0:
@@ -184,9 +190,10 @@ class Solver:
         return float(out[0]), float(out[1])
 
     def get_counts(self):
-        c = np.zeros(6, np.int64)
+        c = np.zeros(8, np.int64)
         self._check(lib().amfmm_get_counts(self._h, _ptr(c, C.c_int64)))
-        keys = ["cells", "depth", "far_pairs", "near_pairs", "leaves", "particles"]
+        keys = ["cells", "depth", "far_pairs", "near_pairs", "leaves", "particles",
+                "near_interactions", "far_evaluations"]
         return dict(zip(keys, (int(v) for v in c)))
 
     def get_tree(self):

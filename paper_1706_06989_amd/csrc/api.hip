@@ -275,6 +275,8 @@ int amfmm_get_counts(amfmm_ctx* ctx, int64_t* counts) {
     counts[3] = c.have_lists ? (c.n_near + c.nleaves) / 2 : 0;
     counts[4] = c.have_tree ? c.nleaves : 0;
     counts[5] = c.have_tree ? c.n : 0;
+    counts[6] = c.have_lists ? amfmm::near_interactions(c) : 0;
+    counts[7] = c.have_lists ? c.n_far : 0;
     return AMFMM_OK;
   });
 }

@@ -290,7 +290,34 @@ __global__ void __launch_bounds__(kBS) k_near(int32_t nleaves, const int32_t* __
   }
 }
 
+__global__ void __launch_bounds__(kBS) k_count_near(int32_t nleaves, const int32_t* __restrict__ leaves,
+                                                    const int32_t* __restrict__ cnt, const int64_t* __restrict__ nstart,
+                                                    const int32_t* __restrict__ ncount, const int32_t* __restrict__ nsrc,
+                                                    unsigned long long* __restrict__ total) {
+  int32_t i = blockIdx.x * kBS + threadIdx.x;
+  if (i >= nleaves) return;
+  const int32_t X = leaves[i];
+  int64_t s = 0;
+  for (int32_t k = 0; k < ncount[X]; ++k) s += cnt[nsrc[nstart[X] + k]];
+  atomicAdd(total, (unsigned long long)((int64_t)cnt[X] * s - cnt[X]));
+}
+
+__global__ void k_zero_u64_one(unsigned long long* p) { *p = 0ull; }
+
 }  // namespace
+
+int64_t near_interactions(Ctx& c) {
+  unsigned long long* tot = (unsigned long long*)ensure(c, c.scratch2, 64);
+  hipLaunchKernelGGL(k_zero_u64_one, dim3(1), dim3(1), 0, c.stream, tot);
+  hipLaunchKernelGGL(k_count_near, dim3(blocks_for(c.nleaves, kBS)), dim3(kBS), 0, c.stream, c.nleaves,
+                     as<int32_t>(c.leaves), as<int32_t>(c.c_count), (const int64_t*)c.near_start.p,
+                     (const int32_t*)c.near_count.p, (const int32_t*)c.near_src.p, tot);
+  AMFMM_HIP(hipGetLastError());
+  unsigned long long h = 0;
+  AMFMM_HIP(hipMemcpyAsync(&h, tot, sizeof(h), hipMemcpyDeviceToHost, c.stream));
+  AMFMM_HIP(hipStreamSynchronize(c.stream));
+  return (int64_t)h;
+}
 
 void far_field(Ctx& c) {
   const int32_t nc = c.ncells;

@@ -122,6 +122,8 @@ void dual_walk(Ctx& c, double theta);
 void far_field(Ctx& c);
 void push_down(Ctx& c);
 void near_field(Ctx& c, double* ax, double* ay, double* az, double* pot);
+// directed near-field particle interactions (i != j) of the current lists
+int64_t near_interactions(Ctx& c);
 
 // ---- direct.hip ----
 void direct_sum(Ctx& c, int64_t n, const double* x, const double* y, const double* z,
