@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libamfmm_hip.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "scan.hip", "sort.hip", "tree.hip", "moments.hip", "walk.hip", "eval.hip",
+SOURCES = ["api.hip", "scan.hip", "sort.hip", "tree.hip", "moments.hip", "walk.hip", "eval.hip", "near.hip",
            "direct.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",

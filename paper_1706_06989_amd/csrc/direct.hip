@@ -1,5 +1,6 @@
 // Direct summation (the exact g_PP of Sec. 3) at a set of targets, and the
 // net force / torque balance metric of Sec. 3 with compensated sums.
+#include "device_math.h"
 #include "internal.h"
 
 namespace amfmm {
@@ -7,34 +8,25 @@ namespace {
 
 constexpr int kBS = 256;
 
-__device__ inline double rsqrt_f64(double r2) {
-  double y = __builtin_amdgcn_rsq(r2);
-  const double h = 0.5 * r2;
-  y = y * fma(-h, y * y, 1.5);
-  y = y * fma(-h, y * y, 1.5);
-  return y;
-}
 
-// one thread per target, sources staged through LDS in index order
+// one thread per target and source chunk, sources staged through LDS in index
+// order; partial sums per chunk are added in chunk order by k_direct_sum
 __global__ void __launch_bounds__(kBS) k_direct(int64_t n, const double* __restrict__ x, const double* __restrict__ y,
                                                 const double* __restrict__ z, const double* __restrict__ m,
-                                                int64_t nt, const int64_t* __restrict__ tg, double G,
-                                                double* __restrict__ ax, double* __restrict__ ay,
-                                                double* __restrict__ az, double* __restrict__ pot,
-                                                double* __restrict__ gabs) {
+                                                int64_t nt, const int64_t* __restrict__ tg, int64_t chunk,
+                                                double* __restrict__ part) {
   __shared__ double4 tile[kBS];
   const int64_t q = (int64_t)blockIdx.x * kBS + threadIdx.x;
   int64_t i = q < nt ? (tg ? tg[q] : q) : 0;
-  const bool in_range = i >= 0 && i < n;  // bad target indices give NaN outputs
-  const bool valid = q < nt;
-  if (!in_range) i = 0;
+  if (i < 0 || i >= n) i = 0;  // out-of-range targets are flagged by k_direct_sum
   const double xi = x[i], yi = y[i], zi = z[i];
   double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0, sa = 0.0;
-  for (int64_t t0 = 0; t0 < n; t0 += kBS) {
+  const int64_t j0 = (int64_t)blockIdx.y * chunk, j1 = min(n, j0 + chunk);
+  for (int64_t t0 = j0; t0 < j1; t0 += kBS) {
     const int64_t j = t0 + threadIdx.x;
-    tile[threadIdx.x] = j < n ? make_double4(x[j], y[j], z[j], m[j]) : make_double4(0, 0, 0, 0);
+    tile[threadIdx.x] = j < j1 ? make_double4(x[j], y[j], z[j], m[j]) : make_double4(0, 0, 0, 0);
     __syncthreads();
-    const int lim = (int)min<int64_t>(kBS, n - t0);
+    const int lim = (int)min<int64_t>(kBS, j1 - t0);
     for (int k = 0; k < lim; ++k) {
       const double4 s = tile[k];
       const double dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
@@ -51,14 +43,33 @@ __global__ void __launch_bounds__(kBS) k_direct(int64_t n, const double* __restr
     }
     __syncthreads();
   }
-  if (valid && !in_range) sx = sy = sz = sp = sa = __builtin_nan("");
-  if (valid) {
-    ax[q] = G * sx;
-    ay[q] = G * sy;
-    az[q] = G * sz;
-    if (pot) pot[q] = G * sp;
-    if (gabs) gabs[q] = G * sa;
+  if (q < nt) {
+    double* o = part + ((int64_t)blockIdx.y * nt + q) * 5;
+    o[0] = sx;
+    o[1] = sy;
+    o[2] = sz;
+    o[3] = sp;
+    o[4] = sa;
   }
+}
+
+__global__ void __launch_bounds__(kBS) k_direct_sum(int64_t n, int64_t nt, const int64_t* __restrict__ tg, int nchunk,
+                                                    const double* __restrict__ part, double G, double* __restrict__ ax,
+                                                    double* __restrict__ ay, double* __restrict__ az,
+                                                    double* __restrict__ pot, double* __restrict__ gabs) {
+  const int64_t q = (int64_t)blockIdx.x * kBS + threadIdx.x;
+  if (q >= nt) return;
+  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int c = 0; c < nchunk; ++c)
+    for (int k = 0; k < 5; ++k) s[k] += part[((int64_t)c * nt + q) * 5 + k];
+  const int64_t i = tg ? tg[q] : q;
+  if (i < 0 || i >= n)
+    for (int k = 0; k < 5; ++k) s[k] = __builtin_nan("");
+  ax[q] = G * s[0];
+  ay[q] = G * s[1];
+  az[q] = G * s[2];
+  if (pot) pot[q] = G * s[3];
+  if (gabs) gabs[q] = G * s[4];
 }
 
 struct KS {  // compensated running sum (Neumaier)
@@ -146,8 +157,18 @@ void direct_sum(Ctx& c, int64_t n, const double* x, const double* y, const doubl
                 int64_t ntarget, const int64_t* targets, double* ax, double* ay, double* az, double* pot,
                 double* gabs) {
   if (ntarget <= 0) return;
-  hipLaunchKernelGGL(k_direct, dim3(blocks_for(ntarget, kBS)), dim3(kBS), 0, c.stream, n, x, y, z, m, ntarget,
-                     targets, c.opt.G, ax, ay, az, pot, gabs);
+  // split the sources so that the launch has enough blocks to fill the chip
+  const int64_t tblocks = (ntarget + kBS - 1) / kBS;
+  int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>((4096 + tblocks - 1) / tblocks, (n + 4095) / 4096));
+  nchunk = std::min<int64_t>(nchunk, 65535);
+  int64_t chunk = (n + nchunk - 1) / nchunk;
+  chunk = (chunk + kBS - 1) / kBS * kBS;
+  nchunk = (n + chunk - 1) / chunk;
+  double* part = (double*)ensure(c, c.scratch2, sizeof(double) * 5 * (size_t)(nchunk * ntarget));
+  hipLaunchKernelGGL(k_direct, dim3((unsigned)tblocks, (unsigned)nchunk), dim3(kBS), 0, c.stream, n, x, y, z, m,
+                     ntarget, targets, chunk, part);
+  hipLaunchKernelGGL(k_direct_sum, dim3((unsigned)tblocks), dim3(kBS), 0, c.stream, n, ntarget, targets,
+                     (int)nchunk, (const double*)part, c.opt.G, ax, ay, az, pot, gabs);
   AMFMM_HIP(hipGetLastError());
 }
 

@@ -206,90 +206,6 @@ __global__ void __launch_bounds__(kBS) k_l2l(int32_t c0, int32_t nl, const int32
   for (int i2 = 0; i2 < 3; ++i2) o[20 + i2] += L[20 + i2];
 }
 
-// near field of one leaf per wave, then the far field at each particle from
-// the leaf's coefficients, scaled by G and written in caller order
-__global__ void __launch_bounds__(kBS) k_near(int32_t nleaves, const int32_t* __restrict__ leaves,
-                                              const int32_t* __restrict__ beg, const int32_t* __restrict__ cnt,
-                                              const double4* __restrict__ pos, const double4* __restrict__ geo,
-                                              const double* __restrict__ loc, const int64_t* __restrict__ nstart,
-                                              const int32_t* __restrict__ ncount, const int32_t* __restrict__ nsrc,
-                                              const int32_t* __restrict__ perm, double G, double* __restrict__ ax,
-                                              double* __restrict__ ay, double* __restrict__ az, double* __restrict__ pot) {
-  const int lane = threadIdx.x & 63;
-  const int32_t li = blockIdx.x * kWaves + (threadIdx.x >> 6);
-  if (li >= nleaves) return;
-  const int32_t X = leaves[li];
-  const int32_t b = beg[X], nt = cnt[X];
-  const int64_t st = nstart[X];
-  const int32_t ns_count = ncount[X];
-  const double4 gx = geo[X];
-  const double* L = loc + (int64_t)X * kLoc;
-  for (int32_t tb = b; tb < b + nt; tb += 64) {
-    const int ntc = min(64, b + nt - tb);
-    const int nsl = 64 / ntc;
-    const int t = lane % ntc, s = lane / ntc;
-    const bool active = s < nsl;
-    const double4 xi = pos[tb + t];
-    double fx = 0.0, fy = 0.0, fz = 0.0, ph = 0.0;
-    if (active) {
-      for (int32_t k = 0; k < ns_count; ++k) {
-        const int32_t Y = nsrc[st + k];
-        const int32_t jb = beg[Y], je = jb + cnt[Y];
-        for (int32_t j = jb + s; j < je; j += nsl) {
-          const double4 q = pos[j];
-          const double dx = q.x - xi.x, dy = q.y - xi.y, dz = q.z - xi.z;
-          const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-          double y = rsqrt_f64(r2);
-          y = r2 > 0.0 ? y : 0.0;
-          const double my = q.w * y;
-          const double my3 = my * y * y;
-          fx = fma(my3, dx, fx);
-          fy = fma(my3, dy, fy);
-          fz = fma(my3, dz, fz);
-          ph -= my;
-        }
-      }
-    }
-    // gather the slices of each target in slice order
-    double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
-    for (int s2 = 0; s2 < nsl; ++s2) {
-      const int src = t + ntc * s2;
-      sx += __shfl(fx, src, 64);
-      sy += __shfl(fy, src, 64);
-      sz += __shfl(fz, src, 64);
-      sp += __shfl(ph, src, 64);
-    }
-    if (s == 0) {
-      // far field at the particle: Taylor polynomial of the leaf's coefficients
-      const double x[3] = {xi.x - gx.x, xi.y - gx.y, xi.z - gx.z};
-      const double xx[6] = {x[0] * x[0], x[0] * x[1], x[0] * x[2], x[1] * x[1], x[1] * x[2], x[2] * x[2]};
-      const double mult[6] = {1.0, 2.0, 2.0, 1.0, 2.0, 1.0};
-      double C3xx[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        double v = 0.0;
-#pragma unroll
-        for (int p = 0; p < 6; ++p) v = fma(mult[p] * L[10 + kT[p][k]], xx[p], v);
-        C3xx[k] = v;
-      }
-      const double C2x[3] = {fma(L[4], x[0], fma(L[5], x[1], L[6] * x[2])),
-                             fma(L[5], x[0], fma(L[7], x[1], L[8] * x[2])),
-                             fma(L[6], x[0], fma(L[8], x[1], L[9] * x[2]))};
-      double g[3], phi = L[0];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        g[k] = L[20 + k] - (L[1 + k] + C2x[k] + 0.5 * C3xx[k]);
-        phi += x[k] * (L[1 + k] + 0.5 * C2x[k] + (1.0 / 6.0) * C3xx[k]);
-      }
-      const int32_t o = perm[tb + t];
-      ax[o] = G * (sx + g[0]);
-      ay[o] = G * (sy + g[1]);
-      az[o] = G * (sz + g[2]);
-      if (pot) pot[o] = G * (sp + phi);
-    }
-  }
-}
-
 __global__ void __launch_bounds__(kBS) k_count_near(int32_t nleaves, const int32_t* __restrict__ leaves,
                                                     const int32_t* __restrict__ cnt, const int64_t* __restrict__ nstart,
                                                     const int32_t* __restrict__ ncount, const int32_t* __restrict__ nsrc,
@@ -344,13 +260,6 @@ void push_down(Ctx& c) {
   }
 }
 
-void near_field(Ctx& c, double* ax, double* ay, double* az, double* pot) {
-  hipLaunchKernelGGL(k_near, dim3(blocks_for(c.nleaves, kWaves)), dim3(kBS), 0, c.stream, c.nleaves,
-                     as<int32_t>(c.leaves), as<int32_t>(c.c_begin), as<int32_t>(c.c_count), (const double4*)c.pos4.p,
-                     (const double4*)c.geo.p, (const double*)c.loc.p, (const int64_t*)c.near_start.p,
-                     (const int32_t*)c.near_count.p, (const int32_t*)c.near_src.p, as<int32_t>(c.perm), c.opt.G, ax,
-                     ay, az, pot);
-  AMFMM_HIP(hipGetLastError());
-}
+
 
 }  // namespace amfmm

@@ -72,7 +72,7 @@ struct Ctx {
   DevBuf far_start, far_count, far_src;     // int32 (start as int64)
   DevBuf near_start, near_count, near_src;
   // walk frontier
-  DevBuf fx, fy, fx2, fy2, fcnt, grp;
+  DevBuf fx, fy, fx2, fy2, fcnt, grp, walkrec;
   double theta = 0.5;
   bool have_tree = false, have_moments = false, have_lists = false;
   // timing
