@@ -56,12 +56,16 @@ typedef struct {
   double learned_tol; /* learned criterion: accept when the predicted pair error <= tol */
   double theta_max;   /* learned criterion: pairs with (R_A+R_B)/d > theta_max always open */
   int64_t max_bytes;  /* cap on device scratch owned by the context (0 = no cap) */
+  int64_t list_bytes; /* device bytes the interaction lists of one batch may take
+                         (0 = automatic); when the whole tree's lists would not
+                         fit, amfmm_solve_gravity walks and evaluates the tree
+                         in batches of subtrees, with identical results */
 } amfmm_options;
 
 typedef struct amfmm_ctx amfmm_ctx;
 
 /* Fills *opt with n_crit = 25, TC, FP64, geometric, G = 1, learned_tol = 1e-4,
- * theta_max = 1, max_bytes = 0. */
+ * theta_max = 1, max_bytes = 0, list_bytes = 0. */
 int amfmm_default_options(amfmm_options* opt);
 
 /* Creates a context bound to hip_stream (a hipStream_t; NULL = null stream)

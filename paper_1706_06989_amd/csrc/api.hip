@@ -66,13 +66,21 @@ static DevBuf* all_bufs(Ctx& c, int i) {
   DevBuf* v[] = {&c.pos4, &c.keys, &c.perm, &c.keys2, &c.perm2, &c.bbox, &c.scratch, &c.scratch2, &c.hist,
                  &c.c_begin, &c.c_count, &c.c_parent, &c.c_child0, &c.c_nchild, &c.leaves, &c.geo, &c.mom,
                  &c.msum, &c.loc, &c.far_start, &c.far_count, &c.far_src, &c.near_start, &c.near_count,
-                 &c.near_src, &c.fx, &c.fy, &c.fx2, &c.fy2, &c.fcnt, &c.grp, &c.walkrec};
+                 &c.near_src, &c.fx, &c.fy, &c.fx2, &c.fy2, &c.fcnt, &c.grp, &c.walkrec, &c.fsave, &c.gsave, &c.counters};
   const int nv = (int)(sizeof(v) / sizeof(v[0]));
   return i < nv ? v[i] : nullptr;
 }
 
-static void record(Ctx& c, int i) {
-  if (c.ev_ok) AMFMM_HIP(hipEventRecord(c.ev[i], c.stream));
+void mark(Ctx& c, int phase) {
+  if (c.ev_used == c.ev_pool.size()) {
+    hipEvent_t e;
+    AMFMM_HIP(hipEventCreate(&e));
+    c.ev_pool.push_back(e);
+    c.ev_phase.push_back(0);
+  }
+  AMFMM_HIP(hipEventRecord(c.ev_pool[c.ev_used], c.stream));
+  c.ev_phase[c.ev_used] = phase;
+  ++c.ev_used;
 }
 
 }  // namespace amfmm
@@ -119,6 +127,7 @@ int amfmm_default_options(amfmm_options* o) {
   o->learned_tol = 1e-4;
   o->theta_max = 1.0;
   o->max_bytes = 0;
+  o->list_bytes = 0;
   return AMFMM_OK;
 }
 
@@ -127,7 +136,7 @@ static int check_options(const amfmm_options* o) {
   if (o->variant < AMFMM_UC || o->variant > AMFMM_TCO) return AMFMM_E_INVALID;
   if (o->precision != AMFMM_FP64 && o->precision != AMFMM_MIXED) return AMFMM_E_INVALID;
   if (o->criterion != AMFMM_GEOMETRIC && o->criterion != AMFMM_LEARNED) return AMFMM_E_INVALID;
-  if (!(o->G == o->G) || o->max_bytes < 0) return AMFMM_E_INVALID;
+  if (!(o->G == o->G) || o->max_bytes < 0 || o->list_bytes < 0) return AMFMM_E_INVALID;
   return AMFMM_OK;
 }
 
@@ -145,9 +154,10 @@ int amfmm_create(const amfmm_options* opt, void* stream, amfmm_ctx** out) {
     delete ctx;
     return AMFMM_E_HIP;
   }
-  bool ok = true;
-  for (auto& e : ctx->c.ev) ok = ok && hipEventCreate(&e) == hipSuccess;
-  ctx->c.ev_ok = ok;
+  if (hipHostMalloc((void**)&ctx->c.pinned, 8 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
+    delete ctx;
+    return AMFMM_E_HIP;
+  }
   *out = ctx;
   return AMFMM_OK;
 }
@@ -157,8 +167,8 @@ int amfmm_destroy(amfmm_ctx* ctx) {
   Ctx& c = ctx->c;
   (void)hipStreamSynchronize(c.stream);
   for (int i = 0; amfmm::all_bufs(c, i); ++i) amfmm::release(c, *amfmm::all_bufs(c, i));
-  for (auto& e : c.ev)
-    if (e) (void)hipEventDestroy(e);
+  for (auto& e : c.ev_pool) (void)hipEventDestroy(e);
+  if (c.pinned) (void)hipHostFree(c.pinned);
   delete ctx;
   return AMFMM_OK;
 }
@@ -175,15 +185,16 @@ static int build_tree_impl(Ctx& c, int64_t n, const double* x, const double* y, 
   if (n < 1 || n >= (int64_t)INT32_MAX) return fail(c, AMFMM_E_INVALID, "n must be in [1, 2^31)");
   if (!x || !y || !z || !m) return fail(c, AMFMM_E_INVALID, "null input pointer");
   c.have_tree = c.have_moments = c.have_lists = false;
-  amfmm::record(c, 0);
+  c.ev_used = 0;
+  amfmm::mark(c, amfmm::kPhValidate);
   int st = amfmm::bbox_validate(c, x, y, z, m, n);
   if (st == AMFMM_E_NONFINITE) return fail(c, st, "non-finite position or mass");
   if (st != AMFMM_OK) return fail(c, st, "masses must be positive");
-  amfmm::record(c, 1);
+  amfmm::mark(c, amfmm::kPhSort);
   amfmm::build_keys_sort(c, x, y, z, m, n);
-  amfmm::record(c, 2);
+  amfmm::mark(c, amfmm::kPhTree);
   amfmm::build_levels(c);
-  amfmm::record(c, 3);
+  amfmm::mark(c, amfmm::kPhEnd);
   c.have_tree = true;
   return AMFMM_OK;
 }
@@ -195,8 +206,10 @@ int amfmm_build_tree(amfmm_ctx* ctx, int64_t n, const double* x, const double* y
 
 static int moments_impl(Ctx& c) {
   if (!c.have_tree) return fail(c, AMFMM_E_STATE, "compute_moments needs build_tree");
+  if (c.ev_used) --c.ev_used;  // continue the timeline of the tree build
+  amfmm::mark(c, amfmm::kPhMoments);
   amfmm::upward_pass(c);
-  amfmm::record(c, 4);
+  amfmm::mark(c, amfmm::kPhEnd);
   return AMFMM_OK;
 }
 
@@ -207,8 +220,12 @@ int amfmm_compute_moments(amfmm_ctx* ctx) {
 static int walk_impl(Ctx& c, double theta) {
   if (!(theta > 0.0 && theta <= 1.0)) return fail(c, AMFMM_E_INVALID, "theta must lie in (0, 1]");
   if (!c.have_moments) return fail(c, AMFMM_E_STATE, "walk needs compute_moments");
+  if (c.ev_used) --c.ev_used;
+  amfmm::mark(c, amfmm::kPhWalk);
   amfmm::dual_walk(c, theta);
-  amfmm::record(c, 5);
+  amfmm::mark(c, amfmm::kPhEnd);
+  c.batched = false;
+  c.far_evals = c.n_far;
   return AMFMM_OK;
 }
 
@@ -216,16 +233,140 @@ int amfmm_walk(amfmm_ctx* ctx, double theta) {
   return guarded(ctx, [&](Ctx& c) -> int { return walk_impl(c, theta); });
 }
 
+static void zero_counters(Ctx& c) {
+  void* p = amfmm::ensure(c, c.counters, 64);
+  amfmm::zero_u64(c, (unsigned long long*)p, 8);
+}
+
+// far field, push-down and near field over all cells, from kept lists
+static void evaluate_all(Ctx& c, double* ax, double* ay, double* az, double* pot) {
+  using namespace amfmm;
+  mark(c, kPhFar);
+  far_field(c, 0, c.ncells);
+  mark(c, kPhPush);
+  for (int l = 1; l <= c.depth; ++l) push_down(c, c.level_start[l], c.level_start[l + 1]);
+  mark(c, kPhNear);
+  near_field(c, (const int32_t*)c.leaves.p, 0, c.nleaves, ax, ay, az, pot);
+  mark(c, kPhEnd);
+}
+
 static int evaluate_impl(Ctx& c, double* ax, double* ay, double* az, double* pot) {
   if (!c.have_lists) return fail(c, AMFMM_E_STATE, "evaluate needs walk");
   if (!ax || !ay || !az) return fail(c, AMFMM_E_INVALID, "null output pointer");
-  amfmm::far_field(c);
-  amfmm::record(c, 6);
-  amfmm::push_down(c);
-  amfmm::record(c, 7);
-  amfmm::near_field(c, ax, ay, az, pot);
-  amfmm::record(c, 8);
+  if (c.ev_used) --c.ev_used;
+  zero_counters(c);
+  evaluate_all(c, ax, ay, az, pot);
   return AMFMM_OK;
+}
+
+// Device bytes the lists and the walk frontier take per particle at this
+// theta: measured on Plummer spheres (about 320 B at theta = 0.5), growing as
+// theta^-3 like the number of interacting pairs.
+static double list_bytes_per_particle(double theta) {
+  const double r = 0.5 / theta;
+  return 320.0 * r * r * r;
+}
+
+static size_t list_budget(Ctx& c) {
+  if (c.opt.list_bytes > 0) return (size_t)c.opt.list_bytes;
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    (void)hipGetLastError();
+    fr = size_t(16) << 30;
+  }
+  size_t b = std::min<size_t>(fr / 3, size_t(48) << 30);
+  if (c.opt.max_bytes > 0) b = std::min<size_t>(b, (size_t)c.opt.max_bytes / 2);
+  return std::max<size_t>(b, size_t(64) << 20);
+}
+
+// Walk and evaluation one batch of subtrees at a time, so that the lists of
+// the whole tree never have to exist at once (small theta, large N).  The top
+// levels are walked and evaluated for all cells; below the split level the
+// cells are cut into contiguous batches of subtrees, each walked to the
+// leaves, evaluated (far field, push-down, near field) and released.  The
+// pairs, and hence the results, are the same as those of the whole walk.
+static void solve_batched(Ctx& c, double theta, double* ax, double* ay, double* az, double* pot) {
+  using namespace amfmm;
+  const double bpp = list_bytes_per_particle(theta);
+  const double budget = (double)list_budget(c);
+  const int64_t pmax = std::max<int64_t>(1, (int64_t)(budget / bpp));
+  int Ls = 1;
+  while (Ls < c.depth && c.level_start[Ls + 1] - c.level_start[Ls] < 512) ++Ls;
+  mark(c, kPhWalk);
+  walk_prepare(c, theta);
+  walk_start(c);
+  std::vector<int32_t> lo(c.level_start.begin(), c.level_start.end() - 1),
+      hi(c.level_start.begin() + 1, c.level_start.end());
+  int64_t fb = 0, nb = 0;
+  walk_levels(c, 0, Ls - 1, lo, hi, fb, nb);
+  c.far_evals = fb;
+  mark(c, kPhFar);
+  far_field(c, 0, c.level_start[Ls]);
+  mark(c, kPhPush);
+  for (int l = 1; l < Ls; ++l) push_down(c, c.level_start[l], c.level_start[l + 1]);
+  mark(c, kPhNear);
+  for (int l = 0; l < Ls; ++l) near_field(c, nullptr, lo[l], hi[l] - lo[l], ax, ay, az, pot);
+  // keep the level-Ls frontier and its groups
+  const int64_t FL = c.frontier;
+  const int32_t nL = c.level_start[Ls + 1] - c.level_start[Ls];
+  int64_t* gbeg;
+  int32_t* gcnt;
+  group_arrays(c, &gbeg, &gcnt);
+  std::vector<int64_t> hbeg(nL);
+  std::vector<int32_t> hcnt(nL);
+  AMFMM_HIP(hipMemcpyAsync(hbeg.data(), gbeg, sizeof(int64_t) * nL, hipMemcpyDeviceToHost, c.stream));
+  AMFMM_HIP(hipMemcpyAsync(hcnt.data(), gcnt, sizeof(int32_t) * nL, hipMemcpyDeviceToHost, c.stream));
+  int32_t* fsave = (int32_t*)ensure(c, c.fsave, sizeof(int32_t) * (FL + 1));
+  AMFMM_HIP(hipMemcpyAsync(fsave, c.fy.p, sizeof(int32_t) * FL, hipMemcpyDeviceToDevice, c.stream));
+  // particle ranges of the cells of every level, to cut batches by level
+  std::vector<int32_t> hb(c.ncells), hc(c.ncells);
+  AMFMM_HIP(hipMemcpyAsync(hb.data(), c.c_begin.p, sizeof(int32_t) * c.ncells, hipMemcpyDeviceToHost, c.stream));
+  AMFMM_HIP(hipMemcpyAsync(hc.data(), c.c_count.p, sizeof(int32_t) * c.ncells, hipMemcpyDeviceToHost, c.stream));
+  AMFMM_HIP(hipStreamSynchronize(c.stream));
+  const int32_t L0 = c.level_start[Ls];
+  std::vector<int64_t> bbeg(nL);
+  int32_t x0 = 0;
+  while (x0 < nL) {
+    int32_t x1 = x0;
+    int64_t parts = 0;
+    while (x1 < nL && (x1 == x0 || parts + hc[L0 + x1] <= pmax)) parts += hc[L0 + x1++];
+    // this batch's groups, relative to its first entry, and its entries
+    const int64_t base = hbeg[x0];
+    int64_t F = 0;
+    for (int32_t i = x0; i < x1; ++i) {
+      bbeg[i - x0] = hbeg[i] - base;
+      F += hcnt[i];
+    }
+    mark(c, kPhWalk);
+    group_arrays(c, &gbeg, &gcnt);
+    AMFMM_HIP(hipMemcpyAsync(gbeg, bbeg.data(), sizeof(int64_t) * (x1 - x0), hipMemcpyHostToDevice, c.stream));
+    AMFMM_HIP(hipMemcpyAsync(gcnt, hcnt.data() + x0, sizeof(int32_t) * (x1 - x0), hipMemcpyHostToDevice, c.stream));
+    int32_t* fy = (int32_t*)ensure(c, c.fy, sizeof(int32_t) * (F + 1));
+    AMFMM_HIP(hipMemcpyAsync(fy, fsave + base, sizeof(int32_t) * F, hipMemcpyDeviceToDevice, c.stream));
+    c.frontier = F;
+    // the batch's cells on each level: those whose particles lie in its range
+    const int32_t pb = hb[L0 + x0], pe = hb[L0 + x1 - 1] + hc[L0 + x1 - 1];
+    std::vector<int32_t> blo(lo), bhi(hi);
+    for (int l = Ls; l <= c.depth; ++l) {
+      const int32_t* first = hb.data() + c.level_start[l];
+      const int32_t* last = hb.data() + c.level_start[l + 1];
+      blo[l] = (int32_t)(std::lower_bound(first, last, pb) - hb.data());
+      bhi[l] = (int32_t)(std::lower_bound(first, last, pe) - hb.data());
+    }
+    int64_t bfb = 0, bnb = 0;
+    walk_levels(c, Ls, c.depth, blo, bhi, bfb, bnb);
+    c.far_evals += bfb;
+    mark(c, kPhFar);
+    for (int l = Ls; l <= c.depth; ++l) far_field(c, blo[l], bhi[l]);
+    mark(c, kPhPush);
+    for (int l = Ls; l <= c.depth; ++l) push_down(c, blo[l], bhi[l]);
+    mark(c, kPhNear);
+    for (int l = Ls; l <= c.depth; ++l) near_field(c, nullptr, blo[l], bhi[l] - blo[l], ax, ay, az, pot);
+    x0 = x1;
+  }
+  mark(c, kPhEnd);
+  c.have_lists = false;  // lists of the last batch only: not kept
+  c.batched = true;
 }
 
 int amfmm_evaluate(amfmm_ctx* ctx, double* ax, double* ay, double* az, double* pot) {
@@ -240,8 +381,19 @@ int amfmm_solve_gravity(amfmm_ctx* ctx, int64_t n, const double* x, const double
     int st = build_tree_impl(c, n, x, y, z, m);
     if (st) return st;
     if ((st = moments_impl(c))) return st;
-    if ((st = walk_impl(c, theta))) return st;
-    return evaluate_impl(c, ax, ay, az, pot);
+    if (c.ev_used) --c.ev_used;
+    zero_counters(c);
+    const double need = list_bytes_per_particle(theta) * (double)n;
+    if (need <= (double)list_budget(c) || c.depth < 3) {
+      amfmm::mark(c, amfmm::kPhWalk);
+      amfmm::dual_walk(c, theta);
+      c.batched = false;
+      c.far_evals = c.n_far;
+      evaluate_all(c, ax, ay, az, pot);
+    } else {
+      solve_batched(c, theta, ax, ay, az, pot);
+    }
+    return AMFMM_OK;
   });
 }
 
@@ -271,12 +423,18 @@ int amfmm_get_counts(amfmm_ctx* ctx, int64_t* counts) {
     if (!counts) return fail(c, AMFMM_E_INVALID, "null pointer");
     counts[0] = c.have_tree ? c.ncells : 0;
     counts[1] = c.have_tree ? c.depth : 0;
-    counts[2] = c.have_lists ? c.n_far / 2 : 0;
+    counts[2] = c.have_lists ? c.n_far / 2 : c.far_evals / 2;
     counts[3] = c.have_lists ? (c.n_near + c.nleaves) / 2 : 0;
     counts[4] = c.have_tree ? c.nleaves : 0;
     counts[5] = c.have_tree ? c.n : 0;
-    counts[6] = c.have_lists ? amfmm::near_interactions(c) : 0;
-    counts[7] = c.have_lists ? c.n_far : 0;
+    counts[6] = 0;
+    counts[7] = c.far_evals;
+    if (c.counters.p) {
+      unsigned long long h = 0;
+      AMFMM_HIP(hipMemcpyAsync(&h, c.counters.p, sizeof(h), hipMemcpyDeviceToHost, c.stream));
+      AMFMM_HIP(hipStreamSynchronize(c.stream));
+      counts[6] = (int64_t)h;
+    }
     return AMFMM_OK;
   });
 }
@@ -362,23 +520,18 @@ int amfmm_get_lists(amfmm_ctx* ctx, int32_t* far_ab, int32_t* near_ab) {
 int amfmm_get_phase_times(amfmm_ctx* ctx, double* ms, int32_t cap) {
   return guarded(ctx, [&](Ctx& c) -> int {
     if (!ms || cap < 0) return fail(c, AMFMM_E_INVALID, "bad arguments");
-    if (!c.ev_ok) return fail(c, AMFMM_E_HIP, "no timing events");
     AMFMM_HIP(hipStreamSynchronize(c.stream));
     double t[9] = {};
-    for (int i = 0; i < 8; ++i) {
+    for (size_t i = 0; i + 1 < c.ev_used; ++i) {
       float v = 0.f;
-      if (hipEventElapsedTime(&v, c.ev[i], c.ev[i + 1]) != hipSuccess) {
+      if (hipEventElapsedTime(&v, c.ev_pool[i], c.ev_pool[i + 1]) != hipSuccess) {
         (void)hipGetLastError();
         v = 0.f;
       }
-      t[i] = v;
+      const int ph = c.ev_phase[i];
+      if (ph >= 0 && ph < amfmm::kPhEnd) t[ph] += v;
     }
-    float all = 0.f;
-    if (hipEventElapsedTime(&all, c.ev[0], c.ev[8]) != hipSuccess) {
-      (void)hipGetLastError();
-      all = 0.f;
-    }
-    t[8] = all;
+    for (int i = 0; i < 8; ++i) t[8] += t[i];
     int k = std::min<int32_t>(cap, 9);
     for (int i = 0; i < k; ++i) ms[i] = t[i];
     return k;

@@ -45,12 +45,13 @@ __device__ inline double wave_sum(double v) {
 }
 
 template <int VARIANT>
-__global__ void __launch_bounds__(kBS) k_far(int32_t nc, const double4* __restrict__ geo, const double* __restrict__ mom,
+__global__ void __launch_bounds__(kBS) k_far(int32_t c_lo, int32_t nc, const double4* __restrict__ geo, const double* __restrict__ mom,
                                              const int64_t* __restrict__ fstart, const int32_t* __restrict__ fcount,
                                              const int32_t* __restrict__ fsrc, double* __restrict__ loc) {
   const int lane = threadIdx.x & 63;
-  const int32_t X = blockIdx.x * kWaves + (threadIdx.x >> 6);
-  if (X >= nc) return;
+  const int32_t Xi = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (Xi >= nc) return;
+  const int32_t X = c_lo + Xi;
   const int32_t cnt = fcount[X];
   const int64_t st = fstart[X];
   const double4 gx = geo[X];
@@ -206,41 +207,25 @@ __global__ void __launch_bounds__(kBS) k_l2l(int32_t c0, int32_t nl, const int32
   for (int i2 = 0; i2 < 3; ++i2) o[20 + i2] += L[20 + i2];
 }
 
-__global__ void __launch_bounds__(kBS) k_count_near(int32_t nleaves, const int32_t* __restrict__ leaves,
-                                                    const int32_t* __restrict__ cnt, const int64_t* __restrict__ nstart,
-                                                    const int32_t* __restrict__ ncount, const int32_t* __restrict__ nsrc,
-                                                    unsigned long long* __restrict__ total) {
-  int32_t i = blockIdx.x * kBS + threadIdx.x;
-  if (i >= nleaves) return;
-  const int32_t X = leaves[i];
-  int64_t s = 0;
-  for (int32_t k = 0; k < ncount[X]; ++k) s += cnt[nsrc[nstart[X] + k]];
-  atomicAdd(total, (unsigned long long)((int64_t)cnt[X] * s - cnt[X]));
+__global__ void k_zero_u64_n(unsigned long long* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
 }
-
-__global__ void k_zero_u64_one(unsigned long long* p) { *p = 0ull; }
 
 }  // namespace
 
-int64_t near_interactions(Ctx& c) {
-  unsigned long long* tot = (unsigned long long*)ensure(c, c.scratch2, 64);
-  hipLaunchKernelGGL(k_zero_u64_one, dim3(1), dim3(1), 0, c.stream, tot);
-  hipLaunchKernelGGL(k_count_near, dim3(blocks_for(c.nleaves, kBS)), dim3(kBS), 0, c.stream, c.nleaves,
-                     as<int32_t>(c.leaves), as<int32_t>(c.c_count), (const int64_t*)c.near_start.p,
-                     (const int32_t*)c.near_count.p, (const int32_t*)c.near_src.p, tot);
+void zero_u64(Ctx& c, unsigned long long* p, int n) {
+  hipLaunchKernelGGL(k_zero_u64_n, dim3(1), dim3(64), 0, c.stream, p, n);
   AMFMM_HIP(hipGetLastError());
-  unsigned long long h = 0;
-  AMFMM_HIP(hipMemcpyAsync(&h, tot, sizeof(h), hipMemcpyDeviceToHost, c.stream));
-  AMFMM_HIP(hipStreamSynchronize(c.stream));
-  return (int64_t)h;
 }
 
-void far_field(Ctx& c) {
-  const int32_t nc = c.ncells;
-  double* loc = (double*)ensure(c, c.loc, sizeof(double) * kLoc * (size_t)nc);
+void far_field(Ctx& c, int32_t c_lo, int32_t c_hi) {
+  const int32_t nc = c_hi - c_lo;
+  if (nc <= 0) return;
+  double* loc = (double*)ensure_keep(c, c.loc, sizeof(double) * kLoc * (size_t)c.ncells,
+                                     sizeof(double) * kLoc * (size_t)c.ncells);
   dim3 grid(blocks_for(nc, kWaves));
   auto args = [&](auto kern) {
-    hipLaunchKernelGGL(kern, grid, dim3(kBS), 0, c.stream, nc, (const double4*)c.geo.p, (const double*)c.mom.p,
+    hipLaunchKernelGGL(kern, grid, dim3(kBS), 0, c.stream, c_lo, nc, (const double4*)c.geo.p, (const double*)c.mom.p,
                        (const int64_t*)c.far_start.p, (const int32_t*)c.far_count.p, (const int32_t*)c.far_src.p, loc);
   };
   switch (c.opt.variant) {
@@ -251,15 +236,12 @@ void far_field(Ctx& c) {
   AMFMM_HIP(hipGetLastError());
 }
 
-void push_down(Ctx& c) {
-  for (int l = 1; l <= c.depth; ++l) {
-    int32_t c0 = c.level_start[l], nl = c.level_start[l + 1] - c0;
-    hipLaunchKernelGGL(k_l2l, dim3(blocks_for(nl, kBS)), dim3(kBS), 0, c.stream, c0, nl,
-                       as<int32_t>(c.c_parent), (const double4*)c.geo.p, as<double>(c.loc));
-    AMFMM_HIP(hipGetLastError());
-  }
+void push_down(Ctx& c, int32_t c_lo, int32_t c_hi) {
+  const int32_t nl = c_hi - c_lo;
+  if (nl <= 0) return;
+  hipLaunchKernelGGL(k_l2l, dim3(blocks_for(nl, kBS)), dim3(kBS), 0, c.stream, c_lo, nl, as<int32_t>(c.c_parent),
+                     (const double4*)c.geo.p, as<double>(c.loc));
+  AMFMM_HIP(hipGetLastError());
 }
-
-
 
 }  // namespace amfmm

@@ -72,14 +72,19 @@ struct Ctx {
   DevBuf far_start, far_count, far_src;     // int32 (start as int64)
   DevBuf near_start, near_count, near_src;
   // walk frontier
-  DevBuf fx, fy, fx2, fy2, fcnt, grp, walkrec;
+  DevBuf fx, fy, fx2, fy2, fcnt, grp, walkrec, fsave, gsave, counters;
+  int64_t grp_width = 0, frontier = 0;
+  int grp_cur = 0;
+  int64_t* pinned = nullptr;  // small pinned host buffer for read-backs
+  int64_t far_evals = 0;      // directed far-field evaluations of the last solve
+  bool batched = false;       // last solve ran batch by batch (lists not kept)
   double theta = 0.5;
   bool have_tree = false, have_moments = false, have_lists = false;
-  // timing
-  hipEvent_t ev[10] = {};
-  bool ev_ok = false;
-  double phase_ms[9] = {};
-  int64_t bytes_cap() const { return opt.max_bytes; }
+  // timing: events recorded at phase changes; the time between two marks
+  // belongs to the phase of the first
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_phase;
+  size_t ev_used = 0;
 };
 
 // allocate (grow-only) a device buffer of at least `bytes`; contents are lost on growth
@@ -116,14 +121,25 @@ void build_levels(Ctx& c);
 void upward_pass(Ctx& c);
 
 // ---- walk.hip ----
-void dual_walk(Ctx& c, double theta);
+void dual_walk(Ctx& c, double theta);  // whole walk, lists kept for every cell
+void walk_prepare(Ctx& c, double theta);
+void walk_start(Ctx& c);  // frontier = {(root, root)} at level 0
+// walks levels [lev_first, lev_last] over the cells [lo[l], hi[l]) of each level,
+// starting from the frontier held in c.fy / c.grp; appends lists at the bases;
+// returns the size of the frontier left for level lev_last + 1
+int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32_t>& lo,
+                    const std::vector<int32_t>& hi, int64_t& far_base, int64_t& near_base);
+void group_arrays(Ctx& c, int64_t** gbeg, int32_t** gcnt);  // current level's groups
 
 // ---- eval.hip ----
-void far_field(Ctx& c);
-void push_down(Ctx& c);
-void near_field(Ctx& c, double* ax, double* ay, double* az, double* pot);
-// directed near-field particle interactions (i != j) of the current lists
-int64_t near_interactions(Ctx& c);
+void far_field(Ctx& c, int32_t c_lo, int32_t c_hi);
+void push_down(Ctx& c, int32_t c_lo, int32_t c_hi);  // cells of one level
+// leaves != nullptr: the first `count` leaves of that list; else the leaves
+// among cells [c_lo, c_lo + count)
+void near_field(Ctx& c, const int32_t* leaves, int32_t c_lo, int32_t count, double* ax, double* ay, double* az,
+                double* pot);
+// fills n (<= 64) device words with zero (a kernel, so it can sit in a graph)
+void zero_u64(Ctx& c, unsigned long long* p, int n);
 
 // ---- direct.hip ----
 void direct_sum(Ctx& c, int64_t n, const double* x, const double* y, const double* z,
@@ -131,6 +147,10 @@ void direct_sum(Ctx& c, int64_t n, const double* x, const double* y, const doubl
                 double* az, double* pot, double* gabs);
 void balance(Ctx& c, int64_t n, const double* x, const double* y, const double* z,
              const double* m, const double* ax, const double* ay, const double* az, double* out);
+
+// phases of a solve (amfmm_get_phase_times order)
+enum Phase { kPhValidate = 0, kPhSort, kPhTree, kPhMoments, kPhWalk, kPhFar, kPhPush, kPhNear, kPhEnd };
+void mark(Ctx& c, int phase);  // records an event; phase kPhEnd closes the timeline
 
 inline unsigned blocks_for(int64_t n, int threads) {
   return (unsigned)((n + threads - 1) / threads);

@@ -50,17 +50,21 @@ __device__ inline void near_tile(const double4* buf, int fill, int s, int nsl, c
   }
 }
 
-__global__ void __launch_bounds__(kBS) k_near(int32_t nleaves, const int32_t* __restrict__ leaves,
+// leaves == nullptr: the targets are the leaves among cells [c_lo, c_lo + nleaves)
+__global__ void __launch_bounds__(kBS) k_near(int32_t nleaves, const int32_t* __restrict__ leaves, int32_t c_lo,
+                                              const int32_t* __restrict__ nch,
                                               const int32_t* __restrict__ beg, const int32_t* __restrict__ cnt,
                                               const double4* __restrict__ pos, const double4* __restrict__ geo,
                                               const double* __restrict__ loc, const int64_t* __restrict__ nstart,
                                               const int32_t* __restrict__ ncount, const int32_t* __restrict__ nsrc,
                                               const int32_t* __restrict__ perm, double G, double* __restrict__ ax,
-                                              double* __restrict__ ay, double* __restrict__ az, double* __restrict__ pot) {
+                                              double* __restrict__ ay, double* __restrict__ az, double* __restrict__ pot,
+                                              unsigned long long* __restrict__ inter) {
   const int lane = threadIdx.x & 63;
   const int32_t li = uniform((int32_t)(blockIdx.x * kWaves + (threadIdx.x >> 6)));
   if (li >= nleaves) return;
-  const int32_t X = uniform(leaves[li]);
+  const int32_t X = uniform(leaves ? leaves[li] : c_lo + li);
+  if (!leaves && uniform(nch[X]) != 0) return;
   const int32_t b = uniform(beg[X]), nt = uniform(cnt[X]);
   const int64_t st = nstart[X];
   const int32_t nsc = uniform(ncount[X]);
@@ -68,6 +72,7 @@ __global__ void __launch_bounds__(kBS) k_near(int32_t nleaves, const int32_t* __
   const double* L = loc + (int64_t)X * kLoc;
   __shared__ double4 lds[kWaves][kCap];
   double4* buf = lds[threadIdx.x >> 6];
+  int64_t nsrc_particles = 0;  // source particles of this leaf's list (lane 0)
   for (int32_t tb = b; tb < b + nt; tb += 64) {
     const int ntc = min(64, b + nt - tb);
     const int ng = (ntc + kTG - 1) / kTG;
@@ -108,6 +113,7 @@ __global__ void __launch_bounds__(kBS) k_near(int32_t nleaves, const int32_t* __
         if (lane < take)
           for (int32_t j = 0; j < cl; ++j) buf[inc - cl + j] = pos[bl + j];
         fill = __shfl(inc, take - 1, 64);
+        if (tb == b) nsrc_particles += fill;
         k += take;
       } else {
         // a single leaf larger than the buffer (coincident points at the
@@ -120,6 +126,7 @@ __global__ void __launch_bounds__(kBS) k_near(int32_t nleaves, const int32_t* __
           if (active) near_tile(buf, part, s, nsl, tx, ty, tz, fx, fy, fz, ph);
           wave_sync();
         }
+        if (tb == b) nsrc_particles += c0;
         k += 1;
         continue;
       }
@@ -163,16 +170,19 @@ __global__ void __launch_bounds__(kBS) k_near(int32_t nleaves, const int32_t* __
       if (pot) pot[o] = G * (sp + phi);
     }
   }
+  if (lane == 0) atomicAdd(inter, (unsigned long long)((int64_t)nt * nsrc_particles - nt));
 }
 
 }  // namespace
 
-void near_field(Ctx& c, double* ax, double* ay, double* az, double* pot) {
-  hipLaunchKernelGGL(k_near, dim3(blocks_for(c.nleaves, kWaves)), dim3(kBS), 0, c.stream, c.nleaves,
-                     as<int32_t>(c.leaves), as<int32_t>(c.c_begin), as<int32_t>(c.c_count), (const double4*)c.pos4.p,
+void near_field(Ctx& c, const int32_t* leaves, int32_t c_lo, int32_t count, double* ax, double* ay, double* az,
+                double* pot) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_near, dim3(blocks_for(count, kWaves)), dim3(kBS), 0, c.stream, count, leaves, c_lo,
+                     as<int32_t>(c.c_nchild), as<int32_t>(c.c_begin), as<int32_t>(c.c_count), (const double4*)c.pos4.p,
                      (const double4*)c.geo.p, (const double*)c.loc.p, (const int64_t*)c.near_start.p,
                      (const int32_t*)c.near_count.p, (const int32_t*)c.near_src.p, as<int32_t>(c.perm), c.opt.G, ax,
-                     ay, az, pot);
+                     ay, az, pot, (unsigned long long*)c.counters.p);
   AMFMM_HIP(hipGetLastError());
 }
 

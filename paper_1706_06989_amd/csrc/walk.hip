@@ -336,85 +336,110 @@ __global__ void k_gather_totals(const int64_t* mex, const int64_t* pex, const in
 
 }  // namespace
 
-void dual_walk(Ctx& c, double theta) {
+void walk_prepare(Ctx& c, double theta) {
   const int32_t nc = c.ncells;
   WalkCell* rec = (WalkCell*)ensure(c, c.walkrec, sizeof(WalkCell) * (size_t)nc);
   hipLaunchKernelGGL(k_pack_cells, dim3(blocks_for(nc, kBS)), dim3(kBS), 0, c.stream, nc, (const double4*)c.geo.p,
                      as<int32_t>(c.c_child0), as<int32_t>(c.c_nchild), as<int32_t>(c.c_parent), rec);
   AMFMM_HIP(hipGetLastError());
-  TreeView t{rec, theta};
-  int64_t* far_start = (int64_t*)ensure(c, c.far_start, sizeof(int64_t) * nc);
-  int32_t* far_count = (int32_t*)ensure(c, c.far_count, sizeof(int32_t) * nc);
-  int64_t* near_start = (int64_t*)ensure(c, c.near_start, sizeof(int64_t) * nc);
-  int32_t* near_count = (int32_t*)ensure(c, c.near_count, sizeof(int32_t) * nc);
-  // per-cell group arrays of the current and the next level (ping-pong)
+  ensure(c, c.far_start, sizeof(int64_t) * nc);
+  ensure(c, c.far_count, sizeof(int32_t) * nc);
+  ensure(c, c.near_start, sizeof(int64_t) * nc);
+  ensure(c, c.near_count, sizeof(int32_t) * nc);
   int32_t maxw = 1;
   for (size_t l = 0; l + 1 < c.level_start.size(); ++l)
     maxw = std::max(maxw, c.level_start[l + 1] - c.level_start[l]);
-  char* g = (char*)ensure(c, c.grp, 2 * (sizeof(int64_t) + sizeof(int32_t)) * ((size_t)maxw + 1));
-  int64_t* gbeg = (int64_t*)g;
-  int64_t* gbeg_n = gbeg + maxw + 1;
-  int32_t* gcnt = (int32_t*)(gbeg_n + maxw + 1);
-  int32_t* gcnt_n = gcnt + maxw + 1;
+  c.grp_width = maxw + 1;
+  ensure(c, c.grp, 2 * (sizeof(int64_t) + sizeof(int32_t)) * (size_t)c.grp_width);
   ensure(c, c.fy, sizeof(int32_t) * 16);
+  c.theta = theta;
+}
+
+// the two group arrays (current, next) of the level ping-pong inside c.grp
+static void group_ptrs(Ctx& c, int which, int64_t** gbeg, int32_t** gcnt) {
+  int64_t* g64 = (int64_t*)c.grp.p;
+  int32_t* g32 = (int32_t*)(g64 + 2 * c.grp_width);
+  *gbeg = g64 + which * c.grp_width;
+  *gcnt = g32 + which * c.grp_width;
+}
+
+void group_arrays(Ctx& c, int64_t** gbeg, int32_t** gcnt) { group_ptrs(c, c.grp_cur, gbeg, gcnt); }
+
+void walk_start(Ctx& c) {
+  int64_t* gbeg;
+  int32_t* gcnt;
+  group_ptrs(c, 0, &gbeg, &gcnt);
+  c.grp_cur = 0;
   hipLaunchKernelGGL(k_walk_init, dim3(1), dim3(1), 0, c.stream, gbeg, gcnt, as<int32_t>(c.fy));
   AMFMM_HIP(hipGetLastError());
-  int64_t F = 1;
-  int64_t far_base = 0, near_base = 0;
+  c.frontier = 1;
+}
+
+int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32_t>& lo,
+                    const std::vector<int32_t>& hi, int64_t& far_base, int64_t& near_base) {
+  TreeView t{(const WalkCell*)c.walkrec.p, c.theta};
   static const bool debug = getenv("AMFMM_DEBUG_WALK") != nullptr;
-  int64_t* tot_host = nullptr;
-  AMFMM_HIP(hipHostMalloc((void**)&tot_host, sizeof(int64_t) * 4, hipHostMallocDefault));
-  try {
-    for (int lev = 0; lev <= c.depth && F > 0; ++lev) {
-      const int32_t c0 = c.level_start[lev], nl = c.level_start[lev + 1] - c0;
-      const int32_t c0n = c.level_start[lev + 1];
-      const size_t L = (size_t)nl + 1;
-      int64_t* w = (int64_t*)ensure(c, c.scratch2, sizeof(int64_t) * (7 * L + 4));
-      int64_t *cm = w, *cp = cm + L, *cq = cp + L, *ns = cq + L, *mex = ns + L, *pex = mex + L, *nbase = pex + L;
-      int64_t* tot = nbase + L;
-      const int32_t* fy = as<int32_t>(c.fy);
-      const unsigned grid = blocks_for(nl, kBS / 64);
-      hipLaunchKernelGGL(k_walk_count, dim3(grid), dim3(kBS), 0, c.stream, t, c0, nl, (const int64_t*)gbeg,
-                         (const int32_t*)gcnt, fy, cm, cp, cq, ns);
-      AMFMM_HIP(hipGetLastError());
-      scan_i64(c, cm, mex, nl);
-      scan_i64(c, cp, pex, nl);
-      scan_i64(c, ns, nbase, nl);
-      hipLaunchKernelGGL(k_gather_totals, dim3(1), dim3(1), 0, c.stream, (const int64_t*)mex, (const int64_t*)pex,
-                         (const int64_t*)nbase, nl, tot);
-      AMFMM_HIP(hipGetLastError());
-      AMFMM_HIP(hipMemcpyAsync(tot_host, tot, sizeof(int64_t) * 3, hipMemcpyDeviceToHost, c.stream));
-      AMFMM_HIP(hipStreamSynchronize(c.stream));
-      const int64_t mt = tot_host[0], pt = tot_host[1], Fn = tot_host[2];
-      if (debug)
-        fprintf(stderr, "walk level %d: cells %d entries %lld far %lld near %lld next %lld\n", lev, nl, (long long)F,
-                (long long)mt, (long long)pt, (long long)Fn);
-      if (Fn >= (int64_t)INT32_MAX) throw Error(AMFMM_E_OOM, "walk frontier exceeds 2^31 entries");
-      int32_t* far_src = (int32_t*)ensure_keep(c, c.far_src, sizeof(int32_t) * (far_base + mt + 1),
-                                               sizeof(int32_t) * far_base);
-      int32_t* near_src = (int32_t*)ensure_keep(c, c.near_src, sizeof(int32_t) * (near_base + pt + 1),
-                                                sizeof(int32_t) * near_base);
-      int32_t* fy_n = (int32_t*)ensure(c, c.fy2, sizeof(int32_t) * (Fn + 1));
-      hipLaunchKernelGGL(k_walk_emit, dim3(grid), dim3(kBS), 0, c.stream, t, c0, nl, c0n, (const int64_t*)gbeg,
-                         (const int32_t*)gcnt, fy, (const int64_t*)cm, (const int64_t*)cp, (const int64_t*)cq, (const int64_t*)mex,
-                         (const int64_t*)pex, (const int64_t*)nbase, far_base, near_base, far_start, far_count,
-                         near_start, near_count, far_src, near_src, gbeg_n, gcnt_n, fy_n);
-      AMFMM_HIP(hipGetLastError());
-      far_base += mt;
-      near_base += pt;
-      std::swap(c.fy, c.fy2);
-      std::swap(gbeg, gbeg_n);
-      std::swap(gcnt, gcnt_n);
-      F = Fn;
-    }
-  } catch (...) {
-    (void)hipHostFree(tot_host);
-    throw;
+  int64_t F = c.frontier;
+  int64_t* tot_host = c.pinned;
+  for (int lev = lev_first; lev <= lev_last && F > 0; ++lev) {
+    const int32_t c0 = lo[lev], nl = hi[lev] - lo[lev];
+    const int32_t c0n = lev + 1 < (int)lo.size() ? lo[lev + 1] : 0;
+    const size_t L = (size_t)nl + 1;
+    int64_t *gbeg, *gbeg_n;
+    int32_t *gcnt, *gcnt_n;
+    group_ptrs(c, c.grp_cur, &gbeg, &gcnt);
+    group_ptrs(c, 1 - c.grp_cur, &gbeg_n, &gcnt_n);
+    int64_t* w = (int64_t*)ensure(c, c.scratch2, sizeof(int64_t) * (7 * L + 4));
+    int64_t *cm = w, *cp = cm + L, *cq = cp + L, *ns = cq + L, *mex = ns + L, *pex = mex + L, *nbase = pex + L;
+    int64_t* tot = nbase + L;
+    const int32_t* fy = as<int32_t>(c.fy);
+    const unsigned grid = blocks_for(nl, kBS / 64);
+    hipLaunchKernelGGL(k_walk_count, dim3(grid), dim3(kBS), 0, c.stream, t, c0, nl, (const int64_t*)gbeg,
+                       (const int32_t*)gcnt, fy, cm, cp, cq, ns);
+    AMFMM_HIP(hipGetLastError());
+    scan_i64(c, cm, mex, nl);
+    scan_i64(c, cp, pex, nl);
+    scan_i64(c, ns, nbase, nl);
+    hipLaunchKernelGGL(k_gather_totals, dim3(1), dim3(1), 0, c.stream, (const int64_t*)mex, (const int64_t*)pex,
+                       (const int64_t*)nbase, nl, tot);
+    AMFMM_HIP(hipGetLastError());
+    AMFMM_HIP(hipMemcpyAsync(tot_host, tot, sizeof(int64_t) * 3, hipMemcpyDeviceToHost, c.stream));
+    AMFMM_HIP(hipStreamSynchronize(c.stream));
+    const int64_t mt = tot_host[0], pt = tot_host[1], Fn = tot_host[2];
+    if (debug)
+      fprintf(stderr, "walk level %d: cells %d entries %lld far %lld near %lld next %lld\n", lev, nl, (long long)F,
+              (long long)mt, (long long)pt, (long long)Fn);
+    if (Fn >= (int64_t)INT32_MAX) throw Error(AMFMM_E_OOM, "walk frontier exceeds 2^31 entries");
+    int32_t* far_src = (int32_t*)ensure_keep(c, c.far_src, sizeof(int32_t) * (far_base + mt + 1),
+                                             sizeof(int32_t) * far_base);
+    int32_t* near_src = (int32_t*)ensure_keep(c, c.near_src, sizeof(int32_t) * (near_base + pt + 1),
+                                              sizeof(int32_t) * near_base);
+    int32_t* fy_n = (int32_t*)ensure(c, c.fy2, sizeof(int32_t) * (Fn + 1));
+    hipLaunchKernelGGL(k_walk_emit, dim3(grid), dim3(kBS), 0, c.stream, t, c0, nl, c0n, (const int64_t*)gbeg,
+                       (const int32_t*)gcnt, fy, (const int64_t*)cm, (const int64_t*)cp, (const int64_t*)cq,
+                       (const int64_t*)mex, (const int64_t*)pex, (const int64_t*)nbase, far_base, near_base,
+                       (int64_t*)c.far_start.p, (int32_t*)c.far_count.p, (int64_t*)c.near_start.p,
+                       (int32_t*)c.near_count.p, far_src, near_src, gbeg_n, gcnt_n, fy_n);
+    AMFMM_HIP(hipGetLastError());
+    far_base += mt;
+    near_base += pt;
+    std::swap(c.fy, c.fy2);
+    c.grp_cur = 1 - c.grp_cur;
+    F = Fn;
   }
-  AMFMM_HIP(hipHostFree(tot_host));
+  c.frontier = F;
+  return F;
+}
+
+void dual_walk(Ctx& c, double theta) {
+  walk_prepare(c, theta);
+  walk_start(c);
+  std::vector<int32_t> lo(c.level_start.begin(), c.level_start.end() - 1),
+      hi(c.level_start.begin() + 1, c.level_start.end());
+  int64_t far_base = 0, near_base = 0;
+  walk_levels(c, 0, c.depth, lo, hi, far_base, near_base);
   c.n_far = far_base;
   c.n_near = near_base;
-  c.theta = theta;
   c.have_lists = true;
 }
 

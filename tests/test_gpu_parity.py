@@ -189,3 +189,24 @@ def test_error_paths():
     # the context still works after errors
     ax, ay, az, p = s.solve_gravity(X, Y, Z, M, 0.5)
     assert torch.isfinite(ax).all()
+
+
+@pytest.mark.parametrize("theta", [0.35, 0.7])
+def test_batched_walk_matches_whole_walk(theta):
+    """Walking and evaluating batch by batch (forced by a tiny list budget)
+    gives bit-identical results and the same interaction counts."""
+    x, y, z, m = W.plummer(1 << 17, seed=12)
+    say("batched", len(x), theta)
+    X, Y, Z, M = to_dev(x, y, z, m)
+    whole = amfmm.Solver()
+    a1 = whole.solve_gravity(X, Y, Z, M, theta)
+    c1 = whole.get_counts()
+    part = amfmm.Solver(list_bytes=1 << 20)
+    a2 = part.solve_gravity(X, Y, Z, M, theta)
+    c2 = part.get_counts()
+    for u, v in zip(a1, a2):
+        assert torch.equal(u, v)
+    assert c1["near_interactions"] == c2["near_interactions"] > 0
+    assert c1["far_evaluations"] == c2["far_evaluations"] > 0
+    ph = part.get_phase_times()
+    assert ph["near+eval"] > 0 and ph["walk"] > 0
