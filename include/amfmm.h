@@ -43,8 +43,13 @@ typedef enum { AMFMM_UC = 0, AMFMM_TC = 1, AMFMM_TCO = 2 } amfmm_variant;
 typedef enum { AMFMM_FP64 = 0, AMFMM_MIXED = 1 } amfmm_precision;
 
 /* Accept/open decision of the walk: the geometric opening criterion of Sec. 2,
- * or the learned error estimate (falls back to the geometric rule when no
- * network is loaded). */
+ * or an error-estimate criterion (the role of the error-based pair selection
+ * the paper cites in Sec. 2): a pair is accepted when its estimated force
+ * error, for each of its two cells, stays below learned_tol times the mean
+ * field estimate of that cell and (R_A+R_B)/d <= theta_max.  The decision is a
+ * function of the unordered pair, so pairwise momentum conservation holds.
+ * Without a field estimate (amfmm_set_field_estimate) the geometric rule is
+ * used. */
 typedef enum { AMFMM_GEOMETRIC = 0, AMFMM_LEARNED = 1 } amfmm_criterion;
 
 typedef struct {
@@ -72,6 +77,11 @@ int amfmm_default_options(amfmm_options* opt);
  * on the current device.  The context owns all scratch. */
 int amfmm_create(const amfmm_options* opt, void* hip_stream, amfmm_ctx** out);
 int amfmm_destroy(amfmm_ctx* ctx);
+/* Per-particle field magnitudes |g| (device pointer, n doubles, caller order)
+ * for the AMFMM_LEARNED criterion, e.g. the accelerations of the previous time
+ * step or of a cheaper solve.  The array is read during the next walks; it
+ * must stay valid until they return.  NULL clears it. */
+int amfmm_set_field_estimate(amfmm_ctx* ctx, const double* gmag);
 /* Rebinds the context to another stream of the same device. */
 int amfmm_set_stream(amfmm_ctx* ctx, void* hip_stream);
 

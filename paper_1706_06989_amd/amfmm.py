@@ -49,6 +49,7 @@ def lib():
         "amfmm_create": (C.c_int, [C.POINTER(amfmm_options), P, C.POINTER(P)]),
         "amfmm_destroy": (C.c_int, [P]),
         "amfmm_set_stream": (C.c_int, [P, P]),
+        "amfmm_set_field_estimate": (C.c_int, [P, pd]),
         "amfmm_build_tree": (C.c_int, [P, i64, pd, pd, pd, pd]),
         "amfmm_compute_moments": (C.c_int, [P]),
         "amfmm_walk": (C.c_int, [P, C.c_double]),
@@ -76,6 +77,7 @@ def lib():
 
 
 EXPORTED = ["amfmm_default_options", "amfmm_create", "amfmm_destroy", "amfmm_set_stream",
+            "amfmm_set_field_estimate",
             "amfmm_build_tree", "amfmm_compute_moments", "amfmm_walk", "amfmm_evaluate",
             "amfmm_solve_gravity", "amfmm_direct", "amfmm_balance", "amfmm_get_counts",
             "amfmm_get_tree", "amfmm_get_moments", "amfmm_get_lists", "amfmm_get_phase_times",
@@ -135,6 +137,14 @@ class Solver:
         if st < 0:
             raise AmfmmError(st, lib().amfmm_last_error(self._h).decode())
         return st
+
+    def set_field_estimate(self, gmag):
+        """Per-particle |g| estimates (CUDA float64, caller order) for the
+        error-estimate criterion; None clears them.  The tensor is kept alive
+        by the solver until replaced."""
+        self._field = gmag
+        self._check(lib().amfmm_set_field_estimate(self._h, _dev(gmag, "gmag") if gmag is not None
+                                                   else None))
 
     def build_tree(self, x, y, z, m):
         self.n = x.numel()

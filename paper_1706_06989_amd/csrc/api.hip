@@ -66,7 +66,7 @@ static DevBuf* all_bufs(Ctx& c, int i) {
   DevBuf* v[] = {&c.pos4, &c.keys, &c.perm, &c.keys2, &c.perm2, &c.bbox, &c.scratch, &c.scratch2, &c.hist,
                  &c.c_begin, &c.c_count, &c.c_parent, &c.c_child0, &c.c_nchild, &c.leaves, &c.geo, &c.mom,
                  &c.msum, &c.loc, &c.far_start, &c.far_count, &c.far_src, &c.near_start, &c.near_count,
-                 &c.near_src, &c.fx, &c.fy, &c.fx2, &c.fy2, &c.fcnt, &c.grp, &c.walkrec, &c.fsave, &c.gsave, &c.counters};
+                 &c.near_src, &c.fx, &c.fy, &c.fx2, &c.fy2, &c.fcnt, &c.grp, &c.walkrec, &c.fsave, &c.gsave, &c.counters, &c.gqueue, &c.gmin};
   const int nv = (int)(sizeof(v) / sizeof(v[0]));
   return i < nv ? v[i] : nullptr;
 }
@@ -109,6 +109,8 @@ static std::vector<T> fetch(Ctx& c, const void* dev, size_t count) {
   AMFMM_HIP(hipStreamSynchronize(c.stream));
   return h;
 }
+
+static void build_near_pairs(Ctx& c);
 
 static int fail(Ctx& c, int code, const char* msg) {
   c.last_error = msg;
@@ -173,6 +175,13 @@ int amfmm_destroy(amfmm_ctx* ctx) {
   return AMFMM_OK;
 }
 
+int amfmm_set_field_estimate(amfmm_ctx* ctx, const double* gmag) {
+  return guarded(ctx, [&](Ctx& c) -> int {
+    c.field = gmag;
+    return AMFMM_OK;
+  });
+}
+
 int amfmm_set_stream(amfmm_ctx* ctx, void* stream) {
   return guarded(ctx, [&](Ctx& c) -> int {
     c.stream = (hipStream_t)stream;
@@ -223,6 +232,7 @@ static int walk_impl(Ctx& c, double theta) {
   if (c.ev_used) --c.ev_used;
   amfmm::mark(c, amfmm::kPhWalk);
   amfmm::dual_walk(c, theta);
+  c.near_pairs_valid = false;
   amfmm::mark(c, amfmm::kPhEnd);
   c.batched = false;
   c.far_evals = c.n_far;
@@ -290,8 +300,23 @@ static void solve_batched(Ctx& c, double theta, double* ax, double* ay, double* 
   const double bpp = list_bytes_per_particle(theta);
   const double budget = (double)list_budget(c);
   const int64_t pmax = std::max<int64_t>(1, (int64_t)(budget / bpp));
+  // particle ranges of all cells (host copy), to pick the split level and cut batches
+  std::vector<int32_t> hb(c.ncells), hc(c.ncells);
+  AMFMM_HIP(hipMemcpyAsync(hb.data(), c.c_begin.p, sizeof(int32_t) * c.ncells, hipMemcpyDeviceToHost, c.stream));
+  AMFMM_HIP(hipMemcpyAsync(hc.data(), c.c_count.p, sizeof(int32_t) * c.ncells, hipMemcpyDeviceToHost, c.stream));
+  AMFMM_HIP(hipStreamSynchronize(c.stream));
+  // split level: the first level with many cells none of which is too large a
+  // share of the particles (dense cores make cells of one level very unequal)
+  const int64_t cap = std::max<int64_t>(4096, c.n / 1024);
   int Ls = 1;
-  while (Ls < c.depth && c.level_start[Ls + 1] - c.level_start[Ls] < 512) ++Ls;
+  for (; Ls < c.depth; ++Ls) {
+    const int32_t a = c.level_start[Ls], b = c.level_start[Ls + 1];
+    if (b - a < 4096) continue;
+    int32_t big = 0;
+    for (int32_t q = a; q < b; ++q) big = std::max(big, hc[q]);
+    if (big <= cap) break;
+  }
+  c.walk_budget = 0;  // the top levels are walked whole
   mark(c, kPhWalk);
   walk_prepare(c, theta);
   walk_start(c);
@@ -318,18 +343,16 @@ static void solve_batched(Ctx& c, double theta, double* ax, double* ay, double* 
   AMFMM_HIP(hipMemcpyAsync(hcnt.data(), gcnt, sizeof(int32_t) * nL, hipMemcpyDeviceToHost, c.stream));
   int32_t* fsave = (int32_t*)ensure(c, c.fsave, sizeof(int32_t) * (FL + 1));
   AMFMM_HIP(hipMemcpyAsync(fsave, c.fy.p, sizeof(int32_t) * FL, hipMemcpyDeviceToDevice, c.stream));
-  // particle ranges of the cells of every level, to cut batches by level
-  std::vector<int32_t> hb(c.ncells), hc(c.ncells);
-  AMFMM_HIP(hipMemcpyAsync(hb.data(), c.c_begin.p, sizeof(int32_t) * c.ncells, hipMemcpyDeviceToHost, c.stream));
-  AMFMM_HIP(hipMemcpyAsync(hc.data(), c.c_count.p, sizeof(int32_t) * c.ncells, hipMemcpyDeviceToHost, c.stream));
   AMFMM_HIP(hipStreamSynchronize(c.stream));
   const int32_t L0 = c.level_start[Ls];
   std::vector<int64_t> bbeg(nL);
+  c.walk_budget = (size_t)budget;
   int32_t x0 = 0;
+  int64_t plim = c.batch_hint > 0 ? std::min(c.batch_hint, pmax) : pmax;
   while (x0 < nL) {
     int32_t x1 = x0;
     int64_t parts = 0;
-    while (x1 < nL && (x1 == x0 || parts + hc[L0 + x1] <= pmax)) parts += hc[L0 + x1++];
+    while (x1 < nL && (x1 == x0 || parts + hc[L0 + x1] <= plim)) parts += hc[L0 + x1++];
     // this batch's groups, relative to its first entry, and its entries
     const int64_t base = hbeg[x0];
     int64_t F = 0;
@@ -354,7 +377,17 @@ static void solve_batched(Ctx& c, double theta, double* ax, double* ay, double* 
       bhi[l] = (int32_t)(std::lower_bound(first, last, pe) - hb.data());
     }
     int64_t bfb = 0, bnb = 0;
-    walk_levels(c, Ls, c.depth, blo, bhi, bfb, bnb);
+    try {
+      walk_levels(c, Ls, c.depth, blo, bhi, bfb, bnb);
+    } catch (const BudgetExceeded&) {
+      // too many pairs for one batch: halve it (a single cell that does not
+      // fit is reported as out of memory)
+      if (x1 - x0 == 1) throw Error(AMFMM_E_OOM, "one subtree's interaction lists exceed the list budget");
+      plim = std::max<int64_t>(1, parts / 2);
+      continue;
+    }
+    c.batch_hint = plim;
+    plim = std::min(pmax, plim + plim / 4);
     c.far_evals += bfb;
     mark(c, kPhFar);
     for (int l = Ls; l <= c.depth; ++l) far_field(c, blo[l], bhi[l]);
@@ -384,15 +417,35 @@ int amfmm_solve_gravity(amfmm_ctx* ctx, int64_t n, const double* x, const double
     if (c.ev_used) --c.ev_used;
     zero_counters(c);
     const double need = list_bytes_per_particle(theta) * (double)n;
-    if (need <= (double)list_budget(c) || c.depth < 3) {
+    const size_t budget = list_budget(c);
+    // a context that needed batches for this size and criterion goes straight to them
+    const bool same = c.hint_n == n && c.hint_theta == theta && c.hint_mode == c.opt.criterion &&
+                      c.hint_tol == c.opt.learned_tol;
+    if (!same) c.batch_hint = 0;
+    bool whole = (need <= (double)budget || c.depth < 3) && !(same && c.batch_hint > 0);
+    if (whole) {
       amfmm::mark(c, amfmm::kPhWalk);
-      amfmm::dual_walk(c, theta);
+      c.walk_budget = c.depth < 3 ? 0 : budget;
+      try {
+        amfmm::dual_walk(c, theta);
+      } catch (const amfmm::BudgetExceeded&) {
+        whole = false;  // the estimate was too low: walk batch by batch
+      }
+      c.walk_budget = 0;
+    }
+    if (whole) {
+      c.near_pairs_valid = false;
       c.batched = false;
       c.far_evals = c.n_far;
       evaluate_all(c, ax, ay, az, pot);
     } else {
       solve_batched(c, theta, ax, ay, az, pot);
+      c.walk_budget = 0;
     }
+    c.hint_n = n;
+    c.hint_theta = theta;
+    c.hint_mode = c.opt.criterion;
+    c.hint_tol = c.opt.learned_tol;
     return AMFMM_OK;
   });
 }
@@ -424,7 +477,11 @@ int amfmm_get_counts(amfmm_ctx* ctx, int64_t* counts) {
     counts[0] = c.have_tree ? c.ncells : 0;
     counts[1] = c.have_tree ? c.depth : 0;
     counts[2] = c.have_lists ? c.n_far / 2 : c.far_evals / 2;
-    counts[3] = c.have_lists ? (c.n_near + c.nleaves) / 2 : 0;
+    counts[3] = 0;
+    if (c.have_lists) {
+      build_near_pairs(c);
+      counts[3] = (int64_t)c.near_pairs_host.size();
+    }
     counts[4] = c.have_tree ? c.nleaves : 0;
     counts[5] = c.have_tree ? c.n : 0;
     counts[6] = 0;
@@ -489,30 +546,65 @@ int amfmm_get_moments(amfmm_ctx* ctx, double* out21) {
   });
 }
 
+// Unordered leaf pairs of the near field.  A near entry X <- Y with a split
+// cell Y stands for every leaf under Y; each directed entry contributes the
+// pairs whose first cell has the lower index, so every pair appears once.
+static void build_near_pairs(Ctx& c) {
+  if (c.near_pairs_valid) return;
+  const size_t nc = (size_t)c.ncells;
+  auto s = fetch<int64_t>(c, c.near_start.p, nc);
+  auto k = fetch<int32_t>(c, c.near_count.p, nc);
+  auto y = fetch<int32_t>(c, c.near_src.p, (size_t)c.n_near);
+  auto ch0 = fetch<int32_t>(c, c.c_child0.p, nc);
+  auto nch = fetch<int32_t>(c, c.c_nchild.p, nc);
+  std::vector<std::pair<int32_t, int32_t>> v;
+  std::vector<int32_t> stack;
+  for (size_t x = 0; x < nc; ++x)
+    for (int32_t j = 0; j < k[x]; ++j) {
+      stack.assign(1, y[(size_t)s[x] + j]);
+      while (!stack.empty()) {
+        int32_t o = stack.back();
+        stack.pop_back();
+        if (nch[o]) {
+          for (int32_t q = ch0[o] + nch[o] - 1; q >= ch0[o]; --q) stack.push_back(q);
+          continue;
+        }
+        if ((int32_t)x <= o) v.emplace_back((int32_t)x, o);
+      }
+    }
+  std::sort(v.begin(), v.end());
+  c.near_pairs_host.swap(v);
+  c.near_pairs_valid = true;
+}
+
 int amfmm_get_lists(amfmm_ctx* ctx, int32_t* far_ab, int32_t* near_ab) {
   return guarded(ctx, [&](Ctx& c) -> int {
     if (!c.have_lists) return fail(c, AMFMM_E_STATE, "no lists");
     const size_t nc = (size_t)c.ncells;
-    auto emit = [&](const amfmm::DevBuf& st, const amfmm::DevBuf& cn, const amfmm::DevBuf& src, int64_t total,
-                    bool with_self, int32_t* out) {
-      if (!out) return;
-      auto s = fetch<int64_t>(c, st.p, nc);
-      auto k = fetch<int32_t>(c, cn.p, nc);
-      auto y = fetch<int32_t>(c, src.p, (size_t)total);
+    if (far_ab) {
+      auto s = fetch<int64_t>(c, c.far_start.p, nc);
+      auto k = fetch<int32_t>(c, c.far_count.p, nc);
+      auto y = fetch<int32_t>(c, c.far_src.p, (size_t)c.n_far);
       std::vector<std::pair<int32_t, int32_t>> v;
       for (size_t x = 0; x < nc; ++x)
         for (int32_t j = 0; j < k[x]; ++j) {
           int32_t o = y[(size_t)s[x] + j];
-          if ((int32_t)x < o || (with_self && (int32_t)x == o)) v.emplace_back((int32_t)x, o);
+          if ((int32_t)x < o) v.emplace_back((int32_t)x, o);
         }
       std::sort(v.begin(), v.end());
       for (size_t i = 0; i < v.size(); ++i) {
-        out[2 * i] = v[i].first;
-        out[2 * i + 1] = v[i].second;
+        far_ab[2 * i] = v[i].first;
+        far_ab[2 * i + 1] = v[i].second;
       }
-    };
-    emit(c.far_start, c.far_count, c.far_src, c.n_far, false, far_ab);
-    emit(c.near_start, c.near_count, c.near_src, c.n_near, true, near_ab);
+    }
+    if (near_ab) {
+      build_near_pairs(c);
+      const auto& v = c.near_pairs_host;
+      for (size_t i = 0; i < v.size(); ++i) {
+        near_ab[2 * i] = v[i].first;
+        near_ab[2 * i + 1] = v[i].second;
+      }
+    }
     return AMFMM_OK;
   });
 }

@@ -25,6 +25,11 @@ struct Error : std::runtime_error {
   Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
 };
 
+// the walk of a batch would exceed the list budget: retry with a smaller batch
+struct BudgetExceeded : Error {
+  BudgetExceeded() : Error(AMFMM_E_OOM, "interaction lists exceed the list budget") {}
+};
+
 #define AMFMM_HIP(call)                                                                   \
   do {                                                                                    \
     hipError_t e_ = (call);                                                               \
@@ -72,12 +77,24 @@ struct Ctx {
   DevBuf far_start, far_count, far_src;     // int32 (start as int64)
   DevBuf near_start, near_count, near_src;
   // walk frontier
-  DevBuf fx, fy, fx2, fy2, fcnt, grp, walkrec, fsave, gsave, counters;
+  DevBuf fx, fy, fx2, fy2, fcnt, grp, walkrec, fsave, gsave, counters, gqueue;
   int64_t grp_width = 0, frontier = 0;
+  double walk_abs_tol = 0.0;
+  int walk_mode = 0;              // 0 geometric, 1 error estimate against the field
+  const double* field = nullptr;  // caller's per-particle field estimate (device)
+  DevBuf gmin;
+  // unordered near-field leaf pairs of the kept lists (built on request)
+  std::vector<std::pair<int32_t, int32_t>> near_pairs_host;
+  bool near_pairs_valid = false;
   int grp_cur = 0;
   int64_t* pinned = nullptr;  // small pinned host buffer for read-backs
   int64_t far_evals = 0;      // directed far-field evaluations of the last solve
   bool batched = false;       // last solve ran batch by batch (lists not kept)
+  size_t walk_budget = 0;     // bytes of lists + frontier a walk may take (0 = unlimited)
+  // batch size that worked for the last solve of the same size and criterion
+  int64_t batch_hint = 0, hint_n = 0;
+  double hint_theta = 0.0, hint_tol = 0.0;
+  int hint_mode = -1;
   double theta = 0.5;
   bool have_tree = false, have_moments = false, have_lists = false;
   // timing: events recorded at phase changes; the time between two marks

@@ -19,6 +19,7 @@
 //
 // Compiled with -ffp-contract=off: the criterion must round exactly as the
 // plain definition does.
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 
@@ -31,45 +32,76 @@ constexpr int kBS = 256;
 
 enum : int { kAccept = 0, kNear = 1, kSplitX = 2, kSplitY = 3 };
 
-// per cell, everything a walk step reads, in one 48-byte record
-struct alignas(16) WalkCell {
+// per cell, everything a walk step reads, in one 64-byte record
+struct alignas(16) WalkRec {
   double gx, gy, gz, gw;  // centre of mass, R_max
-  int32_t ch0;    // first child (-1 for leaves)
-  int32_t nch;    // child count
-  int32_t par;    // parent
-  int32_t next;   // next sibling, -1 for the last child
+  double m, gmin;         // mass, field scale of the cell (see k_gscale)
+  int32_t ch0, par, count, meta;  // first child, parent, particles, nch | has_next << 8
+};
+
+struct WalkCell {
+  double gx, gy, gz, gw, m, gmin;
+  int32_t ch0, nch, par, next, count;
 };
 
 struct TreeView {
-  const WalkCell* rec;
+  const WalkRec* rec;
   double theta;
+  double abs_tol;    // bound on the rounding of any centre of mass (absolute)
+  int mode;          // 0: opening angle theta; 1: error estimate against the field
+  double eps;        // mode 1: accepted error per pair, relative to each cell's field
+  double theta_max;  // mode 1: (R_A + R_B)/d above this never accepted
 };
 
-__device__ inline WalkCell load_cell(const WalkCell* __restrict__ r, int32_t c) {
+__device__ inline WalkCell load_cell(const WalkRec* __restrict__ r, int32_t c) {
   const double2* p = reinterpret_cast<const double2*>(r + c);
-  const int4* q = reinterpret_cast<const int4*>(reinterpret_cast<const char*>(r + c) + 32);
+  const int4* q = reinterpret_cast<const int4*>(reinterpret_cast<const char*>(r + c) + 48);
   WalkCell w;
-  const double2 p0 = p[0], p1 = p[1];
+  const double2 p0 = p[0], p1 = p[1], p2 = p[2];
   w.gx = p0.x;
   w.gy = p0.y;
   w.gz = p1.x;
   w.gw = p1.y;
-  int4 v = q[0];
+  w.m = p2.x;
+  w.gmin = p2.y;
+  const int4 v = q[0];
   w.ch0 = v.x;
-  w.nch = v.y;
-  w.par = v.z;
-  w.next = v.w;
+  w.par = v.y;
+  w.count = v.z;
+  w.nch = v.w & 0xff;
+  w.next = (v.w >> 8) ? c + 1 : -1;
   return w;
 }
 
 __device__ inline int decide(const TreeView& t, int32_t X, const WalkCell& a, int32_t Y, const WalkCell& b) {
   const double dx = a.gx - b.gx, dy = a.gy - b.gy, dz = a.gz - b.gz;
   const double d = sqrt((dx * dx + dy * dy) + dz * dz);
-  const double rhs = (a.gw + b.gw) / t.theta;
-  if (d > 0.0 && d >= rhs) return kAccept;
+  if (t.mode == 0) {
+    const double rhs = (a.gw + b.gw) / t.theta;
+    if (d > 0.0 && d >= rhs) return kAccept;
+  } else {
+    // The force error of a quadrupole-order pair scales as M_other r^3 / d^5
+    // with r = R_A + R_B; accept when that estimate stays below eps times the
+    // field scale of each cell (both cells: a symmetric decision).
+    const double r = a.gw + b.gw;
+    if (d > 0.0 && r <= t.theta_max * d) {
+      const double q = r / d;
+      const double e = (q * q * q) / (d * d);
+      if (e * b.m <= t.eps * a.gmin && e * a.m <= t.eps * b.gmin) return kAccept;
+    }
+  }
   const bool lx = a.nch == 0, ly = b.nch == 0;
   if (lx && ly) return kNear;
-  if (lx) return kSplitY;
+  if (lx) {
+    // Every centre of mass inside Y lies within R_Y of Z_Y, so when even
+    // d + R_Y falls short of R_X/theta no cell below Y can be accepted with the
+    // leaf X and the walk would pair X with every leaf under Y: record Y once
+    // as a near-field source (its whole particle range).  The margin makes the
+    // test safe against rounding of d and of the centres.
+    const double cut = t.mode == 0 ? t.theta : t.theta_max;
+    if ((d + b.gw) * (1.0 + 1e-12) + t.abs_tol < a.gw / cut) return kNear;
+    return kSplitY;
+  }
   if (ly) return kSplitX;
   if (a.gw > b.gw) return kSplitX;
   if (a.gw < b.gw) return kSplitY;
@@ -113,22 +145,74 @@ __device__ inline void traverse(const TreeView& t, int32_t X, int32_t Y, F&& f) 
 }
 
 __global__ void __launch_bounds__(kBS) k_pack_cells(int32_t nc, const double4* __restrict__ geo,
-                                                    const int32_t* __restrict__ ch0, const int32_t* __restrict__ nch,
-                                                    const int32_t* __restrict__ par, WalkCell* __restrict__ rec) {
+                                                    const double* __restrict__ mom, const int32_t* __restrict__ ch0,
+                                                    const int32_t* __restrict__ nch, const int32_t* __restrict__ par,
+                                                    const int32_t* __restrict__ cnt, const double* __restrict__ gmin,
+                                                    WalkRec* __restrict__ rec) {
   int32_t c = blockIdx.x * kBS + threadIdx.x;
   if (c >= nc) return;
-  WalkCell w;
+  WalkRec w;
   const double4 g = geo[c];
   w.gx = g.x;
   w.gy = g.y;
   w.gz = g.z;
   w.gw = g.w;
+  w.m = mom[(int64_t)c * kMom];
+  w.gmin = gmin ? gmin[c] : 0.0;
   w.ch0 = nch[c] ? ch0[c] : -1;
-  w.nch = nch[c];
   const int32_t p = par[c];
   w.par = p;
-  w.next = (p >= 0 && c + 1 < ch0[p] + nch[p]) ? c + 1 : -1;
+  w.count = cnt[c];
+  const int has_next = (p >= 0 && c + 1 < ch0[p] + nch[p]) ? 1 : 0;
+  w.meta = nch[c] | (has_next << 8);
   rec[c] = w;
+}
+
+// Field scale of every cell: the smallest field estimate over its particles,
+// but at least kFieldFloor times their mean (a cell holding a point where the
+// field vanishes would otherwise never be accepted).  Sums run leaf-sequentially
+// in key order and for parents over their children in octant order (a fixed
+// order, so the value is reproducible bit for bit); min is order-free.
+constexpr double kFieldFloor = 0.1;
+
+__global__ void __launch_bounds__(kBS) k_gsum_leaves(const int32_t* __restrict__ leaves, int32_t nleaves,
+                                                     const int32_t* __restrict__ beg, const int32_t* __restrict__ cnt,
+                                                     const int32_t* __restrict__ perm, const double* __restrict__ gmag,
+                                                     double* __restrict__ gsum, double* __restrict__ gmn) {
+  int32_t i = blockIdx.x * kBS + threadIdx.x;
+  if (i >= nleaves) return;
+  const int32_t c = leaves[i];
+  double v = 0.0, w = INFINITY;
+  for (int32_t p = beg[c]; p < beg[c] + cnt[c]; ++p) {
+    const double g = fabs(gmag[perm[p]]);
+    v += g;
+    w = fmin(w, g);
+  }
+  gsum[c] = v;
+  gmn[c] = w;
+}
+
+__global__ void __launch_bounds__(kBS) k_gsum_up(int32_t c0, int32_t nl, const int32_t* __restrict__ ch0,
+                                                 const int32_t* __restrict__ nch, double* __restrict__ gsum,
+                                                 double* __restrict__ gmn) {
+  int32_t i = blockIdx.x * kBS + threadIdx.x;
+  if (i >= nl) return;
+  const int32_t c = c0 + i;
+  if (nch[c] == 0) return;
+  double v = 0.0, w = INFINITY;
+  for (int32_t q = ch0[c]; q < ch0[c] + nch[c]; ++q) {
+    v += gsum[q];
+    w = fmin(w, gmn[q]);
+  }
+  gsum[c] = v;
+  gmn[c] = w;
+}
+
+__global__ void __launch_bounds__(kBS) k_gscale(int32_t nc, const int32_t* __restrict__ cnt,
+                                                const double* __restrict__ gsum, const double* __restrict__ gmn,
+                                                double* __restrict__ gscale) {
+  int32_t c = blockIdx.x * kBS + threadIdx.x;
+  if (c < nc) gscale[c] = fmax(gmn[c], kFieldFloor * (gsum[c] / (double)cnt[c]));
 }
 
 __device__ inline int32_t wave_excl_scan(int32_t v, int32_t* total) {
@@ -151,10 +235,11 @@ __device__ inline int64_t wave_sum64(int64_t v) {
 
 constexpr int kQ = 1024;  // per-wave LDS work queue (power of two)
 
+// orders this wave's queue writes (LDS or global) before its lanes read them
 __device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 struct EmitDst {
@@ -162,6 +247,7 @@ struct EmitDst {
   int32_t* far_src;
   int32_t* near_src;
   int32_t* fy_n;
+  int64_t B0;  // rank of this chunk's first split-X base inside the cell
 };
 
 // All pairs held by target cell X at this level, processed by one wave
@@ -170,18 +256,20 @@ struct EmitDst {
 // pushes Y's children to the queue; when the queue is full the lane descends
 // Y's subtree itself.  The order is a fixed function of the inputs, so the
 // counting run and the emitting run visit the same pairs in the same order.
-template <bool EMIT>
+template <bool EMIT, typename Q>
 __device__ inline void wave_walk(const TreeView& t, int32_t X, const WalkCell& cx, const int32_t* __restrict__ fy,
-                                 int64_t b, int32_t n, int32_t* qbuf, int64_t& tm, int64_t& tp, int64_t& tq,
-                                 EmitDst dst) {
+                                 int64_t b, int32_t n, Q qbuf, int32_t qcap, int64_t& tm, int64_t& tp, int64_t& tq,
+                                 EmitDst dst, unsigned long long* dbg) {
+  const int32_t qmask = qcap - 1;
   const int lane = threadIdx.x & 63;
   int32_t head = 0, tail = 0, fpos = 0;
-  int64_t fo = dst.fo, no = dst.no, B = 0;
+  int64_t fo = dst.fo, no = dst.no, B = dst.B0;
+  unsigned long long dsteps = 0, ddeep = 0, dpairs = 0;
   while (head < tail || fpos < n) {
     int32_t Y = -1;
     if (head < tail) {
       const int k = min(64, tail - head);
-      if (lane < k) Y = qbuf[(head + lane) & (kQ - 1)];
+      if (lane < k) Y = qbuf[(head + lane) & qmask];
       head += k;
     } else {
       const int k = min(64, n - fpos);
@@ -210,15 +298,21 @@ __device__ inline void wave_walk(const TreeView& t, int32_t X, const WalkCell& c
     }
     int32_t ptot;
     const int32_t poff = wave_excl_scan(push, &ptot);
-    const int32_t freeq = kQ - (tail - head);
+    const int32_t freeq = qcap - (tail - head);
     const bool fits = poff + push <= freeq;
     const uint64_t over = __ballot(push > 0 && !fits);
     const int32_t pushed = over ? __shfl(poff, __ffsll((unsigned long long)over) - 1, 64) : ptot;
     if (push > 0 && fits)
-      for (int32_t j = 0; j < push; ++j) qbuf[(tail + poff + j) & (kQ - 1)] = ych0 + j;
+      for (int32_t j = 0; j < push; ++j) qbuf[(tail + poff + j) & qmask] = ych0 + j;
     tail += pushed;
     wave_sync();
     const bool deep = push > 0 && !fits;  // queue full: descend in this lane
+    if (dbg) {
+      const uint64_t dm = __ballot(deep), ym = __ballot(Y >= 0);
+      dsteps += 1;
+      ddeep += __popcll(dm);
+      dpairs += __popcll(ym);
+    }
     if (deep)
       traverse(t, X, Y, [&](int d, int32_t) {
         m += d == kAccept;
@@ -262,63 +356,123 @@ __device__ inline void wave_walk(const TreeView& t, int32_t X, const WalkCell& c
       B += Tq;
     }
   }
+  if (dbg && (threadIdx.x & 63) == 0) {
+    atomicAdd(&dbg[0], dsteps);
+    atomicAdd(&dbg[1], ddeep);
+    atomicAdd(&dbg[2], dpairs);
+  }
+}
+constexpr int kChunkMin = 64;         // frontier entries per wave: at least ...
+constexpr int kChunkMax = 4096;       // ... at most ...
+constexpr int64_t kWavesPerLevel = 1 << 17;  // ... aiming at about this many waves
+constexpr int64_t kGlobalQueueChunks = 4096;  // levels with at most this many chunks ...
+constexpr int32_t kGlobalQueue = 1 << 18;     // ... give each wave a queue this large in global memory
+
+// chunk -> cell map of the level: kcell[k] = i for cbase[i] <= k < cbase[i+1]
+__global__ void __launch_bounds__(kBS) k_chunk_map(int32_t nl, const int64_t* __restrict__ cbase,
+                                                   int32_t* __restrict__ kcell) {
+  const int32_t i = blockIdx.x * kBS + threadIdx.x;
+  if (i >= nl) return;
+  for (int64_t k = cbase[i]; k < cbase[i + 1]; ++k) kcell[k] = i;
 }
 
-__global__ void __launch_bounds__(kBS) k_walk_count(TreeView t, int32_t c0, int32_t nl,
+__global__ void __launch_bounds__(kBS) k_chunk_counts(int32_t nl, const int32_t* __restrict__ gcnt, int32_t chunk,
+                                                      int64_t* __restrict__ nck) {
+  const int32_t i = blockIdx.x * kBS + threadIdx.x;
+  if (i < nl) nck[i] = (gcnt[i] + chunk - 1) / chunk;
+}
+
+// One wave per chunk of a cell's frontier entries: count its terminal pairs.
+// gq != nullptr: the wave's work queue is the global region gq + k * qcap
+// (levels with few chunks, whose pairs fan out widely); else it is in LDS.
+__global__ void __launch_bounds__(kBS) k_walk_count(TreeView t, int32_t c0, int64_t kn, int32_t chunk,
+                                                    const int32_t* __restrict__ kcell, const int64_t* __restrict__ cbase,
                                                     const int64_t* __restrict__ gbeg, const int32_t* __restrict__ gcnt,
-                                                    const int32_t* __restrict__ fy, int64_t* __restrict__ cm,
-                                                    int64_t* __restrict__ cp, int64_t* __restrict__ cq,
-                                                    int64_t* __restrict__ ns) {
+                                                    const int32_t* __restrict__ fy, int64_t* __restrict__ km,
+                                                    int64_t* __restrict__ kp, int64_t* __restrict__ kq,
+                                                    int32_t* __restrict__ gq, int32_t qcap, unsigned long long* dbg) {
   __shared__ int32_t queue[kBS / 64][kQ];
   const int lane = threadIdx.x & 63;
-  const int32_t i = blockIdx.x * (kBS / 64) + (threadIdx.x >> 6);
-  if (i >= nl) return;
+  const int64_t k = (int64_t)blockIdx.x * (kBS / 64) + (threadIdx.x >> 6);
+  if (k >= kn) return;
+  const int32_t i = kcell[k];
   const int32_t X = c0 + i;
   const WalkCell cx = load_cell(t.rec, X);
+  const int64_t e0 = (k - cbase[i]) * chunk;
+  const int32_t n = (int32_t)min<int64_t>(chunk, gcnt[i] - e0);
   int64_t tm = 0, tp = 0, tq = 0;
-  wave_walk<false>(t, X, cx, fy, gbeg[i], gcnt[i], queue[threadIdx.x >> 6], tm, tp, tq, EmitDst{});
+  if (gq)
+    wave_walk<false>(t, X, cx, fy, gbeg[i] + e0, n, gq + k * qcap, qcap, tm, tp, tq, EmitDst{}, dbg);
+  else
+    wave_walk<false>(t, X, cx, fy, gbeg[i] + e0, n, queue[threadIdx.x >> 6], kQ, tm, tp, tq, EmitDst{}, dbg);
   tm = wave_sum64(tm);
   tp = wave_sum64(tp);
   tq = wave_sum64(tq);
   if (lane == 0) {
-    cm[i] = tm;
-    cp[i] = tp;
-    cq[i] = tq;
-    ns[i] = (int64_t)cx.nch * tq;
+    km[k] = tm;
+    kp[k] = tp;
+    kq[k] = tq;
   }
 }
 
-__global__ void __launch_bounds__(kBS) k_walk_emit(TreeView t, int32_t c0, int32_t nl, int32_t c0n,
-                                                   const int64_t* __restrict__ gbeg, const int32_t* __restrict__ gcnt,
-                                                   const int32_t* __restrict__ fy, const int64_t* __restrict__ cm,
-                                                   const int64_t* __restrict__ cp, const int64_t* __restrict__ cq,
-                                                   const int64_t* __restrict__ mex, const int64_t* __restrict__ pex,
-                                                   const int64_t* __restrict__ nbase, int64_t far_base,
-                                                   int64_t near_base, int64_t* __restrict__ far_start,
-                                                   int32_t* __restrict__ far_count, int64_t* __restrict__ near_start,
-                                                   int32_t* __restrict__ near_count, int32_t* __restrict__ far_src,
-                                                   int32_t* __restrict__ near_src, int64_t* __restrict__ gbeg_n,
-                                                   int32_t* __restrict__ gcnt_n, int32_t* __restrict__ fy_n) {
-  __shared__ int32_t queue[kBS / 64][kQ];
-  const int lane = threadIdx.x & 63;
-  const int32_t i = blockIdx.x * (kBS / 64) + (threadIdx.x >> 6);
+// per cell: list extents, the size of its children's entries, and their groups
+__global__ void __launch_bounds__(kBS) k_walk_cells(TreeView t, int32_t c0, int32_t nl, int32_t c0n,
+                                                    const int64_t* __restrict__ cbase, const int64_t* __restrict__ mex,
+                                                    const int64_t* __restrict__ pex, const int64_t* __restrict__ qex,
+                                                    int64_t far_base, int64_t near_base, int64_t* __restrict__ far_start,
+                                                    int32_t* __restrict__ far_count, int64_t* __restrict__ near_start,
+                                                    int32_t* __restrict__ near_count, int64_t* __restrict__ ns) {
+  const int32_t i = blockIdx.x * kBS + threadIdx.x;
   if (i >= nl) return;
   const int32_t X = c0 + i;
-  const WalkCell cx = load_cell(t.rec, X);
-  const int64_t S = cq[i], nb = nbase[i];
-  if (lane == 0) {
-    far_start[X] = far_base + mex[i];
-    far_count[X] = (int32_t)cm[i];
-    near_start[X] = near_base + pex[i];
-    near_count[X] = (int32_t)cp[i];
-  }
-  for (int32_t r = lane; r < cx.nch; r += 64) {
+  const int64_t k0 = cbase[i], k1 = cbase[i + 1];
+  far_start[X] = far_base + mex[k0];
+  far_count[X] = (int32_t)(mex[k1] - mex[k0]);
+  near_start[X] = near_base + pex[k0];
+  near_count[X] = (int32_t)(pex[k1] - pex[k0]);
+  ns[i] = (int64_t)load_cell(t.rec, X).nch * (qex[k1] - qex[k0]);
+}
+
+__global__ void __launch_bounds__(kBS) k_walk_groups(TreeView t, int32_t c0, int32_t nl, int32_t c0n,
+                                                     const int64_t* __restrict__ cbase, const int64_t* __restrict__ qex,
+                                                     const int64_t* __restrict__ nbase, int64_t* __restrict__ gbeg_n,
+                                                     int32_t* __restrict__ gcnt_n) {
+  const int32_t i = blockIdx.x * kBS + threadIdx.x;
+  if (i >= nl) return;
+  const WalkCell cx = load_cell(t.rec, c0 + i);
+  const int64_t S = qex[cbase[i + 1]] - qex[cbase[i]], nb = nbase[i];
+  for (int32_t r = 0; r < cx.nch; ++r) {
     gbeg_n[cx.ch0 + r - c0n] = nb + r * S;
     gcnt_n[cx.ch0 + r - c0n] = (int32_t)S;
   }
+}
+
+// One wave per chunk: write its far and near entries and its children's entries.
+__global__ void __launch_bounds__(kBS) k_walk_emit(TreeView t, int32_t c0, int64_t kn, int32_t chunk,
+                                                   const int32_t* __restrict__ kcell, const int64_t* __restrict__ cbase,
+                                                   const int64_t* __restrict__ gbeg, const int32_t* __restrict__ gcnt,
+                                                   const int32_t* __restrict__ fy, const int64_t* __restrict__ mex,
+                                                   const int64_t* __restrict__ pex, const int64_t* __restrict__ qex,
+                                                   const int64_t* __restrict__ nbase, int64_t far_base,
+                                                   int64_t near_base, int32_t* __restrict__ far_src,
+                                                   int32_t* __restrict__ near_src, int32_t* __restrict__ fy_n,
+                                                   int32_t* __restrict__ gq, int32_t qcap) {
+  __shared__ int32_t queue[kBS / 64][kQ];
+  const int64_t k = (int64_t)blockIdx.x * (kBS / 64) + (threadIdx.x >> 6);
+  if (k >= kn) return;
+  const int32_t i = kcell[k];
+  const int32_t X = c0 + i;
+  const WalkCell cx = load_cell(t.rec, X);
+  const int64_t e0 = (k - cbase[i]) * chunk;
+  const int32_t n = (int32_t)min<int64_t>(chunk, gcnt[i] - e0);
+  const int64_t S = qex[cbase[i + 1]] - qex[cbase[i]];
   int64_t tm = 0, tp = 0, tq = 0;
-  EmitDst dst{far_base + mex[i], near_base + pex[i], nb, S, far_src, near_src, fy_n};
-  wave_walk<true>(t, X, cx, fy, gbeg[i], gcnt[i], queue[threadIdx.x >> 6], tm, tp, tq, dst);
+  EmitDst dst{far_base + mex[k], near_base + pex[k], nbase[i], S, far_src, near_src, fy_n,
+              qex[k] - qex[cbase[i]]};
+  if (gq)
+    wave_walk<true>(t, X, cx, fy, gbeg[i] + e0, n, gq + k * qcap, qcap, tm, tp, tq, dst, nullptr);
+  else
+    wave_walk<true>(t, X, cx, fy, gbeg[i] + e0, n, queue[threadIdx.x >> 6], kQ, tm, tp, tq, dst, nullptr);
 }
 
 __global__ void k_walk_init(int64_t* gbeg, int32_t* gcnt, int32_t* fy) {
@@ -327,10 +481,10 @@ __global__ void k_walk_init(int64_t* gbeg, int32_t* gcnt, int32_t* fy) {
   fy[0] = 0;
 }
 
-__global__ void k_gather_totals(const int64_t* mex, const int64_t* pex, const int64_t* nbase, int32_t nl,
-                                int64_t* out) {
-  out[0] = mex[nl];
-  out[1] = pex[nl];
+__global__ void k_gather_totals(const int64_t* mex, const int64_t* pex, const int64_t* nbase, int64_t kmax,
+                                int32_t nl, int64_t* out) {
+  out[0] = mex[kmax];
+  out[1] = pex[kmax];
   out[2] = nbase[nl];
 }
 
@@ -338,9 +492,28 @@ __global__ void k_gather_totals(const int64_t* mex, const int64_t* pex, const in
 
 void walk_prepare(Ctx& c, double theta) {
   const int32_t nc = c.ncells;
-  WalkCell* rec = (WalkCell*)ensure(c, c.walkrec, sizeof(WalkCell) * (size_t)nc);
+  WalkRec* rec = (WalkRec*)ensure(c, c.walkrec, sizeof(WalkRec) * (size_t)nc);
+  const double* gmin = nullptr;
+  c.walk_mode = (c.opt.criterion == AMFMM_LEARNED && c.field) ? 1 : 0;
+  if (c.walk_mode == 1) {
+    double* gs = (double*)ensure(c, c.gmin, 3 * sizeof(double) * nc);
+    double* gm = gs + nc;
+    double* g = gm + nc;
+    hipLaunchKernelGGL(k_gsum_leaves, dim3(blocks_for(c.nleaves, kBS)), dim3(kBS), 0, c.stream,
+                       as<int32_t>(c.leaves), c.nleaves, as<int32_t>(c.c_begin), as<int32_t>(c.c_count),
+                       as<int32_t>(c.perm), c.field, gs, gm);
+    for (int l = c.depth - 1; l >= 0; --l) {
+      const int32_t c0 = c.level_start[l], nl = c.level_start[l + 1] - c0;
+      hipLaunchKernelGGL(k_gsum_up, dim3(blocks_for(nl, kBS)), dim3(kBS), 0, c.stream, c0, nl,
+                         as<int32_t>(c.c_child0), as<int32_t>(c.c_nchild), gs, gm);
+    }
+    hipLaunchKernelGGL(k_gscale, dim3(blocks_for(nc, kBS)), dim3(kBS), 0, c.stream, nc, as<int32_t>(c.c_count),
+                       (const double*)gs, (const double*)gm, g);
+    gmin = g;
+  }
   hipLaunchKernelGGL(k_pack_cells, dim3(blocks_for(nc, kBS)), dim3(kBS), 0, c.stream, nc, (const double4*)c.geo.p,
-                     as<int32_t>(c.c_child0), as<int32_t>(c.c_nchild), as<int32_t>(c.c_parent), rec);
+                     (const double*)c.mom.p, as<int32_t>(c.c_child0), as<int32_t>(c.c_nchild),
+                     as<int32_t>(c.c_parent), as<int32_t>(c.c_count), gmin, rec);
   AMFMM_HIP(hipGetLastError());
   ensure(c, c.far_start, sizeof(int64_t) * nc);
   ensure(c, c.far_count, sizeof(int32_t) * nc);
@@ -353,6 +526,12 @@ void walk_prepare(Ctx& c, double theta) {
   ensure(c, c.grp, 2 * (sizeof(int64_t) + sizeof(int32_t)) * (size_t)c.grp_width);
   ensure(c, c.fy, sizeof(int32_t) * 16);
   c.theta = theta;
+  double box[6];
+  AMFMM_HIP(hipMemcpyAsync(box, c.bbox.p, sizeof(box), hipMemcpyDeviceToHost, c.stream));
+  AMFMM_HIP(hipStreamSynchronize(c.stream));
+  double scale = 0.0;
+  for (double v : box) scale = std::max(scale, std::fabs(v));
+  c.walk_abs_tol = 1e-9 * scale;
 }
 
 // the two group arrays (current, next) of the level ping-pong inside c.grp
@@ -377,7 +556,8 @@ void walk_start(Ctx& c) {
 
 int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32_t>& lo,
                     const std::vector<int32_t>& hi, int64_t& far_base, int64_t& near_base) {
-  TreeView t{(const WalkCell*)c.walkrec.p, c.theta};
+  TreeView t{(const WalkRec*)c.walkrec.p, c.theta, c.walk_abs_tol, c.walk_mode, c.opt.learned_tol,
+             c.opt.theta_max};
   static const bool debug = getenv("AMFMM_DEBUG_WALK") != nullptr;
   int64_t F = c.frontier;
   int64_t* tot_host = c.pinned;
@@ -385,41 +565,94 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
     const int32_t c0 = lo[lev], nl = hi[lev] - lo[lev];
     const int32_t c0n = lev + 1 < (int)lo.size() ? lo[lev + 1] : 0;
     const size_t L = (size_t)nl + 1;
+    // enough waves to fill the chip, few enough that dispatch does not dominate
+    const int32_t chunk = (int32_t)std::min<int64_t>(
+        kChunkMax, std::max<int64_t>(kChunkMin, (F / kWavesPerLevel + kChunkMin - 1) / kChunkMin * kChunkMin));
+    const int64_t kmax = F / chunk + nl + 1;  // upper bound on the chunks
+    const size_t K = (size_t)kmax + 1;
     int64_t *gbeg, *gbeg_n;
     int32_t *gcnt, *gcnt_n;
     group_ptrs(c, c.grp_cur, &gbeg, &gcnt);
     group_ptrs(c, 1 - c.grp_cur, &gbeg_n, &gcnt_n);
-    int64_t* w = (int64_t*)ensure(c, c.scratch2, sizeof(int64_t) * (7 * L + 4));
-    int64_t *cm = w, *cp = cm + L, *cq = cp + L, *ns = cq + L, *mex = ns + L, *pex = mex + L, *nbase = pex + L;
-    int64_t* tot = nbase + L;
+    int64_t* w = (int64_t*)ensure(c, c.scratch2, sizeof(int64_t) * (4 * L + 6 * K + 8));
+    int64_t *nck = w, *cbase = nck + L, *ns = cbase + L, *nbase = ns + L;
+    int64_t *km = nbase + L, *kp = km + K, *kq = kp + K, *mex = kq + K, *pex = mex + K, *qex = pex + K;
+    int64_t* tot = qex + K;
     const int32_t* fy = as<int32_t>(c.fy);
-    const unsigned grid = blocks_for(nl, kBS / 64);
-    hipLaunchKernelGGL(k_walk_count, dim3(grid), dim3(kBS), 0, c.stream, t, c0, nl, (const int64_t*)gbeg,
-                       (const int32_t*)gcnt, fy, cm, cp, cq, ns);
+    hipLaunchKernelGGL(k_chunk_counts, dim3(blocks_for(nl, kBS)), dim3(kBS), 0, c.stream, nl, (const int32_t*)gcnt,
+                       chunk, nck);
     AMFMM_HIP(hipGetLastError());
-    scan_i64(c, cm, mex, nl);
-    scan_i64(c, cp, pex, nl);
+    scan_i64(c, nck, cbase, nl);
+    AMFMM_HIP(hipMemcpyAsync(tot_host, cbase + nl, sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
+    AMFMM_HIP(hipStreamSynchronize(c.stream));
+    const int64_t kn = tot_host[0];
+    int32_t* kcell = (int32_t*)ensure(c, c.fx, sizeof(int32_t) * (kn + 1));
+    hipLaunchKernelGGL(k_chunk_map, dim3(blocks_for(nl, kBS)), dim3(kBS), 0, c.stream, nl, (const int64_t*)cbase,
+                       kcell);
+    const unsigned kgrid = blocks_for(kn, kBS / 64);
+    // few chunks: a large work queue per wave in global memory
+    int32_t* gq = nullptr;
+    int32_t qcap = kQ;
+    if (kn <= kGlobalQueueChunks) {
+      qcap = kGlobalQueue;
+      gq = (int32_t*)ensure(c, c.gqueue, sizeof(int32_t) * (size_t)kn * qcap);
+    }
+    unsigned long long* dbg = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (debug) {
+      dbg = (unsigned long long*)(tot + 4);
+      zero_u64(c, dbg, 4);
+      AMFMM_HIP(hipEventCreate(&e0));
+      AMFMM_HIP(hipEventCreate(&e1));
+      AMFMM_HIP(hipEventRecord(e0, c.stream));
+    }
+    hipLaunchKernelGGL(k_walk_count, dim3(kgrid), dim3(kBS), 0, c.stream, t, c0, kn, chunk, (const int32_t*)kcell,
+                       (const int64_t*)cbase, (const int64_t*)gbeg, (const int32_t*)gcnt, fy, km, kp, kq, gq, qcap,
+                       dbg);
+    AMFMM_HIP(hipGetLastError());
+    if (debug) AMFMM_HIP(hipEventRecord(e1, c.stream));
+    scan_i64(c, km, mex, kn);
+    scan_i64(c, kp, pex, kn);
+    scan_i64(c, kq, qex, kn);
+    hipLaunchKernelGGL(k_walk_cells, dim3(blocks_for(nl, kBS)), dim3(kBS), 0, c.stream, t, c0, nl, c0n,
+                       (const int64_t*)cbase, (const int64_t*)mex, (const int64_t*)pex, (const int64_t*)qex, far_base,
+                       near_base, (int64_t*)c.far_start.p, (int32_t*)c.far_count.p, (int64_t*)c.near_start.p,
+                       (int32_t*)c.near_count.p, ns);
+    AMFMM_HIP(hipGetLastError());
     scan_i64(c, ns, nbase, nl);
+    hipLaunchKernelGGL(k_walk_groups, dim3(blocks_for(nl, kBS)), dim3(kBS), 0, c.stream, t, c0, nl, c0n,
+                       (const int64_t*)cbase, (const int64_t*)qex, (const int64_t*)nbase, gbeg_n, gcnt_n);
     hipLaunchKernelGGL(k_gather_totals, dim3(1), dim3(1), 0, c.stream, (const int64_t*)mex, (const int64_t*)pex,
-                       (const int64_t*)nbase, nl, tot);
+                       (const int64_t*)nbase, kn, nl, tot);
     AMFMM_HIP(hipGetLastError());
     AMFMM_HIP(hipMemcpyAsync(tot_host, tot, sizeof(int64_t) * 3, hipMemcpyDeviceToHost, c.stream));
     AMFMM_HIP(hipStreamSynchronize(c.stream));
     const int64_t mt = tot_host[0], pt = tot_host[1], Fn = tot_host[2];
-    if (debug)
-      fprintf(stderr, "walk level %d: cells %d entries %lld far %lld near %lld next %lld\n", lev, nl, (long long)F,
-              (long long)mt, (long long)pt, (long long)Fn);
-    if (Fn >= (int64_t)INT32_MAX) throw Error(AMFMM_E_OOM, "walk frontier exceeds 2^31 entries");
+    if (debug) {
+      unsigned long long h[4];
+      AMFMM_HIP(hipMemcpy(h, dbg, sizeof(h), hipMemcpyDeviceToHost));
+      float ms = 0.f;
+      AMFMM_HIP(hipEventElapsedTime(&ms, e0, e1));
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      fprintf(stderr,
+              "walk level %d: cells %d entries %lld far %lld near %lld next %lld | count pass %.3f ms, steps %llu, "
+              "pairs %llu, deep %llu\n",
+              lev, nl, (long long)F, (long long)mt, (long long)pt, (long long)Fn, ms, h[0], h[2], h[1]);
+    }
+    if (Fn >= (int64_t)INT32_MAX / 2) throw BudgetExceeded();
+    if (c.walk_budget &&
+        (double)sizeof(int32_t) * (double)(far_base + mt + near_base + pt + 2 * Fn) > (double)c.walk_budget)
+      throw BudgetExceeded();
     int32_t* far_src = (int32_t*)ensure_keep(c, c.far_src, sizeof(int32_t) * (far_base + mt + 1),
                                              sizeof(int32_t) * far_base);
     int32_t* near_src = (int32_t*)ensure_keep(c, c.near_src, sizeof(int32_t) * (near_base + pt + 1),
                                               sizeof(int32_t) * near_base);
     int32_t* fy_n = (int32_t*)ensure(c, c.fy2, sizeof(int32_t) * (Fn + 1));
-    hipLaunchKernelGGL(k_walk_emit, dim3(grid), dim3(kBS), 0, c.stream, t, c0, nl, c0n, (const int64_t*)gbeg,
-                       (const int32_t*)gcnt, fy, (const int64_t*)cm, (const int64_t*)cp, (const int64_t*)cq,
-                       (const int64_t*)mex, (const int64_t*)pex, (const int64_t*)nbase, far_base, near_base,
-                       (int64_t*)c.far_start.p, (int32_t*)c.far_count.p, (int64_t*)c.near_start.p,
-                       (int32_t*)c.near_count.p, far_src, near_src, gbeg_n, gcnt_n, fy_n);
+    hipLaunchKernelGGL(k_walk_emit, dim3(kgrid), dim3(kBS), 0, c.stream, t, c0, kn, chunk, (const int32_t*)kcell,
+                       (const int64_t*)cbase, (const int64_t*)gbeg, (const int32_t*)gcnt, fy, (const int64_t*)mex,
+                       (const int64_t*)pex, (const int64_t*)qex, (const int64_t*)nbase, far_base, near_base, far_src,
+                       near_src, fy_n, gq, qcap);
     AMFMM_HIP(hipGetLastError());
     far_base += mt;
     near_base += pt;
