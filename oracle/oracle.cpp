@@ -71,6 +71,9 @@ struct orc_tree {
   bool have_moments = false;
   bool have_lists = false;
   double theta = 0.5;
+  int mode = 0;  // 0 opening angle, 1 error estimate against the field scale
+  double eps = 0.0, theta_max = 1.0;
+  std::vector<double> fscale;  // per-cell field scale (mode 1)
   std::vector<std::pair<int32_t, int32_t>> m2l, p2p;
   int64_t coincident = 0;
 };
@@ -302,8 +305,15 @@ bool accept(const orc_tree& t, int32_t a, int32_t b) {
   double dy = A.Z[1] - B.Z[1];
   double dz = A.Z[2] - B.Z[2];
   double d = std::sqrt((dx * dx + dy * dy) + dz * dz);
-  double rhs = (A.Rmax + B.Rmax) / t.theta;
-  return d > 0.0 && d >= rhs;
+  if (t.mode == 0) {
+    double rhs = (A.Rmax + B.Rmax) / t.theta;
+    return d > 0.0 && d >= rhs;
+  }
+  double r = A.Rmax + B.Rmax;
+  if (!(d > 0.0 && r <= t.theta_max * d)) return false;
+  double q = r / d;
+  double e = (q * q * q) / (d * d);
+  return e * B.M <= t.eps * t.fscale[a] && e * A.M <= t.eps * t.fscale[b];
 }
 
 void walk_pair(orc_tree& t, int32_t a, int32_t b) {
@@ -538,9 +548,45 @@ void orc_get_moments(const orc_tree* t, double* out) {
   }
 }
 
+int32_t orc_walk_field(orc_tree* t, double eps, double theta_max, const double* gmag) {
+  if (!(eps > 0.0) || !(theta_max > 0.0 && theta_max <= 1.0) || !gmag) return ORC_E_INVALID;
+  if (!t->have_moments) return ORC_E_STATE;
+  size_t nc = t->cells.size();
+  std::vector<double> gsum(nc, 0.0), gmin(nc, INFINITY);
+  for (size_t ci = nc; ci-- > 0;) {
+    const Cell& C = t->cells[ci];
+    if (is_leaf(C)) {
+      for (int64_t p = C.begin; p < C.begin + C.count; ++p) {
+        double g = std::fabs(gmag[t->perm[p]]);
+        gsum[ci] += g;
+        gmin[ci] = std::min(gmin[ci], g);
+      }
+    } else {
+      for (int32_t c = C.child0; c < C.child0 + C.nchild; ++c) {
+        gsum[ci] += gsum[c];
+        gmin[ci] = std::min(gmin[ci], gmin[c]);
+      }
+    }
+  }
+  t->fscale.assign(nc, 0.0);
+  for (size_t ci = 0; ci < nc; ++ci)
+    t->fscale[ci] = std::max(gmin[ci], 0.1 * (gsum[ci] / (double)t->cells[ci].count));
+  t->mode = 1;
+  t->eps = eps;
+  t->theta_max = theta_max;
+  t->m2l.clear();
+  t->p2p.clear();
+  walk_self(*t, 0);
+  std::sort(t->m2l.begin(), t->m2l.end());
+  std::sort(t->p2p.begin(), t->p2p.end());
+  t->have_lists = true;
+  return ORC_OK;
+}
+
 int32_t orc_walk(orc_tree* t, double theta) {
   if (!(theta > 0.0 && theta <= 1.0)) return ORC_E_INVALID;
   if (!t->have_moments) return ORC_E_STATE;
+  t->mode = 0;
   t->theta = theta;
   t->m2l.clear();
   t->p2p.clear();

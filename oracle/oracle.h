@@ -67,6 +67,14 @@ void orc_get_moments(const orc_tree* t, double* out21);
 
 /* Dual tree walk under the opening criterion (Sec. 2).  theta in (0,1]. */
 int32_t orc_walk(orc_tree* t, double theta);
+/* The same walk with the error-estimate criterion: a pair is accepted when
+ * d > 0, R_A + R_B <= theta_max d and, with q = (R_A + R_B)/d and
+ * e = q^3 / d^2 (the force-error scale of a quadrupole-order pair per unit
+ * source mass), e M_B <= eps s_A and e M_A <= eps s_B, where s is a cell's
+ * field scale: the smallest |gmag| over its particles, but at least 0.1 times
+ * their mean (sums taken leaf-sequentially in key order and over children in
+ * octant order).  gmag: per-particle field magnitudes, caller order. */
+int32_t orc_walk_field(orc_tree* t, double eps, double theta_max, const double* gmag);
 int64_t orc_num_m2l(const orc_tree* t);
 int64_t orc_num_p2p(const orc_tree* t);
 /* unordered pairs {a,b}: m2l with a<b, p2p with a<=b, each list sorted */

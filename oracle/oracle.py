@@ -43,6 +43,8 @@ def lib():
         L.orc_get_moments.argtypes = [P, d]
         L.orc_walk.restype = C.c_int32
         L.orc_walk.argtypes = [P, C.c_double]
+        L.orc_walk_field.restype = C.c_int32
+        L.orc_walk_field.argtypes = [P, C.c_double, C.c_double, d]
         L.orc_num_m2l.restype = C.c_int64
         L.orc_num_m2l.argtypes = [P]
         L.orc_num_p2p.restype = C.c_int64
@@ -144,6 +146,13 @@ class Tree:
 
     def walk(self, theta):
         st = lib().orc_walk(self._t, float(theta))
+        if st:
+            raise OracleError(st)
+
+    def walk_field(self, eps, theta_max, gmag):
+        """Walk with the error-estimate criterion against per-particle |g|."""
+        g = _f64(gmag)
+        st = lib().orc_walk_field(self._t, float(eps), float(theta_max), _d(g))
         if st:
             raise OracleError(st)
 

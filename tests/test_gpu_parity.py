@@ -210,3 +210,36 @@ def test_batched_walk_matches_whole_walk(theta):
     assert c1["far_evaluations"] == c2["far_evaluations"] > 0
     ph = part.get_phase_times()
     assert ph["near+eval"] > 0 and ph["walk"] > 0
+
+
+FIELD_CASES = ["uniform4k", "plummer16k", "twoplummer20k", "duplicates"]
+
+
+@pytest.mark.parametrize("name", FIELD_CASES)
+@pytest.mark.parametrize("eps,tmax", [(1e-4, 0.7), (1e-6, 0.5)])
+def test_field_criterion_lists_and_accelerations(name, eps, tmax):
+    """Error-estimate criterion: with the same per-particle field input both
+    sides select the same pairs bit for bit, and the accelerations agree."""
+    x, y, z, m = CASES[name]()
+    say("field", name, len(x), eps, tmax)
+    at, _, gabs = orc.direct(x, y, z, m)
+    gmag = np.linalg.norm(at, axis=0)
+    s = amfmm.Solver(criterion=amfmm.LEARNED, learned_tol=eps, theta_max=tmax)
+    X, Y, Z, M = to_dev(x, y, z, m)
+    G, = to_dev(gmag)
+    s.set_field_estimate(G)
+    s.build_tree(X, Y, Z, M)
+    s.compute_moments()
+    s.walk(0.5)
+    far, near = s.get_lists()
+    t = orc.Tree(x, y, z, m)
+    t.compute_moments()
+    t.walk_field(eps, tmax, gmag)
+    ofar, onear = t.lists()
+    assert np.array_equal(far, ofar)
+    assert np.array_equal(near, onear)
+    ax, ay, az, p = s.evaluate()
+    acc = np.stack([ax.cpu().numpy(), ay.cpu().numpy(), az.cpu().numpy()])
+    oacc, opot = t.evaluate(orc.TC)
+    assert np.max(np.linalg.norm(acc - oacc, axis=0) / gabs) <= 1e-12
+    assert np.max(np.abs(p.cpu().numpy() - opot) / np.abs(opot)) <= 1e-12

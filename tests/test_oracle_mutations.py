@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle.cpp")
 
 PINS = ["tests/test_oracle_greens.py", "tests/test_oracle_tree.py", "tests/test_oracle_moments.py",
-        "tests/test_oracle_pair.py", "tests/test_oracle_solve.py"]
+        "tests/test_oracle_pair.py", "tests/test_oracle_solve.py", "tests/test_oracle_field_walk.py"]
 
 MUTATIONS = {
     "correction_prefactor_half": ("pt.Fc[i] = -(1.0 / 6.0) * s;", "pt.Fc[i] = -(0.5) * s;"),
@@ -37,6 +37,10 @@ MUTATIONS = {
                        "if (!(cur.count >= n_crit && lev < max_level)) continue;"),
     "near_field_no_reaction": ("gx[j] -= t->m[i] * dx / r3;", "gx[j] -= 0.0 * dx / r3;"),
     "potential_quadratic_half": ("return p + 0.5 * s2 + (1.0 / 6.0) * s3;", "return p + s2 + (1.0 / 6.0) * s3;"),
+    "field_one_sided": ("return e * B.M <= t.eps * t.fscale[a] && e * A.M <= t.eps * t.fscale[b];",
+                        "return e * B.M <= t.eps * t.fscale[a];"),
+    "field_scale_no_floor": ("std::max(gmin[ci], 0.1 * (gsum[ci] / (double)t->cells[ci].count))",
+                             "std::max(gmin[ci], 1.0 * (gsum[ci] / (double)t->cells[ci].count))"),
     "self_walk_skips_pairs": ("for (int32_t b = a + 1; b < C.child0 + C.nchild; ++b) walk_pair(t, a, b);",
                               "for (int32_t b = a + 2; b < C.child0 + C.nchild; ++b) walk_pair(t, a, b);"),
 }
