@@ -1,10 +1,15 @@
 """Benchmark: particles/s of the full gravity solve on one MI355X.
 
-One step = one amfmm_solve_gravity call (validation, bounding cube, keys,
-sort, tree, upward pass, walk, far field, push-down, near field, evaluation at
-the particles, unsort) on inputs already resident in HBM.  Outputs one JSON
-line.  The error of the timed configuration is measured outside the timed
-region against direct summation at a seeded sample of targets.
+One step = the whole force solve on inputs already resident in HBM.  With
+the error-estimate criterion (default) a step is two amfmm_solve_gravity
+calls: a pilot solve with the geometric criterion (theta = 0.5) whose
+accelerations give every cell its field scale, then the solve whose pair
+selection keeps each pair's estimated error below eps times that scale.
+Each solve covers validation, bounding cube, keys, sort, tree, upward pass,
+walk, far field, push-down, near field, evaluation at the particles and the
+unsort.  Outputs one JSON line.  The error of the timed configuration is
+measured outside the timed region against direct summation at a seeded
+sample of targets.
 
 Workload: 16,777,216-particle Plummer sphere (scale radius 1, mass 1,
 truncated at 20, seed 4, equal masses), G = 1, n_crit = 25, TC variant.
@@ -32,30 +37,44 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--n", type=int, default=1 << 24)
-    p.add_argument("--theta", type=float, default=0.5)
+    p.add_argument("--theta", type=float, default=0.5,
+                   help="opening angle (geometric criterion; also the pilot solve)")
+    p.add_argument("--criterion", choices=["geometric", "field"], default="field")
+    p.add_argument("--eps", type=float, default=1.5e-7,
+                   help="error-estimate criterion: accepted pair error relative to the field scale")
+    p.add_argument("--theta-max", type=float, default=0.5)
     p.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     p.add_argument("--variant", choices=["UC", "TC", "TCO"], default="TC")
     p.add_argument("--error-sample", type=int, default=4096)
-    p.add_argument("--cpu-n", type=int, default=1 << 16, help="oracle sample size (0 = skip)")
+    p.add_argument("--cpu-n", type=int, default=1 << 15, help="oracle sample size (0 = skip)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain device copy of known size (for HBM counter scaling)")
     return p.parse_args()
 
 
-def cpu_baseline(n, theta, seed=4):
+def cpu_baseline(n, theta, field, eps, theta_max, seed=4):
     """The CPU oracle as it stands (single thread) on a smaller Plummer sphere
-    of the same generator: particles/s of its full solve."""
+    of the same generator, same configuration: particles/s of its full solve
+    (with the error-estimate criterion: its own pilot solve, then the solve)."""
+    import numpy as np
+
     from oracle import oracle as orc
     from paper_1706_06989_amd import workloads as W
 
     x, y, z, m = W.plummer(n, seed=seed)
     t0 = time.perf_counter()
-    orc.solve(x, y, z, m, theta=theta, variant=orc.TC)
+    a, _ = orc.solve(x, y, z, m, theta=theta, variant=orc.TC)
+    if field:
+        t = orc.Tree(x, y, z, m)
+        t.compute_moments()
+        t.walk_field(eps, theta_max, np.linalg.norm(a, axis=0))
+        t.evaluate(orc.TC)
     dt = time.perf_counter() - t0
+    what = (f"pilot theta={theta} + error-estimate solve eps={eps}" if field else f"theta={theta}")
     return {"value": n / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
             "sample": f"full oracle solve (tree, moments, walk, eqs. 2-4 at every particle, near "
-                      f"field) of a {n}-particle Plummer sphere, same generator, theta={theta}, "
-                      f"TC, single thread, {dt:.1f} s"}
+                      f"field) of a {n}-particle Plummer sphere, same generator, {what}, TC, "
+                      f"single thread, {dt:.1f} s"}
 
 
 def main():
@@ -72,40 +91,66 @@ def main():
 
     variant = {"UC": amfmm.UC, "TC": amfmm.TC, "TCO": amfmm.TCO}[a.variant]
     prec = amfmm.FP64 if a.precision == "fp64" else amfmm.MIXED
+    field = a.criterion == "field"
     x, y, z, m = W.plummer(a.n, seed=4)
     X, Y, Z, M = (torch.from_numpy(v).to("cuda") for v in (x, y, z, m))
     del x, y, z, m
-    solver = amfmm.Solver(variant=variant, precision=prec)
+    pilot = amfmm.Solver(variant=variant, precision=prec)
+    solver = amfmm.Solver(variant=variant, precision=prec,
+                          criterion=amfmm.LEARNED if field else amfmm.GEOMETRIC,
+                          learned_tol=a.eps, theta_max=a.theta_max)
+    pout = pilot._outputs(a.n, False)
     out = solver._outputs(a.n, True)
-    print(f"# bench: n={a.n} theta={a.theta} {a.precision} {a.variant} warmup={a.warmup} "
-          f"steps={a.steps}", file=sys.stderr, flush=True)
-    for i in range(a.warmup):
+    if field:
+        solver.set_field_estimate(pout[0], pout[1], pout[2])
+
+    def step():
+        if field:
+            pilot.solve_gravity(X, Y, Z, M, a.theta, out=pout)
         solver.solve_gravity(X, Y, Z, M, a.theta, out=out)
+
+    print(f"# bench: n={a.n} {a.criterion} theta={a.theta} eps={a.eps} {a.precision} {a.variant} "
+          f"warmup={a.warmup} steps={a.steps}", file=sys.stderr, flush=True)
+    for i in range(a.warmup):
+        step()
         torch.cuda.synchronize()
         print(f"# warmup {i} done", file=sys.stderr, flush=True)
-    phases = {}
+    phases, pphases = {}, {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(a.steps):
-        solver.solve_gravity(X, Y, Z, M, a.theta, out=out)
+        step()
         ph = solver.get_phase_times()  # HIP events on the solver's stream
         for k, v in ph.items():
             phases[k] = phases.get(k, 0.0) + v
-        print(f"# step {i}: {ph['total']:.2f} ms", file=sys.stderr, flush=True)
+        if field:
+            for k, v in pilot.get_phase_times().items():
+                pphases[k] = pphases.get(k, 0.0) + v
+        print(f"# step {i}: {ph['total'] + pphases.get('total', 0.0) / (i + 1):.2f} ms", file=sys.stderr,
+              flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms = dt / a.steps * 1e3
     phases = {k: v / a.steps for k, v in phases.items()}
+    pphases = {k: v / a.steps for k, v in pphases.items()}
     counts = solver.get_counts()
 
     # accuracy of the timed configuration (outside the timed region)
     idx = torch.from_numpy(W.sample_targets(a.n, a.error_sample, seed=99)).to("cuda")
     tx, ty, tz, _, _ = solver.direct(X, Y, Z, M, idx, pot=False, gabs=False)
-    ax, ay, az, _ = out
-    A = torch.stack([ax[idx], ay[idx], az[idx]])
     T = torch.stack([tx, ty, tz])
-    eps = (torch.linalg.norm(A - T, dim=0) / torch.linalg.norm(T, dim=0)).cpu().numpy()
-    fbal, tbal = solver.balance(X, Y, Z, M, ax, ay, az)
+
+    def p_err(o):
+        A = torch.stack([o[0][idx], o[1][idx], o[2][idx]])
+        return (torch.linalg.norm(A - T, dim=0) / torch.linalg.norm(T, dim=0)).cpu().numpy()
+
+    eps = p_err(out)
+    fbal, tbal = solver.balance(X, Y, Z, M, out[0], out[1], out[2])
+    pilot_info = None
+    if field:
+        pe = p_err(pout)
+        pilot_info = {"criterion": "geometric", "theta": a.theta, "ms": round(pphases["total"], 3),
+                      "p99_rel_force_error": float(np.percentile(pe, 99))}
 
     # roofline of the dominant kernel (near field: one launch per step)
     near_ms = phases["near+eval"]
@@ -122,7 +167,7 @@ def main():
 
     cpu = None
     if a.cpu_n > 0:
-        cpu = cpu_baseline(a.cpu_n, a.theta)
+        cpu = cpu_baseline(a.cpu_n, a.theta, field, a.eps, a.theta_max)
 
     line = {
         "metric": METRIC, "value": a.n / (ms * 1e-3), "unit": "particles/s", "n_gpus": 1,
@@ -130,8 +175,10 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if a.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": "plummer16m" if a.n == 1 << 24 else f"plummer{a.n}", "n": a.n,
-                   "theta": a.theta, "variant": a.variant, "precision": a.precision, "n_crit": 25,
-                   "criterion": "geometric",
+                   "criterion": a.criterion, "theta": a.theta,
+                   "eps": a.eps if field else None, "theta_max": a.theta_max if field else None,
+                   "pilot": pilot_info,
+                   "variant": a.variant, "precision": a.precision, "n_crit": 25,
                    "p99_rel_force_error": float(np.percentile(eps, 99)),
                    "mean_rel_force_error": float(eps.mean()),
                    "max_rel_force_error": float(eps.max()), "error_sample": int(len(eps)),

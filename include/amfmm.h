@@ -77,11 +77,12 @@ int amfmm_default_options(amfmm_options* opt);
  * on the current device.  The context owns all scratch. */
 int amfmm_create(const amfmm_options* opt, void* hip_stream, amfmm_ctx** out);
 int amfmm_destroy(amfmm_ctx* ctx);
-/* Per-particle field magnitudes |g| (device pointer, n doubles, caller order)
- * for the AMFMM_LEARNED criterion, e.g. the accelerations of the previous time
- * step or of a cheaper solve.  The array is read during the next walks; it
- * must stay valid until they return.  NULL clears it. */
-int amfmm_set_field_estimate(amfmm_ctx* ctx, const double* gmag);
+/* Per-particle field estimates for the AMFMM_LEARNED criterion, e.g. the
+ * accelerations of the previous time step or of a cheaper solve: device
+ * pointers to n doubles in caller order, either the three components (gx, gy,
+ * gz) or magnitudes in gx with gy = gz = NULL.  The arrays are read during the
+ * next walks and must stay valid until they return.  gx = NULL clears them. */
+int amfmm_set_field_estimate(amfmm_ctx* ctx, const double* gx, const double* gy, const double* gz);
 /* Rebinds the context to another stream of the same device. */
 int amfmm_set_stream(amfmm_ctx* ctx, void* hip_stream);
 

@@ -49,7 +49,7 @@ def lib():
         "amfmm_create": (C.c_int, [C.POINTER(amfmm_options), P, C.POINTER(P)]),
         "amfmm_destroy": (C.c_int, [P]),
         "amfmm_set_stream": (C.c_int, [P, P]),
-        "amfmm_set_field_estimate": (C.c_int, [P, pd]),
+        "amfmm_set_field_estimate": (C.c_int, [P, pd, pd, pd]),
         "amfmm_build_tree": (C.c_int, [P, i64, pd, pd, pd, pd]),
         "amfmm_compute_moments": (C.c_int, [P]),
         "amfmm_walk": (C.c_int, [P, C.c_double]),
@@ -138,13 +138,14 @@ class Solver:
             raise AmfmmError(st, lib().amfmm_last_error(self._h).decode())
         return st
 
-    def set_field_estimate(self, gmag):
-        """Per-particle |g| estimates (CUDA float64, caller order) for the
-        error-estimate criterion; None clears them.  The tensor is kept alive
-        by the solver until replaced."""
-        self._field = gmag
-        self._check(lib().amfmm_set_field_estimate(self._h, _dev(gmag, "gmag") if gmag is not None
-                                                   else None))
+    def set_field_estimate(self, gx, gy=None, gz=None):
+        """Per-particle field estimates (CUDA float64, caller order) for the
+        error-estimate criterion: magnitudes (gx only) or the three
+        components; None clears them.  The tensors are kept alive by the
+        solver until replaced."""
+        self._field = (gx, gy, gz)
+        d = lambda t, nm: _dev(t, nm) if t is not None else None
+        self._check(lib().amfmm_set_field_estimate(self._h, d(gx, "gx"), d(gy, "gy"), d(gz, "gz")))
 
     def build_tree(self, x, y, z, m):
         self.n = x.numel()

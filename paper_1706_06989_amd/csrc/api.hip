@@ -175,9 +175,12 @@ int amfmm_destroy(amfmm_ctx* ctx) {
   return AMFMM_OK;
 }
 
-int amfmm_set_field_estimate(amfmm_ctx* ctx, const double* gmag) {
+int amfmm_set_field_estimate(amfmm_ctx* ctx, const double* gx, const double* gy, const double* gz) {
   return guarded(ctx, [&](Ctx& c) -> int {
-    c.field = gmag;
+    if ((gy == nullptr) != (gz == nullptr)) return fail(c, AMFMM_E_INVALID, "give magnitudes or all three components");
+    c.field = gx;
+    c.field_y = gx ? gy : nullptr;
+    c.field_z = gx ? gz : nullptr;
     return AMFMM_OK;
   });
 }

@@ -81,7 +81,11 @@ struct Ctx {
   int64_t grp_width = 0, frontier = 0;
   double walk_abs_tol = 0.0;
   int walk_mode = 0;              // 0 geometric, 1 error estimate against the field
-  const double* field = nullptr;  // caller's per-particle field estimate (device)
+  // caller's per-particle field estimate (device): magnitudes in `field`, or
+  // components in field, field_y, field_z
+  const double* field = nullptr;
+  const double* field_y = nullptr;
+  const double* field_z = nullptr;
   DevBuf gmin;
   // unordered near-field leaf pairs of the kept lists (built on request)
   std::vector<std::pair<int32_t, int32_t>> near_pairs_host;

@@ -175,16 +175,19 @@ __global__ void __launch_bounds__(kBS) k_pack_cells(int32_t nc, const double4* _
 // order, so the value is reproducible bit for bit); min is order-free.
 constexpr double kFieldFloor = 0.1;
 
+// gy == nullptr: gx holds field magnitudes; else (gx, gy, gz) are components
 __global__ void __launch_bounds__(kBS) k_gsum_leaves(const int32_t* __restrict__ leaves, int32_t nleaves,
                                                      const int32_t* __restrict__ beg, const int32_t* __restrict__ cnt,
-                                                     const int32_t* __restrict__ perm, const double* __restrict__ gmag,
+                                                     const int32_t* __restrict__ perm, const double* __restrict__ gx,
+                                                     const double* __restrict__ gy, const double* __restrict__ gz,
                                                      double* __restrict__ gsum, double* __restrict__ gmn) {
   int32_t i = blockIdx.x * kBS + threadIdx.x;
   if (i >= nleaves) return;
   const int32_t c = leaves[i];
   double v = 0.0, w = INFINITY;
   for (int32_t p = beg[c]; p < beg[c] + cnt[c]; ++p) {
-    const double g = fabs(gmag[perm[p]]);
+    const int32_t o = perm[p];
+    const double g = gy ? sqrt((gx[o] * gx[o] + gy[o] * gy[o]) + gz[o] * gz[o]) : fabs(gx[o]);
     v += g;
     w = fmin(w, g);
   }
@@ -501,7 +504,7 @@ void walk_prepare(Ctx& c, double theta) {
     double* g = gm + nc;
     hipLaunchKernelGGL(k_gsum_leaves, dim3(blocks_for(c.nleaves, kBS)), dim3(kBS), 0, c.stream,
                        as<int32_t>(c.leaves), c.nleaves, as<int32_t>(c.c_begin), as<int32_t>(c.c_count),
-                       as<int32_t>(c.perm), c.field, gs, gm);
+                       as<int32_t>(c.perm), c.field, c.field_y, c.field_z, gs, gm);
     for (int l = c.depth - 1; l >= 0; --l) {
       const int32_t c0 = c.level_start[l], nl = c.level_start[l + 1] - c0;
       hipLaunchKernelGGL(k_gsum_up, dim3(blocks_for(nl, kBS)), dim3(kBS), 0, c.stream, c0, nl,
@@ -640,7 +643,7 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
               "pairs %llu, deep %llu\n",
               lev, nl, (long long)F, (long long)mt, (long long)pt, (long long)Fn, ms, h[0], h[2], h[1]);
     }
-    if (Fn >= (int64_t)INT32_MAX / 2) throw BudgetExceeded();
+    if (Fn >= (int64_t(1) << 34)) throw BudgetExceeded();
     if (c.walk_budget &&
         (double)sizeof(int32_t) * (double)(far_base + mt + near_base + pt + 2 * Fn) > (double)c.walk_budget)
       throw BudgetExceeded();
