@@ -16,8 +16,10 @@
 // -105/R^9.  Eq. 8 keeps only 3 t3 Q_ikl R_k R_l + 3 t2 Q_ikk.
 //
 // One wave per target cell, lanes over its sources, fixed-order butterfly
-// reduction (deterministic).  Near field: one wave per target leaf, lanes =
-// (target, source slice), sources read from the key-sorted double4 array.
+// reduction (deterministic).  Mixed precision: R = Z_X - Z_Y is formed in FP64
+// and rounded, the coefficient terms are FP32 and each lane adds at most
+// kFarFlush of them in FP32 before an FP64 flush; the correction (which
+// cancels M_X,jkl M_Y against M_X M_Y,jkl) stays FP64.
 #include "internal.h"
 
 namespace amfmm {
@@ -44,7 +46,95 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Far-field coefficients of one source (moments M, quadrupole Q2) at R:
+// acc[0] C, acc[1..3] C_k, acc[4..9] C_kl, acc[10..19] C_klm (packed).
+// T = double (FP64 path) or float (mixed path).
+template <typename T>
+__device__ inline void far_coeffs(const T R[3], T M, const T Q2[6], T* acc) {
+  const T r2 = fma(R[0], R[0], fma(R[1], R[1], R[2] * R[2]));
+  T ri;
+  if constexpr (sizeof(T) == 8) ri = rsqrt_f64(r2);
+  else ri = __builtin_amdgcn_rsqf(r2);
+  const T ri2 = ri * ri;
+  const T t1 = ri * ri2;
+  const T t2 = T(-3) * t1 * ri2;
+  const T t3 = T(-5) * t2 * ri2;
+  const T RR[6] = {R[0] * R[0], R[0] * R[1], R[0] * R[2], R[1] * R[1], R[1] * R[2], R[2] * R[2]};
+  // D_kl and D_klm (packed)
+  T D2[6], D3[10];
+#pragma unroll
+  for (int u = 0; u < 6; ++u) D2[u] = t2 * RR[u];
+  D2[0] += t1;
+  D2[3] += t1;
+  D2[5] += t1;
+  D3[0] = fma(t3 * RR[0], R[0], T(3) * t2 * R[0]);
+  D3[1] = fma(t3 * RR[0], R[1], t2 * R[1]);
+  D3[2] = fma(t3 * RR[0], R[2], t2 * R[2]);
+  D3[3] = fma(t3 * RR[3], R[0], t2 * R[0]);
+  D3[4] = t3 * RR[1] * R[2];
+  D3[5] = fma(t3 * RR[5], R[0], t2 * R[0]);
+  D3[6] = fma(t3 * RR[3], R[1], T(3) * t2 * R[1]);
+  D3[7] = fma(t3 * RR[3], R[2], t2 * R[2]);
+  D3[8] = fma(t3 * RR[5], R[1], t2 * R[1]);
+  D3[9] = fma(t3 * RR[5], R[2], T(3) * t2 * R[2]);
+  // contractions of the source quadrupole
+  const T trQ = Q2[0] + Q2[3] + Q2[5];
+  const T QR[3] = {fma(Q2[0], R[0], fma(Q2[1], R[1], Q2[2] * R[2])),
+                   fma(Q2[1], R[0], fma(Q2[3], R[1], Q2[4] * R[2])),
+                   fma(Q2[2], R[0], fma(Q2[4], R[1], Q2[5] * R[2]))};
+  const T RQR = fma(R[0], QR[0], fma(R[1], QR[1], R[2] * QR[2]));
+  acc[0] += fma(-M, ri, T(0.5) * fma(t2, RQR, t1 * trQ));
+  const T a1 = fma(M, t1, T(0.5) * fma(t3, RQR, t2 * trQ));
+#pragma unroll
+  for (int k = 0; k < 3; ++k) acc[1 + k] += fma(a1, R[k], t2 * QR[k]);
+#pragma unroll
+  for (int u = 0; u < 6; ++u) acc[4 + u] = fma(M, D2[u], acc[4 + u]);
+#pragma unroll
+  for (int u = 0; u < 10; ++u) acc[10 + u] = fma(M, D3[u], acc[10 + u]);
+}
+
+// Q_jkl D_ijkl (TC) or Q_jkl D'_ijkl (TCO) of the correction, FP64, with
+// Q = M_X,jkl M_Y - M_X M_Y,jkl; adds to F[3]
 template <int VARIANT>
+__device__ inline void far_correction(const double R[3], double MX, const double OX[10], double M, const double O3[10],
+                                      double F[3]) {
+  const double r2 = fma(R[0], R[0], fma(R[1], R[1], R[2] * R[2]));
+  const double ri = rsqrt_f64(r2);
+  const double ri2 = ri * ri;
+  const double t2 = -3.0 * (ri * ri2) * ri2;
+  const double t3 = -5.0 * t2 * ri2;
+  const double RR[6] = {R[0] * R[0], R[0] * R[1], R[0] * R[2], R[1] * R[1], R[1] * R[2], R[2] * R[2]};
+  double Q[10];
+#pragma unroll
+  for (int u = 0; u < 10; ++u) Q[u] = fma(OX[u], M, -MX * O3[u]);
+  const double mult[6] = {1.0, 2.0, 2.0, 1.0, 2.0, 1.0};
+  double v[3], w[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) s = fma(mult[p] * Q[kT[p][i]], RR[p], s);
+    v[i] = s;
+  }
+  w[0] = Q[0] + Q[3] + Q[5];
+  w[1] = Q[1] + Q[6] + Q[8];
+  w[2] = Q[2] + Q[7] + Q[9];
+  if (VARIANT == AMFMM_TC) {
+    const double t4 = -7.0 * t3 * ri2;
+    const double s = fma(R[0], v[0], fma(R[1], v[1], R[2] * v[2]));
+    const double wR = fma(R[0], w[0], fma(R[1], w[1], R[2] * w[2]));
+#pragma unroll
+    for (int i = 0; i < 3; ++i) F[i] += fma(t4 * s, R[i], 3.0 * fma(t3, fma(R[i], wR, v[i]), t2 * w[i]));
+  } else {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) F[i] += 3.0 * fma(t3, v[i], t2 * w[i]);
+  }
+}
+
+// sources per lane summed in FP32 before an FP64 flush (mixed path)
+constexpr int kFarFlush = 8;
+
+template <int VARIANT, bool MIXED>
 __global__ void __launch_bounds__(kBS) k_far(int32_t c_lo, int32_t nc, const double4* __restrict__ geo, const double* __restrict__ mom,
                                              const int64_t* __restrict__ fstart, const int32_t* __restrict__ fcount,
                                              const int32_t* __restrict__ fsrc, double* __restrict__ loc) {
@@ -60,99 +150,56 @@ __global__ void __launch_bounds__(kBS) k_far(int32_t c_lo, int32_t nc, const dou
   double OX[10];
 #pragma unroll
   for (int u = 0; u < 10; ++u) OX[u] = VARIANT ? mx[7 + u] : 0.0;
-  double acc[23];
+  double acc[20], F[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-  for (int u = 0; u < 23; ++u) acc[u] = 0.0;
-  for (int32_t j = lane; j < cnt; j += 64) {
-    const int32_t Y = fsrc[st + j];
-    const double4 gy = geo[Y];
-    const double* my = mom + (int64_t)Y * kMom;
-    const double M = my[0];
-    double Q2[6], O3[10];
+  for (int u = 0; u < 20; ++u) acc[u] = 0.0;
+  const int64_t step = MIXED ? 64 * kFarFlush : (int64_t)cnt + 64;
+  for (int64_t j0 = lane; j0 < cnt; j0 += step) {
+    float a32[20];
 #pragma unroll
-    for (int u = 0; u < 6; ++u) Q2[u] = my[1 + u];
+    for (int u = 0; u < 20; ++u) a32[u] = 0.0f;
+    const int64_t j1 = j0 + step < cnt ? j0 + step : cnt;
+    for (int64_t j = j0; j < j1; j += 64) {
+      const int32_t Y = fsrc[st + j];
+      const double4 gy = geo[Y];
+      const double* my = mom + (int64_t)Y * kMom;
+      const double M = my[0];
+      const double R[3] = {gx.x - gy.x, gx.y - gy.y, gx.z - gy.z};
+      if (MIXED) {
+        const float Rf[3] = {(float)R[0], (float)R[1], (float)R[2]};
+        float Q2f[6];
 #pragma unroll
-    for (int u = 0; u < 10; ++u) O3[u] = my[7 + u];
-    const double R[3] = {gx.x - gy.x, gx.y - gy.y, gx.z - gy.z};
-    const double r2 = fma(R[0], R[0], fma(R[1], R[1], R[2] * R[2]));
-    const double ri = rsqrt_f64(r2);
-    const double ri2 = ri * ri;
-    const double t1 = ri * ri2;
-    const double t2 = -3.0 * t1 * ri2;
-    const double t3 = -5.0 * t2 * ri2;
-    const double RR[6] = {R[0] * R[0], R[0] * R[1], R[0] * R[2], R[1] * R[1], R[1] * R[2], R[2] * R[2]};
-    // D_kl and D_klm (packed)
-    double D2[6], D3[10];
-#pragma unroll
-    for (int u = 0; u < 6; ++u) D2[u] = t2 * RR[u];
-    D2[0] += t1;
-    D2[3] += t1;
-    D2[5] += t1;
-    D3[0] = fma(t3 * RR[0], R[0], 3.0 * t2 * R[0]);
-    D3[1] = fma(t3 * RR[0], R[1], t2 * R[1]);
-    D3[2] = fma(t3 * RR[0], R[2], t2 * R[2]);
-    D3[3] = fma(t3 * RR[3], R[0], t2 * R[0]);
-    D3[4] = t3 * RR[1] * R[2];
-    D3[5] = fma(t3 * RR[5], R[0], t2 * R[0]);
-    D3[6] = fma(t3 * RR[3], R[1], 3.0 * t2 * R[1]);
-    D3[7] = fma(t3 * RR[3], R[2], t2 * R[2]);
-    D3[8] = fma(t3 * RR[5], R[1], t2 * R[1]);
-    D3[9] = fma(t3 * RR[5], R[2], 3.0 * t2 * R[2]);
-    // contractions of the source quadrupole
-    const double trQ = Q2[0] + Q2[3] + Q2[5];
-    const double QR[3] = {fma(Q2[0], R[0], fma(Q2[1], R[1], Q2[2] * R[2])),
-                          fma(Q2[1], R[0], fma(Q2[3], R[1], Q2[4] * R[2])),
-                          fma(Q2[2], R[0], fma(Q2[4], R[1], Q2[5] * R[2]))};
-    const double RQR = fma(R[0], QR[0], fma(R[1], QR[1], R[2] * QR[2]));
-    // C and C_k
-    acc[0] += fma(-M, ri, 0.5 * fma(t2, RQR, t1 * trQ));
-    const double a1 = fma(M, t1, 0.5 * fma(t3, RQR, t2 * trQ));
-#pragma unroll
-    for (int k = 0; k < 3; ++k) acc[1 + k] += fma(a1, R[k], t2 * QR[k]);
-#pragma unroll
-    for (int u = 0; u < 6; ++u) acc[4 + u] = fma(M, D2[u], acc[4 + u]);
-#pragma unroll
-    for (int u = 0; u < 10; ++u) acc[10 + u] = fma(M, D3[u], acc[10 + u]);
-    if (VARIANT) {
-      double Q[10];
-#pragma unroll
-      for (int u = 0; u < 10; ++u) Q[u] = fma(OX[u], M, -MX * O3[u]);
-      const double mult[6] = {1.0, 2.0, 2.0, 1.0, 2.0, 1.0};
-      double v[3], w[3];
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        double s = 0.0;
-#pragma unroll
-        for (int p = 0; p < 6; ++p) s = fma(mult[p] * Q[kT[p][i]], RR[p], s);
-        v[i] = s;
-      }
-      w[0] = Q[0] + Q[3] + Q[5];
-      w[1] = Q[1] + Q[6] + Q[8];
-      w[2] = Q[2] + Q[7] + Q[9];
-      double F[3];
-      if (VARIANT == AMFMM_TC) {
-        const double t4 = -7.0 * t3 * ri2;
-        const double s = fma(R[0], v[0], fma(R[1], v[1], R[2] * v[2]));
-        const double wR = fma(R[0], w[0], fma(R[1], w[1], R[2] * w[2]));
-#pragma unroll
-        for (int i = 0; i < 3; ++i) F[i] = fma(t4 * s, R[i], 3.0 * fma(t3, fma(R[i], wR, v[i]), t2 * w[i]));
+        for (int u = 0; u < 6; ++u) Q2f[u] = (float)my[1 + u];
+        far_coeffs<float>(Rf, (float)M, Q2f, a32);
       } else {
+        double Q2[6];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) F[i] = 3.0 * fma(t3, v[i], t2 * w[i]);
+        for (int u = 0; u < 6; ++u) Q2[u] = my[1 + u];
+        far_coeffs<double>(R, M, Q2, acc);
       }
+      if (VARIANT) {
+        double O3[10];
 #pragma unroll
-      for (int i = 0; i < 3; ++i) acc[20 + i] += F[i];
+        for (int u = 0; u < 10; ++u) O3[u] = my[7 + u];
+        far_correction<VARIANT>(R, MX, OX, M, O3, F);
+      }
+    }
+    if (MIXED) {
+#pragma unroll
+      for (int u = 0; u < 20; ++u) acc[u] += (double)a32[u];
     }
   }
 #pragma unroll
-  for (int u = 0; u < 23; ++u) acc[u] = wave_sum(acc[u]);
+  for (int u = 0; u < 20; ++u) acc[u] = wave_sum(acc[u]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) F[i] = wave_sum(F[i]);
   if (lane == 0) {
     double* o = loc + (int64_t)X * kLoc;
     const double cf = -1.0 / (6.0 * MX);
 #pragma unroll
     for (int u = 0; u < 20; ++u) o[u] = acc[u];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) o[20 + i] = VARIANT ? cf * acc[20 + i] : 0.0;
+    for (int i = 0; i < 3; ++i) o[20 + i] = VARIANT ? cf * F[i] : 0.0;
     o[23] = 0.0;
   }
 }
@@ -228,10 +275,11 @@ void far_field(Ctx& c, int32_t c_lo, int32_t c_hi) {
     hipLaunchKernelGGL(kern, grid, dim3(kBS), 0, c.stream, c_lo, nc, (const double4*)c.geo.p, (const double*)c.mom.p,
                        (const int64_t*)c.far_start.p, (const int32_t*)c.far_count.p, (const int32_t*)c.far_src.p, loc);
   };
+  const bool mixed = c.opt.precision == AMFMM_MIXED;
   switch (c.opt.variant) {
-    case AMFMM_UC: args(k_far<AMFMM_UC>); break;
-    case AMFMM_TC: args(k_far<AMFMM_TC>); break;
-    default: args(k_far<AMFMM_TCO>); break;
+    case AMFMM_UC: mixed ? args(k_far<AMFMM_UC, true>) : args(k_far<AMFMM_UC, false>); break;
+    case AMFMM_TC: mixed ? args(k_far<AMFMM_TC, true>) : args(k_far<AMFMM_TC, false>); break;
+    default: mixed ? args(k_far<AMFMM_TCO, true>) : args(k_far<AMFMM_TCO, false>); break;
   }
   AMFMM_HIP(hipGetLastError());
 }

@@ -9,6 +9,14 @@
 // (deterministic).  Source leaves that follow each other in particle order
 // are merged into one run; runs are read straight from the key-sorted double4
 // particle array (consecutive lanes read consecutive particles).
+//
+// Mixed precision: targets and staged sources are FP32 offsets from the
+// target leaf's centre of mass (each difference taken in FP64, then rounded),
+// the pair terms are FP32 (hardware reciprocal square root), and each lane's
+// FP32 sums run over at most kFlush sources before they are added to FP64
+// accumulators; the tile sums enter FP64 exactly, so the FP64 accumulator
+// carries what an FP32 compensation term would.  Slices, L2P and the output
+// stay FP64.
 #include "device_math.h"
 #include "internal.h"
 
@@ -28,6 +36,43 @@ __device__ inline void wave_sync() {
 }
 
 __device__ inline int pow2floor(int v) { return 1 << (31 - __builtin_clz(v)); }
+
+constexpr int kFlush = 16;  // FP32 terms per lane and target before an FP64 flush
+
+// FP32 interactions of this lane's targets (offsets t*) with sources
+// buf[s], buf[s+nsl], ...; partial sums flushed into the FP64 accumulators
+__device__ inline void near_tile_f32(const float4* buf, int fill, int s, int nsl, const float* tx, const float* ty,
+                                     const float* tz, double* fx, double* fy, double* fz, double* ph) {
+  for (int j0 = s; j0 < fill; j0 += kFlush * nsl) {
+    const int j1 = min(fill, j0 + kFlush * nsl);
+    float gx[kTG], gy[kTG], gz[kTG], gp[kTG];
+#pragma unroll
+    for (int u = 0; u < kTG; ++u) gx[u] = gy[u] = gz[u] = gp[u] = 0.0f;
+    for (int j = j0; j < j1; j += nsl) {
+      const float4 q = buf[j];
+#pragma unroll
+      for (int u = 0; u < kTG; ++u) {
+        const float dx = q.x - tx[u], dy = q.y - ty[u], dz = q.z - tz[u];
+        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        float y = __builtin_amdgcn_rsqf(r2);
+        y = r2 > 0.0f ? y : 0.0f;
+        const float my = q.w * y;
+        const float my3 = my * (y * y);
+        gx[u] = fmaf(my3, dx, gx[u]);
+        gy[u] = fmaf(my3, dy, gy[u]);
+        gz[u] = fmaf(my3, dz, gz[u]);
+        gp[u] -= my;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kTG; ++u) {
+      fx[u] += (double)gx[u];
+      fy[u] += (double)gy[u];
+      fz[u] += (double)gz[u];
+      ph[u] += (double)gp[u];
+    }
+  }
+}
 
 // interactions of this lane's kTG targets with sources buf[s], buf[s+nsl], ...
 __device__ inline void near_tile(const double4* buf, int fill, int s, int nsl, const double* tx, const double* ty,
@@ -50,7 +95,13 @@ __device__ inline void near_tile(const double4* buf, int fill, int s, int nsl, c
   }
 }
 
+// FP32 offset of a particle from a centre (difference in FP64, then rounded)
+__device__ inline float4 offset32(const double4 p, const double4 c) {
+  return make_float4((float)(p.x - c.x), (float)(p.y - c.y), (float)(p.z - c.z), (float)p.w);
+}
+
 // leaves == nullptr: the targets are the leaves among cells [c_lo, c_lo + nleaves)
+template <bool MIXED>
 __global__ void __launch_bounds__(kBS) k_near(int32_t nleaves, const int32_t* __restrict__ leaves, int32_t c_lo,
                                               const int32_t* __restrict__ nch,
                                               const int32_t* __restrict__ beg, const int32_t* __restrict__ cnt,
@@ -70,8 +121,12 @@ __global__ void __launch_bounds__(kBS) k_near(int32_t nleaves, const int32_t* __
   const int32_t nsc = uniform(ncount[X]);
   const double4 gx = geo[X];
   const double* L = loc + (int64_t)X * kLoc;
+  // FP64 staging holds kCap double4 per wave; the mixed path puts 2 kCap
+  // float4 offsets in the same bytes
   __shared__ double4 lds[kWaves][kCap];
   double4* buf = lds[threadIdx.x >> 6];
+  float4* buf32 = reinterpret_cast<float4*>(buf);
+  constexpr int cap = MIXED ? 2 * kCap : kCap;
   int64_t nsrc_particles = 0;  // source particles of this leaf's list (lane 0)
   for (int32_t tb = b; tb < b + nt; tb += 64) {
     const int ntc = min(64, b + nt - tb);
@@ -80,6 +135,7 @@ __global__ void __launch_bounds__(kBS) k_near(int32_t nleaves, const int32_t* __
     const int g = lane / nsl, s = lane % nsl;
     const bool active = g < ng;
     double tx[kTG], ty[kTG], tz[kTG];
+    float ux[kTG], uy[kTG], uz[kTG];  // mixed: FP32 offsets from the leaf centre
     double fx[kTG], fy[kTG], fz[kTG], ph[kTG];
 #pragma unroll
     for (int q = 0; q < kTG; ++q) {
@@ -88,6 +144,9 @@ __global__ void __launch_bounds__(kBS) k_near(int32_t nleaves, const int32_t* __
       tx[q] = p.x;
       ty[q] = p.y;
       tz[q] = p.z;
+      ux[q] = (float)(p.x - gx.x);
+      uy[q] = (float)(p.y - gx.y);
+      uz[q] = (float)(p.z - gx.z);
       fx[q] = fy[q] = fz[q] = ph[q] = 0.0;
     }
     // The near list is consumed 64 entries at a time: every lane fetches one
@@ -106,12 +165,17 @@ __global__ void __launch_bounds__(kBS) k_near(int32_t nleaves, const int32_t* __
         const int32_t o = __shfl_up(inc, d, 64);
         if (lane >= d) inc += o;
       }
-      const uint64_t fits = __ballot(Yl >= 0 && inc <= kCap);
+      const uint64_t fits = __ballot(Yl >= 0 && inc <= cap);
       const int take = __popcll(fits);  // prefix is monotone: leading lanes fit
       int fill;
       if (take > 0) {
-        if (lane < take)
-          for (int32_t j = 0; j < cl; ++j) buf[inc - cl + j] = pos[bl + j];
+        if (lane < take) {
+          if (MIXED) {
+            for (int32_t j = 0; j < cl; ++j) buf32[inc - cl + j] = offset32(pos[bl + j], gx);
+          } else {
+            for (int32_t j = 0; j < cl; ++j) buf[inc - cl + j] = pos[bl + j];
+          }
+        }
         fill = __shfl(inc, take - 1, 64);
         if (tb == b) nsrc_particles += fill;
         k += take;
@@ -119,11 +183,18 @@ __global__ void __launch_bounds__(kBS) k_near(int32_t nleaves, const int32_t* __
         // a single leaf larger than the buffer (coincident points at the
         // deepest level): stream it in buffer-sized pieces
         const int32_t b0 = __shfl(bl, 0, 64), c0 = __shfl(cl, 0, 64);
-        for (int32_t off = 0; off < c0; off += kCap) {
-          const int part = min(kCap, c0 - off);
-          for (int i = lane; i < part; i += 64) buf[i] = pos[b0 + off + i];
+        for (int32_t off = 0; off < c0; off += cap) {
+          const int part = min(cap, c0 - off);
+          if (MIXED) {
+            for (int i = lane; i < part; i += 64) buf32[i] = offset32(pos[b0 + off + i], gx);
+          } else {
+            for (int i = lane; i < part; i += 64) buf[i] = pos[b0 + off + i];
+          }
           wave_sync();
-          if (active) near_tile(buf, part, s, nsl, tx, ty, tz, fx, fy, fz, ph);
+          if (active) {
+            if (MIXED) near_tile_f32(buf32, part, s, nsl, ux, uy, uz, fx, fy, fz, ph);
+            else near_tile(buf, part, s, nsl, tx, ty, tz, fx, fy, fz, ph);
+          }
           wave_sync();
         }
         if (tb == b) nsrc_particles += c0;
@@ -131,7 +202,10 @@ __global__ void __launch_bounds__(kBS) k_near(int32_t nleaves, const int32_t* __
         continue;
       }
       wave_sync();
-      if (active) near_tile(buf, fill, s, nsl, tx, ty, tz, fx, fy, fz, ph);
+      if (active) {
+        if (MIXED) near_tile_f32(buf32, fill, s, nsl, ux, uy, uz, fx, fy, fz, ph);
+        else near_tile(buf, fill, s, nsl, tx, ty, tz, fx, fy, fz, ph);
+      }
       wave_sync();
     }
     // sum the slices of each group (fixed butterfly)
@@ -178,7 +252,8 @@ __global__ void __launch_bounds__(kBS) k_near(int32_t nleaves, const int32_t* __
 void near_field(Ctx& c, const int32_t* leaves, int32_t c_lo, int32_t count, double* ax, double* ay, double* az,
                 double* pot) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_near, dim3(blocks_for(count, kWaves)), dim3(kBS), 0, c.stream, count, leaves, c_lo,
+  auto kern = c.opt.precision == AMFMM_MIXED ? k_near<true> : k_near<false>;
+  hipLaunchKernelGGL(kern, dim3(blocks_for(count, kWaves)), dim3(kBS), 0, c.stream, count, leaves, c_lo,
                      as<int32_t>(c.c_nchild), as<int32_t>(c.c_begin), as<int32_t>(c.c_count), (const double4*)c.pos4.p,
                      (const double4*)c.geo.p, (const double*)c.loc.p, (const int64_t*)c.near_start.p,
                      (const int32_t*)c.near_count.p, (const int32_t*)c.near_src.p, as<int32_t>(c.perm), c.opt.G, ax,
