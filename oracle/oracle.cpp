@@ -71,9 +71,11 @@ struct orc_tree {
   bool have_moments = false;
   bool have_lists = false;
   double theta = 0.5;
-  int mode = 0;  // 0 opening angle, 1 error estimate against the field scale
+  int mode = 0;  // 0 opening angle, 1 error estimate against the field scale, 2 learned
   double eps = 0.0, theta_max = 1.0;
-  std::vector<double> fscale;  // per-cell field scale (mode 1)
+  std::vector<double> fscale;  // per-cell field scale (modes 1 and 2)
+  std::vector<float> model;    // mode 2: network and feature normalisation
+  std::vector<int> qlev;       // mode 2: quantised quadrupole norm per cell
   std::vector<std::pair<int32_t, int32_t>> m2l, p2p;
   int64_t coincident = 0;
 };
@@ -292,6 +294,96 @@ double eq2_pot_B(const Greens& g, const Moments& A, const double y[3]) {
   return p + 0.5 * s2 - (1.0 / 6.0) * s3;
 }
 
+// ------------------------------------------------- learned pair selection ---
+// Not in the paper: a network predicts the force error of an accepted pair
+// (the role of an error-estimating pair selection, cited in Sec. 2).  Every
+// quantity below is defined so that a GPU implementation can reproduce the
+// decision bit for bit: features use only IEEE-rounded operations on values
+// both sides hold identically (centres, radii, masses, counts) plus a
+// quadrupole norm quantised to 1/64 of M R_max^2; the network runs in FP32
+// with fused multiply-adds in a fixed order on BF16-rounded weights.
+//
+// Model layout (floats): W1[64][8], b1[64], W2[64][64], b2[64], w3[64], b3,
+// then the feature normalisation x = fma(f, a, b) (a[8], b[8]) and the
+// training range of the raw features (lo[8], hi[8]).
+constexpr int kFeat = 8, kHid = 64;
+constexpr int kW1 = 0, kB1 = 512, kW2 = 576, kB2 = 4672, kW3 = 4736, kB3 = 4800;
+constexpr int kNA = 4801, kNB = 4809, kLo = 4817, kHi = 4825, kModel = 4833, kParams = 4801;
+constexpr int kLabelSample = 64;  // particles sampled per cell for a label
+
+// round a float to the nearest BF16 value (ties to even), kept as float
+float bf16(float v) {
+  uint32_t u;
+  std::memcpy(&u, &v, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  u &= 0xFFFF0000u;
+  std::memcpy(&v, &u, 4);
+  return v;
+}
+
+// piecewise-linear base-2 logarithm: x = 2^e (1 + f) with f in [0, 1) gives
+// e + f (at most 0.086 below log2 x, never above)
+double plog2(double x) {
+  if (!(x > 0.0)) return -2048.0;
+  if (std::isinf(x)) return 2048.0;
+  int e;
+  double m = std::frexp(x, &e);  // x = m 2^e, m in [0.5, 1)
+  return (double)(e - 1) + (2.0 * m - 1.0);
+}
+
+// floor(64 ||M_ij||_F / (M R_max^2)), in [0, 64]
+int quad_level(const Moments& mo) {
+  double s = 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) s += mo.M2[i][j] * mo.M2[i][j];
+  double den = mo.M * (mo.Rmax * mo.Rmax);
+  if (!(den > 0.0)) return 0;
+  double k = std::floor(64.0 * (std::sqrt(s) / den));
+  if (k < 0.0) return 0;
+  if (k > 64.0) return 64;
+  return (int)k;
+}
+
+// the eight features of an unordered pair (each symmetric in A and B)
+void pair_features(double d, const Moments& A, const Moments& B, int qa, int qb, int64_t na, int64_t nb,
+                   float f[kFeat]) {
+  double r = A.Rmax + B.Rmax;
+  f[0] = (float)(r / d);                                        // (R_A + R_B) / d
+  f[1] = (float)plog2(r / d);                                   // its logarithm
+  f[2] = (float)(r > 0.0 ? std::fabs(A.Rmax - B.Rmax) / r : 0.0);  // size asymmetry
+  f[3] = (float)(std::fabs(A.M - B.M) / (A.M + B.M));          // mass asymmetry
+  f[4] = (float)((double)(qa + qb) / 128.0);                    // mean quadrupole level
+  f[5] = (float)((double)std::abs(qa - qb) / 64.0);             // its asymmetry
+  f[6] = (float)plog2((double)na * (double)nb);                 // particle counts
+  f[7] = (float)std::fabs(plog2((double)na) - plog2((double)nb));
+}
+
+double pair_distance(const Moments& A, const Moments& B) {
+  double dx = A.Z[0] - B.Z[0];
+  double dy = A.Z[1] - B.Z[1];
+  double dz = A.Z[2] - B.Z[2];
+  return std::sqrt((dx * dx + dy * dy) + dz * dz);
+}
+
+// network output (predicted log2 of the pair's error factor), FP32
+float mlp_infer(const float* P, const float f[kFeat]) {
+  float x[kFeat], h1[kHid], h2[kHid];
+  for (int i = 0; i < kFeat; ++i) x[i] = bf16(std::fmaf(f[i], P[kNA + i], P[kNB + i]));
+  for (int j = 0; j < kHid; ++j) {
+    float s = P[kB1 + j];
+    for (int i = 0; i < kFeat; ++i) s = std::fmaf(bf16(P[kW1 + kFeat * j + i]), x[i], s);
+    h1[j] = bf16(s > 0.0f ? s : 0.0f);
+  }
+  for (int k = 0; k < kHid; ++k) {
+    float s = P[kB2 + k];
+    for (int j = 0; j < kHid; ++j) s = std::fmaf(bf16(P[kW2 + kHid * k + j]), h1[j], s);
+    h2[k] = bf16(s > 0.0f ? s : 0.0f);
+  }
+  float y = P[kB3];
+  for (int k = 0; k < kHid; ++k) y = std::fmaf(bf16(P[kW3 + k]), h2[k], y);
+  return y;
+}
+
 // ------------------------------------------------------------------ walk ---
 // Symmetric dual recursion.  A pair is accepted when |Z_A - Z_B| >= (R_A +
 // R_B)/theta (and the centres differ); two leaves that fail become a near-field
@@ -312,8 +404,25 @@ bool accept(const orc_tree& t, int32_t a, int32_t b) {
   double r = A.Rmax + B.Rmax;
   if (!(d > 0.0 && r <= t.theta_max * d)) return false;
   double q = r / d;
-  double e = (q * q * q) / (d * d);
-  return e * B.M <= t.eps * t.fscale[a] && e * A.M <= t.eps * t.fscale[b];
+  if (t.mode == 1) {
+    double e = (q * q * q) / (d * d);
+    return e * B.M <= t.eps * t.fscale[a] && e * A.M <= t.eps * t.fscale[b];
+  }
+  // Learned: the error of the pair on A is f M_B / d^2 with f the predicted
+  // error factor; accept when f <= u = min over both cells of eps s d^2 / M.
+  // Where the analytic factor q^3 sits far from u the network is not asked:
+  // q^3 <= u/4 accepts, q^3 > 16 u opens.  Features outside the training
+  // range fall back to the opening angle theta.
+  double u = std::min((t.eps * t.fscale[a]) * (d * d) / B.M, (t.eps * t.fscale[b]) * (d * d) / A.M);
+  double q3 = q * q * q;
+  if (q3 <= 0.25 * u) return true;
+  if (q3 > 16.0 * u) return false;
+  float f[kFeat];
+  pair_features(d, A, B, t.qlev[a], t.qlev[b], t.cells[a].count, t.cells[b].count, f);
+  const float* P = t.model.data();
+  for (int i = 0; i < kFeat; ++i)
+    if (!(f[i] >= P[kLo + i] && f[i] <= P[kHi + i])) return d >= r / t.theta;
+  return mlp_infer(P, f) <= (float)plog2(u);
 }
 
 void walk_pair(orc_tree& t, int32_t a, int32_t b) {
@@ -548,9 +657,13 @@ void orc_get_moments(const orc_tree* t, double* out) {
   }
 }
 
-int32_t orc_walk_field(orc_tree* t, double eps, double theta_max, const double* gmag) {
-  if (!(eps > 0.0) || !(theta_max > 0.0 && theta_max <= 1.0) || !gmag) return ORC_E_INVALID;
-  if (!t->have_moments) return ORC_E_STATE;
+}  // extern "C"
+
+namespace {
+// Field scale of every cell from per-particle field magnitudes: the smallest
+// |g| over its particles, but at least 0.1 times their mean (sums over leaves
+// in key order, parents over children in octant order)
+void set_field_scales(orc_tree* t, const double* gmag) {
   size_t nc = t->cells.size();
   std::vector<double> gsum(nc, 0.0), gmin(nc, INFINITY);
   for (size_t ci = nc; ci-- > 0;) {
@@ -571,16 +684,192 @@ int32_t orc_walk_field(orc_tree* t, double eps, double theta_max, const double* 
   t->fscale.assign(nc, 0.0);
   for (size_t ci = 0; ci < nc; ++ci)
     t->fscale[ci] = std::max(gmin[ci], 0.1 * (gsum[ci] / (double)t->cells[ci].count));
-  t->mode = 1;
-  t->eps = eps;
-  t->theta_max = theta_max;
+}
+
+void run_walk(orc_tree* t) {
   t->m2l.clear();
   t->p2p.clear();
   walk_self(*t, 0);
   std::sort(t->m2l.begin(), t->m2l.end());
   std::sort(t->p2p.begin(), t->p2p.end());
   t->have_lists = true;
+}
+}  // namespace
+
+extern "C" {
+
+int32_t orc_walk_field(orc_tree* t, double eps, double theta_max, const double* gmag) {
+  if (!(eps > 0.0) || !(theta_max > 0.0 && theta_max <= 1.0) || !gmag) return ORC_E_INVALID;
+  if (!t->have_moments) return ORC_E_STATE;
+  set_field_scales(t, gmag);
+  t->mode = 1;
+  t->eps = eps;
+  t->theta_max = theta_max;
+  run_walk(t);
   return ORC_OK;
+}
+
+int32_t orc_walk_learned(orc_tree* t, double eps, double theta_max, double theta, const double* gmag,
+                         const float* model) {
+  if (!(theta > 0.0 && theta <= 1.0)) return ORC_E_INVALID;
+  if (!model) return orc_walk(t, theta);  // no network: the opening angle
+  if (!(eps > 0.0) || !(theta_max > 0.0 && theta_max <= 1.0) || !gmag) return ORC_E_INVALID;
+  if (!t->have_moments) return ORC_E_STATE;
+  set_field_scales(t, gmag);
+  t->model.assign(model, model + kModel);
+  t->qlev.resize(t->cells.size());
+  for (size_t c = 0; c < t->cells.size(); ++c) t->qlev[c] = quad_level(t->mom[c]);
+  t->mode = 2;
+  t->eps = eps;
+  t->theta_max = theta_max;
+  t->theta = theta;
+  run_walk(t);
+  return ORC_OK;
+}
+
+void orc_pair_features(const orc_tree* t, int64_t np, const int32_t* pairs, float* feats) {
+  std::vector<int> q(t->cells.size());
+  for (size_t c = 0; c < t->cells.size(); ++c) q[c] = quad_level(t->mom[c]);
+  for (int64_t k = 0; k < np; ++k) {
+    int32_t a = pairs[2 * k], b = pairs[2 * k + 1];
+    const Moments& A = t->mom[a];
+    const Moments& B = t->mom[b];
+    pair_features(pair_distance(A, B), A, B, q[a], q[b], t->cells[a].count, t->cells[b].count,
+                  feats + kFeat * k);
+  }
+}
+
+// Label of a pair: log2 of the rms, over up to 64 sampled particles of each
+// cell, of |g_pair - g_direct| / (M_other / d^2), where g_pair is the method's
+// acceleration from the other cell alone (eq. 3 about the own centre, with the
+// correction of the variant) and g_direct the direct sum over the other
+// cell's particles.  Particle k of ns samples of a cell is begin + k N / ns.
+int32_t orc_pair_labels(const orc_tree* t, int32_t variant, int64_t np, const int32_t* pairs,
+                        double* labels) {
+  if (!t->have_moments) return ORC_E_STATE;
+  if (variant < ORC_UC || variant > ORC_TCO) return ORC_E_INVALID;
+  int64_t nc = (int64_t)t->cells.size();
+  for (int64_t k = 0; k < np; ++k) {
+    int32_t a = pairs[2 * k], b = pairs[2 * k + 1];
+    if (a < 0 || b < 0 || a >= nc || b >= nc || a == b) return ORC_E_INVALID;
+    double d = pair_distance(t->mom[a], t->mom[b]);
+    if (!(d > 0.0)) return ORC_E_INVALID;
+    double sum = 0.0;
+    int64_t cnt = 0;
+    for (int side = 0; side < 2; ++side) {
+      int32_t ct = side ? b : a, cs = side ? a : b;
+      const Cell& T = t->cells[ct];
+      const Cell& S = t->cells[cs];
+      const Moments& MT = t->mom[ct];
+      const Moments& MS = t->mom[cs];
+      PairTerms pt;
+      pair_terms(MT, MS, variant, pt);  // R = Z_T - Z_S: T is the field cell of eq. 3
+      int64_t ns = std::min<int64_t>(T.count, kLabelSample);
+      for (int64_t s = 0; s < ns; ++s) {
+        int64_t p = T.begin + (s * T.count) / ns;
+        double xv[3] = {t->x[p] - MT.Z[0], t->y[p] - MT.Z[1], t->z[p] - MT.Z[2]};
+        double g[3];
+        eq3_accel(pt.g, MS, xv, g);
+        for (int dd = 0; dd < 3; ++dd) g[dd] += pt.Fc[dd] / MT.M;
+        double gd[3] = {0.0, 0.0, 0.0};
+        for (int64_t j = S.begin; j < S.begin + S.count; ++j) {
+          double dx = t->x[j] - t->x[p];
+          double dy = t->y[j] - t->y[p];
+          double dz = t->z[j] - t->z[p];
+          double r2 = (dx * dx + dy * dy) + dz * dz;
+          double r3 = r2 * std::sqrt(r2);
+          gd[0] += t->m[j] * dx / r3;
+          gd[1] += t->m[j] * dy / r3;
+          gd[2] += t->m[j] * dz / r3;
+        }
+        double ex = g[0] - gd[0], ey = g[1] - gd[1], ez = g[2] - gd[2];
+        double e = std::sqrt((ex * ex + ey * ey) + ez * ez) / (MS.M / (d * d));
+        sum += e * e;
+        ++cnt;
+      }
+    }
+    labels[k] = std::log2(std::sqrt(sum / (double)cnt));
+  }
+  return ORC_OK;
+}
+
+float orc_bf16_round(float v) { return bf16(v); }
+double orc_plog2(double x) { return plog2(x); }
+
+void orc_mlp_predict(const float* model, int64_t n, const float* feats, float* y) {
+  for (int64_t r = 0; r < n; ++r) y[r] = mlp_infer(model, feats + kFeat * r);
+}
+
+// Mean pinball loss at quantile tau of the network over n rows and its
+// gradient with respect to the parameters (FP64 arithmetic).  With round != 0
+// the forward pass rounds weights, inputs and hidden activations to BF16 as
+// inference does and the gradient passes straight through the roundings;
+// with round == 0 nothing is rounded (the exact function, for finite
+// differences).  The subgradient at a zero residual is -tau.
+double orc_mlp_grad(const float* model, int64_t n, const float* feats, const float* labels, double tau,
+                    int32_t round, double* grad) {
+  auto rd = [&](double v) { return round ? (double)bf16((float)v) : v; };
+  std::vector<double> W1(kHid * kFeat), W2(kHid * kHid), w3(kHid);
+  for (int i = 0; i < kHid * kFeat; ++i) W1[i] = rd(model[kW1 + i]);
+  for (int i = 0; i < kHid * kHid; ++i) W2[i] = rd(model[kW2 + i]);
+  for (int i = 0; i < kHid; ++i) w3[i] = rd(model[kW3 + i]);
+  for (int i = 0; i < kParams; ++i) grad[i] = 0.0;
+  double loss = 0.0;
+  for (int64_t r = 0; r < n; ++r) {
+    double x[kFeat], z1[kHid], h1[kHid], z2[kHid], h2[kHid];
+    for (int i = 0; i < kFeat; ++i) {
+      double v = round ? (double)std::fmaf(feats[kFeat * r + i], model[kNA + i], model[kNB + i])
+                       : (double)feats[kFeat * r + i] * model[kNA + i] + model[kNB + i];
+      x[i] = rd(v);
+    }
+    for (int j = 0; j < kHid; ++j) {
+      double s = model[kB1 + j];
+      for (int i = 0; i < kFeat; ++i) s += W1[kFeat * j + i] * x[i];
+      z1[j] = s;
+      h1[j] = rd(s > 0.0 ? s : 0.0);
+    }
+    for (int k = 0; k < kHid; ++k) {
+      double s = model[kB2 + k];
+      for (int j = 0; j < kHid; ++j) s += W2[kHid * k + j] * h1[j];
+      z2[k] = s;
+      h2[k] = rd(s > 0.0 ? s : 0.0);
+    }
+    double y = model[kB3];
+    for (int k = 0; k < kHid; ++k) y += w3[k] * h2[k];
+    double res = (double)labels[r] - y;
+    loss += res < 0.0 ? (tau - 1.0) * res : tau * res;
+    double dy = (res < 0.0 ? 1.0 - tau : -tau) / (double)n;
+    grad[kB3] += dy;
+    double dz2[kHid];
+    for (int k = 0; k < kHid; ++k) {
+      grad[kW3 + k] += dy * h2[k];
+      dz2[k] = z2[k] > 0.0 ? dy * w3[k] : 0.0;
+      grad[kB2 + k] += dz2[k];
+      for (int j = 0; j < kHid; ++j) grad[kW2 + kHid * k + j] += dz2[k] * h1[j];
+    }
+    for (int j = 0; j < kHid; ++j) {
+      double dh = 0.0;
+      for (int k = 0; k < kHid; ++k) dh += dz2[k] * W2[kHid * k + j];
+      double dz1 = z1[j] > 0.0 ? dh : 0.0;
+      grad[kB1 + j] += dz1;
+      for (int i = 0; i < kFeat; ++i) grad[kW1 + kFeat * j + i] += dz1 * x[i];
+    }
+  }
+  return loss / (double)n;
+}
+
+// One Adam step (Kingma & Ba 2015) on the first kParams entries, step t >= 1
+void orc_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t t, double lr, double beta1,
+                  double beta2, double eps) {
+  double c1 = 1.0 - std::pow(beta1, (double)t), c2 = 1.0 - std::pow(beta2, (double)t);
+  for (int i = 0; i < kParams; ++i) {
+    double g = grad[i];
+    double mi = beta1 * m[i] + (1.0 - beta1) * g;
+    double vi = beta2 * v[i] + (1.0 - beta2) * g * g;
+    m[i] = (float)mi;
+    v[i] = (float)vi;
+    params[i] = (float)(params[i] - lr * (mi / c1) / (std::sqrt(vi / c2) + eps));
+  }
 }
 
 int32_t orc_walk(orc_tree* t, double theta) {
@@ -588,12 +877,7 @@ int32_t orc_walk(orc_tree* t, double theta) {
   if (!t->have_moments) return ORC_E_STATE;
   t->mode = 0;
   t->theta = theta;
-  t->m2l.clear();
-  t->p2p.clear();
-  walk_self(*t, 0);
-  std::sort(t->m2l.begin(), t->m2l.end());
-  std::sort(t->p2p.begin(), t->p2p.end());
-  t->have_lists = true;
+  run_walk(t);
   return ORC_OK;
 }
 

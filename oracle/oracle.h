@@ -120,6 +120,36 @@ void orc_pair_far(int64_t nA, const double* xa, const double* ya, const double* 
                   const double* zb, const double* mb, int32_t variant, double* gA, double* phiA,
                   double* gB, double* phiB);
 
+/* ---- learned pair selection (not in the paper; see the notes in oracle.cpp) ----
+ * Model: ORC_MLP_MODEL floats (network, then feature normalisation a[8], b[8]
+ * and the training range lo[8], hi[8]); the trainable parameters are its first
+ * ORC_MLP_PARAMS entries. */
+#define ORC_MLP_PARAMS 4801
+#define ORC_MLP_MODEL 4833
+/* Walk whose accept decision asks the network (error factor against eps times
+ * the field scale of each cell, as orc_walk_field); model == NULL gives the
+ * opening-angle walk with theta, which is also the fallback for features
+ * outside the training range. */
+int32_t orc_walk_learned(orc_tree* t, double eps, double theta_max, double theta, const double* gmag,
+                         const float* model);
+/* Features (8 floats per pair) and labels (log2 error factor) of cell pairs
+ * (a, b), 2 int32 per pair; labels need moments and a != b, d > 0. */
+void orc_pair_features(const orc_tree* t, int64_t np, const int32_t* pairs, float* feats);
+int32_t orc_pair_labels(const orc_tree* t, int32_t variant, int64_t np, const int32_t* pairs,
+                        double* labels);
+/* BF16 rounding (nearest, ties to even) and the piecewise-linear log2 that
+ * the features and the decision use. */
+float orc_bf16_round(float v);
+double orc_plog2(double x);
+/* FP32 inference exactly as the walk runs it. */
+void orc_mlp_predict(const float* model, int64_t n, const float* feats, float* y);
+/* Mean pinball loss at quantile tau and its gradient (ORC_MLP_PARAMS doubles). */
+double orc_mlp_grad(const float* model, int64_t n, const float* feats, const float* labels, double tau,
+                    int32_t round, double* grad);
+/* One Adam step (t >= 1) on the ORC_MLP_PARAMS parameters. */
+void orc_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t t, double lr, double beta1,
+                  double beta2, double eps);
+
 #ifdef __cplusplus
 }
 #endif

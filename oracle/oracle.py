@@ -66,6 +66,21 @@ def lib():
         L.orc_cluster_moments.argtypes = [C.c_int64, d, d, d, d, d]
         L.orc_pair_far.argtypes = [C.c_int64, d, d, d, d, C.c_int64, d, d, d, d, C.c_int32,
                                    d, d, d, d]
+        f = C.POINTER(C.c_float)
+        L.orc_walk_learned.restype = C.c_int32
+        L.orc_walk_learned.argtypes = [P, C.c_double, C.c_double, C.c_double, d, f]
+        L.orc_pair_features.argtypes = [P, C.c_int64, i32, f]
+        L.orc_pair_labels.restype = C.c_int32
+        L.orc_pair_labels.argtypes = [P, C.c_int32, C.c_int64, i32, d]
+        L.orc_bf16_round.restype = C.c_float
+        L.orc_bf16_round.argtypes = [C.c_float]
+        L.orc_plog2.restype = C.c_double
+        L.orc_plog2.argtypes = [C.c_double]
+        L.orc_mlp_predict.argtypes = [f, C.c_int64, f, f]
+        L.orc_mlp_grad.restype = C.c_double
+        L.orc_mlp_grad.argtypes = [f, C.c_int64, f, f, C.c_double, C.c_int32, d]
+        L.orc_mlp_adam.argtypes = [f, f, f, f, C.c_int64, C.c_double, C.c_double, C.c_double,
+                                   C.c_double]
         _lib = L
     return _lib
 
@@ -156,6 +171,34 @@ class Tree:
         if st:
             raise OracleError(st)
 
+    def walk_learned(self, eps, theta_max, theta, gmag, model):
+        """Walk whose accept decision asks the network (model: MLP_MODEL floats,
+        or None for the opening-angle walk)."""
+        g = _f64(gmag)
+        mp = None
+        if model is not None:
+            model = _f32(model)
+            assert model.size == MLP_MODEL
+            mp = _fp(model)
+        st = lib().orc_walk_learned(self._t, float(eps), float(theta_max), float(theta), _d(g), mp)
+        if st:
+            raise OracleError(st)
+
+    def pair_features(self, pairs):
+        pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+        out = np.zeros((len(pairs), 8), np.float32)
+        lib().orc_pair_features(self._t, len(pairs), pairs.ctypes.data_as(C.POINTER(C.c_int32)), _fp(out))
+        return out
+
+    def pair_labels(self, pairs, variant=TC):
+        pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+        out = np.zeros(len(pairs))
+        st = lib().orc_pair_labels(self._t, variant, len(pairs), pairs.ctypes.data_as(C.POINTER(C.c_int32)),
+                                   _d(out))
+        if st:
+            raise OracleError(st)
+        return out
+
     def lists(self):
         nm = lib().orc_num_m2l(self._t)
         npp = lib().orc_num_p2p(self._t)
@@ -231,6 +274,51 @@ def greens(R):
     D4p = np.zeros((3, 3, 3, 3))
     lib().orc_greens(_d(R), _d(D0), _d(D1), _d(D2), _d(D3), _d(D4), _d(D4p))
     return D0[0], D1, D2, D3, D4, D4p
+
+
+# ------------------------------------------------- learned pair selection --
+MLP_PARAMS = 4801
+MLP_MODEL = 4833
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _fp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def bf16_round(v):
+    return float(lib().orc_bf16_round(float(v)))
+
+
+def plog2(x):
+    return float(lib().orc_plog2(float(x)))
+
+
+def mlp_predict(model, feats):
+    model, feats = _f32(model), _f32(feats).reshape(-1, 8)
+    y = np.zeros(len(feats), np.float32)
+    lib().orc_mlp_predict(_fp(model), len(feats), _fp(feats), _fp(y))
+    return y
+
+
+def mlp_grad(model, feats, labels, tau=0.9, round=True):
+    """(mean pinball loss, gradient over the MLP_PARAMS trainable entries)."""
+    model, feats, labels = _f32(model), _f32(feats).reshape(-1, 8), _f32(labels)
+    g = np.zeros(MLP_PARAMS)
+    loss = lib().orc_mlp_grad(_fp(model), len(feats), _fp(feats), _fp(labels), float(tau), int(bool(round)), _d(g))
+    return loss, g
+
+
+def mlp_adam(params, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step; params, m, v (float32) are updated in place."""
+    for a in (params, m, v):
+        assert a.dtype == np.float32 and a.flags.c_contiguous
+    g = _f32(grad)
+    lib().orc_mlp_adam(_fp(params), _fp(g), _fp(m), _fp(v), int(t), float(lr), float(beta1), float(beta2),
+                       float(eps))
 
 
 def cluster_moments(x, y, z, m):

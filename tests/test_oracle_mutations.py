@@ -4,7 +4,8 @@ Each case plants one mistake in a copy of the oracle's source (CPU only),
 builds it, and runs the oracle's pin suite against that copy, which must then
 fail.  The mistakes cover every step: keys, tree, moments, walk, the Green's
 function derivatives, eqs. 2-4, the correction of eq. 7 (prefactor and sign)
-and the near field.
+the near field, and the learned pair selection (rounding, logarithm, features,
+labels, gradient, gating).
 """
 import os
 import subprocess
@@ -16,7 +17,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle.cpp")
 
 PINS = ["tests/test_oracle_greens.py", "tests/test_oracle_tree.py", "tests/test_oracle_moments.py",
-        "tests/test_oracle_pair.py", "tests/test_oracle_solve.py", "tests/test_oracle_field_walk.py"]
+        "tests/test_oracle_pair.py", "tests/test_oracle_solve.py", "tests/test_oracle_field_walk.py",
+        "tests/test_oracle_learned.py"]
 
 MUTATIONS = {
     "correction_prefactor_half": ("pt.Fc[i] = -(1.0 / 6.0) * s;", "pt.Fc[i] = -(0.5) * s;"),
@@ -41,6 +43,16 @@ MUTATIONS = {
                         "return e * B.M <= t.eps * t.fscale[a];"),
     "field_scale_no_floor": ("std::max(gmin[ci], 0.1 * (gsum[ci] / (double)t->cells[ci].count))",
                              "std::max(gmin[ci], 1.0 * (gsum[ci] / (double)t->cells[ci].count))"),
+    "learned_gate_low": ("if (q3 <= 0.25 * u) return true;", "if (q3 <= 1.0 * u) return true;"),
+    "learned_one_cell": ("double u = std::min((t.eps * t.fscale[a]) * (d * d) / B.M, (t.eps * t.fscale[b]) * (d * d) / A.M);",
+                         "double u = (t.eps * t.fscale[a]) * (d * d) / B.M;"),
+    "label_own_mass": ("double e = std::sqrt((ex * ex + ey * ey) + ez * ez) / (MS.M / (d * d));",
+                       "double e = std::sqrt((ex * ex + ey * ey) + ez * ez) / (MT.M / (d * d));"),
+    "grad_no_relu_mask": ("double dz1 = z1[j] > 0.0 ? dh : 0.0;", "double dz1 = dh;"),
+    "plog2_off_by_one": ("return (double)(e - 1) + (2.0 * m - 1.0);", "return (double)(e) + (2.0 * m - 1.0);"),
+    "bf16_truncates": ("u += 0x7FFFu + ((u >> 16) & 1u);", "u += 0u;"),
+    "feature_antisymmetric": ("f[5] = (float)((double)std::abs(qa - qb) / 64.0);",
+                              "f[5] = (float)((double)(qa - qb) / 64.0);"),
     "self_walk_skips_pairs": ("for (int32_t b = a + 1; b < C.child0 + C.nchild; ++b) walk_pair(t, a, b);",
                               "for (int32_t b = a + 2; b < C.child0 + C.nchild; ++b) walk_pair(t, a, b);"),
 }
