@@ -331,14 +331,17 @@ double plog2(double x) {
   return (double)(e - 1) + (2.0 * m - 1.0);
 }
 
-// floor(64 ||M_ij||_F / (M R_max^2)), in [0, 64]
+// ||M_ij||_F / (M R_max^2) lies in [0, 1] (1 for a cell whose particles lie
+// on a line through Z at equal distance, e.g. two equal masses); quantised to
+// the nearest multiple of 1/64, so that such exact values sit mid-bin where
+// the rounding of M_ij cannot move them across a bin boundary
 int quad_level(const Moments& mo) {
   double s = 0.0;
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) s += mo.M2[i][j] * mo.M2[i][j];
   double den = mo.M * (mo.Rmax * mo.Rmax);
   if (!(den > 0.0)) return 0;
-  double k = std::floor(64.0 * (std::sqrt(s) / den));
+  double k = std::floor(64.0 * (std::sqrt(s) / den) + 0.5);
   if (k < 0.0) return 0;
   if (k > 64.0) return 64;
   return (int)k;
