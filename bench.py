@@ -97,8 +97,8 @@ def main():
     del x, y, z, m
     pilot = amfmm.Solver(variant=variant, precision=prec)
     solver = amfmm.Solver(variant=variant, precision=prec,
-                          criterion=amfmm.LEARNED if field else amfmm.GEOMETRIC,
-                          learned_tol=a.eps, theta_max=a.theta_max)
+                          criterion=amfmm.ESTIMATE if field else amfmm.GEOMETRIC,
+                          error_tol=a.eps, theta_max=a.theta_max)
     pout = pilot._outputs(a.n, False)
     out = solver._outputs(a.n, True)
     if field:

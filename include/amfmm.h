@@ -42,15 +42,23 @@ typedef enum { AMFMM_UC = 0, AMFMM_TC = 1, AMFMM_TCO = 2 } amfmm_variant;
  * and the correction of eq. 7/8 stay in FP64. */
 typedef enum { AMFMM_FP64 = 0, AMFMM_MIXED = 1 } amfmm_precision;
 
-/* Accept/open decision of the walk: the geometric opening criterion of Sec. 2,
- * or an error-estimate criterion (the role of the error-based pair selection
- * the paper cites in Sec. 2): a pair is accepted when its estimated force
- * error, for each of its two cells, stays below learned_tol times the mean
- * field estimate of that cell and (R_A+R_B)/d <= theta_max.  The decision is a
- * function of the unordered pair, so pairwise momentum conservation holds.
- * Without a field estimate (amfmm_set_field_estimate) the geometric rule is
- * used. */
-typedef enum { AMFMM_GEOMETRIC = 0, AMFMM_LEARNED = 1 } amfmm_criterion;
+/* Accept/open decision of the walk.
+ * GEOMETRIC: the opening criterion of Sec. 2, |Z_A - Z_B| >= (R_A + R_B)/theta.
+ * ESTIMATE: an error-estimate criterion (the role of the error-based pair
+ *   selection that Sec. 2 cites): with q = (R_A + R_B)/d and field scales s
+ *   (per cell: the smallest field estimate over its particles, at least 0.1
+ *   times their mean), a pair is accepted when q <= theta_max and
+ *   q^3 M_B / d^2 <= error_tol s_A and q^3 M_A / d^2 <= error_tol s_B.
+ * LEARNED: as ESTIMATE, but the analytic error factor q^3 is replaced by the
+ *   network's prediction f (amfmm_set_model) where q^3 lies within [u/4, 16 u]
+ *   of the allowed factor u = min(error_tol s_A d^2 / M_B, error_tol s_B d^2 /
+ *   M_A); below the band the pair is accepted, above it opened; pairs whose
+ *   features fall outside the model's training range use the geometric rule
+ *   with the solve's theta.
+ * Every rule is a function of the unordered pair, so pairwise momentum
+ * conservation holds.  Without a field estimate (amfmm_set_field_estimate),
+ * and for LEARNED without a model, the geometric rule is used. */
+typedef enum { AMFMM_GEOMETRIC = 0, AMFMM_ESTIMATE = 1, AMFMM_LEARNED = 2 } amfmm_criterion;
 
 typedef struct {
   int32_t n_crit;     /* most particles in a leaf; the paper runs 25 (Sec. 2) */
@@ -58,8 +66,8 @@ typedef struct {
   int32_t precision;  /* amfmm_precision */
   int32_t criterion;  /* amfmm_criterion */
   double G;           /* gravitational constant applied to all outputs */
-  double learned_tol; /* learned criterion: accept when the predicted pair error <= tol */
-  double theta_max;   /* learned criterion: pairs with (R_A+R_B)/d > theta_max always open */
+  double error_tol;   /* ESTIMATE / LEARNED: accepted pair error relative to the field scale */
+  double theta_max;   /* ESTIMATE / LEARNED: pairs with (R_A+R_B)/d > theta_max always open */
   int64_t max_bytes;  /* cap on device scratch owned by the context (0 = no cap) */
   int64_t list_bytes; /* device bytes the interaction lists of one batch may take
                          (0 = automatic); when the whole tree's lists would not
@@ -69,7 +77,7 @@ typedef struct {
 
 typedef struct amfmm_ctx amfmm_ctx;
 
-/* Fills *opt with n_crit = 25, TC, FP64, geometric, G = 1, learned_tol = 1e-4,
+/* Fills *opt with n_crit = 25, TC, FP64, geometric, G = 1, error_tol = 1e-4,
  * theta_max = 1, max_bytes = 0, list_bytes = 0. */
 int amfmm_default_options(amfmm_options* opt);
 
@@ -77,7 +85,7 @@ int amfmm_default_options(amfmm_options* opt);
  * on the current device.  The context owns all scratch. */
 int amfmm_create(const amfmm_options* opt, void* hip_stream, amfmm_ctx** out);
 int amfmm_destroy(amfmm_ctx* ctx);
-/* Per-particle field estimates for the AMFMM_LEARNED criterion, e.g. the
+/* Per-particle field estimates for the ESTIMATE and LEARNED criteria, e.g. the
  * accelerations of the previous time step or of a cheaper solve: device
  * pointers to n doubles in caller order, either the three components (gx, gy,
  * gz) or magnitudes in gx with gy = gz = NULL.  The arrays are read during the
@@ -131,6 +139,53 @@ int amfmm_direct(amfmm_ctx* ctx, int64_t n, const double* x, const double* y, co
 int amfmm_balance(amfmm_ctx* ctx, int64_t n, const double* x, const double* y, const double* z,
                   const double* m, const double* ax, const double* ay, const double* az,
                   double* out);
+
+/* ---- learned pair selection (not in the paper; see amfmm_criterion) ----
+ * A model is AMFMM_MLP_MODEL floats: a network 8 -> 64 -> 64 -> 1 with ReLU,
+ * W1[64][8], b1[64], W2[64][64], b2[64], w3[64], b3 (the AMFMM_MLP_PARAMS
+ * trainable parameters), then the feature normalisation x = fma(f, a, b),
+ * a[8], b[8], and the training range of the raw features, lo[8], hi[8].
+ * Inference rounds weights, inputs and hidden activations to BF16 and sums
+ * in FP32 (fused multiply-adds in index order).  Its output is the predicted
+ * log2 of a pair's error factor: the rms over the pair's particles of
+ * |g_pair - g_direct| / (M_other / d^2).  Features of a pair (A, B), d the
+ * centre distance, all symmetric: (R_A+R_B)/d, plog2 of it, |R_A-R_B|/(R_A+R_B),
+ * |M_A-M_B|/(M_A+M_B), (k_A+k_B)/128, |k_A-k_B|/64 with k = floor(64
+ * ||M_ij||_F / (M R_max^2) + 1/2), plog2(N_A N_B), |plog2 N_A - plog2 N_B|, where
+ * plog2(2^e (1+f)) = e + f. */
+#define AMFMM_MLP_PARAMS 4801
+#define AMFMM_MLP_MODEL 4833
+
+/* Installs a model (host pointer, AMFMM_MLP_MODEL finite floats, copied) for
+ * the LEARNED criterion; NULL removes it. */
+int amfmm_set_model(amfmm_ctx* ctx, const float* model);
+/* Features (8 floats per pair) and labels (log2 error factor, doubles) of np
+ * cell pairs of the context's tree (after amfmm_compute_moments); pairs:
+ * device int32, 2 per pair (distinct cells with distinct centres, else
+ * AMFMM_E_INVALID is not detected: the caller passes pairs of a walk's far
+ * field).  A label samples up to 64 particles of each cell (particle k of ns
+ * is first + k N / ns) and evaluates the pair alone with the variant given
+ * against direct summation over the other cell.  Outputs are device arrays. */
+int amfmm_pair_features(amfmm_ctx* ctx, int64_t np, const int32_t* pairs, float* feats);
+int amfmm_pair_labels(amfmm_ctx* ctx, int32_t variant, int64_t np, const int32_t* pairs, double* labels);
+/* FP32 inference exactly as the walk runs it: model (device, AMFMM_MLP_MODEL
+ * floats, weights rounded on the fly), feats (device, 8 per row), y (device). */
+int amfmm_mlp_predict(amfmm_ctx* ctx, int64_t n, const float* model, const float* feats, float* y);
+/* Mean pinball loss at quantile tau over n rows and its gradient with respect
+ * to the AMFMM_MLP_PARAMS parameters (device float array grad), computed on
+ * the GPU: forward with BF16 matrix-core products and FP32 accumulation,
+ * backward with FP32 matrix-core products, gradients straight through the
+ * BF16 roundings, subgradient -tau at a zero residual.  loss: host double. */
+int amfmm_mlp_grad(amfmm_ctx* ctx, int64_t n, const float* model, const float* feats, const float* labels,
+                   double tau, float* grad, double* loss);
+/* steps Adam steps (Kingma & Ba) of the pinball loss on batches of `batch`
+ * rows: step s uses rows (step0 + s) * batch + r modulo n, r < batch, and
+ * Adam step number step0 + s + 1 (beta1 0.9, beta2 0.999, eps 1e-8).  model,
+ * adam_m, adam_v: device, updated in place (the moment arrays start at zero
+ * for step0 = 0).  last_loss (host, may be NULL): loss of the last batch. */
+int amfmm_mlp_train(amfmm_ctx* ctx, int64_t n, const float* feats, const float* labels, float* model,
+                    float* adam_m, float* adam_v, int64_t step0, int32_t steps, int32_t batch, double lr,
+                    double tau, double* last_loss);
 
 /* ---- introspection (host buffers owned by the caller; synchronising) ---- */
 /* counts[0..7] = cells, depth, far-field pairs, near-field pairs (unordered,

@@ -18,14 +18,15 @@ LIB_PATH = os.path.join(HERE, "libamfmm_hip.so")
 OK, E_INVALID, E_NONFINITE, E_OOM, E_HIP, E_STATE = 0, -1, -2, -3, -4, -5
 UC, TC, TCO = 0, 1, 2
 FP64, MIXED = 0, 1
-GEOMETRIC, LEARNED = 0, 1
+GEOMETRIC, ESTIMATE, LEARNED = 0, 1, 2
+MLP_PARAMS, MLP_MODEL = 4801, 4833
 PHASES = ["validate+bbox", "keys+sort", "tree", "moments", "walk", "far", "push-down",
           "near+eval", "total"]
 
 
 class amfmm_options(C.Structure):
     _fields_ = [("n_crit", C.c_int32), ("variant", C.c_int32), ("precision", C.c_int32),
-                ("criterion", C.c_int32), ("G", C.c_double), ("learned_tol", C.c_double),
+                ("criterion", C.c_int32), ("G", C.c_double), ("error_tol", C.c_double),
                 ("theta_max", C.c_double), ("max_bytes", C.c_int64), ("list_bytes", C.c_int64)]
 
 
@@ -65,6 +66,13 @@ def lib():
         "amfmm_get_moments": (C.c_int, [P, d]),
         "amfmm_get_lists": (C.c_int, [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "amfmm_get_phase_times": (C.c_int, [P, d, i32]),
+        "amfmm_set_model": (C.c_int, [P, C.POINTER(C.c_float)]),
+        "amfmm_pair_features": (C.c_int, [P, i64, pd, pd]),
+        "amfmm_pair_labels": (C.c_int, [P, i32, i64, pd, pd]),
+        "amfmm_mlp_predict": (C.c_int, [P, i64, pd, pd, pd]),
+        "amfmm_mlp_grad": (C.c_int, [P, i64, pd, pd, pd, C.c_double, pd, d]),
+        "amfmm_mlp_train": (C.c_int, [P, i64, pd, pd, pd, pd, pd, i64, i32, i32, C.c_double,
+                                      C.c_double, d]),
         "amfmm_status_string": (C.c_char_p, [C.c_int]),
         "amfmm_last_error": (C.c_char_p, [P]),
     }
@@ -81,7 +89,8 @@ EXPORTED = ["amfmm_default_options", "amfmm_create", "amfmm_destroy", "amfmm_set
             "amfmm_build_tree", "amfmm_compute_moments", "amfmm_walk", "amfmm_evaluate",
             "amfmm_solve_gravity", "amfmm_direct", "amfmm_balance", "amfmm_get_counts",
             "amfmm_get_tree", "amfmm_get_moments", "amfmm_get_lists", "amfmm_get_phase_times",
-            "amfmm_status_string", "amfmm_last_error"]
+            "amfmm_set_model", "amfmm_pair_features", "amfmm_pair_labels", "amfmm_mlp_predict",
+            "amfmm_mlp_grad", "amfmm_mlp_train", "amfmm_status_string", "amfmm_last_error"]
 
 
 class AmfmmError(RuntimeError):
@@ -98,6 +107,14 @@ def _dev(t, name):
     return C.c_void_p(t.data_ptr())
 
 
+def _devt(t, name, dtype):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA (ROCm) tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    return C.c_void_p(t.data_ptr())
+
+
 def _ptr(a, ctype):
     return a.ctypes.data_as(C.POINTER(ctype))
 
@@ -106,12 +123,12 @@ class Solver:
     """One amfmm context.  Method names follow the C ABI without the prefix."""
 
     def __init__(self, n_crit=25, variant=TC, precision=FP64, criterion=GEOMETRIC, G=1.0,
-                 learned_tol=1e-4, theta_max=1.0, max_bytes=0, list_bytes=0, stream=None):
+                 error_tol=1e-4, theta_max=1.0, max_bytes=0, list_bytes=0, stream=None):
         L = lib()
         o = amfmm_options()
         L.amfmm_default_options(C.byref(o))
         o.n_crit, o.variant, o.precision, o.criterion = n_crit, variant, precision, criterion
-        o.G, o.learned_tol, o.theta_max, o.max_bytes = G, learned_tol, theta_max, max_bytes
+        o.G, o.error_tol, o.theta_max, o.max_bytes = G, error_tol, theta_max, max_bytes
         o.list_bytes = list_bytes
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = C.c_void_p()
@@ -146,6 +163,61 @@ class Solver:
         self._field = (gx, gy, gz)
         d = lambda t, nm: _dev(t, nm) if t is not None else None
         self._check(lib().amfmm_set_field_estimate(self._h, d(gx, "gx"), d(gy, "gy"), d(gz, "gz")))
+
+    def set_model(self, model):
+        """Install a network (AMFMM_MLP_MODEL floats, host array or None)."""
+        if model is None:
+            self._check(lib().amfmm_set_model(self._h, None))
+            return
+        m = np.ascontiguousarray(model, dtype=np.float32)
+        if m.size != MLP_MODEL:
+            raise ValueError(f"a model has {MLP_MODEL} floats")
+        self._check(lib().amfmm_set_model(self._h, _ptr(m, C.c_float)))
+
+    def pair_features(self, pairs):
+        """pairs: CUDA int32 tensor [np, 2] of cells of the current tree."""
+        np_ = pairs.shape[0]
+        out = torch.empty((np_, 8), dtype=torch.float32, device=pairs.device)
+        self._check(lib().amfmm_pair_features(self._h, np_, _devt(pairs, "pairs", torch.int32),
+                                              _devt(out, "feats", torch.float32)))
+        return out
+
+    def pair_labels(self, pairs, variant=TC):
+        np_ = pairs.shape[0]
+        out = torch.empty(np_, dtype=torch.float64, device=pairs.device)
+        self._check(lib().amfmm_pair_labels(self._h, variant, np_, _devt(pairs, "pairs", torch.int32),
+                                            _devt(out, "labels", torch.float64)))
+        return out
+
+    def mlp_predict(self, model, feats):
+        """model: CUDA float32 [MLP_MODEL]; feats: CUDA float32 [n, 8]."""
+        n = feats.shape[0]
+        y = torch.empty(n, dtype=torch.float32, device=feats.device)
+        self._check(lib().amfmm_mlp_predict(self._h, n, _devt(model, "model", torch.float32),
+                                            _devt(feats, "feats", torch.float32), _devt(y, "y", torch.float32)))
+        return y
+
+    def mlp_grad(self, model, feats, labels, tau=0.9):
+        n = feats.shape[0]
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=feats.device)
+        loss = np.zeros(1)
+        self._check(lib().amfmm_mlp_grad(self._h, n, _devt(model, "model", torch.float32),
+                                         _devt(feats, "feats", torch.float32),
+                                         _devt(labels, "labels", torch.float32), float(tau),
+                                         _devt(g, "grad", torch.float32), _ptr(loss, C.c_double)))
+        return float(loss[0]), g
+
+    def mlp_train(self, feats, labels, model, adam_m, adam_v, step0, steps, batch, lr, tau=0.9):
+        """Adam steps on the pinball loss; model, adam_m, adam_v updated in place."""
+        n = feats.shape[0]
+        loss = np.zeros(1)
+        self._check(lib().amfmm_mlp_train(self._h, n, _devt(feats, "feats", torch.float32),
+                                          _devt(labels, "labels", torch.float32),
+                                          _devt(model, "model", torch.float32),
+                                          _devt(adam_m, "adam_m", torch.float32),
+                                          _devt(adam_v, "adam_v", torch.float32), int(step0), int(steps),
+                                          int(batch), float(lr), float(tau), _ptr(loss, C.c_double)))
+        return float(loss[0])
 
     def build_tree(self, x, y, z, m):
         self.n = x.numel()

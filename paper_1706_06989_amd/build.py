@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libamfmm_hip.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["api.hip", "scan.hip", "sort.hip", "tree.hip", "moments.hip", "walk.hip", "eval.hip", "near.hip",
-           "direct.hip"]
+           "direct.hip", "mlp.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall",
@@ -44,7 +44,7 @@ def build(verbose=False):
             print(out)
     objs = [o for o, _ in results]
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    cmd = ["hipcc", "-shared", "-fPIC", "-Wl,--no-undefined", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}{r.stderr}")

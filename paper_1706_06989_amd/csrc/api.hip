@@ -2,6 +2,7 @@
 // timing and introspection.  Internal errors are C++ exceptions that never
 // cross the ABI: every entry point turns them into an amfmm_status.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <utility>
 
@@ -66,7 +67,8 @@ static DevBuf* all_bufs(Ctx& c, int i) {
   DevBuf* v[] = {&c.pos4, &c.keys, &c.perm, &c.keys2, &c.perm2, &c.bbox, &c.scratch, &c.scratch2, &c.hist,
                  &c.c_begin, &c.c_count, &c.c_parent, &c.c_child0, &c.c_nchild, &c.leaves, &c.geo, &c.mom,
                  &c.msum, &c.loc, &c.far_start, &c.far_count, &c.far_src, &c.near_start, &c.near_count,
-                 &c.near_src, &c.fx, &c.fy, &c.fx2, &c.fy2, &c.fcnt, &c.grp, &c.walkrec, &c.fsave, &c.gsave, &c.counters, &c.gqueue, &c.gmin};
+                 &c.near_src, &c.fx, &c.fy, &c.fx2, &c.fy2, &c.fcnt, &c.grp, &c.walkrec, &c.fsave, &c.gsave, &c.counters, &c.gqueue, &c.gmin, &c.model, &c.mlp_tmp, &c.mlp_part,
+                 &c.mlp_grad};
   const int nv = (int)(sizeof(v) / sizeof(v[0]));
   return i < nv ? v[i] : nullptr;
 }
@@ -126,7 +128,7 @@ int amfmm_default_options(amfmm_options* o) {
   o->precision = AMFMM_FP64;
   o->criterion = AMFMM_GEOMETRIC;
   o->G = 1.0;
-  o->learned_tol = 1e-4;
+  o->error_tol = 1e-4;
   o->theta_max = 1.0;
   o->max_bytes = 0;
   o->list_bytes = 0;
@@ -137,7 +139,7 @@ static int check_options(const amfmm_options* o) {
   if (o->n_crit < 1 || o->n_crit > 4096) return AMFMM_E_INVALID;
   if (o->variant < AMFMM_UC || o->variant > AMFMM_TCO) return AMFMM_E_INVALID;
   if (o->precision != AMFMM_FP64 && o->precision != AMFMM_MIXED) return AMFMM_E_INVALID;
-  if (o->criterion != AMFMM_GEOMETRIC && o->criterion != AMFMM_LEARNED) return AMFMM_E_INVALID;
+  if (o->criterion < AMFMM_GEOMETRIC || o->criterion > AMFMM_LEARNED) return AMFMM_E_INVALID;
   if (!(o->G == o->G) || o->max_bytes < 0 || o->list_bytes < 0) return AMFMM_E_INVALID;
   return AMFMM_OK;
 }
@@ -181,6 +183,77 @@ int amfmm_set_field_estimate(amfmm_ctx* ctx, const double* gx, const double* gy,
     c.field = gx;
     c.field_y = gx ? gy : nullptr;
     c.field_z = gx ? gz : nullptr;
+    return AMFMM_OK;
+  });
+}
+
+int amfmm_set_model(amfmm_ctx* ctx, const float* model) {
+  return guarded(ctx, [&](Ctx& c) -> int {
+    if (!model) {
+      amfmm::release(c, c.model);
+      return AMFMM_OK;
+    }
+    for (int i = 0; i < AMFMM_MLP_MODEL; ++i)
+      if (!std::isfinite(model[i]) && !(i >= 4817 && std::isinf(model[i])))
+        return fail(c, AMFMM_E_NONFINITE, "model holds a NaN or an infinite weight");
+    float* tmp = (float*)amfmm::ensure(c, c.mlp_tmp, sizeof(float) * AMFMM_MLP_MODEL);
+    float* dst = (float*)amfmm::ensure(c, c.model, sizeof(float) * AMFMM_MLP_MODEL);
+    AMFMM_HIP(hipMemcpyAsync(tmp, model, sizeof(float) * AMFMM_MLP_MODEL, hipMemcpyHostToDevice, c.stream));
+    amfmm::round_model(c, tmp, dst);
+    amfmm::sync(c);
+    c.hint_n = 0;  // decisions change: forget the batch size of earlier solves
+    return AMFMM_OK;
+  });
+}
+
+int amfmm_pair_features(amfmm_ctx* ctx, int64_t np, const int32_t* pairs, float* feats) {
+  return guarded(ctx, [&](Ctx& c) -> int {
+    if (np < 0 || (np > 0 && (!pairs || !feats))) return fail(c, AMFMM_E_INVALID, "bad pair arguments");
+    amfmm::compute_pair_features(c, np, pairs, feats);
+    return AMFMM_OK;
+  });
+}
+
+int amfmm_pair_labels(amfmm_ctx* ctx, int32_t variant, int64_t np, const int32_t* pairs, double* labels) {
+  return guarded(ctx, [&](Ctx& c) -> int {
+    if (np < 0 || (np > 0 && (!pairs || !labels))) return fail(c, AMFMM_E_INVALID, "bad pair arguments");
+    if (variant < AMFMM_UC || variant > AMFMM_TCO) return fail(c, AMFMM_E_INVALID, "bad variant");
+    amfmm::compute_pair_labels(c, variant, np, pairs, labels);
+    return AMFMM_OK;
+  });
+}
+
+int amfmm_mlp_predict(amfmm_ctx* ctx, int64_t n, const float* model, const float* feats, float* y) {
+  return guarded(ctx, [&](Ctx& c) -> int {
+    if (n < 0 || !model || (n > 0 && (!feats || !y))) return fail(c, AMFMM_E_INVALID, "bad arguments");
+    amfmm::mlp_predict(c, n, model, feats, y);
+    return AMFMM_OK;
+  });
+}
+
+int amfmm_mlp_grad(amfmm_ctx* ctx, int64_t n, const float* model, const float* feats, const float* labels,
+                   double tau, float* grad, double* loss) {
+  return guarded(ctx, [&](Ctx& c) -> int {
+    if (n < 1 || n >= (int64_t)INT32_MAX || !model || !feats || !labels || !grad)
+      return fail(c, AMFMM_E_INVALID, "bad arguments");
+    if (!(tau > 0.0 && tau < 1.0)) return fail(c, AMFMM_E_INVALID, "tau must lie in (0, 1)");
+    const double l = amfmm::mlp_grad(c, n, model, feats, labels, tau, grad);
+    if (loss) *loss = l;
+    return AMFMM_OK;
+  });
+}
+
+int amfmm_mlp_train(amfmm_ctx* ctx, int64_t n, const float* feats, const float* labels, float* model,
+                    float* adam_m, float* adam_v, int64_t step0, int32_t steps, int32_t batch, double lr,
+                    double tau, double* last_loss) {
+  return guarded(ctx, [&](Ctx& c) -> int {
+    if (n < 1 || n >= (int64_t)INT32_MAX || !feats || !labels || !model || !adam_m || !adam_v)
+      return fail(c, AMFMM_E_INVALID, "bad arguments");
+    if (step0 < 0 || steps < 0 || batch < 1 || batch > (1 << 20) || !(lr > 0.0))
+      return fail(c, AMFMM_E_INVALID, "bad training schedule");
+    if (!(tau > 0.0 && tau < 1.0)) return fail(c, AMFMM_E_INVALID, "tau must lie in (0, 1)");
+    const double l = amfmm::mlp_train(c, n, feats, labels, model, adam_m, adam_v, step0, steps, batch, lr, tau);
+    if (last_loss) *last_loss = l;
     return AMFMM_OK;
   });
 }
@@ -423,7 +496,7 @@ int amfmm_solve_gravity(amfmm_ctx* ctx, int64_t n, const double* x, const double
     const size_t budget = list_budget(c);
     // a context that needed batches for this size and criterion goes straight to them
     const bool same = c.hint_n == n && c.hint_theta == theta && c.hint_mode == c.opt.criterion &&
-                      c.hint_tol == c.opt.learned_tol;
+                      c.hint_tol == c.opt.error_tol;
     if (!same) c.batch_hint = 0;
     bool whole = (need <= (double)budget || c.depth < 3) && !(same && c.batch_hint > 0);
     if (whole) {
@@ -448,7 +521,7 @@ int amfmm_solve_gravity(amfmm_ctx* ctx, int64_t n, const double* x, const double
     c.hint_n = n;
     c.hint_theta = theta;
     c.hint_mode = c.opt.criterion;
-    c.hint_tol = c.opt.learned_tol;
+    c.hint_tol = c.opt.error_tol;
     return AMFMM_OK;
   });
 }

@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "amfmm.h"
+
 namespace amfmm {
 
 // T[p][m]: packed triple index of sorted(pair p, m) with pairs xx xy xz yy yz zz
@@ -26,6 +28,91 @@ __device__ inline double rsqrt_f64_1nr(double r2) {
   double y = __builtin_amdgcn_rsq(r2);
   const double h = 0.5 * r2;
   return y * fma(-h, y * y, 1.5);
+}
+
+// Far-field coefficients of one source (moments M, quadrupole Q2) at R:
+// acc[0] C, acc[1..3] C_k, acc[4..9] C_kl, acc[10..19] C_klm (packed).
+// T = double (FP64 path) or float (mixed path).
+template <typename T>
+__device__ inline void far_coeffs(const T R[3], T M, const T Q2[6], T* acc) {
+  const T r2 = fma(R[0], R[0], fma(R[1], R[1], R[2] * R[2]));
+  T ri;
+  if constexpr (sizeof(T) == 8) ri = rsqrt_f64(r2);
+  else ri = __builtin_amdgcn_rsqf(r2);
+  const T ri2 = ri * ri;
+  const T t1 = ri * ri2;
+  const T t2 = T(-3) * t1 * ri2;
+  const T t3 = T(-5) * t2 * ri2;
+  const T RR[6] = {R[0] * R[0], R[0] * R[1], R[0] * R[2], R[1] * R[1], R[1] * R[2], R[2] * R[2]};
+  // D_kl and D_klm (packed)
+  T D2[6], D3[10];
+#pragma unroll
+  for (int u = 0; u < 6; ++u) D2[u] = t2 * RR[u];
+  D2[0] += t1;
+  D2[3] += t1;
+  D2[5] += t1;
+  D3[0] = fma(t3 * RR[0], R[0], T(3) * t2 * R[0]);
+  D3[1] = fma(t3 * RR[0], R[1], t2 * R[1]);
+  D3[2] = fma(t3 * RR[0], R[2], t2 * R[2]);
+  D3[3] = fma(t3 * RR[3], R[0], t2 * R[0]);
+  D3[4] = t3 * RR[1] * R[2];
+  D3[5] = fma(t3 * RR[5], R[0], t2 * R[0]);
+  D3[6] = fma(t3 * RR[3], R[1], T(3) * t2 * R[1]);
+  D3[7] = fma(t3 * RR[3], R[2], t2 * R[2]);
+  D3[8] = fma(t3 * RR[5], R[1], t2 * R[1]);
+  D3[9] = fma(t3 * RR[5], R[2], T(3) * t2 * R[2]);
+  // contractions of the source quadrupole
+  const T trQ = Q2[0] + Q2[3] + Q2[5];
+  const T QR[3] = {fma(Q2[0], R[0], fma(Q2[1], R[1], Q2[2] * R[2])),
+                   fma(Q2[1], R[0], fma(Q2[3], R[1], Q2[4] * R[2])),
+                   fma(Q2[2], R[0], fma(Q2[4], R[1], Q2[5] * R[2]))};
+  const T RQR = fma(R[0], QR[0], fma(R[1], QR[1], R[2] * QR[2]));
+  acc[0] += fma(-M, ri, T(0.5) * fma(t2, RQR, t1 * trQ));
+  const T a1 = fma(M, t1, T(0.5) * fma(t3, RQR, t2 * trQ));
+#pragma unroll
+  for (int k = 0; k < 3; ++k) acc[1 + k] += fma(a1, R[k], t2 * QR[k]);
+#pragma unroll
+  for (int u = 0; u < 6; ++u) acc[4 + u] = fma(M, D2[u], acc[4 + u]);
+#pragma unroll
+  for (int u = 0; u < 10; ++u) acc[10 + u] = fma(M, D3[u], acc[10 + u]);
+}
+
+// Q_jkl D_ijkl (TC) or Q_jkl D'_ijkl (TCO) of the correction, FP64, with
+// Q = M_X,jkl M_Y - M_X M_Y,jkl; adds to F[3]
+template <int VARIANT>
+__device__ inline void far_correction(const double R[3], double MX, const double OX[10], double M, const double O3[10],
+                                      double F[3]) {
+  const double r2 = fma(R[0], R[0], fma(R[1], R[1], R[2] * R[2]));
+  const double ri = rsqrt_f64(r2);
+  const double ri2 = ri * ri;
+  const double t2 = -3.0 * (ri * ri2) * ri2;
+  const double t3 = -5.0 * t2 * ri2;
+  const double RR[6] = {R[0] * R[0], R[0] * R[1], R[0] * R[2], R[1] * R[1], R[1] * R[2], R[2] * R[2]};
+  double Q[10];
+#pragma unroll
+  for (int u = 0; u < 10; ++u) Q[u] = fma(OX[u], M, -MX * O3[u]);
+  const double mult[6] = {1.0, 2.0, 2.0, 1.0, 2.0, 1.0};
+  double v[3], w[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) s = fma(mult[p] * Q[kT3[p][i]], RR[p], s);
+    v[i] = s;
+  }
+  w[0] = Q[0] + Q[3] + Q[5];
+  w[1] = Q[1] + Q[6] + Q[8];
+  w[2] = Q[2] + Q[7] + Q[9];
+  if (VARIANT == AMFMM_TC) {
+    const double t4 = -7.0 * t3 * ri2;
+    const double s = fma(R[0], v[0], fma(R[1], v[1], R[2] * v[2]));
+    const double wR = fma(R[0], w[0], fma(R[1], w[1], R[2] * w[2]));
+#pragma unroll
+    for (int i = 0; i < 3; ++i) F[i] += fma(t4 * s, R[i], 3.0 * fma(t3, fma(R[i], wR, v[i]), t2 * w[i]));
+  } else {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) F[i] += 3.0 * fma(t3, v[i], t2 * w[i]);
+  }
 }
 
 template <typename T>

@@ -80,7 +80,9 @@ struct Ctx {
   DevBuf fx, fy, fx2, fy2, fcnt, grp, walkrec, fsave, gsave, counters, gqueue;
   int64_t grp_width = 0, frontier = 0;
   double walk_abs_tol = 0.0;
-  int walk_mode = 0;              // 0 geometric, 1 error estimate against the field
+  int walk_mode = 0;              // 0 geometric, 1 error estimate, 2 learned
+  DevBuf model;                   // learned criterion: network with BF16-rounded weights
+  DevBuf mlp_tmp, mlp_part, mlp_grad;  // inference and training scratch
   // caller's per-particle field estimate (device): magnitudes in `field`, or
   // components in field, field_y, field_z
   const double* field = nullptr;
@@ -161,6 +163,20 @@ void near_field(Ctx& c, const int32_t* leaves, int32_t c_lo, int32_t count, doub
                 double* pot);
 // fills n (<= 64) device words with zero (a kernel, so it can sit in a graph)
 void zero_u64(Ctx& c, unsigned long long* p, int n);
+
+// ---- mlp.hip ----
+// features (8 floats) and labels (log2 error factor) of cell pairs (device)
+void compute_pair_features(Ctx& c, int64_t np, const int32_t* pairs, float* feats);
+void compute_pair_labels(Ctx& c, int variant, int64_t np, const int32_t* pairs, double* labels);
+// model with its weights rounded to BF16 (device to device)
+void round_model(Ctx& c, const float* in, float* out);
+void mlp_predict(Ctx& c, int64_t n, const float* model, const float* feats, float* y);
+// gradient into grad (device); returns the loss (synchronises)
+double mlp_grad(Ctx& c, int64_t n, const float* model, const float* feats, const float* labels, double tau,
+                float* grad);
+// Adam steps; returns the loss of the last batch (synchronises)
+double mlp_train(Ctx& c, int64_t n, const float* feats, const float* labels, float* model, float* am, float* av,
+                 int64_t step0, int32_t steps, int32_t batch, double lr, double tau);
 
 // ---- direct.hip ----
 void direct_sum(Ctx& c, int64_t n, const double* x, const double* y, const double* z,

@@ -24,6 +24,7 @@
 #include <cstdlib>
 
 #include "internal.h"
+#include "learned.h"
 
 namespace amfmm {
 namespace {
@@ -36,21 +37,23 @@ enum : int { kAccept = 0, kNear = 1, kSplitX = 2, kSplitY = 3 };
 struct alignas(16) WalkRec {
   double gx, gy, gz, gw;  // centre of mass, R_max
   double m, gmin;         // mass, field scale of the cell (see k_gscale)
-  int32_t ch0, par, count, meta;  // first child, parent, particles, nch | has_next << 8
+  // first child, parent, particles, nch | has_next << 8 | quadrupole level << 16
+  int32_t ch0, par, count, meta;
 };
 
 struct WalkCell {
   double gx, gy, gz, gw, m, gmin;
-  int32_t ch0, nch, par, next, count;
+  int32_t ch0, nch, par, next, count, qlev;
 };
 
 struct TreeView {
   const WalkRec* rec;
   double theta;
   double abs_tol;    // bound on the rounding of any centre of mass (absolute)
-  int mode;          // 0: opening angle theta; 1: error estimate against the field
-  double eps;        // mode 1: accepted error per pair, relative to each cell's field
-  double theta_max;  // mode 1: (R_A + R_B)/d above this never accepted
+  int mode;          // 0: opening angle theta; 1: error estimate; 2: learned
+  double eps;        // modes 1, 2: accepted error per pair, relative to each cell's field
+  double theta_max;  // modes 1, 2: (R_A + R_B)/d above this never accepted
+  const float* model;  // mode 2: network (BF16-rounded weights)
 };
 
 __device__ inline WalkCell load_cell(const WalkRec* __restrict__ r, int32_t c) {
@@ -69,10 +72,14 @@ __device__ inline WalkCell load_cell(const WalkRec* __restrict__ r, int32_t c) {
   w.par = v.y;
   w.count = v.z;
   w.nch = v.w & 0xff;
-  w.next = (v.w >> 8) ? c + 1 : -1;
+  w.next = ((v.w >> 8) & 1) ? c + 1 : -1;
+  w.qlev = (v.w >> 16) & 0xff;
   return w;
 }
 
+// LEARNED: compile the network's decision in (mode 2); kernels of the other
+// modes stay free of it (and of its registers)
+template <bool LEARNED>
 __device__ inline int decide(const TreeView& t, int32_t X, const WalkCell& a, int32_t Y, const WalkCell& b) {
   const double dx = a.gx - b.gx, dy = a.gy - b.gy, dz = a.gz - b.gz;
   const double d = sqrt((dx * dx + dy * dy) + dz * dz);
@@ -82,12 +89,18 @@ __device__ inline int decide(const TreeView& t, int32_t X, const WalkCell& a, in
   } else {
     // The force error of a quadrupole-order pair scales as M_other r^3 / d^5
     // with r = R_A + R_B; accept when that estimate stays below eps times the
-    // field scale of each cell (both cells: a symmetric decision).
+    // field scale of each cell (both cells: a symmetric decision).  Mode 2
+    // asks the network where the estimate is close to the bound.
     const double r = a.gw + b.gw;
     if (d > 0.0 && r <= t.theta_max * d) {
-      const double q = r / d;
-      const double e = (q * q * q) / (d * d);
-      if (e * b.m <= t.eps * a.gmin && e * a.m <= t.eps * b.gmin) return kAccept;
+      if (!LEARNED || t.mode == 1) {
+        const double q = r / d;
+        const double e = (q * q * q) / (d * d);
+        if (e * b.m <= t.eps * a.gmin && e * a.m <= t.eps * b.gmin) return kAccept;
+      } else {
+        const PairSide A{a.gw, a.m, a.qlev, a.count}, B{b.gw, b.m, b.qlev, b.count};
+        if (learned_accept(t.model, t.eps, t.theta, d, A, a.gmin, B, b.gmin)) return kAccept;
+      }
     }
   }
   const bool lx = a.nch == 0, ly = b.nch == 0;
@@ -110,7 +123,7 @@ __device__ inline int decide(const TreeView& t, int32_t X, const WalkCell& a, in
 
 // Visits the terminal pairs of entry (X, Y) in depth-first order (children of
 // Y in octant order) and calls f(kind, Y') for each.
-template <typename F>
+template <bool LEARNED, typename F>
 __device__ inline void traverse(const TreeView& t, int32_t X, int32_t Y, F&& f) {
   const WalkCell a = load_cell(t.rec, X);
   if (X == Y) {
@@ -124,7 +137,7 @@ __device__ inline void traverse(const TreeView& t, int32_t X, int32_t Y, F&& f) 
   int32_t cur = Y;
   WalkCell b = load_cell(t.rec, cur);
   for (;;) {
-    int d = decide(t, X, a, cur, b);
+    int d = decide<LEARNED>(t, X, a, cur, b);
     if (d == kSplitY) {
       cur = b.ch0;
       b = load_cell(t.rec, cur);
@@ -157,14 +170,15 @@ __global__ void __launch_bounds__(kBS) k_pack_cells(int32_t nc, const double4* _
   w.gy = g.y;
   w.gz = g.z;
   w.gw = g.w;
-  w.m = mom[(int64_t)c * kMom];
+  const double* mo = mom + (int64_t)c * kMom;
+  w.m = mo[0];
   w.gmin = gmin ? gmin[c] : 0.0;
   w.ch0 = nch[c] ? ch0[c] : -1;
   const int32_t p = par[c];
   w.par = p;
   w.count = cnt[c];
   const int has_next = (p >= 0 && c + 1 < ch0[p] + nch[p]) ? 1 : 0;
-  w.meta = nch[c] | (has_next << 8);
+  w.meta = nch[c] | (has_next << 8) | (quad_level(mo[0], g.w, mo + 1) << 16);
   rec[c] = w;
 }
 
@@ -259,7 +273,7 @@ struct EmitDst {
 // pushes Y's children to the queue; when the queue is full the lane descends
 // Y's subtree itself.  The order is a fixed function of the inputs, so the
 // counting run and the emitting run visit the same pairs in the same order.
-template <bool EMIT, typename Q>
+template <bool EMIT, bool LEARNED, typename Q>
 __device__ inline void wave_walk(const TreeView& t, int32_t X, const WalkCell& cx, const int32_t* __restrict__ fy,
                                  int64_t b, int32_t n, Q qbuf, int32_t qcap, int64_t& tm, int64_t& tp, int64_t& tq,
                                  EmitDst dst, unsigned long long* dbg) {
@@ -289,7 +303,7 @@ __device__ inline void wave_walk(const TreeView& t, int32_t X, const WalkCell& c
         else q = cx.nch;
       } else {
         const WalkCell cy = load_cell(t.rec, Y);
-        const int d = decide(t, X, cx, Y, cy);
+        const int d = decide<LEARNED>(t, X, cx, Y, cy);
         m = d == kAccept;
         p = d == kNear;
         q = d == kSplitX;
@@ -317,7 +331,7 @@ __device__ inline void wave_walk(const TreeView& t, int32_t X, const WalkCell& c
       dpairs += __popcll(ym);
     }
     if (deep)
-      traverse(t, X, Y, [&](int d, int32_t) {
+      traverse<LEARNED>(t, X, Y, [&](int d, int32_t) {
         m += d == kAccept;
         p += d == kNear;
         q += d == kSplitX;
@@ -333,7 +347,7 @@ __device__ inline void wave_walk(const TreeView& t, int32_t X, const WalkCell& c
       const int32_t oq = wave_excl_scan(q, &Tq);
       if (deep) {
         int64_t f = fo + om, g = no + op, bb = B + oq;
-        traverse(t, X, Y, [&](int d, int32_t Z) {
+        traverse<LEARNED>(t, X, Y, [&](int d, int32_t Z) {
           if (d == kAccept) {
             dst.far_src[f++] = Z;
           } else if (d == kNear) {
@@ -388,6 +402,7 @@ __global__ void __launch_bounds__(kBS) k_chunk_counts(int32_t nl, const int32_t*
 // One wave per chunk of a cell's frontier entries: count its terminal pairs.
 // gq != nullptr: the wave's work queue is the global region gq + k * qcap
 // (levels with few chunks, whose pairs fan out widely); else it is in LDS.
+template <bool LEARNED>
 __global__ void __launch_bounds__(kBS) k_walk_count(TreeView t, int32_t c0, int64_t kn, int32_t chunk,
                                                     const int32_t* __restrict__ kcell, const int64_t* __restrict__ cbase,
                                                     const int64_t* __restrict__ gbeg, const int32_t* __restrict__ gcnt,
@@ -405,9 +420,9 @@ __global__ void __launch_bounds__(kBS) k_walk_count(TreeView t, int32_t c0, int6
   const int32_t n = (int32_t)min<int64_t>(chunk, gcnt[i] - e0);
   int64_t tm = 0, tp = 0, tq = 0;
   if (gq)
-    wave_walk<false>(t, X, cx, fy, gbeg[i] + e0, n, gq + k * qcap, qcap, tm, tp, tq, EmitDst{}, dbg);
+    wave_walk<false, LEARNED>(t, X, cx, fy, gbeg[i] + e0, n, gq + k * qcap, qcap, tm, tp, tq, EmitDst{}, dbg);
   else
-    wave_walk<false>(t, X, cx, fy, gbeg[i] + e0, n, queue[threadIdx.x >> 6], kQ, tm, tp, tq, EmitDst{}, dbg);
+    wave_walk<false, LEARNED>(t, X, cx, fy, gbeg[i] + e0, n, queue[threadIdx.x >> 6], kQ, tm, tp, tq, EmitDst{}, dbg);
   tm = wave_sum64(tm);
   tp = wave_sum64(tp);
   tq = wave_sum64(tq);
@@ -451,6 +466,7 @@ __global__ void __launch_bounds__(kBS) k_walk_groups(TreeView t, int32_t c0, int
 }
 
 // One wave per chunk: write its far and near entries and its children's entries.
+template <bool LEARNED>
 __global__ void __launch_bounds__(kBS) k_walk_emit(TreeView t, int32_t c0, int64_t kn, int32_t chunk,
                                                    const int32_t* __restrict__ kcell, const int64_t* __restrict__ cbase,
                                                    const int64_t* __restrict__ gbeg, const int32_t* __restrict__ gcnt,
@@ -473,9 +489,9 @@ __global__ void __launch_bounds__(kBS) k_walk_emit(TreeView t, int32_t c0, int64
   EmitDst dst{far_base + mex[k], near_base + pex[k], nbase[i], S, far_src, near_src, fy_n,
               qex[k] - qex[cbase[i]]};
   if (gq)
-    wave_walk<true>(t, X, cx, fy, gbeg[i] + e0, n, gq + k * qcap, qcap, tm, tp, tq, dst, nullptr);
+    wave_walk<true, LEARNED>(t, X, cx, fy, gbeg[i] + e0, n, gq + k * qcap, qcap, tm, tp, tq, dst, nullptr);
   else
-    wave_walk<true>(t, X, cx, fy, gbeg[i] + e0, n, queue[threadIdx.x >> 6], kQ, tm, tp, tq, dst, nullptr);
+    wave_walk<true, LEARNED>(t, X, cx, fy, gbeg[i] + e0, n, queue[threadIdx.x >> 6], kQ, tm, tp, tq, dst, nullptr);
 }
 
 __global__ void k_walk_init(int64_t* gbeg, int32_t* gcnt, int32_t* fy) {
@@ -497,8 +513,10 @@ void walk_prepare(Ctx& c, double theta) {
   const int32_t nc = c.ncells;
   WalkRec* rec = (WalkRec*)ensure(c, c.walkrec, sizeof(WalkRec) * (size_t)nc);
   const double* gmin = nullptr;
-  c.walk_mode = (c.opt.criterion == AMFMM_LEARNED && c.field) ? 1 : 0;
-  if (c.walk_mode == 1) {
+  c.walk_mode = 0;
+  if (c.field && c.opt.criterion == AMFMM_ESTIMATE) c.walk_mode = 1;
+  if (c.field && c.opt.criterion == AMFMM_LEARNED && c.model.p) c.walk_mode = 2;
+  if (c.walk_mode != 0) {
     double* gs = (double*)ensure(c, c.gmin, 3 * sizeof(double) * nc);
     double* gm = gs + nc;
     double* g = gm + nc;
@@ -559,9 +577,10 @@ void walk_start(Ctx& c) {
 
 int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32_t>& lo,
                     const std::vector<int32_t>& hi, int64_t& far_base, int64_t& near_base) {
-  TreeView t{(const WalkRec*)c.walkrec.p, c.theta, c.walk_abs_tol, c.walk_mode, c.opt.learned_tol,
-             c.opt.theta_max};
+  TreeView t{(const WalkRec*)c.walkrec.p, c.theta, c.walk_abs_tol, c.walk_mode, c.opt.error_tol,
+             c.opt.theta_max, (const float*)c.model.p};
   static const bool debug = getenv("AMFMM_DEBUG_WALK") != nullptr;
+  const bool learned = c.walk_mode == 2;
   int64_t F = c.frontier;
   int64_t* tot_host = c.pinned;
   for (int lev = lev_first; lev <= lev_last && F > 0; ++lev) {
@@ -609,7 +628,7 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
       AMFMM_HIP(hipEventCreate(&e1));
       AMFMM_HIP(hipEventRecord(e0, c.stream));
     }
-    hipLaunchKernelGGL(k_walk_count, dim3(kgrid), dim3(kBS), 0, c.stream, t, c0, kn, chunk, (const int32_t*)kcell,
+    hipLaunchKernelGGL(learned ? k_walk_count<true> : k_walk_count<false>, dim3(kgrid), dim3(kBS), 0, c.stream, t, c0, kn, chunk, (const int32_t*)kcell,
                        (const int64_t*)cbase, (const int64_t*)gbeg, (const int32_t*)gcnt, fy, km, kp, kq, gq, qcap,
                        dbg);
     AMFMM_HIP(hipGetLastError());
@@ -652,7 +671,7 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
     int32_t* near_src = (int32_t*)ensure_keep(c, c.near_src, sizeof(int32_t) * (near_base + pt + 1),
                                               sizeof(int32_t) * near_base);
     int32_t* fy_n = (int32_t*)ensure(c, c.fy2, sizeof(int32_t) * (Fn + 1));
-    hipLaunchKernelGGL(k_walk_emit, dim3(kgrid), dim3(kBS), 0, c.stream, t, c0, kn, chunk, (const int32_t*)kcell,
+    hipLaunchKernelGGL(learned ? k_walk_emit<true> : k_walk_emit<false>, dim3(kgrid), dim3(kBS), 0, c.stream, t, c0, kn, chunk, (const int32_t*)kcell,
                        (const int64_t*)cbase, (const int64_t*)gbeg, (const int32_t*)gcnt, fy, (const int64_t*)mex,
                        (const int64_t*)pex, (const int64_t*)qex, (const int64_t*)nbase, far_base, near_base, far_src,
                        near_src, fy_n, gq, qcap);

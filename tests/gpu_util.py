@@ -26,6 +26,17 @@ def gpu_solve(x, y, z, m, theta, variant=amfmm.TC, precision=amfmm.FP64, n_crit=
     return acc, p.cpu().numpy(), s
 
 
+def dup_points():
+    """300 uniform points plus 40 coincident ones (a leaf deeper than the key
+    resolution allows to split)."""
+    from paper_1706_06989_amd import workloads as W
+    x, y, z, m = W.uniform_cube(300, seed=7)
+    x = np.concatenate([x, np.full(40, 0.25)])
+    y = np.concatenate([y, np.full(40, 0.5)])
+    z = np.concatenate([z, np.full(40, 0.75)])
+    return x, y, z, np.full(len(x), 1.0 / len(x))
+
+
 def tree_parts(x, y, z, m, n_crit=25):
     s = amfmm.Solver(n_crit=n_crit)
     X, Y, Z, M = to_dev(x, y, z, m)

@@ -14,17 +14,9 @@ import torch
 from oracle import oracle as orc
 from paper_1706_06989_amd import amfmm
 from paper_1706_06989_amd import workloads as W
-from tests.gpu_util import gpu_solve, say, to_dev, tree_parts
+from tests.gpu_util import dup_points, gpu_solve, say, to_dev, tree_parts
 
 pytestmark = pytest.mark.gpu
-
-
-def dup_points():
-    x, y, z, m = W.uniform_cube(300, seed=7)
-    x = np.concatenate([x, np.full(40, 0.25)])
-    y = np.concatenate([y, np.full(40, 0.5)])
-    z = np.concatenate([z, np.full(40, 0.75)])
-    return x, y, z, np.full(len(x), 1.0 / len(x))
 
 
 CASES = {
@@ -224,7 +216,7 @@ def test_field_criterion_lists_and_accelerations(name, eps, tmax):
     say("field", name, len(x), eps, tmax)
     at, _, gabs = orc.direct(x, y, z, m)
     gmag = np.linalg.norm(at, axis=0)
-    s = amfmm.Solver(criterion=amfmm.LEARNED, learned_tol=eps, theta_max=tmax)
+    s = amfmm.Solver(criterion=amfmm.ESTIMATE, error_tol=eps, theta_max=tmax)
     X, Y, Z, M = to_dev(x, y, z, m)
     G, = to_dev(gmag)
     s.set_field_estimate(G)
