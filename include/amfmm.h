@@ -49,12 +49,13 @@ typedef enum { AMFMM_FP64 = 0, AMFMM_MIXED = 1 } amfmm_precision;
  *   (per cell: the smallest field estimate over its particles, at least 0.1
  *   times their mean), a pair is accepted when q <= theta_max and
  *   q^3 M_B / d^2 <= error_tol s_A and q^3 M_A / d^2 <= error_tol s_B.
- * LEARNED: as ESTIMATE, but the analytic error factor q^3 is replaced by the
- *   network's prediction f (amfmm_set_model) where q^3 lies within [u/4, 16 u]
- *   of the allowed factor u = min(error_tol s_A d^2 / M_B, error_tol s_B d^2 /
- *   M_A); below the band the pair is accepted, above it opened; pairs whose
- *   features fall outside the model's training range use the geometric rule
- *   with the solve's theta.
+ * LEARNED: as ESTIMATE, but for pairs with N_A N_B >= learned_min_work the
+ *   analytic error factor q^3 is replaced by the network's prediction f
+ *   (amfmm_set_model) where q^3 lies within [u/4, 16 u] of the allowed factor
+ *   u = min(error_tol s_A d^2 / M_B, error_tol s_B d^2 / M_A); below the band
+ *   the pair is accepted, above it opened.  Smaller pairs, and pairs whose
+ *   features fall outside the model's training range, are accepted when
+ *   q^3 <= u (the analytic factor).
  * Every rule is a function of the unordered pair, so pairwise momentum
  * conservation holds.  Without a field estimate (amfmm_set_field_estimate),
  * and for LEARNED without a model, the geometric rule is used. */
@@ -73,12 +74,16 @@ typedef struct {
                          (0 = automatic); when the whole tree's lists would not
                          fit, amfmm_solve_gravity walks and evaluates the tree
                          in batches of subtrees, with identical results */
+  int64_t learned_min_work; /* LEARNED: the network decides pairs with N_A N_B >=
+                               this (default 4096); smaller pairs, where a network
+                               evaluation costs more than the work it can save,
+                               take the analytic estimate q^3 <= u */
 } amfmm_options;
 
 typedef struct amfmm_ctx amfmm_ctx;
 
 /* Fills *opt with n_crit = 25, TC, FP64, geometric, G = 1, error_tol = 1e-4,
- * theta_max = 1, max_bytes = 0, list_bytes = 0. */
+ * theta_max = 1, max_bytes = 0, list_bytes = 0, learned_min_work = 4096. */
 int amfmm_default_options(amfmm_options* opt);
 
 /* Creates a context bound to hip_stream (a hipStream_t; NULL = null stream)
@@ -151,8 +156,8 @@ int amfmm_balance(amfmm_ctx* ctx, int64_t n, const double* x, const double* y, c
  * |g_pair - g_direct| / (M_other / d^2).  Features of a pair (A, B), d the
  * centre distance, all symmetric: (R_A+R_B)/d, plog2 of it, |R_A-R_B|/(R_A+R_B),
  * |M_A-M_B|/(M_A+M_B), (k_A+k_B)/128, |k_A-k_B|/64 with k = floor(64
- * ||M_ij||_F / (M R_max^2) + 1/2), plog2(N_A N_B), |plog2 N_A - plog2 N_B|, where
- * plog2(2^e (1+f)) = e + f. */
+ * ||M_ij||_F / (M R_max^2) + 1/2), plog2(N_A N_B), |plog2 N_A - plog2 N_B| (counts
+ * saturated at 1024), where plog2(2^e (1+f)) = e + f. */
 #define AMFMM_MLP_PARAMS 4801
 #define AMFMM_MLP_MODEL 4833
 

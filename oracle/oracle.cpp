@@ -76,6 +76,7 @@ struct orc_tree {
   std::vector<double> fscale;  // per-cell field scale (modes 1 and 2)
   std::vector<float> model;    // mode 2: network and feature normalisation
   std::vector<int> qlev;       // mode 2: quantised quadrupole norm per cell
+  int64_t min_work = 0;        // mode 2: least N_A N_B for which the network decides
   std::vector<std::pair<int32_t, int32_t>> m2l, p2p;
   int64_t coincident = 0;
 };
@@ -310,6 +311,7 @@ constexpr int kFeat = 8, kHid = 64;
 constexpr int kW1 = 0, kB1 = 512, kW2 = 576, kB2 = 4672, kW3 = 4736, kB3 = 4800;
 constexpr int kNA = 4801, kNB = 4809, kLo = 4817, kHi = 4825, kModel = 4833, kParams = 4801;
 constexpr int kLabelSample = 64;  // particles sampled per cell for a label
+constexpr int64_t kCountCap = 1024;  // particle counts saturate here in the features
 
 // round a float to the nearest BF16 value (ties to even), kept as float
 float bf16(float v) {
@@ -357,8 +359,11 @@ void pair_features(double d, const Moments& A, const Moments& B, int qa, int qb,
   f[3] = (float)(std::fabs(A.M - B.M) / (A.M + B.M));          // mass asymmetry
   f[4] = (float)((double)(qa + qb) / 128.0);                    // mean quadrupole level
   f[5] = (float)((double)std::abs(qa - qb) / 64.0);             // its asymmetry
-  f[6] = (float)plog2((double)na * (double)nb);                 // particle counts
-  f[7] = (float)std::fabs(plog2((double)na) - plog2((double)nb));
+  // particle counts, saturated at kCountCap: beyond it a cell behaves as a
+  // continuum and the count carries no information about the error
+  double ca = (double)std::min<int64_t>(na, kCountCap), cb = (double)std::min<int64_t>(nb, kCountCap);
+  f[6] = (float)plog2(ca * cb);
+  f[7] = (float)std::fabs(plog2(ca) - plog2(cb));
 }
 
 double pair_distance(const Moments& A, const Moments& B) {
@@ -414,17 +419,20 @@ bool accept(const orc_tree& t, int32_t a, int32_t b) {
   // Learned: the error of the pair on A is f M_B / d^2 with f the predicted
   // error factor; accept when f <= u = min over both cells of eps s d^2 / M.
   // Where the analytic factor q^3 sits far from u the network is not asked:
-  // q^3 <= u/4 accepts, q^3 > 16 u opens.  Features outside the training
-  // range fall back to the opening angle theta.
+  // q^3 <= u/4 accepts, q^3 > 16 u opens.  Small pairs and pairs whose
+  // features fall outside the training range take the analytic factor.
   double u = std::min((t.eps * t.fscale[a]) * (d * d) / B.M, (t.eps * t.fscale[b]) * (d * d) / A.M);
   double q3 = q * q * q;
   if (q3 <= 0.25 * u) return true;
   if (q3 > 16.0 * u) return false;
+  // small pairs (a network evaluation would cost more than the work it saves)
+  // take the analytic factor
+  if (t.cells[a].count * t.cells[b].count < t.min_work) return q3 <= u;
   float f[kFeat];
   pair_features(d, A, B, t.qlev[a], t.qlev[b], t.cells[a].count, t.cells[b].count, f);
   const float* P = t.model.data();
   for (int i = 0; i < kFeat; ++i)
-    if (!(f[i] >= P[kLo + i] && f[i] <= P[kHi + i])) return d >= r / t.theta;
+    if (!(f[i] >= P[kLo + i] && f[i] <= P[kHi + i])) return q3 <= u;
   return mlp_infer(P, f) <= (float)plog2(u);
 }
 
@@ -713,7 +721,7 @@ int32_t orc_walk_field(orc_tree* t, double eps, double theta_max, const double* 
 }
 
 int32_t orc_walk_learned(orc_tree* t, double eps, double theta_max, double theta, const double* gmag,
-                         const float* model) {
+                         const float* model, int64_t min_work) {
   if (!(theta > 0.0 && theta <= 1.0)) return ORC_E_INVALID;
   if (!model) return orc_walk(t, theta);  // no network: the opening angle
   if (!(eps > 0.0) || !(theta_max > 0.0 && theta_max <= 1.0) || !gmag) return ORC_E_INVALID;
@@ -723,6 +731,7 @@ int32_t orc_walk_learned(orc_tree* t, double eps, double theta_max, double theta
   t->qlev.resize(t->cells.size());
   for (size_t c = 0; c < t->cells.size(); ++c) t->qlev[c] = quad_level(t->mom[c]);
   t->mode = 2;
+  t->min_work = min_work;
   t->eps = eps;
   t->theta_max = theta_max;
   t->theta = theta;

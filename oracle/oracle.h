@@ -127,11 +127,11 @@ void orc_pair_far(int64_t nA, const double* xa, const double* ya, const double* 
 #define ORC_MLP_PARAMS 4801
 #define ORC_MLP_MODEL 4833
 /* Walk whose accept decision asks the network (error factor against eps times
- * the field scale of each cell, as orc_walk_field); model == NULL gives the
- * opening-angle walk with theta, which is also the fallback for features
- * outside the training range. */
+ * the field scale of each cell, as orc_walk_field) for pairs with N_A N_B >=
+ * min_work and features inside the training range; other pairs take the
+ * analytic factor q^3.  model == NULL gives the opening-angle walk with theta. */
 int32_t orc_walk_learned(orc_tree* t, double eps, double theta_max, double theta, const double* gmag,
-                         const float* model);
+                         const float* model, int64_t min_work);
 /* Features (8 floats per pair) and labels (log2 error factor) of cell pairs
  * (a, b), 2 int32 per pair; labels need moments and a != b, d > 0. */
 void orc_pair_features(const orc_tree* t, int64_t np, const int32_t* pairs, float* feats);

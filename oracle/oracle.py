@@ -68,7 +68,7 @@ def lib():
                                    d, d, d, d]
         f = C.POINTER(C.c_float)
         L.orc_walk_learned.restype = C.c_int32
-        L.orc_walk_learned.argtypes = [P, C.c_double, C.c_double, C.c_double, d, f]
+        L.orc_walk_learned.argtypes = [P, C.c_double, C.c_double, C.c_double, d, f, C.c_int64]
         L.orc_pair_features.argtypes = [P, C.c_int64, i32, f]
         L.orc_pair_labels.restype = C.c_int32
         L.orc_pair_labels.argtypes = [P, C.c_int32, C.c_int64, i32, d]
@@ -171,16 +171,16 @@ class Tree:
         if st:
             raise OracleError(st)
 
-    def walk_learned(self, eps, theta_max, theta, gmag, model):
+    def walk_learned(self, eps, theta_max, theta, gmag, model, min_work=4096):
         """Walk whose accept decision asks the network (model: MLP_MODEL floats,
-        or None for the opening-angle walk)."""
+        or None for the opening-angle walk) for pairs with N_A N_B >= min_work."""
         g = _f64(gmag)
         mp = None
         if model is not None:
             model = _f32(model)
             assert model.size == MLP_MODEL
             mp = _fp(model)
-        st = lib().orc_walk_learned(self._t, float(eps), float(theta_max), float(theta), _d(g), mp)
+        st = lib().orc_walk_learned(self._t, float(eps), float(theta_max), float(theta), _d(g), mp, int(min_work))
         if st:
             raise OracleError(st)
 

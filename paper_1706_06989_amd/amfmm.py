@@ -27,7 +27,8 @@ PHASES = ["validate+bbox", "keys+sort", "tree", "moments", "walk", "far", "push-
 class amfmm_options(C.Structure):
     _fields_ = [("n_crit", C.c_int32), ("variant", C.c_int32), ("precision", C.c_int32),
                 ("criterion", C.c_int32), ("G", C.c_double), ("error_tol", C.c_double),
-                ("theta_max", C.c_double), ("max_bytes", C.c_int64), ("list_bytes", C.c_int64)]
+                ("theta_max", C.c_double), ("max_bytes", C.c_int64), ("list_bytes", C.c_int64),
+                ("learned_min_work", C.c_int64)]
 
 
 _lib = None
@@ -123,13 +124,15 @@ class Solver:
     """One amfmm context.  Method names follow the C ABI without the prefix."""
 
     def __init__(self, n_crit=25, variant=TC, precision=FP64, criterion=GEOMETRIC, G=1.0,
-                 error_tol=1e-4, theta_max=1.0, max_bytes=0, list_bytes=0, stream=None):
+                 error_tol=1e-4, theta_max=1.0, max_bytes=0, list_bytes=0, learned_min_work=4096,
+                 stream=None):
         L = lib()
         o = amfmm_options()
         L.amfmm_default_options(C.byref(o))
         o.n_crit, o.variant, o.precision, o.criterion = n_crit, variant, precision, criterion
         o.G, o.error_tol, o.theta_max, o.max_bytes = G, error_tol, theta_max, max_bytes
         o.list_bytes = list_bytes
+        o.learned_min_work = learned_min_work
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = C.c_void_p()
         st = L.amfmm_create(C.byref(o), C.c_void_p(self.stream.cuda_stream), C.byref(h))

@@ -130,6 +130,7 @@ int amfmm_default_options(amfmm_options* o) {
   o->G = 1.0;
   o->error_tol = 1e-4;
   o->theta_max = 1.0;
+  o->learned_min_work = 4096;
   o->max_bytes = 0;
   o->list_bytes = 0;
   return AMFMM_OK;
@@ -140,7 +141,7 @@ static int check_options(const amfmm_options* o) {
   if (o->variant < AMFMM_UC || o->variant > AMFMM_TCO) return AMFMM_E_INVALID;
   if (o->precision != AMFMM_FP64 && o->precision != AMFMM_MIXED) return AMFMM_E_INVALID;
   if (o->criterion < AMFMM_GEOMETRIC || o->criterion > AMFMM_LEARNED) return AMFMM_E_INVALID;
-  if (!(o->G == o->G) || o->max_bytes < 0 || o->list_bytes < 0) return AMFMM_E_INVALID;
+  if (!(o->G == o->G) || o->max_bytes < 0 || o->list_bytes < 0 || o->learned_min_work < 0) return AMFMM_E_INVALID;
   return AMFMM_OK;
 }
 

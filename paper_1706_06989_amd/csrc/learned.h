@@ -27,6 +27,7 @@ static_assert(kB3 + 1 == AMFMM_MLP_PARAMS, "parameter layout");
 // analytic error factor q^3 against the allowed factor u: below u/4 accept,
 // above 16 u open, in between the network decides
 constexpr double kGateLo = 0.25, kGateHi = 16.0;
+constexpr int32_t kCountCap = 1024;  // particle counts saturate here in the features
 
 // nearest BF16 value (ties to even), as float
 __host__ __device__ inline float bf16r(float v) {
@@ -72,38 +73,59 @@ __device__ inline void pair_features(double d, const PairSide& A, const PairSide
   f[3] = (float)(fabs(A.M - B.M) / (A.M + B.M));
   f[4] = (float)((double)(A.q + B.q) / 128.0);
   f[5] = (float)((double)abs(A.q - B.q) / 64.0);
-  f[6] = (float)plog2((double)A.n * (double)B.n);
-  f[7] = (float)fabs(plog2((double)A.n) - plog2((double)B.n));
+  // counts saturate at kCountCap (a larger cell behaves as a continuum)
+  const double ca = (double)(A.n < kCountCap ? A.n : kCountCap), cb = (double)(B.n < kCountCap ? B.n : kCountCap);
+  f[6] = (float)plog2(ca * cb);
+  f[7] = (float)fabs(plog2(ca) - plog2(cb));
 }
 
 // FP32 inference; P holds BF16-rounded weights (biases and normalisation as
-// given).  Uniform across the wave: the weight reads become scalar loads.
-__device__ inline float mlp_infer(const float* __restrict__ P, const float f[kFeat]) {
-  float x[kFeat], h1[kHid];
+// given) and is the same for every lane: the weight reads become scalar
+// loads.  Kept out of line so that the walk kernels calling it keep their
+// own register budget.
+__device__ __noinline__ float mlp_infer8(const float* __restrict__ Pin, float f0, float f1, float f2, float f3,
+                                         float f4, float f5, float f6, float f7) {
+  const uint64_t pu = (uint64_t)Pin;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)pu);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(pu >> 32));
+  const float* __restrict__ P = (const float*)(((uint64_t)hi << 32) | lo);
+  const float f[kFeat] = {f0, f1, f2, f3, f4, f5, f6, f7};
+  float x[kFeat];
 #pragma unroll
   for (int i = 0; i < kFeat; ++i) x[i] = bf16r(fmaf(f[i], P[kNA + i], P[kNB + i]));
-#pragma unroll
-  for (int j = 0; j < kHid; ++j) {
-    float s = P[kB1 + j];
-#pragma unroll
-    for (int i = 0; i < kFeat; ++i) s = fmaf(P[kW1 + kFeat * j + i], x[i], s);
-    h1[j] = bf16r(s > 0.0f ? s : 0.0f);
-  }
+  // Layer 2 in two halves of its outputs; the hidden layer 1 is recomputed
+  // per half (j outer), so only 32 accumulators are live.  Every output k
+  // still sums its inputs j = 0..63 in order: the result is the same as with
+  // the layers evaluated one after the other.
   float y = P[kB3];
-  for (int k = 0; k < kHid; ++k) {
-    float s = P[kB2 + k];
+  for (int half = 0; half < 2; ++half) {
+    float s2[kHid / 2];
 #pragma unroll
-    for (int j = 0; j < kHid; ++j) s = fmaf(P[kW2 + kHid * k + j], h1[j], s);
-    y = fmaf(P[kW3 + k], bf16r(s > 0.0f ? s : 0.0f), y);
+    for (int k = 0; k < kHid / 2; ++k) s2[k] = P[kB2 + half * (kHid / 2) + k];
+    for (int j = 0; j < kHid; ++j) {
+      float s = P[kB1 + j];
+#pragma unroll
+      for (int i = 0; i < kFeat; ++i) s = fmaf(P[kW1 + kFeat * j + i], x[i], s);
+      const float h = bf16r(s > 0.0f ? s : 0.0f);
+#pragma unroll
+      for (int k = 0; k < kHid / 2; ++k) s2[k] = fmaf(P[kW2 + kHid * (half * (kHid / 2) + k) + j], h, s2[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < kHid / 2; ++k) y = fmaf(P[kW3 + half * (kHid / 2) + k], bf16r(s2[k] > 0.0f ? s2[k] : 0.0f), y);
   }
   return y;
 }
 
+__device__ inline float mlp_infer(const float* __restrict__ P, const float f[kFeat]) {
+  return mlp_infer8(P, f[0], f[1], f[2], f[3], f[4], f[5], f[6], f[7]);
+}
+
 // Learned accept decision of a pair with d > 0 and R_A + R_B <= theta_max d;
-// s = field scales, eps = accepted error relative to them, theta = fallback
-// opening angle for features outside the training range
-__device__ inline bool learned_accept(const float* __restrict__ P, double eps, double theta, double d,
-                                      const PairSide& A, double sA, const PairSide& B, double sB) {
+// s = field scales, eps = accepted error relative to them, min_work = least
+// N_A N_B for which the network is asked; smaller pairs and pairs with
+// features outside the training range take the analytic factor q^3
+__device__ inline bool learned_accept(const float* __restrict__ P, double eps, int64_t min_work,
+                                      double d, const PairSide& A, double sA, const PairSide& B, double sB) {
   const double r = A.R + B.R;
   const double q = r / d;
   const double uA = (eps * sA) * (d * d) / B.M, uB = (eps * sB) * (d * d) / A.M;
@@ -111,12 +133,13 @@ __device__ inline bool learned_accept(const float* __restrict__ P, double eps, d
   const double q3 = q * q * q;
   if (q3 <= kGateLo * u) return true;
   if (q3 > kGateHi * u) return false;
+  if ((int64_t)A.n * (int64_t)B.n < min_work) return q3 <= u;
   float f[kFeat];
   pair_features(d, A, B, f);
   bool in = true;
 #pragma unroll
   for (int i = 0; i < kFeat; ++i) in = in && (f[i] >= P[kLo + i] && f[i] <= P[kHi + i]);
-  if (!in) return d >= r / theta;
+  if (!in) return q3 <= u;
   return mlp_infer(P, f) <= (float)plog2(u);
 }
 

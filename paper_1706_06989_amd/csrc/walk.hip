@@ -54,6 +54,7 @@ struct TreeView {
   double eps;        // modes 1, 2: accepted error per pair, relative to each cell's field
   double theta_max;  // modes 1, 2: (R_A + R_B)/d above this never accepted
   const float* model;  // mode 2: network (BF16-rounded weights)
+  int64_t min_work;    // mode 2: least N_A N_B for which the network is asked
 };
 
 __device__ inline WalkCell load_cell(const WalkRec* __restrict__ r, int32_t c) {
@@ -99,7 +100,7 @@ __device__ inline int decide(const TreeView& t, int32_t X, const WalkCell& a, in
         if (e * b.m <= t.eps * a.gmin && e * a.m <= t.eps * b.gmin) return kAccept;
       } else {
         const PairSide A{a.gw, a.m, a.qlev, a.count}, B{b.gw, b.m, b.qlev, b.count};
-        if (learned_accept(t.model, t.eps, t.theta, d, A, a.gmin, B, b.gmin)) return kAccept;
+        if (learned_accept(t.model, t.eps, t.min_work, d, A, a.gmin, B, b.gmin)) return kAccept;
       }
     }
   }
@@ -578,7 +579,7 @@ void walk_start(Ctx& c) {
 int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32_t>& lo,
                     const std::vector<int32_t>& hi, int64_t& far_base, int64_t& near_base) {
   TreeView t{(const WalkRec*)c.walkrec.p, c.theta, c.walk_abs_tol, c.walk_mode, c.opt.error_tol,
-             c.opt.theta_max, (const float*)c.model.p};
+             c.opt.theta_max, (const float*)c.model.p, c.opt.learned_min_work};
   static const bool debug = getenv("AMFMM_DEBUG_WALK") != nullptr;
   const bool learned = c.walk_mode == 2;
   int64_t F = c.frontier;

@@ -129,8 +129,8 @@ LIST_CASES = {
 
 
 @pytest.mark.parametrize("name", sorted(LIST_CASES))
-@pytest.mark.parametrize("eps,b3", [(1e-5, -6.0), (1e-4, -3.0)])
-def test_learned_walk_bit_exact(name, eps, b3):
+@pytest.mark.parametrize("eps,b3,min_work", [(1e-5, -6.0, 1), (1e-4, -3.0, 1), (1e-5, -6.0, 4096)])
+def test_learned_walk_bit_exact(name, eps, b3, min_work):
     """Same model and field input on both sides: the same pairs, bit for bit,
     and the same accelerations to 1e-12."""
     x, y, z, m = LIST_CASES[name]()
@@ -143,9 +143,9 @@ def test_learned_walk_bit_exact(name, eps, b3):
     far0, _ = t.lists()
     feats = t.pair_features(far0) if len(far0) else None
     P = random_model(10, feats, b3)
-    t.walk_learned(eps, 0.8, 0.5, gmag, P)
+    t.walk_learned(eps, 0.8, 0.5, gmag, P, min_work)
     ofar, onear = t.lists()
-    s = amfmm.Solver(criterion=amfmm.LEARNED, error_tol=eps, theta_max=0.8)
+    s = amfmm.Solver(criterion=amfmm.LEARNED, error_tol=eps, theta_max=0.8, learned_min_work=min_work)
     s.set_model(P)
     X, Y, Z, M = to_dev(x, y, z, m)
     G, = to_dev(gmag)

@@ -159,9 +159,9 @@ def test_features_symmetric_and_in_range(plummer_tree):
     assert np.all(f[:, 0] <= 0.7 * (1 + 1e-6)) and np.all(f[:, 0] >= 0)
     assert np.all((f[:, 2] >= 0) & (f[:, 2] <= 1) & (f[:, 3] >= 0) & (f[:, 3] <= 1))
     assert np.all((f[:, 4] >= 0) & (f[:, 4] <= 1) & (f[:, 5] >= 0) & (f[:, 5] <= 1))
-    # the counts feature is the plog2 of N_A N_B
+    # the counts feature is the plog2 of N_A N_B (counts saturated at 1024)
     c = t.cells()
-    na, nb = c["count"][far[:, 0]], c["count"][far[:, 1]]
+    na, nb = np.minimum(c["count"][far[:, 0]], 1024), np.minimum(c["count"][far[:, 1]], 1024)
     ref = np.array([orc.plog2(float(u) * float(v)) for u, v in zip(na, nb)], np.float32)
     assert np.array_equal(f[:, 6], ref)
 
@@ -239,31 +239,38 @@ def test_learned_walk_gating(plummer_tree):
         P[4800] = out
         P[4825:4833] = 1e30
         P[4817:4825] = -1e30
-        t.walk_learned(eps, 0.7, 0.5, g, P)
+        t.walk_learned(eps, 0.7, 0.5, g, P, min_work=1)
         got = t.lists()
         t.walk_field(eps * factor, 0.7, g)
         ref = t.lists()
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
 
 
-def test_learned_walk_out_of_range_falls_back_to_theta(plummer_tree):
-    """With an empty training range every band pair is decided by the opening
-    angle; the result still covers every particle pair exactly once."""
-    (x, y, z, m), t, g = plummer_tree
+def test_learned_walk_small_pairs_take_the_analytic_factor(plummer_tree):
+    """With min_work above every N_A N_B the network is never asked: the
+    decision is q^3 <= u, the analytic error-estimate walk."""
+    _, t, g = plummer_tree
     P = np.zeros(orc.MLP_MODEL, np.float32)
+    P[4800] = -1000.0
+    P[4825:4833] = 1e30
+    P[4817:4825] = -1e30
+    t.walk_learned(2e-5, 0.7, 0.5, g, P, min_work=1 << 40)
+    got = t.lists()
+    t.walk_field(2e-5, 0.7, g)
+    ref = t.lists()
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+
+
+def test_learned_walk_out_of_range_takes_the_analytic_factor(plummer_tree):
+    """With an empty training range every band pair takes the analytic factor:
+    the error-estimate walk."""
+    _, t, g = plummer_tree
+    P = np.zeros(orc.MLP_MODEL, np.float32)
+    P[4800] = -1000.0
     P[4817:4825] = 1e30
     P[4825:4833] = -1e30
-    t.walk_learned(1e-5, 0.7, 0.4, g, P)
-    far, near = t.lists()
-    c = t.cells()
-    n = len(x)
-    # coverage: sum over pairs of N_A N_B (self pairs N(N-1)/2) = n(n-1)/2
-    cnt = c["count"].astype(np.int64)
-    tot = (cnt[far[:, 0]] * cnt[far[:, 1]]).sum()
-    same = near[:, 0] == near[:, 1]
-    tot += (cnt[near[~same, 0]] * cnt[near[~same, 1]]).sum()
-    tot += (cnt[near[same, 0]] * (cnt[near[same, 0]] - 1) // 2).sum()
-    assert tot == n * (n - 1) // 2
-    f = t.pair_features(far)
-    t.walk_field(1e-5, 0.7, g)
-    assert not np.array_equal(far, t.lists()[0]) or len(f) == 0
+    t.walk_learned(2e-5, 0.7, 0.4, g, P, min_work=1)
+    got = t.lists()
+    t.walk_field(2e-5, 0.7, g)
+    ref = t.lists()
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])

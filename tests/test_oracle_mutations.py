@@ -44,6 +44,8 @@ MUTATIONS = {
     "field_scale_no_floor": ("std::max(gmin[ci], 0.1 * (gsum[ci] / (double)t->cells[ci].count))",
                              "std::max(gmin[ci], 1.0 * (gsum[ci] / (double)t->cells[ci].count))"),
     "learned_gate_low": ("if (q3 <= 0.25 * u) return true;", "if (q3 <= 1.0 * u) return true;"),
+    "learned_small_pairs_accept_all": ("if (t.cells[a].count * t.cells[b].count < t.min_work) return q3 <= u;",
+                                       "if (t.cells[a].count * t.cells[b].count < t.min_work) return true;"),
     "learned_one_cell": ("double u = std::min((t.eps * t.fscale[a]) * (d * d) / B.M, (t.eps * t.fscale[b]) * (d * d) / A.M);",
                          "double u = (t.eps * t.fscale[a]) * (d * d) / B.M;"),
     "label_own_mass": ("double e = std::sqrt((ex * ex + ey * ey) + ez * ez) / (MS.M / (d * d));",
