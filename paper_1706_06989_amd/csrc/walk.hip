@@ -23,6 +23,7 @@
 #include <cstdio>
 #include <cstdlib>
 
+#include "device_math.h"
 #include "internal.h"
 #include "learned.h"
 
@@ -55,6 +56,7 @@ struct TreeView {
   double theta_max;  // modes 1, 2: (R_A + R_B)/d above this never accepted
   const float* model;  // mode 2: network (BF16-rounded weights)
   int64_t min_work;    // mode 2: least N_A N_B for which the network is asked
+  const double* mmin;  // modes 1, 2: smallest leaf mass below each cell
 };
 
 __device__ inline WalkCell load_cell(const WalkRec* __restrict__ r, int32_t c) {
@@ -114,6 +116,18 @@ __device__ inline int decide(const TreeView& t, int32_t X, const WalkCell& a, in
     // test safe against rounding of d and of the centres.
     const double cut = t.mode == 0 ? t.theta : t.theta_max;
     if ((d + b.gw) * (1.0 + 1e-12) + t.abs_tol < a.gw / cut) return kNear;
+    if (t.mode != 0) {
+      // Error-estimate modes: a cell Y' below Y has d' <= d + R_Y, mass at
+      // least the smallest leaf mass m below Y, and R_X + R_Y' >= R_X, so its
+      // estimate e' M_Y' = (R_X + R_Y')^3 M_Y' / d'^5 is at least
+      // R_X^3 m / (d + R_Y)^5.  When that exceeds what any rule accepts (eps
+      // s_X, times the network's upper gate in mode 2) no pair below Y is
+      // accepted with X either: Y is a near-field source as a whole.
+      const double D = (d + b.gw + t.abs_tol) * (1.0 + 1e-9);
+      const double D2 = D * D;
+      const double lim = (t.mode == 2 ? kGateHi : 1.0) * t.eps * a.gmin;
+      if ((a.gw * a.gw * a.gw) * t.mmin[Y] > lim * (D2 * D2 * D)) return kNear;
+    }
     return kSplitY;
   }
   if (ly) return kSplitX;
@@ -231,6 +245,27 @@ __global__ void __launch_bounds__(kBS) k_gscale(int32_t nc, const int32_t* __res
                                                 double* __restrict__ gscale) {
   int32_t c = blockIdx.x * kBS + threadIdx.x;
   if (c < nc) gscale[c] = fmax(gmn[c], kFieldFloor * (gsum[c] / (double)cnt[c]));
+}
+
+// smallest leaf mass below every cell (leaves: their mass; parents: the
+// smallest over their children), for the subtree near-field test
+__global__ void __launch_bounds__(kBS) k_mmin_leaves(const int32_t* __restrict__ leaves, int32_t nleaves,
+                                                     const double* __restrict__ mom, double* __restrict__ mmin) {
+  int32_t i = blockIdx.x * kBS + threadIdx.x;
+  if (i >= nleaves) return;
+  const int32_t c = leaves[i];
+  mmin[c] = mom[(int64_t)c * kMom];
+}
+
+__global__ void __launch_bounds__(kBS) k_mmin_up(int32_t c0, int32_t nl, const int32_t* __restrict__ ch0,
+                                                 const int32_t* __restrict__ nch, double* __restrict__ mmin) {
+  int32_t i = blockIdx.x * kBS + threadIdx.x;
+  if (i >= nl) return;
+  const int32_t c = c0 + i;
+  if (nch[c] == 0) return;
+  double w = INFINITY;
+  for (int32_t q = ch0[c]; q < ch0[c] + nch[c]; ++q) w = fmin(w, mmin[q]);
+  mmin[c] = w;
 }
 
 __device__ inline int32_t wave_excl_scan(int32_t v, int32_t* total) {
@@ -518,9 +553,17 @@ void walk_prepare(Ctx& c, double theta) {
   if (c.field && c.opt.criterion == AMFMM_ESTIMATE) c.walk_mode = 1;
   if (c.field && c.opt.criterion == AMFMM_LEARNED && c.model.p) c.walk_mode = 2;
   if (c.walk_mode != 0) {
-    double* gs = (double*)ensure(c, c.gmin, 3 * sizeof(double) * nc);
+    double* gs = (double*)ensure(c, c.gmin, 4 * sizeof(double) * nc);
     double* gm = gs + nc;
     double* g = gm + nc;
+    double* mm = g + nc;
+    hipLaunchKernelGGL(k_mmin_leaves, dim3(blocks_for(c.nleaves, kBS)), dim3(kBS), 0, c.stream,
+                       as<int32_t>(c.leaves), c.nleaves, (const double*)c.mom.p, mm);
+    for (int l = c.depth - 1; l >= 0; --l) {
+      const int32_t c0 = c.level_start[l], nl = c.level_start[l + 1] - c0;
+      hipLaunchKernelGGL(k_mmin_up, dim3(blocks_for(nl, kBS)), dim3(kBS), 0, c.stream, c0, nl,
+                         as<int32_t>(c.c_child0), as<int32_t>(c.c_nchild), mm);
+    }
     hipLaunchKernelGGL(k_gsum_leaves, dim3(blocks_for(c.nleaves, kBS)), dim3(kBS), 0, c.stream,
                        as<int32_t>(c.leaves), c.nleaves, as<int32_t>(c.c_begin), as<int32_t>(c.c_count),
                        as<int32_t>(c.perm), c.field, c.field_y, c.field_z, gs, gm);
@@ -579,7 +622,8 @@ void walk_start(Ctx& c) {
 int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32_t>& lo,
                     const std::vector<int32_t>& hi, int64_t& far_base, int64_t& near_base) {
   TreeView t{(const WalkRec*)c.walkrec.p, c.theta, c.walk_abs_tol, c.walk_mode, c.opt.error_tol,
-             c.opt.theta_max, (const float*)c.model.p, c.opt.learned_min_work};
+             c.opt.theta_max, (const float*)c.model.p, c.opt.learned_min_work,
+             c.walk_mode != 0 ? (const double*)c.gmin.p + 3 * (size_t)c.ncells : nullptr};
   static const bool debug = getenv("AMFMM_DEBUG_WALK") != nullptr;
   const bool learned = c.walk_mode == 2;
   int64_t F = c.frontier;
