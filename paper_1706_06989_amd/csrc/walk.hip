@@ -447,7 +447,9 @@ __global__ void __launch_bounds__(kBS) k_walk_count(TreeView t, int32_t c0, int6
                                                     int32_t* __restrict__ gq, int32_t qcap, unsigned long long* dbg) {
   __shared__ int32_t queue[kBS / 64][kQ];
   const int lane = threadIdx.x & 63;
-  const int64_t k = (int64_t)blockIdx.x * (kBS / 64) + (threadIdx.x >> 6);
+  // wave-uniform (readfirstlane): the cell's record and bookkeeping are
+  // loaded once per wave into scalar registers
+  const int64_t k = uniform((int32_t)(blockIdx.x * (kBS / 64) + (threadIdx.x >> 6)));
   if (k >= kn) return;
   const int32_t i = kcell[k];
   const int32_t X = c0 + i;
@@ -513,7 +515,9 @@ __global__ void __launch_bounds__(kBS) k_walk_emit(TreeView t, int32_t c0, int64
                                                    int32_t* __restrict__ near_src, int32_t* __restrict__ fy_n,
                                                    int32_t* __restrict__ gq, int32_t qcap) {
   __shared__ int32_t queue[kBS / 64][kQ];
-  const int64_t k = (int64_t)blockIdx.x * (kBS / 64) + (threadIdx.x >> 6);
+  // wave-uniform (readfirstlane): the cell's record and bookkeeping are
+  // loaded once per wave into scalar registers
+  const int64_t k = uniform((int32_t)(blockIdx.x * (kBS / 64) + (threadIdx.x >> 6)));
   if (k >= kn) return;
   const int32_t i = kcell[k];
   const int32_t X = c0 + i;
