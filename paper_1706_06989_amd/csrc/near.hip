@@ -169,14 +169,24 @@ __global__ void __launch_bounds__(kBS) k_near(int32_t nleaves, const int32_t* __
       const int take = __popcll(fits);  // prefix is monotone: leading lanes fit
       int fill;
       if (take > 0) {
-        if (lane < take) {
-          if (MIXED) {
-            for (int32_t j = 0; j < cl; ++j) buf32[inc - cl + j] = offset32(pos[bl + j], gx);
-          } else {
-            for (int32_t j = 0; j < cl; ++j) buf[inc - cl + j] = pos[bl + j];
+        fill = __shfl(inc, take - 1, 64);
+        // Cooperative copy: buffer slot v belongs to the entry e with
+        // end[e-1] <= v < end[e] (binary search over the lanes' prefix ends),
+        // so consecutive lanes copy consecutive particles of an entry.
+        const int32_t endx = lane < take ? inc : INT32_MAX;
+        const int32_t startx = inc - cl;
+        for (int32_t v0 = 0; v0 < fill; v0 += 64) {
+          const int32_t v = v0 + lane;
+          int e = 0;
+#pragma unroll
+          for (int st = 32; st >= 1; st >>= 1)
+            if (__shfl(endx, e + st - 1, 64) <= v) e += st;
+          const int32_t s0 = __shfl(startx, e, 64), b0 = __shfl(bl, e, 64);
+          if (v < fill) {
+            if (MIXED) buf32[v] = offset32(pos[b0 + v - s0], gx);
+            else buf[v] = pos[b0 + v - s0];
           }
         }
-        fill = __shfl(inc, take - 1, 64);
         if (tb == b) nsrc_particles += fill;
         k += take;
       } else {
@@ -221,20 +231,18 @@ __global__ void __launch_bounds__(kBS) k_near(int32_t nleaves, const int32_t* __
     // lane s < 4 of group g finishes target g*4 + s
     const int t = g * kTG + s;
     if (active && s < kTG && t < ntc) {
-      double px = tx[0], py = ty[0], pz = tz[0], sx = fx[0], sy = fy[0], sz = fz[0], sp = ph[0];
+      double sx = fx[0], sy = fy[0], sz = fz[0], sp = ph[0];
 #pragma unroll
       for (int u = 1; u < kTG; ++u) {
         if (s == u) {
-          px = tx[u];
-          py = ty[u];
-          pz = tz[u];
           sx = fx[u];
           sy = fy[u];
           sz = fz[u];
           sp = ph[u];
         }
       }
-      const double x[3] = {px - gx.x, py - gx.y, pz - gx.z};
+      const double4 pt = pos[tb + t];  // reloaded: the mixed path keeps no FP64 copy
+      const double x[3] = {pt.x - gx.x, pt.y - gx.y, pt.z - gx.z};
       double gl[3], phi;
       eval_local(L, x, gl, phi);
       const int32_t o = perm[tb + t];
