@@ -410,12 +410,20 @@ bool accept(const orc_tree& t, int32_t a, int32_t b) {
     return d > 0.0 && d >= rhs;
   }
   double r = A.Rmax + B.Rmax;
+  if (t.mode == 1) {
+    // error estimate (R_A + R_B)^3 M_other / d^5 against eps times each
+    // cell's field scale, and (R_A + R_B) <= theta_max d, in product form
+    // (squared, no division or root) with d2 = d^2
+    double d2 = (dx * dx + dy * dy) + dz * dz;
+    if (!(d2 > 0.0 && r * r <= (t.theta_max * t.theta_max) * d2)) return false;
+    double r2 = r * r;
+    double r6 = (r2 * r2) * r2;
+    double d10 = ((d2 * d2) * (d2 * d2)) * d2;
+    double wa = t.eps * t.fscale[a], wb = t.eps * t.fscale[b];
+    return r6 * (B.M * B.M) <= (wa * wa) * d10 && r6 * (A.M * A.M) <= (wb * wb) * d10;
+  }
   if (!(d > 0.0 && r <= t.theta_max * d)) return false;
   double q = r / d;
-  if (t.mode == 1) {
-    double e = (q * q * q) / (d * d);
-    return e * B.M <= t.eps * t.fscale[a] && e * A.M <= t.eps * t.fscale[b];
-  }
   // Learned: the error of the pair on A is f M_B / d^2 with f the predicted
   // error factor; accept when f <= u = min over both cells of eps s d^2 / M.
   // Where the analytic factor q^3 sits far from u the network is not asked:

@@ -115,6 +115,19 @@ __device__ inline void far_correction(const double R[3], double MX, const double
   }
 }
 
+// Inclusive prefix sum over the 64 lanes with DPP row shifts and row
+// broadcasts (all lanes active): four shifts within each row of 16, then row
+// 0's total into row 1 and row 2's into row 3, then row 1's into rows 2, 3.
+__device__ inline int32_t wave_incl_scan(int32_t v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return v;
+}
+
 template <typename T>
 __device__ inline T uniform(T v) {
   return (T)__builtin_amdgcn_readfirstlane((int)v);

@@ -159,12 +159,7 @@ __global__ void __launch_bounds__(kBS) k_near(int32_t nleaves, const int32_t* __
       const int32_t Yl = kk < nsc ? nsrc[st + kk] : -1;
       const int32_t bl = Yl >= 0 ? beg[Yl] : 0;
       const int32_t cl = Yl >= 0 ? cnt[Yl] : 0;
-      int32_t inc = cl;  // inclusive prefix over lanes
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const int32_t o = __shfl_up(inc, d, 64);
-        if (lane >= d) inc += o;
-      }
+      const int32_t inc = wave_incl_scan(cl);  // inclusive prefix over lanes
       const uint64_t fits = __ballot(Yl >= 0 && inc <= cap);
       const int take = __popcll(fits);  // prefix is monotone: leading lanes fit
       int fill;

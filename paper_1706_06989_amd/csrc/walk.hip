@@ -54,6 +54,7 @@ struct TreeView {
   int mode;          // 0: opening angle theta; 1: error estimate; 2: learned
   double eps;        // modes 1, 2: accepted error per pair, relative to each cell's field
   double theta_max;  // modes 1, 2: (R_A + R_B)/d above this never accepted
+  double theta_max2; // theta_max^2
   const float* model;  // mode 2: network (BF16-rounded weights)
   int64_t min_work;    // mode 2: least N_A N_B for which the network is asked
   const double* mmin;  // modes 1, 2: smallest leaf mass below each cell
@@ -85,25 +86,30 @@ __device__ inline WalkCell load_cell(const WalkRec* __restrict__ r, int32_t c) {
 template <bool LEARNED>
 __device__ inline int decide(const TreeView& t, int32_t X, const WalkCell& a, int32_t Y, const WalkCell& b) {
   const double dx = a.gx - b.gx, dy = a.gy - b.gy, dz = a.gz - b.gz;
-  const double d = sqrt((dx * dx + dy * dy) + dz * dz);
+  const double d2 = (dx * dx + dy * dy) + dz * dz;
+  const double r = a.gw + b.gw;
   if (t.mode == 0) {
-    const double rhs = (a.gw + b.gw) / t.theta;
+    const double d = sqrt(d2);
+    const double rhs = r / t.theta;
     if (d > 0.0 && d >= rhs) return kAccept;
-  } else {
+  } else if (!LEARNED || t.mode == 1) {
     // The force error of a quadrupole-order pair scales as M_other r^3 / d^5
     // with r = R_A + R_B; accept when that estimate stays below eps times the
-    // field scale of each cell (both cells: a symmetric decision).  Mode 2
-    // asks the network where the estimate is close to the bound.
-    const double r = a.gw + b.gw;
+    // field scale of each cell (both cells: a symmetric decision) and r <=
+    // theta_max d.  Product form, squared: no division or root.
+    if (d2 > 0.0 && r * r <= t.theta_max2 * d2) {
+      const double r2 = r * r;
+      const double r6 = (r2 * r2) * r2;
+      const double d10 = ((d2 * d2) * (d2 * d2)) * d2;
+      const double wa = t.eps * a.gmin, wb = t.eps * b.gmin;
+      if (r6 * (b.m * b.m) <= (wa * wa) * d10 && r6 * (a.m * a.m) <= (wb * wb) * d10) return kAccept;
+    }
+  } else {
+    // mode 2: the network decides where the estimate is close to the bound
+    const double d = sqrt(d2);
     if (d > 0.0 && r <= t.theta_max * d) {
-      if (!LEARNED || t.mode == 1) {
-        const double q = r / d;
-        const double e = (q * q * q) / (d * d);
-        if (e * b.m <= t.eps * a.gmin && e * a.m <= t.eps * b.gmin) return kAccept;
-      } else {
-        const PairSide A{a.gw, a.m, a.qlev, a.count}, B{b.gw, b.m, b.qlev, b.count};
-        if (learned_accept(t.model, t.eps, t.min_work, d, A, a.gmin, B, b.gmin)) return kAccept;
-      }
+      const PairSide A{a.gw, a.m, a.qlev, a.count}, B{b.gw, b.m, b.qlev, b.count};
+      if (learned_accept(t.model, t.eps, t.min_work, d, A, a.gmin, B, b.gmin)) return kAccept;
     }
   }
   const bool lx = a.nch == 0, ly = b.nch == 0;
@@ -115,6 +121,7 @@ __device__ inline int decide(const TreeView& t, int32_t X, const WalkCell& a, in
     // as a near-field source (its whole particle range).  The margin makes the
     // test safe against rounding of d and of the centres.
     const double cut = t.mode == 0 ? t.theta : t.theta_max;
+    const double d = sqrt(d2);
     if ((d + b.gw) * (1.0 + 1e-12) + t.abs_tol < a.gw / cut) return kNear;
     if (t.mode != 0) {
       // Error-estimate modes: a cell Y' below Y has d' <= d + R_Y, mass at
@@ -269,14 +276,8 @@ __global__ void __launch_bounds__(kBS) k_mmin_up(int32_t c0, int32_t nl, const i
 }
 
 __device__ inline int32_t wave_excl_scan(int32_t v, int32_t* total) {
-  const int lane = threadIdx.x & 63;
-  int32_t inc = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int32_t o = __shfl_up(inc, d, 64);
-    if (lane >= d) inc += o;
-  }
-  *total = __shfl(inc, 63, 64);
+  const int32_t inc = wave_incl_scan(v);
+  *total = __builtin_amdgcn_readlane(inc, 63);
   return inc - v;
 }
 
@@ -626,7 +627,7 @@ void walk_start(Ctx& c) {
 int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32_t>& lo,
                     const std::vector<int32_t>& hi, int64_t& far_base, int64_t& near_base) {
   TreeView t{(const WalkRec*)c.walkrec.p, c.theta, c.walk_abs_tol, c.walk_mode, c.opt.error_tol,
-             c.opt.theta_max, (const float*)c.model.p, c.opt.learned_min_work,
+             c.opt.theta_max, c.opt.theta_max * c.opt.theta_max, (const float*)c.model.p, c.opt.learned_min_work,
              c.walk_mode != 0 ? (const double*)c.gmin.p + 3 * (size_t)c.ncells : nullptr};
   static const bool debug = getenv("AMFMM_DEBUG_WALK") != nullptr;
   const bool learned = c.walk_mode == 2;

@@ -50,8 +50,9 @@ MUTATIONS = {
                        "if (!(cur.count >= n_crit && lev < max_level)) continue;"),
     "near_field_no_reaction": ("gx[j] -= t->m[i] * dx / r3;", "gx[j] -= 0.0 * dx / r3;"),
     "potential_quadratic_half": ("return p + 0.5 * s2 + (1.0 / 6.0) * s3;", "return p + s2 + (1.0 / 6.0) * s3;"),
-    "field_one_sided": ("return e * B.M <= t.eps * t.fscale[a] && e * A.M <= t.eps * t.fscale[b];",
-                        "return e * B.M <= t.eps * t.fscale[a];"),
+    "field_one_sided": ("return r6 * (B.M * B.M) <= (wa * wa) * d10 && r6 * (A.M * A.M) <= (wb * wb) * d10;",
+                        "return r6 * (B.M * B.M) <= (wa * wa) * d10;"),
+    "field_cube_not_sixth": ("double r6 = (r2 * r2) * r2;", "double r6 = r2 * r2;"),
     "field_scale_no_floor": ("std::max(gmin[ci], 0.1 * (gsum[ci] / (double)t->cells[ci].count))",
                              "std::max(gmin[ci], 1.0 * (gsum[ci] / (double)t->cells[ci].count))"),
     "learned_gate_low": ("if (q3 <= 0.25 * u) return true;", "if (q3 <= 1.0 * u) return true;"),
