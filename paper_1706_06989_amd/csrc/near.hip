@@ -26,7 +26,7 @@ namespace {
 constexpr int kBS = 256;
 constexpr int kWaves = kBS / 64;
 constexpr int kTG = 4;    // targets per lane
-constexpr int kCap = 384; // source particles per wave staged in LDS
+constexpr int kCap = 320; // source particles per wave staged in LDS (4 workgroups per CU)
 
 // make this wave's LDS writes visible to its other lanes before they read
 __device__ inline void wave_sync() {
@@ -102,7 +102,7 @@ __device__ inline float4 offset32(const double4 p, const double4 c) {
 
 // leaves == nullptr: the targets are the leaves among cells [c_lo, c_lo + nleaves)
 template <bool MIXED>
-__global__ void __launch_bounds__(kBS) k_near(int32_t nleaves, const int32_t* __restrict__ leaves, int32_t c_lo,
+__global__ void __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(4))) k_near(int32_t nleaves, const int32_t* __restrict__ leaves, int32_t c_lo,
                                               const int32_t* __restrict__ nch,
                                               const int32_t* __restrict__ beg, const int32_t* __restrict__ cnt,
                                               const double4* __restrict__ pos, const double4* __restrict__ geo,
