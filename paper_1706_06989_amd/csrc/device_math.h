@@ -128,6 +128,19 @@ __device__ inline int32_t wave_incl_scan(int32_t v) {
   return v;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (block b on XCD
+// b mod 8), each with its own L2.  This bijection on [0, nb) gives each XCD
+// runs of kRun consecutive work blocks (runs dealt round-robin, so the load
+// stays balanced), so that neighbouring cells, which share sources, are
+// served by the same L2.  Blocks past the last full round keep their index.
+constexpr uint32_t kXcds = 8, kRun = 32;
+__device__ inline uint32_t xcd_block(uint32_t b, uint32_t nb) {
+  const uint32_t full = nb / (kXcds * kRun) * (kXcds * kRun);
+  if (b >= full) return b;
+  const uint32_t x = b % kXcds, q = b / kXcds;
+  return ((q / kRun) * kXcds + x) * kRun + q % kRun;
+}
+
 template <typename T>
 __device__ inline T uniform(T v) {
   return (T)__builtin_amdgcn_readfirstlane((int)v);

@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(kBS) k_far(int32_t c_lo, int32_t nc, const dou
                                              const int64_t* __restrict__ fstart, const int32_t* __restrict__ fcount,
                                              const int32_t* __restrict__ fsrc, double* __restrict__ loc) {
   const int lane = threadIdx.x & 63;
-  const int32_t Xi = uniform((int32_t)(blockIdx.x * kWaves + (threadIdx.x >> 6)));
+  const int32_t Xi = uniform((int32_t)(xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6)));
   if (Xi >= nc) return;
   const int32_t X = c_lo + Xi;
   const int32_t cnt = fcount[X];

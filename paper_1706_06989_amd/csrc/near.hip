@@ -112,7 +112,7 @@ __global__ void __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(4))) k
                                               double* __restrict__ ay, double* __restrict__ az, double* __restrict__ pot,
                                               unsigned long long* __restrict__ inter) {
   const int lane = threadIdx.x & 63;
-  const int32_t li = uniform((int32_t)(blockIdx.x * kWaves + (threadIdx.x >> 6)));
+  const int32_t li = uniform((int32_t)(xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6)));
   if (li >= nleaves) return;
   const int32_t X = uniform(leaves ? leaves[li] : c_lo + li);
   if (!leaves && uniform(nch[X]) != 0) return;

@@ -450,7 +450,7 @@ __global__ void __launch_bounds__(kBS) k_walk_count(TreeView t, int32_t c0, int6
   const int lane = threadIdx.x & 63;
   // wave-uniform (readfirstlane): the cell's record and bookkeeping are
   // loaded once per wave into scalar registers
-  const int64_t k = uniform((int32_t)(blockIdx.x * (kBS / 64) + (threadIdx.x >> 6)));
+  const int64_t k = uniform((int32_t)(xcd_block(blockIdx.x, gridDim.x) * (kBS / 64) + (threadIdx.x >> 6)));
   if (k >= kn) return;
   const int32_t i = kcell[k];
   const int32_t X = c0 + i;
@@ -518,7 +518,7 @@ __global__ void __launch_bounds__(kBS) k_walk_emit(TreeView t, int32_t c0, int64
   __shared__ int32_t queue[kBS / 64][kQ];
   // wave-uniform (readfirstlane): the cell's record and bookkeeping are
   // loaded once per wave into scalar registers
-  const int64_t k = uniform((int32_t)(blockIdx.x * (kBS / 64) + (threadIdx.x >> 6)));
+  const int64_t k = uniform((int32_t)(xcd_block(blockIdx.x, gridDim.x) * (kBS / 64) + (threadIdx.x >> 6)));
   if (k >= kn) return;
   const int32_t i = kcell[k];
   const int32_t X = c0 + i;
