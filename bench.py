@@ -1,20 +1,21 @@
 """Benchmark: particles/s of the full gravity solve on one MI355X.
 
-One step = the whole force solve on inputs already resident in HBM.  With
-the error-estimate criterion (default) a step is two amfmm_solve_gravity
-calls: a pilot solve with the geometric criterion (theta = 0.5) whose
-accelerations give every cell its field scale, then the solve whose pair
-selection keeps each pair's estimated error below eps times that scale.
-Each solve covers validation, bounding cube, keys, sort, tree, upward pass,
-walk, far field, push-down, near field, evaluation at the particles and the
-unsort.  Outputs one JSON line.  The error of the timed configuration is
-measured outside the timed region against direct summation at a seeded
-sample of targets.
+One step = the whole force solve on inputs already resident in HBM.  With an
+error-estimate criterion (default) a step is two amfmm_solve_gravity calls: a
+pilot solve with the geometric criterion (theta = 0.5) whose accelerations
+give every cell its field scale, then the solve whose pair selection keeps
+each pair's estimated error below eps times that scale.  Each solve covers
+validation, bounding cube, keys, sort, tree, upward pass, walk, far field,
+push-down, near field, evaluation at the particles and the unsort.  Outputs
+one JSON line.  The error of the timed configuration is measured outside the
+timed region against direct summation at a seeded sample of targets.
 
 Workload: 16,777,216-particle Plummer sphere (scale radius 1, mass 1,
-truncated at 20, seed 4, equal masses), G = 1, n_crit = 25, TC variant.
+truncated at 20, seed 4, equal masses), G = 1, n_crit = 25, TC variant,
+mixed precision (FP32 pair terms, FP64 accumulation and correction).
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -25,10 +26,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "particles/s full force solve, N=16M Plummer, at 1e-4 p99 force error"
-PEAK_FP64_TFLOPS = 78.6  # MI355X vector FP64
-PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (published; packed)
+PEAK_FP64_TFLOPS = 78.6  # MI355X vector FP64 (non-packed FP32 issues at the same rate)
 PEAK_HBM_GBS = 8000.0
 NEAR_FLOPS = 20  # per directed particle interaction (3 sub, 5 r^2, 1 rsqrt, 2 r^-3, 1 mass, 6 acc, 2 pot)
+# per directed far-field pair (cell-pair evaluation of eqs. 2-4 with the
+# correction of eq. 7 in closed form; counted from the kernel's arithmetic,
+# fma = 2): R (3) + coefficients (147 with a one-instruction FP32 rsqrt, 156
+# with the refined FP64 one) + correction (157, FP64)
+FAR_FLOPS = {"fp64": 3 + 156 + 157, "mixed": 3 + 147 + 157}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_far_traffic_plummer16m.json")
+FAR_SOURCES = [os.path.join(ROOT, "paper_1706_06989_amd", "csrc", f) for f in ("eval.hip", "device_math.h")]
 
 
 def parse():
@@ -39,22 +46,42 @@ def parse():
     p.add_argument("--n", type=int, default=1 << 24)
     p.add_argument("--theta", type=float, default=0.5,
                    help="opening angle (geometric criterion; also the pilot solve)")
-    p.add_argument("--criterion", choices=["geometric", "field"], default="field")
+    p.add_argument("--criterion", choices=["geometric", "estimate", "learned"], default="estimate")
     p.add_argument("--eps", type=float, default=1.5e-7,
                    help="error-estimate criterion: accepted pair error relative to the field scale")
     p.add_argument("--theta-max", type=float, default=0.5)
-    p.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    p.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
     p.add_argument("--variant", choices=["UC", "TC", "TCO"], default="TC")
     p.add_argument("--error-sample", type=int, default=4096)
-    p.add_argument("--cpu-n", type=int, default=1 << 15, help="oracle sample size (0 = skip)")
+    p.add_argument("--cpu-n", type=int, default=1 << 16, help="oracle sample size (0 = skip)")
     p.add_argument("--copy-calibration", action="store_true",
-                   help="also run a plain device copy of known size (for HBM counter scaling)")
+                   help="also run a plain device copy of known size (scale for HBM byte counters)")
     return p.parse_args()
 
 
-def cpu_baseline(n, theta, field, eps, theta_max, seed=4):
+def source_hash():
+    h = hashlib.sha256()
+    for f in FAR_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def far_traffic():
+    """HBM bytes per k_far launch from the committed counter summary (FETCH_SIZE
+    and WRITE_SIZE, scaled by the copy calibration), or None when absent or
+    taken on other far-field sources."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(n, theta, criterion, eps, theta_max, seed=4):
     """The CPU oracle as it stands (single thread) on a smaller Plummer sphere
-    of the same generator, same configuration: particles/s of its full solve
+    of the same generator and configuration: particles/s of its full solve
     (with the error-estimate criterion: its own pilot solve, then the solve)."""
     import numpy as np
 
@@ -64,16 +91,17 @@ def cpu_baseline(n, theta, field, eps, theta_max, seed=4):
     x, y, z, m = W.plummer(n, seed=seed)
     t0 = time.perf_counter()
     a, _ = orc.solve(x, y, z, m, theta=theta, variant=orc.TC)
-    if field:
+    if criterion != "geometric":
         t = orc.Tree(x, y, z, m)
         t.compute_moments()
         t.walk_field(eps, theta_max, np.linalg.norm(a, axis=0))
         t.evaluate(orc.TC)
     dt = time.perf_counter() - t0
-    what = (f"pilot theta={theta} + error-estimate solve eps={eps}" if field else f"theta={theta}")
+    what = (f"pilot theta={theta} + error-estimate solve eps={eps} theta_max={theta_max}"
+            if criterion != "geometric" else f"theta={theta}")
     return {"value": n / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
             "sample": f"full oracle solve (tree, moments, walk, eqs. 2-4 at every particle, near "
-                      f"field) of a {n}-particle Plummer sphere, same generator, {what}, TC, "
+                      f"field) of a {n}-particle Plummer sphere, same generator, {what}, TC, FP64, "
                       f"single thread, {dt:.1f} s"}
 
 
@@ -91,14 +119,26 @@ def main():
 
     variant = {"UC": amfmm.UC, "TC": amfmm.TC, "TCO": amfmm.TCO}[a.variant]
     prec = amfmm.FP64 if a.precision == "fp64" else amfmm.MIXED
-    field = a.criterion == "field"
+    field = a.criterion != "geometric"
+    model_info = None
+    model = None
+    if a.criterion == "learned":
+        # trained on the GPU before the timed region (library kernels)
+        from paper_1706_06989_amd import learned
+        t0 = time.perf_counter()
+        f, lab = learned.training_set(n_plummer=1 << 20)
+        model, losses = learned.train(f, lab)
+        model_info = {"pairs": int(len(lab)), "loss": [losses[0], losses[-1]],
+                      "train_s": round(time.perf_counter() - t0, 2)}
     x, y, z, m = W.plummer(a.n, seed=4)
     X, Y, Z, M = (torch.from_numpy(v).to("cuda") for v in (x, y, z, m))
     del x, y, z, m
+    crit = {"geometric": amfmm.GEOMETRIC, "estimate": amfmm.ESTIMATE, "learned": amfmm.LEARNED}[a.criterion]
     pilot = amfmm.Solver(variant=variant, precision=prec)
-    solver = amfmm.Solver(variant=variant, precision=prec,
-                          criterion=amfmm.ESTIMATE if field else amfmm.GEOMETRIC,
-                          error_tol=a.eps, theta_max=a.theta_max)
+    solver = amfmm.Solver(variant=variant, precision=prec, criterion=crit, error_tol=a.eps,
+                          theta_max=a.theta_max)
+    if model is not None:
+        solver.set_model(model)
     pout = pilot._outputs(a.n, False)
     out = solver._outputs(a.n, True)
     if field:
@@ -152,22 +192,33 @@ def main():
         pilot_info = {"criterion": "geometric", "theta": a.theta, "ms": round(pphases["total"], 3),
                       "p99_rel_force_error": float(np.percentile(pe, 99))}
 
-    # roofline of the dominant kernel (near field: one launch per step)
-    near_ms = phases["near+eval"]
+    # Roofline of the dominant kernel, the far field (k_far: the largest single
+    # kernel of the step), and of the near field beside it.  Both phases are
+    # bracketed by HIP events on the library's stream; a phase holds exactly
+    # that kernel's launches, so phase time / launches is the average launch.
     far_ms = phases["far"]
-    near_tflops = NEAR_FLOPS * counts["near_interactions"] / (near_ms * 1e-3) / 1e12
-    dominant = "near" if near_ms >= far_ms else "far"
-    roof = {"kernel": "k_near (near field + evaluation at particles)", "bound": "alu",
-            "achieved": round(near_tflops, 3),
-            "peak": PEAK_FP64_TFLOPS if a.precision == "fp64" else PEAK_FP32_TFLOPS,
-            "unit": "TFLOP/s", "traffic": None,
-            "algorithmic": f"{NEAR_FLOPS} flop x {counts['near_interactions']} interactions",
-            "avg_launch_ms": round(near_ms, 3), "dominant_phase": dominant}
-    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    near_ms = phases["near+eval"]
+    far_flops = FAR_FLOPS[a.precision] * counts["far_evaluations"]
+    near_flops = NEAR_FLOPS * counts["near_interactions"]
+    far_tf = far_flops / (far_ms * 1e-3) / 1e12
+    near_tf = near_flops / (near_ms * 1e-3) / 1e12
+    tb = far_traffic()
+    roof = {"kernel": "k_far (far field: eqs. 2-4 + correction per directed cell pair)", "bound": "alu",
+            "achieved": round(far_tf, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(far_tf / PEAK_FP64_TFLOPS, 4),
+            "traffic": tb,
+            "algorithmic": f"{FAR_FLOPS[a.precision]} flop x {counts['far_evaluations']} directed pairs "
+                           f"per step over {counts['far_launches']} launches",
+            "avg_launch_ms": round(far_ms / max(1, counts["far_launches"]), 3),
+            "near_field": {"kernel": "k_near", "bound": "alu", "achieved": round(near_tf, 3),
+                           "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                           "frac": round(near_tf / PEAK_FP64_TFLOPS, 4),
+                           "algorithmic": f"{NEAR_FLOPS} flop x {counts['near_interactions']} interactions",
+                           "avg_launch_ms": round(near_ms / max(1, counts["near_launches"]), 3)}}
 
     cpu = None
     if a.cpu_n > 0:
-        cpu = cpu_baseline(a.cpu_n, a.theta, field, a.eps, a.theta_max)
+        cpu = cpu_baseline(a.cpu_n, a.theta, a.criterion, a.eps, a.theta_max)
 
     line = {
         "metric": METRIC, "value": a.n / (ms * 1e-3), "unit": "particles/s", "n_gpus": 1,
@@ -188,12 +239,15 @@ def main():
         "roofline": roof, "cpu_baseline": cpu,
     }
     if a.copy_calibration:
-        buf = torch.empty(1 << 28, dtype=torch.uint8, device="cuda")
+        # 1 GiB read + 1 GiB written by one copy kernel per call
+        buf = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(buf)
         for _ in range(3):
             dst.copy_(buf)
         torch.cuda.synchronize()
         line["copy_calibration_bytes"] = int(buf.numel())
+    if model_info:
+        line["config"]["model"] = model_info
     print(json.dumps(line), flush=True)
 
 

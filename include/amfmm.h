@@ -193,10 +193,12 @@ int amfmm_mlp_train(amfmm_ctx* ctx, int64_t n, const float* feats, const float* 
                     double tau, double* last_loss);
 
 /* ---- introspection (host buffers owned by the caller; synchronising) ---- */
-/* counts[0..7] = cells, depth, far-field pairs, near-field pairs (unordered,
+/* counts[0..9] = cells, depth, far-field pairs, near-field pairs (unordered,
  * as amfmm_get_lists returns them), leaves, particles, near-field particle
- * interactions (directed, i != j), far-field evaluations (directed cell pairs) */
-int amfmm_get_counts(amfmm_ctx* ctx, int64_t* counts8);
+ * interactions (directed, i != j), far-field evaluations (directed cell
+ * pairs), far-field kernel launches and near-field kernel launches of the
+ * last evaluation */
+int amfmm_get_counts(amfmm_ctx* ctx, int64_t* counts10);
 /* sorted keys (n), permutation perm[s] = caller index of sorted particle s (n),
  * and per cell (in (level, first particle) order): level, begin, count,
  * parent, first child (-1 for leaves), child count.  Any pointer may be NULL. */

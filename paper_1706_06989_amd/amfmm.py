@@ -277,10 +277,10 @@ class Solver:
         return float(out[0]), float(out[1])
 
     def get_counts(self):
-        c = np.zeros(8, np.int64)
+        c = np.zeros(10, np.int64)
         self._check(lib().amfmm_get_counts(self._h, _ptr(c, C.c_int64)))
         keys = ["cells", "depth", "far_pairs", "near_pairs", "leaves", "particles",
-                "near_interactions", "far_evaluations"]
+                "near_interactions", "far_evaluations", "far_launches", "near_launches"]
         return dict(zip(keys, (int(v) for v in c)))
 
     def get_tree(self):

@@ -321,6 +321,7 @@ int amfmm_walk(amfmm_ctx* ctx, double theta) {
 }
 
 static void zero_counters(Ctx& c) {
+  c.far_launches = c.near_launches = 0;
   void* p = amfmm::ensure(c, c.counters, 64);
   amfmm::zero_u64(c, (unsigned long long*)p, 8);
 }
@@ -563,6 +564,8 @@ int amfmm_get_counts(amfmm_ctx* ctx, int64_t* counts) {
     counts[5] = c.have_tree ? c.n : 0;
     counts[6] = 0;
     counts[7] = c.far_evals;
+    counts[8] = c.far_launches;
+    counts[9] = c.near_launches;
     if (c.counters.p) {
       unsigned long long h = 0;
       AMFMM_HIP(hipMemcpyAsync(&h, c.counters.p, sizeof(h), hipMemcpyDeviceToHost, c.stream));

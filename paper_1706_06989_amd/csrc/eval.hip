@@ -179,6 +179,7 @@ void far_field(Ctx& c, int32_t c_lo, int32_t c_hi) {
     hipLaunchKernelGGL(kern, grid, dim3(kBS), 0, c.stream, c_lo, nc, (const double4*)c.geo.p, (const double*)c.mom.p,
                        (const int64_t*)c.far_start.p, (const int32_t*)c.far_count.p, (const int32_t*)c.far_src.p, loc);
   };
+  ++c.far_launches;
   const bool mixed = c.opt.precision == AMFMM_MIXED;
   switch (c.opt.variant) {
     case AMFMM_UC: mixed ? args(k_far<AMFMM_UC, true>) : args(k_far<AMFMM_UC, false>); break;

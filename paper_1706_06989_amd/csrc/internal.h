@@ -95,6 +95,7 @@ struct Ctx {
   int grp_cur = 0;
   int64_t* pinned = nullptr;  // small pinned host buffer for read-backs
   int64_t far_evals = 0;      // directed far-field evaluations of the last solve
+  int64_t far_launches = 0, near_launches = 0;  // kernel launches of the last evaluation
   bool batched = false;       // last solve ran batch by batch (lists not kept)
   size_t walk_budget = 0;     // bytes of lists + frontier a walk may take (0 = unlimited)
   // batch size that worked for the last solve of the same size and criterion

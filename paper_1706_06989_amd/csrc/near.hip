@@ -255,6 +255,7 @@ __global__ void __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(4))) k
 void near_field(Ctx& c, const int32_t* leaves, int32_t c_lo, int32_t count, double* ax, double* ay, double* az,
                 double* pot) {
   if (count <= 0) return;
+  ++c.near_launches;
   auto kern = c.opt.precision == AMFMM_MIXED ? k_near<true> : k_near<false>;
   hipLaunchKernelGGL(kern, dim3(blocks_for(count, kWaves)), dim3(kBS), 0, c.stream, count, leaves, c_lo,
                      as<int32_t>(c.c_nchild), as<int32_t>(c.c_begin), as<int32_t>(c.c_count), (const double4*)c.pos4.p,
