@@ -1,0 +1,118 @@
+"""Parity at the configurations' full sizes.
+
+* Plummer 2^20 (seed 2), FP64, theta = 0.5: tree and both interaction lists
+  bit for bit against the oracle, accelerations at 256 sampled particles
+  (evaluated one by one by the oracle) to 1e-12 of gabs, balances at round-off.
+* Two Plummer spheres 2^22 (seed 3), theta = 0.5, FP64 and mixed: sampled
+  accelerations against the oracle (FP64 1e-12 of gabs; mixed 1e-4 at worst
+  and 2e-6 at the 99th percentile, the bounds of the mixed-precision tests).
+* Plummer 2^24 (seed 4) in the benchmark's configuration (pilot geometric
+  solve + error-estimate solve, eps 1.5e-7, theta_max 0.5, mixed, TC): the
+  oracle cannot walk 2e10 pairs, so properties that hold at any size: p99 of
+  the force error against direct summation at 4096 sampled targets below 1e-4,
+  force and torque balance, and the mixed solve against the FP64 solve from
+  the same field estimate (the same pairs) within the mixed-precision bound.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as orc
+from paper_1706_06989_amd import amfmm
+from paper_1706_06989_amd import workloads as W
+from tests.gpu_util import say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def host(t3):
+    return np.stack([t3[0].cpu().numpy(), t3[1].cpu().numpy(), t3[2].cpu().numpy()])
+
+
+def test_plummer_2p20_fp64_against_oracle():
+    n = 1 << 20
+    x, y, z, m = W.plummer(n, seed=2)
+    say("full size: plummer 2^20 fp64")
+    X, Y, Z, M = to_dev(x, y, z, m)
+    s = amfmm.Solver()
+    s.build_tree(X, Y, Z, M)
+    s.compute_moments()
+    s.walk(0.5)
+    ax, ay, az, p = s.evaluate()
+    g = s.get_tree()
+    far, near = s.get_lists()
+    t = orc.Tree(x, y, z, m)
+    k, perm = t.keys()
+    assert np.array_equal(g["keys"], k) and np.array_equal(g["perm"], perm)
+    c = t.cells()
+    for f in ("level", "begin", "count", "parent", "child0", "nchild"):
+        assert np.array_equal(g[f], c[f]), f
+    t.compute_moments()
+    t.walk(0.5)
+    ofar, onear = t.lists()
+    assert np.array_equal(far, ofar) and np.array_equal(near, onear)
+    idx = W.sample_targets(n, 256, seed=99)
+    oa, op = t.evaluate_sample(idx)
+    _, _, gabs = orc.direct(x, y, z, m, idx)
+    acc = host((ax, ay, az))[:, idx]
+    err = np.linalg.norm(acc - oa, axis=0) / gabs
+    say(f"  lists {len(far)} far {len(near)} near; sampled max err/gabs {err.max():.2e}")
+    assert err.max() <= 1e-12
+    assert np.max(np.abs(p.cpu().numpy()[idx] - op) / np.abs(op)) <= 1e-12
+    fb, tb = s.balance(X, Y, Z, M, ax, ay, az)
+    assert fb <= 1e-13 and tb <= 1e-13, (fb, tb)
+
+
+def test_two_plummer_2p22_fp64_and_mixed_against_oracle():
+    n = 1 << 22
+    x, y, z, m = W.two_plummer(n, seed=3)
+    say("full size: two plummer 2^22")
+    X, Y, Z, M = to_dev(x, y, z, m)
+    t = orc.Tree(x, y, z, m)
+    t.compute_moments()
+    t.walk(0.5)
+    idx = W.sample_targets(n, 256, seed=99)
+    oa, _ = t.evaluate_sample(idx)
+    _, _, gabs = orc.direct(x, y, z, m, idx)
+    for prec in (amfmm.FP64, amfmm.MIXED):
+        s = amfmm.Solver(precision=prec)
+        o = s.solve_gravity(X, Y, Z, M, 0.5, pot=False)
+        err = np.linalg.norm(host(o)[:, idx] - oa, axis=0) / gabs
+        fb, tb = s.balance(X, Y, Z, M, o[0], o[1], o[2])
+        say(f"  precision {prec}: sampled max err/gabs {err.max():.2e}, p99 {np.percentile(err, 99):.2e}; "
+            f"balances {fb:.1e} {tb:.1e}")
+        if prec == amfmm.FP64:
+            assert err.max() <= 1e-12
+            assert fb <= 1e-13 and tb <= 1e-13
+        else:
+            assert err.max() <= 1e-4 and np.percentile(err, 99) <= 2e-6
+            assert fb <= 1e-7 and tb <= 1e-7
+
+
+def test_plummer_2p24_benchmark_configuration():
+    n = 1 << 24
+    x, y, z, m = W.plummer(n, seed=4)
+    say("full size: plummer 2^24, benchmark configuration")
+    X, Y, Z, M = to_dev(x, y, z, m)
+    del x, y, z, m
+    pilot = amfmm.Solver(precision=amfmm.MIXED)
+    gx, gy, gz, _ = pilot.solve_gravity(X, Y, Z, M, 0.5, pot=False)
+    tg = torch.from_numpy(W.sample_targets(n, 4096, seed=99)).cuda()
+    tx, ty, tz, _, _ = pilot.direct(X, Y, Z, M, tg, pot=False, gabs=False)
+    T = torch.stack([tx, ty, tz])
+    outs = {}
+    for prec in (amfmm.MIXED, amfmm.FP64):
+        s = amfmm.Solver(precision=prec, criterion=amfmm.ESTIMATE, error_tol=1.5e-7, theta_max=0.5)
+        s.set_field_estimate(gx, gy, gz)
+        o = s.solve_gravity(X, Y, Z, M, 0.5, pot=False)
+        A = torch.stack([o[0][tg], o[1][tg], o[2][tg]])
+        e = (torch.linalg.norm(A - T, dim=0) / torch.linalg.norm(T, dim=0)).cpu().numpy()
+        fb, tb = s.balance(X, Y, Z, M, o[0], o[1], o[2])
+        say(f"  precision {prec}: p99 {np.percentile(e, 99):.3e}, max {e.max():.3e}, balances {fb:.1e} {tb:.1e}")
+        assert np.percentile(e, 99) <= 1e-4
+        assert fb <= 1e-7 and tb <= 1e-7
+        outs[prec] = A.cpu().numpy()
+        s.close()
+    d = np.linalg.norm(outs[amfmm.MIXED] - outs[amfmm.FP64], axis=0) / np.linalg.norm(outs[amfmm.FP64], axis=0)
+    say(f"  mixed against FP64 (same pairs): p99 {np.percentile(d, 99):.2e}, max {d.max():.2e}")
+    assert np.percentile(d, 99) <= 2e-6 and d.max() <= 1e-4
