@@ -75,6 +75,12 @@ int32_t orc_walk(orc_tree* t, double theta);
  * their mean (sums taken leaf-sequentially in key order and over children in
  * octant order).  gmag: per-particle field magnitudes, caller order. */
 int32_t orc_walk_field(orc_tree* t, double eps, double theta_max, const double* gmag);
+/* Walk with the multipole error estimate (see oracle.cpp): per-pair error
+ * from the source's traceless octupole and quadrupole norms and both cells'
+ * extents, against eps times each cell's field scale (as orc_walk_field). */
+int32_t orc_walk_multipole(orc_tree* t, double eps, double theta_max, const double* gmag);
+/* Quantised traceless quadrupole and octupole norm levels of every cell. */
+void orc_multipole_levels(const orc_tree* t, int32_t* k2, int32_t* k3);
 int64_t orc_num_m2l(const orc_tree* t);
 int64_t orc_num_p2p(const orc_tree* t);
 /* unordered pairs {a,b}: m2l with a<b, p2p with a<=b, each list sorted */

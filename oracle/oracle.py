@@ -45,6 +45,9 @@ def lib():
         L.orc_walk.argtypes = [P, C.c_double]
         L.orc_walk_field.restype = C.c_int32
         L.orc_walk_field.argtypes = [P, C.c_double, C.c_double, d]
+        L.orc_walk_multipole.restype = C.c_int32
+        L.orc_walk_multipole.argtypes = [P, C.c_double, C.c_double, d]
+        L.orc_multipole_levels.argtypes = [P, i32, i32]
         L.orc_num_m2l.restype = C.c_int64
         L.orc_num_m2l.argtypes = [P]
         L.orc_num_p2p.restype = C.c_int64
@@ -198,6 +201,20 @@ class Tree:
         if st:
             raise OracleError(st)
         return out
+
+    def walk_multipole(self, eps, theta_max, gmag):
+        """Walk with the multipole error estimate against per-particle |g|."""
+        g = _f64(gmag)
+        st = lib().orc_walk_multipole(self._t, float(eps), float(theta_max), _d(g))
+        if st:
+            raise OracleError(st)
+
+    def multipole_levels(self):
+        k2 = np.zeros(self.num_cells, np.int32)
+        k3 = np.zeros(self.num_cells, np.int32)
+        lib().orc_multipole_levels(self._t, k2.ctypes.data_as(C.POINTER(C.c_int32)),
+                                   k3.ctypes.data_as(C.POINTER(C.c_int32)))
+        return k2, k3
 
     def lists(self):
         nm = lib().orc_num_m2l(self._t)

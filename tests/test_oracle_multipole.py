@@ -1,0 +1,169 @@
+"""Pins of the oracle's multipole error-estimate walk (the error-based pair
+selection the paper's Sec. 2 refers to, with an estimate built from the
+source's traceless octupole and quadrupole norms and both cells' extents).
+
+The norm levels are recomputed here from each cell's particles; every
+accepted pair is checked against the estimate; every particle pair is covered
+exactly once; the tolerance controls the accuracy; a vanishing tolerance gives
+direct summation; and the estimate is tied to the errors the method actually
+makes on accepted pairs (measured against direct sums)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_1706_06989_amd import workloads as W
+
+W1, W2, W3, W4, W5 = 1.159, 3.73, 0.967, 0.232, 2.68  # the calibrated weights (see oracle.cpp)
+KQ = 128.0
+
+
+def levels_from_particles(t, x, y, z, m):
+    """Traceless norm levels of every cell, from its particles (numpy)."""
+    c = t.cells()
+    _, perm = t.keys()
+    xs, ys, zs, ms = x[perm], y[perm], z[perm], m[perm]
+    k2 = np.zeros(t.num_cells, np.int64)
+    k3 = np.zeros(t.num_cells, np.int64)
+    for ci in range(t.num_cells):
+        sl = slice(c["begin"][ci], c["begin"][ci] + c["count"][ci])
+        mu = ms[sl]
+        M = mu.sum()
+        P = np.stack([xs[sl], ys[sl], zs[sl]], 1)
+        Zc = (mu[:, None] * P).sum(0) / M
+        X = P - Zc
+        R = np.sqrt((X ** 2).sum(1)).max()
+        Q = np.einsum("n,ni,nj->ij", mu, X, X)
+        O = np.einsum("n,ni,nj,nk->ijk", mu, X, X, X)
+        Qt = Q - np.eye(3) * np.trace(Q) / 3
+        v = np.einsum("ijj->i", O)
+        d = np.eye(3)
+        Ot = O - (np.einsum("i,jk->ijk", v, d) + np.einsum("j,ik->ijk", v, d) + np.einsum("k,ij->ijk", v, d)) / 5
+        for arr, norm, p in ((k2, np.linalg.norm(Qt), 2), (k3, np.linalg.norm(Ot), 3)):
+            den = M * R ** p
+            arr[ci] = 0 if den <= 0 else int(min(KQ, max(0.0, math.floor(KQ * norm / den + 0.5))))
+    return k2, k3
+
+
+def estimate(rt, rs, k2s, k3s, d, ms):
+    P = W3 * (k3s / KQ) * rs ** 3 + W2 * (k2s / KQ) * rs ** 2 * rt + W1 * rt ** 3
+    Q = W4 * rs ** 4 + W5 * rt ** 4
+    return (P * d + Q) * ms / d ** 6
+
+
+def field_scale(t, gmag):
+    c = t.cells()
+    _, perm = t.keys()
+    g = np.abs(gmag)[perm]
+    s = np.empty(t.num_cells)
+    for ci in range(t.num_cells):
+        v = g[c["begin"][ci]:c["begin"][ci] + c["count"][ci]]
+        s[ci] = max(v.min(), 0.1 * v.mean())
+    return s
+
+
+def test_norm_levels_match_particle_sums():
+    x, y, z, m = W.two_plummer(3000, seed=31)
+    t = orc.Tree(x, y, z, m, n_crit=12)
+    t.compute_moments()
+    k2, k3 = t.multipole_levels()
+    r2, r3 = levels_from_particles(t, x, y, z, m)
+    assert np.array_equal(k2, r2) and np.array_equal(k3, r3)
+    # two equal masses: the quadrupole is M R^2 diag(2/3, -1/3, -1/3) in its
+    # axis, traceless norm sqrt(6)/3 M R^2, octupole zero
+    t2 = orc.Tree(np.array([0.0, 1.0]), np.zeros(2), np.zeros(2), np.ones(2), n_crit=4)
+    t2.compute_moments()
+    a2, a3 = t2.multipole_levels()
+    assert a2[0] == math.floor(KQ * math.sqrt(6) / 3 + 0.5) and a3[0] == 0
+
+
+@pytest.mark.parametrize("eps,tmax", [(1e-3, 0.7), (1e-5, 0.5)])
+def test_multipole_walk_covers_pairs_and_meets_estimate(eps, tmax):
+    x, y, z, m = W.two_plummer(800, seed=17)
+    a, _, _ = orc.direct(x, y, z, m)
+    gmag = np.linalg.norm(a, axis=0)
+    t = orc.Tree(x, y, z, m, n_crit=8)
+    t.compute_moments()
+    t.walk_multipole(eps, tmax, gmag)
+    m2l, p2p = t.lists()
+    c = t.cells()
+    n = len(x)
+    cover = np.zeros((n, n), np.int32)
+    rng = lambda ci: slice(c["begin"][ci], c["begin"][ci] + c["count"][ci])
+    for A, B in m2l:
+        cover[rng(A), rng(B)] += 1
+        cover[rng(B), rng(A)] += 1
+    for A, B in p2p:
+        cover[rng(A), rng(B)] += 1
+        if A != B:
+            cover[rng(B), rng(A)] += 1
+    assert np.all(cover[~np.eye(n, dtype=bool)] == 1)
+    mo = t.moments()
+    s = field_scale(t, gmag)
+    k2, k3 = levels_from_particles(t, x, y, z, m)
+    for A, B in m2l:
+        d = np.linalg.norm(mo[A, 1:4] - mo[B, 1:4])
+        RA, RB = mo[A, 4], mo[B, 4]
+        assert RA + RB <= tmax * d * (1 + 1e-12)
+        assert estimate(RA, RB, k2[B], k3[B], d, mo[B, 0]) <= eps * s[A] * (1 + 1e-9)
+        assert estimate(RB, RA, k2[A], k3[A], d, mo[A, 0]) <= eps * s[B] * (1 + 1e-9)
+    assert len(m2l) > 0
+
+
+def test_multipole_tolerance_controls_error():
+    x, y, z, m = W.plummer(6000, seed=18)
+    at, _, _ = orc.direct(x, y, z, m)
+    gmag = np.linalg.norm(at, axis=0)
+    res = []
+    t = orc.Tree(x, y, z, m)
+    t.compute_moments()
+    for eps in (1e-3, 1e-4, 1e-5, 1e-6):
+        t.walk_multipole(eps, 0.7, gmag)
+        a, _ = t.evaluate(orc.TC)
+        res.append(np.percentile(orc.rel_force_error(a, at), 99))
+    assert all(u > v for u, v in zip(res, res[1:])), res
+
+
+def test_multipole_vanishing_tolerance_is_direct_sum():
+    x, y, z, m = W.plummer(500, seed=19)
+    at, _, gabs = orc.direct(x, y, z, m)
+    t = orc.Tree(x, y, z, m)
+    t.compute_moments()
+    t.walk_multipole(1e-30, 1.0, np.linalg.norm(at, axis=0))
+    a, _ = t.evaluate(orc.TC)
+    assert np.max(np.linalg.norm(a - at, axis=0) / gabs) <= 1e-13
+
+
+def test_estimate_tracks_measured_pair_errors():
+    """On accepted pairs of a Plummer walk, the largest error the method makes
+    on a particle of the field cell (its pair acceleration against the direct
+    sum over the source cell) stays near the estimate: median ratio below 1,
+    90th percentile below 3."""
+    x, y, z, m = W.plummer(6000, seed=23)
+    at, _, _ = orc.direct(x, y, z, m)
+    t = orc.Tree(x, y, z, m)
+    t.compute_moments()
+    t.walk_multipole(3e-4, 0.7, np.linalg.norm(at, axis=0))
+    far, _ = t.lists()
+    c = t.cells()
+    mo = t.moments()
+    k2, k3 = t.multipole_levels()
+    _, perm = t.keys()
+    xs, ys, zs, ms = x[perm], y[perm], z[perm], m[perm]
+    rng = np.random.default_rng(4)
+    ratios = []
+    for A, B in far[rng.choice(len(far), min(400, len(far)), replace=False)]:
+        if mo[A, 4] + mo[B, 4] == 0:
+            continue
+        part = lambda ci: tuple(v[c["begin"][ci]:c["begin"][ci] + c["count"][ci]] for v in (xs, ys, zs, ms))
+        PA, PB = part(A), part(B)
+        gA, _, _, _ = orc.pair_far(PA, PB, orc.TC)
+        d3 = np.stack([PB[k][None, :] - PA[k][:, None] for k in range(3)])
+        r3 = np.sqrt((d3 ** 2).sum(0)) ** 3
+        gd = (PB[3][None, :] * d3 / r3).sum(2).T
+        err = np.linalg.norm(gA - gd, axis=1).max()
+        d = np.linalg.norm(mo[A, 1:4] - mo[B, 1:4])
+        ratios.append(err / estimate(mo[A, 4], mo[B, 4], k2[B], k3[B], d, mo[B, 0]))
+    ratios = np.array(ratios)
+    assert np.median(ratios) <= 1.0 and np.percentile(ratios, 90) <= 3.0, np.percentile(ratios, [50, 90])

@@ -27,6 +27,8 @@ def pins_for(name):
     cannot see it and only cost time)."""
     if name.startswith("field_"):
         return FIELD_PINS
+    if name.startswith("multipole_"):
+        return ["tests/test_oracle_multipole.py"]
     if name.split("_")[0] in ("learned", "label", "grad", "plog2", "bf16", "feature"):
         return LEARNED_PINS
     return CORE_PINS
@@ -67,6 +69,14 @@ MUTATIONS = {
     "bf16_truncates": ("u += 0x7FFFu + ((u >> 16) & 1u);", "u += 0u;"),
     "feature_antisymmetric": ("f[5] = (float)((double)std::abs(qa - qb) / 64.0);",
                               "f[5] = (float)((double)(qa - qb) / 64.0);"),
+    "multipole_one_sided": ("return ea <= (t.eps * t.fscale[a]) * d6 && eb <= (t.eps * t.fscale[b]) * d6;",
+                            "return ea <= (t.eps * t.fscale[a]) * d6;"),
+    "multipole_power_of_d": ("double d6 = (d2 * d2) * d2;", "double d6 = (d2 * d2) * d;"),
+    "multipole_extents_swapped": ("double ea = multipole_bracket(A.Rmax, B.Rmax, t.k2[b], t.k3[b], d) * B.M;",
+                                  "double ea = multipole_bracket(B.Rmax, A.Rmax, t.k2[b], t.k3[b], d) * B.M;"),
+    "multipole_octupole_not_traceless": ("double w = mo.M3[i][j][k] - (v[i] * kdelta(j, k) + v[j] * kdelta(i, k) + v[k] * kdelta(i, j)) / 5.0;",
+                                         "double w = mo.M3[i][j][k];"),
+    "multipole_no_target_truncation": ("kMw1 * (rt2 * rt);", "0.0 * (rt2 * rt);"),
     "self_walk_skips_pairs": ("for (int32_t b = a + 1; b < C.child0 + C.nchild; ++b) walk_pair(t, a, b);",
                               "for (int32_t b = a + 2; b < C.child0 + C.nchild; ++b) walk_pair(t, a, b);"),
 }
