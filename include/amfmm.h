@@ -56,10 +56,18 @@ typedef enum { AMFMM_FP64 = 0, AMFMM_MIXED = 1 } amfmm_precision;
  *   the pair is accepted, above it opened.  Smaller pairs, and pairs whose
  *   features fall outside the model's training range, are accepted when
  *   q^3 <= u (the analytic factor).
+ * MULTIPOLE: an error-estimate criterion from the parts a third-order
+ *   expansion drops: with k2, k3 the Frobenius norms of the source's traceless
+ *   quadrupole and octupole in units of M R_max^2 and M R_max^3 (held to the
+ *   nearest 1/128), the error on A from B is estimated as
+ *   e_A = ((w3 k3_B R_B^3 + w2 k2_B R_B^2 R_A + w1 R_A^3) d + w4 R_B^4 + w5 R_A^4) M_B / d^6
+ *   (w1..w5 = 1.159, 3.73, 0.967, 0.232, 2.68, fitted once to measured pair
+ *   errors of this method); a pair is accepted when (R_A + R_B) <= theta_max d,
+ *   e_A <= error_tol s_A and e_B <= error_tol s_B.
  * Every rule is a function of the unordered pair, so pairwise momentum
  * conservation holds.  Without a field estimate (amfmm_set_field_estimate),
  * and for LEARNED without a model, the geometric rule is used. */
-typedef enum { AMFMM_GEOMETRIC = 0, AMFMM_ESTIMATE = 1, AMFMM_LEARNED = 2 } amfmm_criterion;
+typedef enum { AMFMM_GEOMETRIC = 0, AMFMM_ESTIMATE = 1, AMFMM_LEARNED = 2, AMFMM_MULTIPOLE = 3 } amfmm_criterion;
 
 typedef struct {
   int32_t n_crit;     /* most particles in a leaf; the paper runs 25 (Sec. 2) */
@@ -67,8 +75,8 @@ typedef struct {
   int32_t precision;  /* amfmm_precision */
   int32_t criterion;  /* amfmm_criterion */
   double G;           /* gravitational constant applied to all outputs */
-  double error_tol;   /* ESTIMATE / LEARNED: accepted pair error relative to the field scale */
-  double theta_max;   /* ESTIMATE / LEARNED: pairs with (R_A+R_B)/d > theta_max always open */
+  double error_tol;   /* ESTIMATE / LEARNED / MULTIPOLE: accepted pair error relative to the field scale */
+  double theta_max;   /* ESTIMATE / LEARNED / MULTIPOLE: pairs with (R_A+R_B)/d > theta_max always open */
   int64_t max_bytes;  /* cap on device scratch owned by the context (0 = no cap) */
   int64_t list_bytes; /* device bytes the interaction lists of one batch may take
                          (0 = automatic); when the whole tree's lists would not

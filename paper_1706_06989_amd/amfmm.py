@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libamfmm_hip.so")
 OK, E_INVALID, E_NONFINITE, E_OOM, E_HIP, E_STATE = 0, -1, -2, -3, -4, -5
 UC, TC, TCO = 0, 1, 2
 FP64, MIXED = 0, 1
-GEOMETRIC, ESTIMATE, LEARNED = 0, 1, 2
+GEOMETRIC, ESTIMATE, LEARNED, MULTIPOLE = 0, 1, 2, 3
 MLP_PARAMS, MLP_MODEL = 4801, 4833
 PHASES = ["validate+bbox", "keys+sort", "tree", "moments", "walk", "far", "push-down",
           "near+eval", "total"]

@@ -140,7 +140,7 @@ static int check_options(const amfmm_options* o) {
   if (o->n_crit < 1 || o->n_crit > 4096) return AMFMM_E_INVALID;
   if (o->variant < AMFMM_UC || o->variant > AMFMM_TCO) return AMFMM_E_INVALID;
   if (o->precision != AMFMM_FP64 && o->precision != AMFMM_MIXED) return AMFMM_E_INVALID;
-  if (o->criterion < AMFMM_GEOMETRIC || o->criterion > AMFMM_LEARNED) return AMFMM_E_INVALID;
+  if (o->criterion < AMFMM_GEOMETRIC || o->criterion > AMFMM_MULTIPOLE) return AMFMM_E_INVALID;
   if (!(o->G == o->G) || o->max_bytes < 0 || o->list_bytes < 0 || o->learned_min_work < 0) return AMFMM_E_INVALID;
   return AMFMM_OK;
 }
@@ -372,7 +372,9 @@ static size_t list_budget(Ctx& c) {
 // levels are walked and evaluated for all cells; below the split level the
 // cells are cut into contiguous batches of subtrees, each walked to the
 // leaves, evaluated (far field, push-down, near field) and released.  The
-// pairs, and hence the results, are the same as those of the whole walk.
+// pairs are the same as those of the whole walk; the results agree up to
+// rounding (how a level's frontier is cut into work chunks depends on its
+// size, and with it the order in which a cell's pairs are listed and summed).
 static void solve_batched(Ctx& c, double theta, double* ax, double* ay, double* az, double* pot) {
   using namespace amfmm;
   const double bpp = list_bytes_per_particle(theta);

@@ -38,26 +38,28 @@ enum : int { kAccept = 0, kNear = 1, kSplitX = 2, kSplitY = 3 };
 struct alignas(16) WalkRec {
   double gx, gy, gz, gw;  // centre of mass, R_max
   double m, gmin;         // mass, field scale of the cell (see k_gscale)
-  // first child, parent, particles, nch | has_next << 8 | quadrupole level << 16
+  // first child, parent, particles, meta: nch (bits 0-3) | has_next (4) |
+  // quadrupole level of the learned features (5-11) | traceless quadrupole
+  // level (12-19) | traceless octupole level (20-27)
   int32_t ch0, par, count, meta;
 };
 
 struct WalkCell {
   double gx, gy, gz, gw, m, gmin;
-  int32_t ch0, nch, par, next, count, qlev;
+  int32_t ch0, nch, par, next, count, qlev, k2, k3;
 };
 
 struct TreeView {
   const WalkRec* rec;
   double theta;
   double abs_tol;    // bound on the rounding of any centre of mass (absolute)
-  int mode;          // 0: opening angle theta; 1: error estimate; 2: learned
-  double eps;        // modes 1, 2: accepted error per pair, relative to each cell's field
-  double theta_max;  // modes 1, 2: (R_A + R_B)/d above this never accepted
+  int mode;          // 0: opening angle theta; 1: error estimate; 2: learned; 3: multipole estimate
+  double eps;        // modes 1-3: accepted error per pair, relative to each cell's field
+  double theta_max;  // modes 1-3: (R_A + R_B)/d above this never accepted
   double theta_max2; // theta_max^2
   const float* model;  // mode 2: network (BF16-rounded weights)
   int64_t min_work;    // mode 2: least N_A N_B for which the network is asked
-  const double* mmin;  // modes 1, 2: smallest leaf mass below each cell
+  const double* mmin;  // modes 1-3: smallest leaf mass below each cell
 };
 
 __device__ inline WalkCell load_cell(const WalkRec* __restrict__ r, int32_t c) {
@@ -75,15 +77,39 @@ __device__ inline WalkCell load_cell(const WalkRec* __restrict__ r, int32_t c) {
   w.ch0 = v.x;
   w.par = v.y;
   w.count = v.z;
-  w.nch = v.w & 0xff;
-  w.next = ((v.w >> 8) & 1) ? c + 1 : -1;
-  w.qlev = (v.w >> 16) & 0xff;
+  w.nch = v.w & 0xf;
+  w.next = ((v.w >> 4) & 1) ? c + 1 : -1;
+  w.qlev = (v.w >> 5) & 0x7f;
+  w.k2 = (v.w >> 12) & 0xff;
+  w.k3 = (v.w >> 20) & 0xff;
   return w;
 }
 
-// LEARNED: compile the network's decision in (mode 2); kernels of the other
-// modes stay free of it (and of its registers)
-template <bool LEARNED>
+// Which decisions a kernel carries besides modes 0 and 1: the network's
+// (mode 2) or the multipole estimate's (mode 3); kernels of the other modes
+// stay free of their code and registers.
+enum : int { kExtBase = 0, kExtLearned = 2, kExtMultipole = 3 };
+
+// The multipole estimate of the error of an accepted pair on field cell T
+// from source S (Sec. 2's error-based selection, built from the parts a
+// third-order expansion drops: S's traceless octupole, S's traceless
+// quadrupole over T's extent, and the truncation of S's field over T; the next
+// order adds R^4/d terms), per unit mass of S and times d^6:
+//   P d + Q,  P = w3 k3_S R_S^3 + w2 k2_S R_S^2 R_T + w1 R_T^3,  Q = w4 R_S^4 + w5 R_T^4
+// with k2, k3 the traceless norms in units of M R^2, M R^3.  The weights were
+// fitted once to measured pair errors of this method; w1 >= 1 is used by the
+// subtree rule in decide().
+constexpr double kMw1 = 1.159, kMw2 = 3.73, kMw3 = 0.967, kMw4 = 0.232, kMw5 = 2.68;
+constexpr double kMq = 128.0;  // the norm ratios are held to the nearest 1/128
+
+__device__ inline double multipole_bracket(double rt, double rs, int k2s, int k3s, double d) {
+  const double rt2 = rt * rt, rs2 = rs * rs;
+  const double P = ((kMw3 * (k3s / kMq)) * (rs2 * rs) + (kMw2 * (k2s / kMq)) * (rs2 * rt)) + kMw1 * (rt2 * rt);
+  const double Q = kMw4 * (rs2 * rs2) + kMw5 * (rt2 * rt2);
+  return P * d + Q;
+}
+
+template <int EXT>
 __device__ inline int decide(const TreeView& t, int32_t X, const WalkCell& a, int32_t Y, const WalkCell& b) {
   const double dx = a.gx - b.gx, dy = a.gy - b.gy, dz = a.gz - b.gz;
   const double d2 = (dx * dx + dy * dy) + dz * dz;
@@ -92,7 +118,7 @@ __device__ inline int decide(const TreeView& t, int32_t X, const WalkCell& a, in
     const double d = sqrt(d2);
     const double rhs = r / t.theta;
     if (d > 0.0 && d >= rhs) return kAccept;
-  } else if (!LEARNED || t.mode == 1) {
+  } else if (EXT == kExtBase || t.mode == 1) {
     // The force error of a quadrupole-order pair scales as M_other r^3 / d^5
     // with r = R_A + R_B; accept when that estimate stays below eps times the
     // field scale of each cell (both cells: a symmetric decision) and r <=
@@ -103,6 +129,16 @@ __device__ inline int decide(const TreeView& t, int32_t X, const WalkCell& a, in
       const double d10 = ((d2 * d2) * (d2 * d2)) * d2;
       const double wa = t.eps * a.gmin, wb = t.eps * b.gmin;
       if (r6 * (b.m * b.m) <= (wa * wa) * d10 && r6 * (a.m * a.m) <= (wb * wb) * d10) return kAccept;
+    }
+  } else if (EXT == kExtMultipole) {
+    // mode 3: (P_A d + Q_A) M_B <= eps s_A d^6 and the same for B, in product
+    // form (one root, no division)
+    if (d2 > 0.0 && r * r <= t.theta_max2 * d2) {
+      const double d = sqrt(d2);
+      const double d6 = (d2 * d2) * d2;
+      const double ea = multipole_bracket(a.gw, b.gw, b.k2, b.k3, d) * b.m;
+      const double eb = multipole_bracket(b.gw, a.gw, a.k2, a.k3, d) * a.m;
+      if (ea <= (t.eps * a.gmin) * d6 && eb <= (t.eps * b.gmin) * d6) return kAccept;
     }
   } else {
     // mode 2: the network decides where the estimate is close to the bound
@@ -128,8 +164,10 @@ __device__ inline int decide(const TreeView& t, int32_t X, const WalkCell& a, in
       // least the smallest leaf mass m below Y, and R_X + R_Y' >= R_X, so its
       // estimate e' M_Y' = (R_X + R_Y')^3 M_Y' / d'^5 is at least
       // R_X^3 m / (d + R_Y)^5.  When that exceeds what any rule accepts (eps
-      // s_X, times the network's upper gate in mode 2) no pair below Y is
-      // accepted with X either: Y is a near-field source as a whole.
+      // s_X, times the network's upper gate in mode 2; in mode 3 the
+      // estimate's w1 R_X^3 M_Y' / d'^5 term alone is at least as large, w1 >= 1)
+      // no pair below Y is accepted with X either: Y is a near-field source as
+      // a whole.
       const double D = (d + b.gw + t.abs_tol) * (1.0 + 1e-9);
       const double D2 = D * D;
       const double lim = (t.mode == 2 ? kGateHi : 1.0) * t.eps * a.gmin;
@@ -145,7 +183,7 @@ __device__ inline int decide(const TreeView& t, int32_t X, const WalkCell& a, in
 
 // Visits the terminal pairs of entry (X, Y) in depth-first order (children of
 // Y in octant order) and calls f(kind, Y') for each.
-template <bool LEARNED, typename F>
+template <int EXT, typename F>
 __device__ inline void traverse(const TreeView& t, int32_t X, int32_t Y, F&& f) {
   const WalkCell a = load_cell(t.rec, X);
   if (X == Y) {
@@ -159,7 +197,7 @@ __device__ inline void traverse(const TreeView& t, int32_t X, int32_t Y, F&& f) 
   int32_t cur = Y;
   WalkCell b = load_cell(t.rec, cur);
   for (;;) {
-    int d = decide<LEARNED>(t, X, a, cur, b);
+    int d = decide<EXT>(t, X, a, cur, b);
     if (d == kSplitY) {
       cur = b.ch0;
       b = load_cell(t.rec, cur);
@@ -177,6 +215,57 @@ __device__ inline void traverse(const TreeView& t, int32_t X, int32_t Y, F&& f) 
       b = load_cell(t.rec, cur);
     }
   }
+}
+
+// Frobenius norms of the traceless parts of M_ij (packed xx xy xz yy yz zz)
+// and of M_ijk (packed xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz): M_ij -
+// delta_ij tr/3 and M_ijk - (v_i delta_jk + v_j delta_ik + v_k delta_ij)/5,
+// v_i = M_ijj.  Squares are summed over all index tuples in row-major order
+// (the order of the plain definition, so the result rounds the same way).
+__device__ inline double traceless_norm2(const double* Q) {
+  const double m[3][3] = {{Q[0], Q[1], Q[2]}, {Q[1], Q[3], Q[4]}, {Q[2], Q[4], Q[5]}};
+  const double tr = m[0][0] + m[1][1] + m[2][2];
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double v = m[i][j] - (i == j ? tr / 3.0 : 0.0);
+      s += v * v;
+    }
+  return sqrt(s);
+}
+
+// packed position of M_ijk (symmetric: any order of i, j, k)
+__device__ inline int oct_index(int i, int j, int k) {
+  constexpr int idx[27] = {0, 1, 2, 1, 3, 4, 2, 4, 5, 1, 3, 4, 3, 6, 7, 4, 7, 8, 2, 4, 5, 4, 7, 8, 5, 8, 9};
+  return idx[9 * i + 3 * j + k];
+}
+
+__device__ inline double traceless_norm3(const double* O) {
+  double v[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) v[i] = O[oct_index(i, 0, 0)] + O[oct_index(i, 1, 1)] + O[oct_index(i, 2, 2)];
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double dij = i == j ? 1.0 : 0.0, dik = i == k ? 1.0 : 0.0, djk = j == k ? 1.0 : 0.0;
+        const double w = O[oct_index(i, j, k)] - (v[i] * djk + v[j] * dik + v[k] * dij) / 5.0;
+        s += w * w;
+      }
+  return sqrt(s);
+}
+
+// norm / (M R^p) to the nearest 1/kMq, in [0, kMq] (0 where M R^p = 0)
+__device__ inline int norm_level(double norm, double M, double R, int p) {
+  const double den = M * (p == 2 ? R * R : R * R * R);
+  if (!(den > 0.0)) return 0;
+  const double k = floor(kMq * (norm / den) + 0.5);
+  return k < 0.0 ? 0 : (k > kMq ? (int)kMq : (int)k);
 }
 
 __global__ void __launch_bounds__(kBS) k_pack_cells(int32_t nc, const double4* __restrict__ geo,
@@ -200,7 +289,9 @@ __global__ void __launch_bounds__(kBS) k_pack_cells(int32_t nc, const double4* _
   w.par = p;
   w.count = cnt[c];
   const int has_next = (p >= 0 && c + 1 < ch0[p] + nch[p]) ? 1 : 0;
-  w.meta = nch[c] | (has_next << 8) | (quad_level(mo[0], g.w, mo + 1) << 16);
+  const int k2 = norm_level(traceless_norm2(mo + 1), mo[0], g.w, 2);
+  const int k3 = norm_level(traceless_norm3(mo + 7), mo[0], g.w, 3);
+  w.meta = nch[c] | (has_next << 4) | (quad_level(mo[0], g.w, mo + 1) << 5) | (k2 << 12) | (k3 << 20);
   rec[c] = w;
 }
 
@@ -310,7 +401,7 @@ struct EmitDst {
 // pushes Y's children to the queue; when the queue is full the lane descends
 // Y's subtree itself.  The order is a fixed function of the inputs, so the
 // counting run and the emitting run visit the same pairs in the same order.
-template <bool EMIT, bool LEARNED, typename Q>
+template <bool EMIT, int EXT, typename Q>
 __device__ inline void wave_walk(const TreeView& t, int32_t X, const WalkCell& cx, const int32_t* __restrict__ fy,
                                  int64_t b, int32_t n, Q qbuf, int32_t qcap, int64_t& tm, int64_t& tp, int64_t& tq,
                                  EmitDst dst, unsigned long long* dbg) {
@@ -340,7 +431,7 @@ __device__ inline void wave_walk(const TreeView& t, int32_t X, const WalkCell& c
         else q = cx.nch;
       } else {
         const WalkCell cy = load_cell(t.rec, Y);
-        const int d = decide<LEARNED>(t, X, cx, Y, cy);
+        const int d = decide<EXT>(t, X, cx, Y, cy);
         m = d == kAccept;
         p = d == kNear;
         q = d == kSplitX;
@@ -368,7 +459,7 @@ __device__ inline void wave_walk(const TreeView& t, int32_t X, const WalkCell& c
       dpairs += __popcll(ym);
     }
     if (deep)
-      traverse<LEARNED>(t, X, Y, [&](int d, int32_t) {
+      traverse<EXT>(t, X, Y, [&](int d, int32_t) {
         m += d == kAccept;
         p += d == kNear;
         q += d == kSplitX;
@@ -384,7 +475,7 @@ __device__ inline void wave_walk(const TreeView& t, int32_t X, const WalkCell& c
       const int32_t oq = wave_excl_scan(q, &Tq);
       if (deep) {
         int64_t f = fo + om, g = no + op, bb = B + oq;
-        traverse<LEARNED>(t, X, Y, [&](int d, int32_t Z) {
+        traverse<EXT>(t, X, Y, [&](int d, int32_t Z) {
           if (d == kAccept) {
             dst.far_src[f++] = Z;
           } else if (d == kNear) {
@@ -439,7 +530,7 @@ __global__ void __launch_bounds__(kBS) k_chunk_counts(int32_t nl, const int32_t*
 // One wave per chunk of a cell's frontier entries: count its terminal pairs.
 // gq != nullptr: the wave's work queue is the global region gq + k * qcap
 // (levels with few chunks, whose pairs fan out widely); else it is in LDS.
-template <bool LEARNED>
+template <int EXT>
 __global__ void __launch_bounds__(kBS) k_walk_count(TreeView t, int32_t c0, int64_t kn, int32_t chunk,
                                                     const int32_t* __restrict__ kcell, const int64_t* __restrict__ cbase,
                                                     const int64_t* __restrict__ gbeg, const int32_t* __restrict__ gcnt,
@@ -459,9 +550,9 @@ __global__ void __launch_bounds__(kBS) k_walk_count(TreeView t, int32_t c0, int6
   const int32_t n = (int32_t)min<int64_t>(chunk, gcnt[i] - e0);
   int64_t tm = 0, tp = 0, tq = 0;
   if (gq)
-    wave_walk<false, LEARNED>(t, X, cx, fy, gbeg[i] + e0, n, gq + k * qcap, qcap, tm, tp, tq, EmitDst{}, dbg);
+    wave_walk<false, EXT>(t, X, cx, fy, gbeg[i] + e0, n, gq + k * qcap, qcap, tm, tp, tq, EmitDst{}, dbg);
   else
-    wave_walk<false, LEARNED>(t, X, cx, fy, gbeg[i] + e0, n, queue[threadIdx.x >> 6], kQ, tm, tp, tq, EmitDst{}, dbg);
+    wave_walk<false, EXT>(t, X, cx, fy, gbeg[i] + e0, n, queue[threadIdx.x >> 6], kQ, tm, tp, tq, EmitDst{}, dbg);
   tm = wave_sum64(tm);
   tp = wave_sum64(tp);
   tq = wave_sum64(tq);
@@ -505,7 +596,7 @@ __global__ void __launch_bounds__(kBS) k_walk_groups(TreeView t, int32_t c0, int
 }
 
 // One wave per chunk: write its far and near entries and its children's entries.
-template <bool LEARNED>
+template <int EXT>
 __global__ void __launch_bounds__(kBS) k_walk_emit(TreeView t, int32_t c0, int64_t kn, int32_t chunk,
                                                    const int32_t* __restrict__ kcell, const int64_t* __restrict__ cbase,
                                                    const int64_t* __restrict__ gbeg, const int32_t* __restrict__ gcnt,
@@ -530,9 +621,9 @@ __global__ void __launch_bounds__(kBS) k_walk_emit(TreeView t, int32_t c0, int64
   EmitDst dst{far_base + mex[k], near_base + pex[k], nbase[i], S, far_src, near_src, fy_n,
               qex[k] - qex[cbase[i]]};
   if (gq)
-    wave_walk<true, LEARNED>(t, X, cx, fy, gbeg[i] + e0, n, gq + k * qcap, qcap, tm, tp, tq, dst, nullptr);
+    wave_walk<true, EXT>(t, X, cx, fy, gbeg[i] + e0, n, gq + k * qcap, qcap, tm, tp, tq, dst, nullptr);
   else
-    wave_walk<true, LEARNED>(t, X, cx, fy, gbeg[i] + e0, n, queue[threadIdx.x >> 6], kQ, tm, tp, tq, dst, nullptr);
+    wave_walk<true, EXT>(t, X, cx, fy, gbeg[i] + e0, n, queue[threadIdx.x >> 6], kQ, tm, tp, tq, dst, nullptr);
 }
 
 __global__ void k_walk_init(int64_t* gbeg, int32_t* gcnt, int32_t* fy) {
@@ -557,6 +648,7 @@ void walk_prepare(Ctx& c, double theta) {
   c.walk_mode = 0;
   if (c.field && c.opt.criterion == AMFMM_ESTIMATE) c.walk_mode = 1;
   if (c.field && c.opt.criterion == AMFMM_LEARNED && c.model.p) c.walk_mode = 2;
+  if (c.field && c.opt.criterion == AMFMM_MULTIPOLE) c.walk_mode = 3;
   if (c.walk_mode != 0) {
     double* gs = (double*)ensure(c, c.gmin, 4 * sizeof(double) * nc);
     double* gm = gs + nc;
@@ -630,7 +722,7 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
              c.opt.theta_max, c.opt.theta_max * c.opt.theta_max, (const float*)c.model.p, c.opt.learned_min_work,
              c.walk_mode != 0 ? (const double*)c.gmin.p + 3 * (size_t)c.ncells : nullptr};
   static const bool debug = getenv("AMFMM_DEBUG_WALK") != nullptr;
-  const bool learned = c.walk_mode == 2;
+  const int ext = c.walk_mode == 2 ? kExtLearned : (c.walk_mode == 3 ? kExtMultipole : kExtBase);
   int64_t F = c.frontier;
   int64_t* tot_host = c.pinned;
   for (int lev = lev_first; lev <= lev_last && F > 0; ++lev) {
@@ -678,7 +770,8 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
       AMFMM_HIP(hipEventCreate(&e1));
       AMFMM_HIP(hipEventRecord(e0, c.stream));
     }
-    hipLaunchKernelGGL(learned ? k_walk_count<true> : k_walk_count<false>, dim3(kgrid), dim3(kBS), 0, c.stream, t, c0, kn, chunk, (const int32_t*)kcell,
+    hipLaunchKernelGGL(ext == kExtLearned ? k_walk_count<kExtLearned>
+                       : (ext == kExtMultipole ? k_walk_count<kExtMultipole> : k_walk_count<kExtBase>), dim3(kgrid), dim3(kBS), 0, c.stream, t, c0, kn, chunk, (const int32_t*)kcell,
                        (const int64_t*)cbase, (const int64_t*)gbeg, (const int32_t*)gcnt, fy, km, kp, kq, gq, qcap,
                        dbg);
     AMFMM_HIP(hipGetLastError());
@@ -721,7 +814,8 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
     int32_t* near_src = (int32_t*)ensure_keep(c, c.near_src, sizeof(int32_t) * (near_base + pt + 1),
                                               sizeof(int32_t) * near_base);
     int32_t* fy_n = (int32_t*)ensure(c, c.fy2, sizeof(int32_t) * (Fn + 1));
-    hipLaunchKernelGGL(learned ? k_walk_emit<true> : k_walk_emit<false>, dim3(kgrid), dim3(kBS), 0, c.stream, t, c0, kn, chunk, (const int32_t*)kcell,
+    hipLaunchKernelGGL(ext == kExtLearned ? k_walk_emit<kExtLearned>
+                       : (ext == kExtMultipole ? k_walk_emit<kExtMultipole> : k_walk_emit<kExtBase>), dim3(kgrid), dim3(kBS), 0, c.stream, t, c0, kn, chunk, (const int32_t*)kcell,
                        (const int64_t*)cbase, (const int64_t*)gbeg, (const int32_t*)gcnt, fy, (const int64_t*)mex,
                        (const int64_t*)pex, (const int64_t*)qex, (const int64_t*)nbase, far_base, near_base, far_src,
                        near_src, fy_n, gq, qcap);
