@@ -1,10 +1,11 @@
 """Benchmark: particles/s of the full gravity solve on one MI355X.
 
 One step = the whole force solve on inputs already resident in HBM.  With an
-error-estimate criterion (default) a step is two amfmm_solve_gravity calls: a
-pilot solve with the geometric criterion (theta = 0.5) whose accelerations
-give every cell its field scale, then the solve whose pair selection keeps
-each pair's estimated error below eps times that scale.  Each solve covers
+error-estimate criterion (default: the multipole estimate) a step is two
+amfmm_solve_gravity calls: a pilot solve with the geometric criterion
+(theta = 1.0) whose accelerations give every cell its field scale, then the
+solve whose pair selection keeps each pair's estimated error below eps times
+that scale.  Each solve covers
 validation, bounding cube, keys, sort, tree, upward pass, walk, far field,
 push-down, near field, evaluation at the particles and the unsort.  Outputs
 one JSON line.  The error of the timed configuration is measured outside the
@@ -48,8 +49,8 @@ def parse():
                    help="opening angle (geometric criterion; also the pilot solve)")
     p.add_argument("--pilot-theta", type=float, default=1.0,
                    help="opening angle of the pilot solve that gives the field estimate")
-    p.add_argument("--criterion", choices=["geometric", "estimate", "learned"], default="estimate")
-    p.add_argument("--eps", type=float, default=1.5e-7,
+    p.add_argument("--criterion", choices=["geometric", "estimate", "learned", "multipole"], default="multipole")
+    p.add_argument("--eps", type=float, default=5e-8,
                    help="error-estimate criterion: accepted pair error relative to the field scale")
     p.add_argument("--theta-max", type=float, default=0.5)
     p.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
@@ -96,10 +97,11 @@ def cpu_baseline(n, theta, criterion, eps, theta_max, seed=4):
     if criterion != "geometric":
         t = orc.Tree(x, y, z, m)
         t.compute_moments()
-        t.walk_field(eps, theta_max, np.linalg.norm(a, axis=0))
+        walk = t.walk_multipole if criterion == "multipole" else t.walk_field
+        walk(eps, theta_max, np.linalg.norm(a, axis=0))
         t.evaluate(orc.TC)
     dt = time.perf_counter() - t0
-    what = (f"pilot theta={theta} + error-estimate solve eps={eps} theta_max={theta_max}"
+    what = (f"pilot theta={theta} + {criterion} error-estimate solve eps={eps} theta_max={theta_max}"
             if criterion != "geometric" else f"theta={theta}")
     return {"value": n / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
             "sample": f"full oracle solve (tree, moments, walk, eqs. 2-4 at every particle, near "
@@ -135,7 +137,8 @@ def main():
     x, y, z, m = W.plummer(a.n, seed=4)
     X, Y, Z, M = (torch.from_numpy(v).to("cuda") for v in (x, y, z, m))
     del x, y, z, m
-    crit = {"geometric": amfmm.GEOMETRIC, "estimate": amfmm.ESTIMATE, "learned": amfmm.LEARNED}[a.criterion]
+    crit = {"geometric": amfmm.GEOMETRIC, "estimate": amfmm.ESTIMATE, "learned": amfmm.LEARNED,
+            "multipole": amfmm.MULTIPOLE}[a.criterion]
     pilot = amfmm.Solver(variant=variant, precision=prec)
     solver = amfmm.Solver(variant=variant, precision=prec, criterion=crit, error_tol=a.eps,
                           theta_max=a.theta_max)
@@ -220,7 +223,7 @@ def main():
 
     cpu = None
     if a.cpu_n > 0:
-        cpu = cpu_baseline(a.cpu_n, a.theta, a.criterion, a.eps, a.theta_max)
+        cpu = cpu_baseline(a.cpu_n, a.pilot_theta if field else a.theta, a.criterion, a.eps, a.theta_max)
 
     line = {
         "metric": METRIC, "value": a.n / (ms * 1e-3), "unit": "particles/s", "n_gpus": 1,

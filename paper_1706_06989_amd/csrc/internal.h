@@ -78,6 +78,11 @@ struct Ctx {
   DevBuf near_start, near_count, near_src;
   // walk frontier
   DevBuf fx, fy, fx2, fy2, fcnt, grp, walkrec, fsave, gsave, counters, gqueue;
+  DevBuf stage;  // walk: per-chunk staging windows of one level's terminal pairs
+  // walk: terminal pairs per frontier entry of every level (far, near, split-X
+  // bases; -1 = unknown) from the last walk under the rule walk_ratio_key
+  std::vector<double> walk_ratio;
+  double walk_ratio_key[4] = {-1.0, -1.0, -1.0, -1.0};
   int64_t grp_width = 0, frontier = 0;
   double walk_abs_tol = 0.0;
   int walk_mode = 0;              // 0 geometric, 1 error estimate, 2 learned

@@ -387,22 +387,57 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// Staging of a level's terminal pairs.  Every chunk owns a window of each
+// staging array (far, near, split-X bases) sized by the pairs its entries are
+// expected to produce; a chunk that outgrows a window takes one spill region
+// of twice the window from that list's shared pool (one atomic).  A chunk that
+// outgrows that too, or finds the pool exhausted, stops writing (its counts
+// still run on) and is walked again by the emitting kernel.
+struct StageLayout {
+  int32_t* win[3];             // window arrays
+  int32_t* spill[3];           // spill pools
+  int64_t* ksec;               // per chunk and list: spill offset, -1 = none
+  unsigned long long* used;    // spill entries handed out, per list
+  int64_t spill_cap[3];        // entries in each spill pool
+  int64_t cap16[3];            // window capacity per entry, in 1/16
+  int64_t slack[3];            // window slack per chunk
+};
+
+// window of list w of the chunk whose entries start at frontier position e
+// (chunk index k): [lo(e, k), lo(e + n, k + 1)); the windows tile the array
+__device__ inline int64_t stage_lo(const StageLayout& s, int w, int64_t e, int64_t k) {
+  return ((s.cap16[w] * e) >> 4) + k * s.slack[w];
+}
+
+// Where a wave's terminal pairs go.  EMIT: straight to their final places
+// (far/near lists at fo/no, split-X bases replicated for every child of X in
+// fy_n).  STAGE: to its windows and spill regions (positions fo, no, B count
+// from 0, split-X bases once each).
 struct EmitDst {
   int64_t fo, no, nb, S;
   int32_t* far_src;
   int32_t* near_src;
   int32_t* fy_n;
   int64_t B0;  // rank of this chunk's first split-X base inside the cell
+  // STAGE
+  const StageLayout* sl;
+  int32_t* win[3];
+  int64_t wcap[3];
+  int64_t chunk;
 };
+
+enum : int { kStage = 0, kEmit = 1 };
 
 // All pairs held by target cell X at this level, processed by one wave
 // breadth-first: each step gives every lane one pair (taken first from the
 // wave's queue, else from X's frontier entries); a pair whose rule opens Y
 // pushes Y's children to the queue; when the queue is full the lane descends
 // Y's subtree itself.  The order is a fixed function of the inputs, so the
-// counting run and the emitting run visit the same pairs in the same order.
-template <bool EMIT, int EXT, typename Q>
-__device__ inline void wave_walk(const TreeView& t, int32_t X, const WalkCell& cx, const int32_t* __restrict__ fy,
+// staging run and an emitting run visit the same pairs in the same order.
+// Returns the chunk's totals in tm, tp, tq, and (STAGE) whether it ran out
+// of room.
+template <int PASS, int EXT, typename Q>
+__device__ inline bool wave_walk(const TreeView& t, int32_t X, const WalkCell& cx, const int32_t* __restrict__ fy,
                                  int64_t b, int32_t n, Q qbuf, int32_t qcap, int64_t& tm, int64_t& tp, int64_t& tq,
                                  EmitDst dst, unsigned long long* dbg) {
   const int32_t qmask = qcap - 1;
@@ -410,6 +445,47 @@ __device__ inline void wave_walk(const TreeView& t, int32_t X, const WalkCell& c
   int32_t head = 0, tail = 0, fpos = 0;
   int64_t fo = dst.fo, no = dst.no, B = dst.B0;
   unsigned long long dsteps = 0, ddeep = 0, dpairs = 0;
+  int64_t sec[3] = {-1, -1, -1};  // STAGE: spill offsets (wave-uniform)
+  bool ovf = false;                // STAGE: out of room; writes stop
+  auto stage_put = [&](int w, int64_t f, int32_t v) {
+    if (!ovf) {
+      if (f < dst.wcap[w]) dst.win[w][f] = v;
+      else dst.sl->spill[w][sec[w] + (f - dst.wcap[w])] = v;
+    }
+  };
+  auto put_far = [&](int64_t f, int32_t v) {
+    if (PASS == kEmit) dst.far_src[f] = v;
+    else stage_put(0, f, v);
+  };
+  auto put_near = [&](int64_t g, int32_t v) {
+    if (PASS == kEmit) dst.near_src[g] = v;
+    else stage_put(1, g, v);
+  };
+  auto put_split = [&](int64_t r, int32_t v) {
+    if (PASS == kEmit) {
+      for (int32_t c = 0; c < cx.nch; ++c) dst.fy_n[dst.nb + c * dst.S + r] = v;
+    } else {
+      stage_put(2, r, v);
+    }
+  };
+  // STAGE: room for positions below `end` of list w
+  auto reserve = [&](int w, int64_t end) {
+    const int64_t cap = dst.wcap[w];
+    if (ovf || end <= cap || (sec[w] >= 0 && end <= 3 * cap)) return;
+    if (sec[w] >= 0 || end > 3 * cap) {
+      ovf = true;
+      return;
+    }
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(&dst.sl->used[w], (unsigned long long)(2 * cap));
+    base = __shfl(base, 0, 64);
+    if (base + (unsigned long long)(2 * cap) > (unsigned long long)dst.sl->spill_cap[w]) {
+      ovf = true;
+      return;
+    }
+    sec[w] = (int64_t)base;
+    if (lane == 0) dst.sl->ksec[3 * dst.chunk + w] = sec[w];
+  };
   while (head < tail || fpos < n) {
     int32_t Y = -1;
     if (head < tail) {
@@ -464,54 +540,51 @@ __device__ inline void wave_walk(const TreeView& t, int32_t X, const WalkCell& c
         p += d == kNear;
         q += d == kSplitX;
       });
-    if (!EMIT) {
-      tm += m;
-      tp += p;
-      tq += q;
-    } else {
-      int32_t Tm, Tp, Tq;
-      const int32_t om = wave_excl_scan(m, &Tm);
-      const int32_t op = wave_excl_scan(p, &Tp);
-      const int32_t oq = wave_excl_scan(q, &Tq);
-      if (deep) {
-        int64_t f = fo + om, g = no + op, bb = B + oq;
-        traverse<EXT>(t, X, Y, [&](int d, int32_t Z) {
-          if (d == kAccept) {
-            dst.far_src[f++] = Z;
-          } else if (d == kNear) {
-            dst.near_src[g++] = Z;
-          } else {
-            for (int32_t r = 0; r < cx.nch; ++r) dst.fy_n[dst.nb + r * dst.S + bb] = Z;
-            ++bb;
-          }
-        });
-      } else if (self) {
-        if (p) dst.near_src[no + op] = X;
-        for (int32_t j = 0; j < q; ++j)
-          for (int32_t r = 0; r < cx.nch; ++r) dst.fy_n[dst.nb + r * dst.S + B + oq + j] = cx.ch0 + j;
-      } else if (m) {
-        dst.far_src[fo + om] = Y;
-      } else if (p) {
-        dst.near_src[no + op] = Y;
-      } else if (q) {
-        for (int32_t r = 0; r < cx.nch; ++r) dst.fy_n[dst.nb + r * dst.S + B + oq] = Y;
-      }
-      fo += Tm;
-      no += Tp;
-      B += Tq;
+    int32_t Tm, Tp, Tq;
+    const int32_t om = wave_excl_scan(m, &Tm);
+    const int32_t op = wave_excl_scan(p, &Tp);
+    const int32_t oq = wave_excl_scan(q, &Tq);
+    if (PASS == kStage) {
+      reserve(0, fo + Tm);
+      reserve(1, no + Tp);
+      reserve(2, B + Tq);
     }
+    if (deep) {
+      int64_t f = fo + om, g = no + op, bb = B + oq;
+      traverse<EXT>(t, X, Y, [&](int d, int32_t Z) {
+        if (d == kAccept) put_far(f++, Z);
+        else if (d == kNear) put_near(g++, Z);
+        else put_split(bb++, Z);
+      });
+    } else if (self) {
+      if (p) put_near(no + op, X);
+      for (int32_t j = 0; j < q; ++j) put_split(B + oq + j, cx.ch0 + j);
+    } else if (m) {
+      put_far(fo + om, Y);
+    } else if (p) {
+      put_near(no + op, Y);
+    } else if (q) {
+      put_split(B + oq, Y);
+    }
+    fo += Tm;
+    no += Tp;
+    B += Tq;
   }
+  tm = fo - dst.fo;
+  tp = no - dst.no;
+  tq = B - dst.B0;
+
   if (dbg && (threadIdx.x & 63) == 0) {
     atomicAdd(&dbg[0], dsteps);
     atomicAdd(&dbg[1], ddeep);
     atomicAdd(&dbg[2], dpairs);
   }
+  return ovf;
 }
-constexpr int kChunkMin = 64;         // frontier entries per wave: at least ...
-constexpr int kChunkMax = 4096;       // ... at most ...
-constexpr int64_t kWavesPerLevel = 1 << 17;  // ... aiming at about this many waves
-constexpr int64_t kGlobalQueueChunks = 4096;  // levels with at most this many chunks ...
-constexpr int32_t kGlobalQueue = 1 << 18;     // ... give each wave a queue this large in global memory
+constexpr int kChunkMax = 4096;               // frontier entries per wave: at most this many,
+constexpr int64_t kWavesPerLevel = 1 << 17;   // aiming at about this many waves per level
+constexpr int64_t kGlobalQueueBytes = int64_t(1) << 31;  // global work queues of a level: at most this many bytes,
+constexpr int32_t kGlobalQueueMax = 1 << 18;  // at most this many entries per wave, used when at least 4 kQ
 
 // chunk -> cell map of the level: kcell[k] = i for cbase[i] <= k < cbase[i+1]
 __global__ void __launch_bounds__(kBS) k_chunk_map(int32_t nl, const int64_t* __restrict__ cbase,
@@ -527,16 +600,18 @@ __global__ void __launch_bounds__(kBS) k_chunk_counts(int32_t nl, const int32_t*
   if (i < nl) nck[i] = (gcnt[i] + chunk - 1) / chunk;
 }
 
-// One wave per chunk of a cell's frontier entries: count its terminal pairs.
-// gq != nullptr: the wave's work queue is the global region gq + k * qcap
-// (levels with few chunks, whose pairs fan out widely); else it is in LDS.
+// One wave per chunk of a cell's frontier entries: walk it once, writing its
+// terminal pairs to its staging room, and record its counts (and whether it
+// ran out of room).
 template <int EXT>
-__global__ void __launch_bounds__(kBS) k_walk_count(TreeView t, int32_t c0, int64_t kn, int32_t chunk,
+__global__ void __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(EXT == kExtLearned ? 1 : 4))) k_walk_stage(TreeView t, int32_t c0, int64_t kn, int32_t chunk,
                                                     const int32_t* __restrict__ kcell, const int64_t* __restrict__ cbase,
                                                     const int64_t* __restrict__ gbeg, const int32_t* __restrict__ gcnt,
-                                                    const int32_t* __restrict__ fy, int64_t* __restrict__ km,
-                                                    int64_t* __restrict__ kp, int64_t* __restrict__ kq,
-                                                    int32_t* __restrict__ gq, int32_t qcap, unsigned long long* dbg) {
+                                                    const int32_t* __restrict__ fy, const StageLayout* __restrict__ sl,
+                                                    int64_t* __restrict__ km, int64_t* __restrict__ kp,
+                                                    int64_t* __restrict__ kq, int32_t* __restrict__ kov,
+                                                    unsigned long long* __restrict__ nov, int32_t* __restrict__ gq,
+                                                    int32_t qcap, unsigned long long* dbg) {
   __shared__ int32_t queue[kBS / 64][kQ];
   const int lane = threadIdx.x & 63;
   // wave-uniform (readfirstlane): the cell's record and bookkeeping are
@@ -548,18 +623,26 @@ __global__ void __launch_bounds__(kBS) k_walk_count(TreeView t, int32_t c0, int6
   const WalkCell cx = load_cell(t.rec, X);
   const int64_t e0 = (k - cbase[i]) * chunk;
   const int32_t n = (int32_t)min<int64_t>(chunk, gcnt[i] - e0);
+  const int64_t e = gbeg[i] + e0;
+  EmitDst dst{0, 0, 0, 0, nullptr, nullptr, nullptr, 0, sl, {}, {}, k};
+#pragma unroll
+  for (int w = 0; w < 3; ++w) {
+    const int64_t lo = stage_lo(*sl, w, e, k);
+    dst.win[w] = sl->win[w] + lo;
+    dst.wcap[w] = stage_lo(*sl, w, e + n, k + 1) - lo;
+  }
   int64_t tm = 0, tp = 0, tq = 0;
+  bool over;
   if (gq)
-    wave_walk<false, EXT>(t, X, cx, fy, gbeg[i] + e0, n, gq + k * qcap, qcap, tm, tp, tq, EmitDst{}, dbg);
+    over = wave_walk<kStage, EXT>(t, X, cx, fy, e, n, gq + k * qcap, qcap, tm, tp, tq, dst, dbg);
   else
-    wave_walk<false, EXT>(t, X, cx, fy, gbeg[i] + e0, n, queue[threadIdx.x >> 6], kQ, tm, tp, tq, EmitDst{}, dbg);
-  tm = wave_sum64(tm);
-  tp = wave_sum64(tp);
-  tq = wave_sum64(tq);
+    over = wave_walk<kStage, EXT>(t, X, cx, fy, e, n, queue[threadIdx.x >> 6], kQ, tm, tp, tq, dst, dbg);
   if (lane == 0) {
     km[k] = tm;
     kp[k] = tp;
     kq[k] = tq;
+    kov[k] = over ? 1 : 0;
+    if (over) atomicAdd(nov, 1ull);
   }
 }
 
@@ -595,22 +678,65 @@ __global__ void __launch_bounds__(kBS) k_walk_groups(TreeView t, int32_t c0, int
   }
 }
 
-// One wave per chunk: write its far and near entries and its children's entries.
+// One wave per staged chunk that did not run out of room: copy its windows
+// (and spill regions) to the final lists (split-X bases once for every child
+// of the cell).
+__global__ void __launch_bounds__(kBS) k_walk_compact(TreeView t, int32_t c0, int64_t kn, int32_t chunk,
+                                                      const int32_t* __restrict__ kcell,
+                                                      const int64_t* __restrict__ cbase,
+                                                      const int64_t* __restrict__ gbeg,
+                                                      const int32_t* __restrict__ gcnt,
+                                                      const StageLayout* __restrict__ slp,
+                                                      const int64_t* __restrict__ mex, const int64_t* __restrict__ pex,
+                                                      const int64_t* __restrict__ qex, const int64_t* __restrict__ nbase,
+                                                      const int32_t* __restrict__ kov, int64_t far_base,
+                                                      int64_t near_base, int32_t* __restrict__ far_src,
+                                                      int32_t* __restrict__ near_src, int32_t* __restrict__ fy_n) {
+  const int lane = threadIdx.x & 63;
+  const int64_t k = uniform((int32_t)(blockIdx.x * (kBS / 64) + (threadIdx.x >> 6)));
+  if (k >= kn || kov[k]) return;
+  const StageLayout& sl = *slp;
+  const int32_t i = kcell[k];
+  const int64_t e0 = (k - cbase[i]) * chunk;
+  const int64_t e = gbeg[i] + e0;
+  const int64_t n = min<int64_t>(chunk, gcnt[i] - e0);
+  // source position j of list w: the window, then the spill region
+  auto src = [&](int w, int64_t j) {
+    const int64_t lo = stage_lo(sl, w, e, k);
+    const int64_t cap = stage_lo(sl, w, e + n, k + 1) - lo;
+    return j < cap ? sl.win[w][lo + j] : sl.spill[w][sl.ksec[3 * k + w] + (j - cap)];
+  };
+  const int64_t nm = mex[k + 1] - mex[k], np = pex[k + 1] - pex[k], nq = qex[k + 1] - qex[k];
+  int32_t* df = far_src + far_base + mex[k];
+  int32_t* dn = near_src + near_base + pex[k];
+  for (int64_t j = lane; j < nm; j += 64) df[j] = src(0, j);
+  for (int64_t j = lane; j < np; j += 64) dn[j] = src(1, j);
+  if (nq) {
+    const int32_t nch = load_cell(t.rec, c0 + i).nch;
+    const int64_t S = qex[cbase[i + 1]] - qex[cbase[i]];
+    int32_t* dq = fy_n + nbase[i] + (qex[k] - qex[cbase[i]]);
+    for (int64_t j = lane; j < nq; j += 64) {
+      const int32_t v = src(2, j);
+      for (int32_t r = 0; r < nch; ++r) dq[r * S + j] = v;
+    }
+  }
+}
+
+// One wave per chunk whose staging overflowed: walk it again, writing its far
+// and near entries and its children's entries straight to their places.
 template <int EXT>
 __global__ void __launch_bounds__(kBS) k_walk_emit(TreeView t, int32_t c0, int64_t kn, int32_t chunk,
                                                    const int32_t* __restrict__ kcell, const int64_t* __restrict__ cbase,
                                                    const int64_t* __restrict__ gbeg, const int32_t* __restrict__ gcnt,
                                                    const int32_t* __restrict__ fy, const int64_t* __restrict__ mex,
                                                    const int64_t* __restrict__ pex, const int64_t* __restrict__ qex,
-                                                   const int64_t* __restrict__ nbase, int64_t far_base,
-                                                   int64_t near_base, int32_t* __restrict__ far_src,
+                                                   const int64_t* __restrict__ nbase, const int32_t* __restrict__ kov,
+                                                   int64_t far_base, int64_t near_base, int32_t* __restrict__ far_src,
                                                    int32_t* __restrict__ near_src, int32_t* __restrict__ fy_n,
                                                    int32_t* __restrict__ gq, int32_t qcap) {
   __shared__ int32_t queue[kBS / 64][kQ];
-  // wave-uniform (readfirstlane): the cell's record and bookkeeping are
-  // loaded once per wave into scalar registers
   const int64_t k = uniform((int32_t)(xcd_block(blockIdx.x, gridDim.x) * (kBS / 64) + (threadIdx.x >> 6)));
-  if (k >= kn) return;
+  if (k >= kn || !kov[k]) return;
   const int32_t i = kcell[k];
   const int32_t X = c0 + i;
   const WalkCell cx = load_cell(t.rec, X);
@@ -619,11 +745,11 @@ __global__ void __launch_bounds__(kBS) k_walk_emit(TreeView t, int32_t c0, int64
   const int64_t S = qex[cbase[i + 1]] - qex[cbase[i]];
   int64_t tm = 0, tp = 0, tq = 0;
   EmitDst dst{far_base + mex[k], near_base + pex[k], nbase[i], S, far_src, near_src, fy_n,
-              qex[k] - qex[cbase[i]]};
+              qex[k] - qex[cbase[i]], nullptr, {}, {}, k};
   if (gq)
-    wave_walk<true, EXT>(t, X, cx, fy, gbeg[i] + e0, n, gq + k * qcap, qcap, tm, tp, tq, dst, nullptr);
+    wave_walk<kEmit, EXT>(t, X, cx, fy, gbeg[i] + e0, n, gq + k * qcap, qcap, tm, tp, tq, dst, nullptr);
   else
-    wave_walk<true, EXT>(t, X, cx, fy, gbeg[i] + e0, n, queue[threadIdx.x >> 6], kQ, tm, tp, tq, dst, nullptr);
+    wave_walk<kEmit, EXT>(t, X, cx, fy, gbeg[i] + e0, n, queue[threadIdx.x >> 6], kQ, tm, tp, tq, dst, nullptr);
 }
 
 __global__ void k_walk_init(int64_t* gbeg, int32_t* gcnt, int32_t* fy) {
@@ -632,11 +758,12 @@ __global__ void k_walk_init(int64_t* gbeg, int32_t* gcnt, int32_t* fy) {
   fy[0] = 0;
 }
 
-__global__ void k_gather_totals(const int64_t* mex, const int64_t* pex, const int64_t* nbase, int64_t kmax,
-                                int32_t nl, int64_t* out) {
+__global__ void k_gather_totals(const int64_t* mex, const int64_t* pex, const int64_t* qex, const int64_t* nbase,
+                                int64_t kmax, int32_t nl, int64_t* out) {
   out[0] = mex[kmax];
   out[1] = pex[kmax];
   out[2] = nbase[nl];
+  out[3] = qex[kmax];
 }
 
 }  // namespace
@@ -716,6 +843,46 @@ void walk_start(Ctx& c) {
   c.frontier = 1;
 }
 
+// Staging room of a level.  Expected terminal pairs per entry: those the
+// level produced the last time it was walked under the same rule (windows
+// 1.5x that), else the level above's in this walk (2.5x), else a default;
+// plus a slack per chunk.  Spill pools: 0.75x the windows.  The whole is held
+// within `limit` bytes (scaled down; below a quarter of the wanted size no
+// staging: every chunk with output is emitted by the second pass).  Returns
+// the bytes: windows, spill pools, then the spill offsets (3 int64 per chunk).
+static size_t stage_layout(Ctx& c, int lev, int64_t F, int64_t kn, const double* prev, size_t limit,
+                           StageLayout& sl) {
+  double r[3] = {4.0, 1.0, 2.0}, alpha = 1.0;
+  const size_t at = 3 * (size_t)lev;
+  if (at + 2 < c.walk_ratio.size() && c.walk_ratio[at] >= 0.0) {
+    for (int w = 0; w < 3; ++w) r[w] = c.walk_ratio[at + w];
+    alpha = 1.5;
+  } else if (prev) {
+    for (int w = 0; w < 3; ++w) r[w] = prev[w];
+    alpha = 2.5;
+  }
+  constexpr double kSpill = 0.75;
+  const int64_t slack[3] = {32, 8, 8};
+  const double offsets = 3.0 * sizeof(int64_t) * (double)kn;
+  double ints = 0.0;
+  for (int w = 0; w < 3; ++w) ints += (1.0 + kSpill) * (alpha * r[w] * (double)F + (double)(kn * slack[w]));
+  double scale = 1.0;
+  if (ints * sizeof(int32_t) + offsets > (double)limit)
+    scale = std::max(0.0, ((double)limit - offsets) / (ints * sizeof(int32_t)));
+  if (scale < 0.25) scale = 0.0;
+  size_t n = 0;
+  for (int w = 0; w < 3; ++w) {
+    sl.cap16[w] = (int64_t)std::ceil(16.0 * alpha * r[w] * scale);
+    sl.slack[w] = (int64_t)((double)slack[w] * scale);
+    const int64_t win = ((sl.cap16[w] * F) >> 4) + kn * sl.slack[w] + 1;
+    sl.spill_cap[w] = (int64_t)(kSpill * (double)win);
+    n += (size_t)(win + sl.spill_cap[w]);
+  }
+  return sizeof(int32_t) * n + 3 * sizeof(int64_t) * (size_t)kn + 64;
+}
+
+__global__ void k_set_layout(StageLayout v, StageLayout* out) { *out = v; }
+
 int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32_t>& lo,
                     const std::vector<int32_t>& hi, int64_t& far_base, int64_t& near_base) {
   TreeView t{(const WalkRec*)c.walkrec.p, c.theta, c.walk_abs_tol, c.walk_mode, c.opt.error_tol,
@@ -723,25 +890,43 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
              c.walk_mode != 0 ? (const double*)c.gmin.p + 3 * (size_t)c.ncells : nullptr};
   static const bool debug = getenv("AMFMM_DEBUG_WALK") != nullptr;
   const int ext = c.walk_mode == 2 ? kExtLearned : (c.walk_mode == 3 ? kExtMultipole : kExtBase);
+  // per-level ratios of terminal pairs to entries, kept while the rule stays the same
+  const double key[4] = {(double)c.walk_mode, c.theta, c.opt.error_tol, c.opt.theta_max};
+  if (!std::equal(key, key + 4, c.walk_ratio_key) || c.walk_ratio.size() < 3 * lo.size()) {
+    std::copy(key, key + 4, c.walk_ratio_key);
+    c.walk_ratio.assign(3 * lo.size(), -1.0);
+  }
+  // staging room: a third of the free device memory, at most 48 GiB
+  size_t fr = 0, totm = 0;
+  if (hipMemGetInfo(&fr, &totm) != hipSuccess) {
+    (void)hipGetLastError();
+    fr = size_t(16) << 30;
+  }
+  const size_t stage_limit = std::min<size_t>(fr / 3 + c.stage.cap, size_t(48) << 30);
+  double prev[3];
+  bool have_prev = false;
   int64_t F = c.frontier;
   int64_t* tot_host = c.pinned;
   for (int lev = lev_first; lev <= lev_last && F > 0; ++lev) {
     const int32_t c0 = lo[lev], nl = hi[lev] - lo[lev];
     const int32_t c0n = lev + 1 < (int)lo.size() ? lo[lev + 1] : 0;
     const size_t L = (size_t)nl + 1;
-    // enough waves to fill the chip, few enough that dispatch does not dominate
-    const int32_t chunk = (int32_t)std::min<int64_t>(
-        kChunkMax, std::max<int64_t>(kChunkMin, (F / kWavesPerLevel + kChunkMin - 1) / kChunkMin * kChunkMin));
+    // enough waves to fill the chip (small frontiers: one entry per wave),
+    // few enough that dispatch does not dominate
+    const int32_t chunk = (int32_t)std::min<int64_t>(kChunkMax, std::max<int64_t>(1, (F + kWavesPerLevel - 1) / kWavesPerLevel));
     const int64_t kmax = F / chunk + nl + 1;  // upper bound on the chunks
     const size_t K = (size_t)kmax + 1;
     int64_t *gbeg, *gbeg_n;
     int32_t *gcnt, *gcnt_n;
     group_ptrs(c, c.grp_cur, &gbeg, &gcnt);
     group_ptrs(c, 1 - c.grp_cur, &gbeg_n, &gcnt_n);
-    int64_t* w = (int64_t*)ensure(c, c.scratch2, sizeof(int64_t) * (4 * L + 6 * K + 8));
+    int64_t* w = (int64_t*)ensure(c, c.scratch2, sizeof(int64_t) * (4 * L + 7 * K + 48));
     int64_t *nck = w, *cbase = nck + L, *ns = cbase + L, *nbase = ns + L;
     int64_t *km = nbase + L, *kp = km + K, *kq = kp + K, *mex = kq + K, *pex = mex + K, *qex = pex + K;
-    int64_t* tot = qex + K;
+    int32_t* kov = (int32_t*)(qex + K);
+    // [0..3] totals, [4] chunks out of room, [5..7] spill used, [8..11] debug
+    // counters, [16..] the staging layout
+    int64_t* tot = qex + 2 * K;
     const int32_t* fy = as<int32_t>(c.fy);
     hipLaunchKernelGGL(k_chunk_counts, dim3(blocks_for(nl, kBS)), dim3(kBS), 0, c.stream, nl, (const int32_t*)gcnt,
                        chunk, nck);
@@ -754,26 +939,48 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
     hipLaunchKernelGGL(k_chunk_map, dim3(blocks_for(nl, kBS)), dim3(kBS), 0, c.stream, nl, (const int64_t*)cbase,
                        kcell);
     const unsigned kgrid = blocks_for(kn, kBS / 64);
-    // few chunks: a large work queue per wave in global memory
+    // few chunks: a larger work queue per wave, in global memory
     int32_t* gq = nullptr;
     int32_t qcap = kQ;
-    if (kn <= kGlobalQueueChunks) {
-      qcap = kGlobalQueue;
-      gq = (int32_t*)ensure(c, c.gqueue, sizeof(int32_t) * (size_t)kn * qcap);
+    {
+      int64_t g = kGlobalQueueMax;
+      while (g > 4 * kQ && (int64_t)sizeof(int32_t) * g * kn > kGlobalQueueBytes) g >>= 1;
+      if ((int64_t)sizeof(int32_t) * g * kn <= kGlobalQueueBytes) {
+        qcap = (int32_t)g;
+        gq = (int32_t*)ensure(c, c.gqueue, sizeof(int32_t) * (size_t)kn * qcap);
+      }
     }
-    unsigned long long* dbg = nullptr;
+    StageLayout sl{};
+    const size_t stage_bytes = stage_layout(c, lev, F, kn, have_prev ? prev : nullptr, stage_limit, sl);
+    {
+      int64_t* st64 = (int64_t*)ensure(c, c.stage, stage_bytes);
+      sl.ksec = st64;
+      int32_t* st = (int32_t*)(st64 + 3 * kn);
+      for (int w = 0; w < 3; ++w) {
+        sl.win[w] = st;
+        st += ((sl.cap16[w] * F) >> 4) + kn * sl.slack[w] + 1;
+        sl.spill[w] = st;
+        st += sl.spill_cap[w];
+      }
+    }
+    unsigned long long* nov = (unsigned long long*)(tot + 4);
+    sl.used = nov + 1;
+    unsigned long long* dbg = debug ? (unsigned long long*)(tot + 8) : nullptr;
+    StageLayout* sl_dev = (StageLayout*)(tot + 16);
+    zero_u64(c, nov, debug ? 8 : 4);
+    hipLaunchKernelGGL(k_set_layout, dim3(1), dim3(1), 0, c.stream, sl, sl_dev);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (debug) {
-      dbg = (unsigned long long*)(tot + 4);
-      zero_u64(c, dbg, 4);
       AMFMM_HIP(hipEventCreate(&e0));
       AMFMM_HIP(hipEventCreate(&e1));
       AMFMM_HIP(hipEventRecord(e0, c.stream));
     }
-    hipLaunchKernelGGL(ext == kExtLearned ? k_walk_count<kExtLearned>
-                       : (ext == kExtMultipole ? k_walk_count<kExtMultipole> : k_walk_count<kExtBase>), dim3(kgrid), dim3(kBS), 0, c.stream, t, c0, kn, chunk, (const int32_t*)kcell,
-                       (const int64_t*)cbase, (const int64_t*)gbeg, (const int32_t*)gcnt, fy, km, kp, kq, gq, qcap,
-                       dbg);
+    hipLaunchKernelGGL(ext == kExtLearned     ? k_walk_stage<kExtLearned>
+                       : ext == kExtMultipole ? k_walk_stage<kExtMultipole>
+                                              : k_walk_stage<kExtBase>,
+                       dim3(kgrid), dim3(kBS), 0, c.stream, t, c0, kn, chunk, (const int32_t*)kcell,
+                       (const int64_t*)cbase, (const int64_t*)gbeg, (const int32_t*)gcnt, fy,
+                       (const StageLayout*)sl_dev, km, kp, kq, kov, nov, gq, qcap, dbg);
     AMFMM_HIP(hipGetLastError());
     if (debug) AMFMM_HIP(hipEventRecord(e1, c.stream));
     scan_i64(c, km, mex, kn);
@@ -788,11 +995,11 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
     hipLaunchKernelGGL(k_walk_groups, dim3(blocks_for(nl, kBS)), dim3(kBS), 0, c.stream, t, c0, nl, c0n,
                        (const int64_t*)cbase, (const int64_t*)qex, (const int64_t*)nbase, gbeg_n, gcnt_n);
     hipLaunchKernelGGL(k_gather_totals, dim3(1), dim3(1), 0, c.stream, (const int64_t*)mex, (const int64_t*)pex,
-                       (const int64_t*)nbase, kn, nl, tot);
+                       (const int64_t*)qex, (const int64_t*)nbase, kn, nl, tot);
     AMFMM_HIP(hipGetLastError());
-    AMFMM_HIP(hipMemcpyAsync(tot_host, tot, sizeof(int64_t) * 3, hipMemcpyDeviceToHost, c.stream));
+    AMFMM_HIP(hipMemcpyAsync(tot_host, tot, sizeof(int64_t) * 5, hipMemcpyDeviceToHost, c.stream));
     AMFMM_HIP(hipStreamSynchronize(c.stream));
-    const int64_t mt = tot_host[0], pt = tot_host[1], Fn = tot_host[2];
+    const int64_t mt = tot_host[0], pt = tot_host[1], Fn = tot_host[2], qt = tot_host[3], novh = tot_host[4];
     if (debug) {
       unsigned long long h[4];
       AMFMM_HIP(hipMemcpy(h, dbg, sizeof(h), hipMemcpyDeviceToHost));
@@ -801,10 +1008,16 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
       fprintf(stderr,
-              "walk level %d: cells %d entries %lld far %lld near %lld next %lld | count pass %.3f ms, steps %llu, "
-              "pairs %llu, deep %llu\n",
-              lev, nl, (long long)F, (long long)mt, (long long)pt, (long long)Fn, ms, h[0], h[2], h[1]);
+              "walk level %d: cells %d entries %lld chunks %lld (x%d) far %lld near %lld next %lld | staging pass "
+              "%.3f ms, steps %llu, pairs %llu, deep %llu, overflowed %lld\n",
+              lev, nl, (long long)F, (long long)kn, chunk, (long long)mt, (long long)pt, (long long)Fn, ms, h[0],
+              h[2], h[1], (long long)novh);
     }
+    prev[0] = (double)mt / (double)F;
+    prev[1] = (double)pt / (double)F;
+    prev[2] = (double)qt / (double)F;
+    have_prev = true;
+    if ((size_t)lev < lo.size()) std::copy(prev, prev + 3, c.walk_ratio.begin() + 3 * (size_t)lev);
     if (Fn >= (int64_t(1) << 34)) throw BudgetExceeded();
     if (c.walk_budget &&
         (double)sizeof(int32_t) * (double)(far_base + mt + near_base + pt + 2 * Fn) > (double)c.walk_budget)
@@ -814,11 +1027,20 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
     int32_t* near_src = (int32_t*)ensure_keep(c, c.near_src, sizeof(int32_t) * (near_base + pt + 1),
                                               sizeof(int32_t) * near_base);
     int32_t* fy_n = (int32_t*)ensure(c, c.fy2, sizeof(int32_t) * (Fn + 1));
-    hipLaunchKernelGGL(ext == kExtLearned ? k_walk_emit<kExtLearned>
-                       : (ext == kExtMultipole ? k_walk_emit<kExtMultipole> : k_walk_emit<kExtBase>), dim3(kgrid), dim3(kBS), 0, c.stream, t, c0, kn, chunk, (const int32_t*)kcell,
-                       (const int64_t*)cbase, (const int64_t*)gbeg, (const int32_t*)gcnt, fy, (const int64_t*)mex,
-                       (const int64_t*)pex, (const int64_t*)qex, (const int64_t*)nbase, far_base, near_base, far_src,
-                       near_src, fy_n, gq, qcap);
+    if (novh < kn)
+      hipLaunchKernelGGL(k_walk_compact, dim3(blocks_for(kn, kBS / 64)), dim3(kBS), 0, c.stream, t, c0, kn, chunk,
+                         (const int32_t*)kcell, (const int64_t*)cbase, (const int64_t*)gbeg, (const int32_t*)gcnt,
+                         (const StageLayout*)sl_dev, (const int64_t*)mex,
+                         (const int64_t*)pex, (const int64_t*)qex, (const int64_t*)nbase, (const int32_t*)kov,
+                         far_base, near_base, far_src, near_src, fy_n);
+    if (novh > 0)
+      hipLaunchKernelGGL(ext == kExtLearned     ? k_walk_emit<kExtLearned>
+                         : ext == kExtMultipole ? k_walk_emit<kExtMultipole>
+                                                : k_walk_emit<kExtBase>,
+                         dim3(kgrid), dim3(kBS), 0, c.stream, t, c0, kn, chunk, (const int32_t*)kcell,
+                         (const int64_t*)cbase, (const int64_t*)gbeg, (const int32_t*)gcnt, fy, (const int64_t*)mex,
+                         (const int64_t*)pex, (const int64_t*)qex, (const int64_t*)nbase, (const int32_t*)kov,
+                         far_base, near_base, far_src, near_src, fy_n, gq, qcap);
     AMFMM_HIP(hipGetLastError());
     far_base += mt;
     near_base += pt;

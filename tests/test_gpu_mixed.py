@@ -76,10 +76,23 @@ def test_mixed_balances_and_truth():
 
 
 def test_mixed_batched_matches_whole():
-    """The batched walk gives the same mixed-precision result bit for bit."""
+    """The batched walk selects the same pairs as the whole walk (the same
+    counts); a cell's pairs may be summed in another order (the frontier of a
+    level is cut into work chunks by its size), which under mixed precision
+    moves results by FP32 rounding only: p99 2e-6 and max 1e-5 of gabs."""
     x, y, z, m = W.plummer(1 << 16, seed=12)
     X, Y, Z, M = to_dev(x, y, z, m)
-    a1 = amfmm.Solver(precision=amfmm.MIXED).solve_gravity(X, Y, Z, M, 0.4)
-    a2 = amfmm.Solver(precision=amfmm.MIXED, list_bytes=1 << 20).solve_gravity(X, Y, Z, M, 0.4)
-    for u, v in zip(a1, a2):
-        assert torch.equal(u, v)
+    s1 = amfmm.Solver(precision=amfmm.MIXED)
+    a1 = s1.solve_gravity(X, Y, Z, M, 0.4)
+    s2 = amfmm.Solver(precision=amfmm.MIXED, list_bytes=1 << 20)
+    a2 = s2.solve_gravity(X, Y, Z, M, 0.4)
+    c1, c2 = s1.get_counts(), s2.get_counts()
+    for k in ("near_interactions", "far_evaluations"):
+        assert c1[k] == c2[k] > 0
+    idx = W.sample_targets(len(x), 1024, seed=99)
+    _, _, gabs = orc.direct(x, y, z, m, idx)
+    h1 = np.stack([v.cpu().numpy() for v in a1[:3]])[:, idx]
+    h2 = np.stack([v.cpu().numpy() for v in a2[:3]])[:, idx]
+    e = np.linalg.norm(h1 - h2, axis=0) / gabs
+    say(f"batched against whole (mixed): p99 {np.percentile(e, 99):.2e}, max {e.max():.2e}")
+    assert np.percentile(e, 99) <= 2e-6 and e.max() <= 1e-5
