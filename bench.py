@@ -35,8 +35,14 @@ NEAR_FLOPS = 20  # per directed particle interaction (3 sub, 5 r^2, 1 rsqrt, 2 r
 # fma = 2): R (3) + coefficients (147 with a one-instruction FP32 rsqrt, 156
 # with the refined FP64 one) + correction (157, FP64)
 FAR_FLOPS = {"fp64": 3 + 156 + 157, "mixed": 3 + 147 + 157}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_far_traffic_plummer16m.json")
-FAR_SOURCES = [os.path.join(ROOT, "paper_1706_06989_amd", "csrc", f) for f in ("eval.hip", "device_math.h")]
+WALK_BYTES = 64  # per candidate pair of the walk: one cell record read to decide it
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_plummer16m.json")
+# sources each kernel's code comes from (a traffic figure holds while they are unchanged)
+KERNEL_SOURCES = {
+    "walk": ("walk.hip", "device_math.h", "learned.h", "internal.h"),
+    "far": ("eval.hip", "device_math.h", "internal.h"),
+    "near": ("near.hip", "device_math.h", "internal.h"),
+}
 
 
 def parse():
@@ -62,24 +68,25 @@ def parse():
     return p.parse_args()
 
 
-def source_hash():
+def source_hash(kernel):
     h = hashlib.sha256()
-    for f in FAR_SOURCES:
-        h.update(open(f, "rb").read())
+    for f in KERNEL_SOURCES[kernel]:
+        h.update(open(os.path.join(ROOT, "paper_1706_06989_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def far_traffic():
-    """HBM bytes per k_far launch from the committed counter summary (FETCH_SIZE
-    and WRITE_SIZE, scaled by the copy calibration), or None when absent or
-    taken on other far-field sources."""
+def traffic(kernel, config):
+    """HBM bytes per launch of a kernel from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by the copy calibration), or None when
+    absent, taken on other sources of that kernel or on another configuration."""
     try:
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if t.get("source_hash") != source_hash():
+    k = t.get("kernels", {}).get(kernel)
+    if not k or k.get("source_hash") != source_hash(kernel) or t.get("config") != config:
         return None
-    return t.get("bytes_per_launch")
+    return k.get("bytes_per_launch")
 
 
 def cpu_baseline(n, theta, criterion, eps, theta_max, seed=4):
@@ -197,29 +204,42 @@ def main():
         pilot_info = {"criterion": "geometric", "theta": a.pilot_theta, "ms": round(pphases["total"], 3),
                       "p99_rel_force_error": float(np.percentile(pe, 99))}
 
-    # Roofline of the dominant kernel, the far field (k_far: the largest single
-    # kernel of the step), and of the near field beside it.  Both phases are
-    # bracketed by HIP events on the library's stream; a phase holds exactly
-    # that kernel's launches, so phase time / launches is the average launch.
-    far_ms = phases["far"]
-    near_ms = phases["near+eval"]
-    far_flops = FAR_FLOPS[a.precision] * counts["far_evaluations"]
-    near_flops = NEAR_FLOPS * counts["near_interactions"]
-    far_tf = far_flops / (far_ms * 1e-3) / 1e12
-    near_tf = near_flops / (near_ms * 1e-3) / 1e12
-    tb = far_traffic()
-    roof = {"kernel": "k_far (far field: eqs. 2-4 + correction per directed cell pair)", "bound": "alu",
-            "achieved": round(far_tf, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(far_tf / PEAK_FP64_TFLOPS, 4),
-            "traffic": tb,
-            "algorithmic": f"{FAR_FLOPS[a.precision]} flop x {counts['far_evaluations']} directed pairs "
-                           f"per step over {counts['far_launches']} launches",
-            "avg_launch_ms": round(far_ms / max(1, counts["far_launches"]), 3),
-            "near_field": {"kernel": "k_near", "bound": "alu", "achieved": round(near_tf, 3),
-                           "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                           "frac": round(near_tf / PEAK_FP64_TFLOPS, 4),
-                           "algorithmic": f"{NEAR_FLOPS} flop x {counts['near_interactions']} interactions",
-                           "avg_launch_ms": round(near_ms / max(1, counts["near_launches"]), 3)}}
+    # Roofline of the step's three large kernels; the one with the most time is
+    # the dominant kernel (the top-level object), the others sit beside it.
+    # Each is bracketed by HIP events on the library's stream (a phase holds
+    # exactly that kernel's launches), so phase time / launches is the average
+    # launch duration.
+    cfg_key = {"n": a.n, "criterion": a.criterion, "eps": a.eps if field else None,
+               "theta": a.theta, "precision": a.precision, "variant": a.variant}
+    kern = {
+        "walk": {"kernel": "k_walk_stage (the walk's one pass: a decision per candidate pair, terminal pairs "
+                           "staged)", "bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM_GBS,
+                 "ms": phases["walk-pass"], "launches": counts["walk_pass_launches"],
+                 "work": WALK_BYTES * counts["walk_candidates"] / 1e9,
+                 "algorithmic": f"{WALK_BYTES} B (one cell record) x {counts['walk_candidates']} candidate pairs"},
+        "far": {"kernel": "k_far (far field: eqs. 2-4 + correction per directed cell pair)", "bound": "alu",
+                "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS, "ms": phases["far"], "launches": counts["far_launches"],
+                "work": FAR_FLOPS[a.precision] * counts["far_evaluations"] / 1e12,
+                "algorithmic": f"{FAR_FLOPS[a.precision]} flop x {counts['far_evaluations']} directed pairs"},
+        "near": {"kernel": "k_near (near field + evaluation at the particles)", "bound": "alu", "unit": "TFLOP/s",
+                 "peak": PEAK_FP64_TFLOPS, "ms": phases["near+eval"], "launches": counts["near_launches"],
+                 "work": NEAR_FLOPS * counts["near_interactions"] / 1e12,
+                 "algorithmic": f"{NEAR_FLOPS} flop x {counts['near_interactions']} interactions"},
+    }
+
+    def roof(name):
+        k = kern[name]
+        achieved = k["work"] / (k["ms"] * 1e-3)
+        tb = traffic(name, cfg_key)
+        launches = max(1, k["launches"])
+        return {"kernel": k["kernel"], "bound": k["bound"], "achieved": round(achieved, 3), "peak": k["peak"],
+                "unit": k["unit"], "frac": round(achieved / k["peak"], 4), "traffic": tb,
+                "algorithmic": k["algorithmic"] + f" per step over {k['launches']} launches",
+                "avg_launch_ms": round(k["ms"] / launches, 3), "step_ms": round(k["ms"], 3)}
+
+    dominant = max(kern, key=lambda n: kern[n]["ms"])
+    roofline = roof(dominant)
+    roofline["others"] = {n: roof(n) for n in kern if n != dominant}
 
     cpu = None
     if a.cpu_n > 0:
@@ -241,7 +261,7 @@ def main():
                    "meets_1e-4_p99": bool(np.percentile(eps, 99) <= 1e-4),
                    "force_balance": fbal, "torque_balance": tbal,
                    "phase_ms": {k: round(v, 3) for k, v in phases.items()}, "counts": counts},
-        "roofline": roof, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu,
     }
     if a.copy_calibration:
         # 1 GiB read + 1 GiB written by one copy kernel per call

@@ -201,12 +201,13 @@ int amfmm_mlp_train(amfmm_ctx* ctx, int64_t n, const float* feats, const float* 
                     double tau, double* last_loss);
 
 /* ---- introspection (host buffers owned by the caller; synchronising) ---- */
-/* counts[0..9] = cells, depth, far-field pairs, near-field pairs (unordered,
+/* counts[0..11] = cells, depth, far-field pairs, near-field pairs (unordered,
  * as amfmm_get_lists returns them), leaves, particles, near-field particle
  * interactions (directed, i != j), far-field evaluations (directed cell
  * pairs), far-field kernel launches and near-field kernel launches of the
- * last evaluation */
-int amfmm_get_counts(amfmm_ctx* ctx, int64_t* counts10);
+ * last evaluation, candidate pairs of the last walk (directed pairs it took a
+ * decision on, self pairs included) and launches of the walk's pass kernel */
+int amfmm_get_counts(amfmm_ctx* ctx, int64_t* counts12);
 /* sorted keys (n), permutation perm[s] = caller index of sorted particle s (n),
  * and per cell (in (level, first particle) order): level, begin, count,
  * parent, first child (-1 for leaves), child count.  Any pointer may be NULL. */
@@ -219,7 +220,9 @@ int amfmm_get_moments(amfmm_ctx* ctx, double* out21);
 int amfmm_get_lists(amfmm_ctx* ctx, int32_t* far_ab, int32_t* near_ab);
 /* milliseconds of the phases of the last solve: [0] validate+bbox, [1] keys+sort,
  * [2] tree levels, [3] moments, [4] walk, [5] far field, [6] push-down,
- * [7] near field + evaluation at particles, [8] total.  Returns the count written. */
+ * [7] near field + evaluation at particles, [8] total, [9] the walk's pass
+ * over the pairs (its staging kernel alone; part of [4]).  Returns the count
+ * written (at most cap, at most 10). */
 int amfmm_get_phase_times(amfmm_ctx* ctx, double* ms, int32_t cap);
 
 const char* amfmm_status_string(int status);

@@ -21,7 +21,7 @@ FP64, MIXED = 0, 1
 GEOMETRIC, ESTIMATE, LEARNED, MULTIPOLE = 0, 1, 2, 3
 MLP_PARAMS, MLP_MODEL = 4801, 4833
 PHASES = ["validate+bbox", "keys+sort", "tree", "moments", "walk", "far", "push-down",
-          "near+eval", "total"]
+          "near+eval", "total", "walk-pass"]
 
 
 class amfmm_options(C.Structure):
@@ -277,10 +277,11 @@ class Solver:
         return float(out[0]), float(out[1])
 
     def get_counts(self):
-        c = np.zeros(10, np.int64)
+        c = np.zeros(12, np.int64)
         self._check(lib().amfmm_get_counts(self._h, _ptr(c, C.c_int64)))
         keys = ["cells", "depth", "far_pairs", "near_pairs", "leaves", "particles",
-                "near_interactions", "far_evaluations", "far_launches", "near_launches"]
+                "near_interactions", "far_evaluations", "far_launches", "near_launches",
+                "walk_candidates", "walk_pass_launches"]
         return dict(zip(keys, (int(v) for v in c)))
 
     def get_tree(self):

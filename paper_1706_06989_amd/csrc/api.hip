@@ -320,10 +320,12 @@ int amfmm_walk(amfmm_ctx* ctx, double theta) {
   return guarded(ctx, [&](Ctx& c) -> int { return walk_impl(c, theta); });
 }
 
+// counters of an evaluation: near interactions (counters[0]) and launches
+// (the walk's own are reset when a walk starts)
 static void zero_counters(Ctx& c) {
   c.far_launches = c.near_launches = 0;
   void* p = amfmm::ensure(c, c.counters, 64);
-  amfmm::zero_u64(c, (unsigned long long*)p, 8);
+  amfmm::zero_u64(c, (unsigned long long*)p, 1);
 }
 
 // far field, push-down and near field over all cells, from kept lists
@@ -428,7 +430,13 @@ static void solve_batched(Ctx& c, double theta, double* ax, double* ay, double* 
   std::vector<int64_t> bbeg(nL);
   c.walk_budget = (size_t)budget;
   int32_t x0 = 0;
-  int64_t plim = c.batch_hint > 0 ? std::min(c.batch_hint, pmax) : pmax;
+  // batch size in particles: the last solve's, never above 9/10 of a size
+  // that has exceeded the budget for this problem
+  auto capped = [&](int64_t v) {
+    v = std::min(v, pmax);
+    return c.batch_fail > 0 ? std::max<int64_t>(1, std::min(v, c.batch_fail - c.batch_fail / 10)) : v;
+  };
+  int64_t plim = capped(c.batch_hint > 0 ? c.batch_hint : pmax);
   while (x0 < nL) {
     int32_t x1 = x0;
     int64_t parts = 0;
@@ -463,11 +471,12 @@ static void solve_batched(Ctx& c, double theta, double* ax, double* ay, double* 
       // too many pairs for one batch: halve it (a single cell that does not
       // fit is reported as out of memory)
       if (x1 - x0 == 1) throw Error(AMFMM_E_OOM, "one subtree's interaction lists exceed the list budget");
+      c.batch_fail = c.batch_fail > 0 ? std::min(c.batch_fail, parts) : parts;
       plim = std::max<int64_t>(1, parts / 2);
       continue;
     }
     c.batch_hint = plim;
-    plim = std::min(pmax, plim + plim / 4);
+    plim = capped(plim + plim / 4);
     c.far_evals += bfb;
     mark(c, kPhFar);
     for (int l = Ls; l <= c.depth; ++l) far_field(c, blo[l], bhi[l]);
@@ -501,7 +510,7 @@ int amfmm_solve_gravity(amfmm_ctx* ctx, int64_t n, const double* x, const double
     // a context that needed batches for this size and criterion goes straight to them
     const bool same = c.hint_n == n && c.hint_theta == theta && c.hint_mode == c.opt.criterion &&
                       c.hint_tol == c.opt.error_tol;
-    if (!same) c.batch_hint = 0;
+    if (!same) c.batch_hint = c.batch_fail = 0;
     bool whole = (need <= (double)budget || c.depth < 3) && !(same && c.batch_hint > 0);
     if (whole) {
       amfmm::mark(c, amfmm::kPhWalk);
@@ -568,6 +577,8 @@ int amfmm_get_counts(amfmm_ctx* ctx, int64_t* counts) {
     counts[7] = c.far_evals;
     counts[8] = c.far_launches;
     counts[9] = c.near_launches;
+    counts[10] = c.walk_candidates;
+    counts[11] = c.pass_launches;
     if (c.counters.p) {
       unsigned long long h = 0;
       AMFMM_HIP(hipMemcpyAsync(&h, c.counters.p, sizeof(h), hipMemcpyDeviceToHost, c.stream));
@@ -695,7 +706,7 @@ int amfmm_get_phase_times(amfmm_ctx* ctx, double* ms, int32_t cap) {
   return guarded(ctx, [&](Ctx& c) -> int {
     if (!ms || cap < 0) return fail(c, AMFMM_E_INVALID, "bad arguments");
     AMFMM_HIP(hipStreamSynchronize(c.stream));
-    double t[9] = {};
+    double t[amfmm::kPhEnd + 1] = {};
     for (size_t i = 0; i + 1 < c.ev_used; ++i) {
       float v = 0.f;
       if (hipEventElapsedTime(&v, c.ev_pool[i], c.ev_pool[i + 1]) != hipSuccess) {
@@ -705,9 +716,16 @@ int amfmm_get_phase_times(amfmm_ctx* ctx, double* ms, int32_t cap) {
       const int ph = c.ev_phase[i];
       if (ph >= 0 && ph < amfmm::kPhEnd) t[ph] += v;
     }
-    for (int i = 0; i < 8; ++i) t[8] += t[i];
-    int k = std::min<int32_t>(cap, 9);
-    for (int i = 0; i < k; ++i) ms[i] = t[i];
+    // [0..7] phases (the walk including its pass), [8] total, [9] walk pass
+    const double pass = t[amfmm::kPhWalkPass];
+    t[amfmm::kPhWalk] += pass;
+    double out[10];
+    for (int i = 0; i < 8; ++i) out[i] = t[i];
+    out[8] = 0.0;
+    for (int i = 0; i < 8; ++i) out[8] += t[i];
+    out[9] = pass;
+    int k = std::min<int32_t>(cap, 10);
+    for (int i = 0; i < k; ++i) ms[i] = out[i];
     return k;
   });
 }

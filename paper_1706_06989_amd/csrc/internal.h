@@ -101,10 +101,13 @@ struct Ctx {
   int64_t* pinned = nullptr;  // small pinned host buffer for read-backs
   int64_t far_evals = 0;      // directed far-field evaluations of the last solve
   int64_t far_launches = 0, near_launches = 0;  // kernel launches of the last evaluation
+  int64_t pass_launches = 0;    // launches of the walk's pass kernel in the last walk
+  int64_t walk_candidates = 0;  // pairs the last walk decided on (batches over budget excluded)
   bool batched = false;       // last solve ran batch by batch (lists not kept)
   size_t walk_budget = 0;     // bytes of lists + frontier a walk may take (0 = unlimited)
   // batch size that worked for the last solve of the same size and criterion
   int64_t batch_hint = 0, hint_n = 0;
+  int64_t batch_fail = 0;  // smallest batch (particles) that exceeded the budget, same problem
   double hint_theta = 0.0, hint_tol = 0.0;
   int hint_mode = -1;
   double theta = 0.5;
@@ -192,7 +195,9 @@ void balance(Ctx& c, int64_t n, const double* x, const double* y, const double* 
              const double* m, const double* ax, const double* ay, const double* az, double* out);
 
 // phases of a solve (amfmm_get_phase_times order)
-enum Phase { kPhValidate = 0, kPhSort, kPhTree, kPhMoments, kPhWalk, kPhFar, kPhPush, kPhNear, kPhEnd };
+// kPhWalkPass: the walk's one pass over the pairs (its staging kernel), a part
+// of the walk that is also reported on its own
+enum Phase { kPhValidate = 0, kPhSort, kPhTree, kPhMoments, kPhWalk, kPhFar, kPhPush, kPhNear, kPhWalkPass, kPhEnd };
 void mark(Ctx& c, int phase);  // records an event; phase kPhEnd closes the timeline
 
 inline unsigned blocks_for(int64_t n, int threads) {

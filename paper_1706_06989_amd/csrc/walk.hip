@@ -181,8 +181,9 @@ __device__ inline int decide(const TreeView& t, int32_t X, const WalkCell& a, in
   return X < Y ? kSplitX : kSplitY;
 }
 
-// Visits the terminal pairs of entry (X, Y) in depth-first order (children of
-// Y in octant order) and calls f(kind, Y') for each.
+// Visits the pairs of entry (X, Y) in depth-first order (children of Y in
+// octant order) and calls f(kind, Y') for each decision: the terminal ones
+// and the opened ones (kSplitY, Y itself first).
 template <int EXT, typename F>
 __device__ inline void traverse(const TreeView& t, int32_t X, int32_t Y, F&& f) {
   const WalkCell a = load_cell(t.rec, X);
@@ -199,6 +200,7 @@ __device__ inline void traverse(const TreeView& t, int32_t X, int32_t Y, F&& f) 
   for (;;) {
     int d = decide<EXT>(t, X, a, cur, b);
     if (d == kSplitY) {
+      f(kSplitY, cur);
       cur = b.ch0;
       b = load_cell(t.rec, cur);
       continue;
@@ -389,14 +391,34 @@ __device__ inline void wave_sync() {
 
 // Staging of a level's terminal pairs.  Every chunk owns a window of each
 // staging array (far, near, split-X bases) sized by the pairs its entries are
-// expected to produce; a chunk that outgrows a window takes one spill region
-// of twice the window from that list's shared pool (one atomic).  A chunk that
-// outgrows that too, or finds the pool exhausted, stops writing (its counts
-// still run on) and is walked again by the emitting kernel.
+// expected to produce; a chunk that outgrows a window continues in spill
+// regions taken from that list's shared pool (one atomic each), of doubling
+// sizes: region j holds u 2^j entries, u the power of two at least twice the
+// window and at least kSpillMin, so kRegions regions hold 255 u.  A chunk that
+// outgrows them, or finds the pool exhausted, stops writing (its counts still
+// run on) and is walked again by the emitting kernel.
+constexpr int64_t kSpillMin = 1024;
+constexpr int kRegions = 8;
+
+// log2 of the first spill region's size for a window of `cap` entries
+__host__ __device__ inline int spill_shift(int64_t cap) {
+  int sh = 10;  // kSpillMin
+  while ((int64_t(1) << sh) < 2 * cap) ++sh;
+  return sh;
+}
+
+// spill region of position g past the window, and the offset inside it
+__device__ inline int spill_region(int64_t g, int sh, int64_t* off) {
+  const uint64_t q = (uint64_t)(g >> sh) + 1;
+  const int j = 63 - __builtin_clzll(q);
+  *off = g - (((int64_t(1) << j) - 1) << sh);
+  return j;
+}
+
 struct StageLayout {
   int32_t* win[3];             // window arrays
   int32_t* spill[3];           // spill pools
-  int64_t* ksec;               // per chunk and list: spill offset, -1 = none
+  int64_t* ksec;               // per chunk and list: kRegions spill region offsets
   unsigned long long* used;    // spill entries handed out, per list
   int64_t spill_cap[3];        // entries in each spill pool
   int64_t cap16[3];            // window capacity per entry, in 1/16
@@ -424,6 +446,7 @@ struct EmitDst {
   int32_t* win[3];
   int64_t wcap[3];
   int64_t chunk;
+  int64_t* lreg;  // this wave's spill region offsets in LDS (3 x kRegions)
 };
 
 enum : int { kStage = 0, kEmit = 1 };
@@ -434,23 +457,29 @@ enum : int { kStage = 0, kEmit = 1 };
 // pushes Y's children to the queue; when the queue is full the lane descends
 // Y's subtree itself.  The order is a fixed function of the inputs, so the
 // staging run and an emitting run visit the same pairs in the same order.
-// Returns the chunk's totals in tm, tp, tq, and (STAGE) whether it ran out
-// of room.
+// Returns the chunk's totals in tm, tp, tq, the pairs it decided on (its
+// candidate pairs, taken from the frontier or the queue, self pairs included)
+// in td, and (STAGE) whether it ran out of room.
 template <int PASS, int EXT, typename Q>
 __device__ inline bool wave_walk(const TreeView& t, int32_t X, const WalkCell& cx, const int32_t* __restrict__ fy,
                                  int64_t b, int32_t n, Q qbuf, int32_t qcap, int64_t& tm, int64_t& tp, int64_t& tq,
-                                 EmitDst dst, unsigned long long* dbg) {
+                                 int64_t& td, EmitDst dst, unsigned long long* dbg) {
   const int32_t qmask = qcap - 1;
   const int lane = threadIdx.x & 63;
   int32_t head = 0, tail = 0, fpos = 0;
   int64_t fo = dst.fo, no = dst.no, B = dst.B0;
   unsigned long long dsteps = 0, ddeep = 0, dpairs = 0;
-  int64_t sec[3] = {-1, -1, -1};  // STAGE: spill offsets (wave-uniform)
-  bool ovf = false;                // STAGE: out of room; writes stop
+  int32_t nreg[3] = {0, 0, 0};  // STAGE: spill regions held (wave-uniform)
+  bool ovf = false;              // STAGE: out of room; writes stop
   auto stage_put = [&](int w, int64_t f, int32_t v) {
     if (!ovf) {
-      if (f < dst.wcap[w]) dst.win[w][f] = v;
-      else dst.sl->spill[w][sec[w] + (f - dst.wcap[w])] = v;
+      if (f < dst.wcap[w]) {
+        dst.win[w][f] = v;
+      } else {
+        int64_t off;
+        const int j = spill_region(f - dst.wcap[w], spill_shift(dst.wcap[w]), &off);
+        dst.sl->spill[w][dst.lreg[w * kRegions + j] + off] = v;
+      }
     }
   };
   auto put_far = [&](int64_t f, int32_t v) {
@@ -471,20 +500,26 @@ __device__ inline bool wave_walk(const TreeView& t, int32_t X, const WalkCell& c
   // STAGE: room for positions below `end` of list w
   auto reserve = [&](int w, int64_t end) {
     const int64_t cap = dst.wcap[w];
-    if (ovf || end <= cap || (sec[w] >= 0 && end <= 3 * cap)) return;
-    if (sec[w] >= 0 || end > 3 * cap) {
-      ovf = true;
-      return;
+    const int sh = spill_shift(cap);
+    while (!ovf && end > cap + ((((int64_t)1 << nreg[w]) - 1) << sh)) {
+      if (nreg[w] == kRegions) {
+        ovf = true;
+        break;
+      }
+      const int64_t size = int64_t(1) << (sh + nreg[w]);
+      unsigned long long base = 0;
+      if (lane == 0) base = atomicAdd(&dst.sl->used[w], (unsigned long long)size);
+      base = __shfl(base, 0, 64);
+      if (base + (unsigned long long)size > (unsigned long long)dst.sl->spill_cap[w]) {
+        ovf = true;
+        break;
+      }
+      if (lane == 0) {
+        dst.lreg[w * kRegions + nreg[w]] = (int64_t)base;
+        dst.sl->ksec[(3 * dst.chunk + w) * kRegions + nreg[w]] = (int64_t)base;
+      }
+      ++nreg[w];
     }
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(&dst.sl->used[w], (unsigned long long)(2 * cap));
-    base = __shfl(base, 0, 64);
-    if (base + (unsigned long long)(2 * cap) > (unsigned long long)dst.sl->spill_cap[w]) {
-      ovf = true;
-      return;
-    }
-    sec[w] = (int64_t)base;
-    if (lane == 0) dst.sl->ksec[3 * dst.chunk + w] = sec[w];
   };
   while (head < tail || fpos < n) {
     int32_t Y = -1;
@@ -498,6 +533,7 @@ __device__ inline bool wave_walk(const TreeView& t, int32_t X, const WalkCell& c
       fpos += k;
     }
     wave_sync();  // queue slots just read may be reused by this step's pushes
+    td += __popcll(__ballot(Y >= 0));
     int32_t m = 0, p = 0, q = 0, push = 0, ych0 = 0;
     bool self = false;
     if (Y >= 0) {
@@ -534,12 +570,21 @@ __device__ inline bool wave_walk(const TreeView& t, int32_t X, const WalkCell& c
       ddeep += __popcll(dm);
       dpairs += __popcll(ym);
     }
+    int32_t nd = 0;  // decisions inside a descent
     if (deep)
       traverse<EXT>(t, X, Y, [&](int d, int32_t) {
         m += d == kAccept;
         p += d == kNear;
         q += d == kSplitX;
+        ++nd;
       });
+    if (__ballot(deep)) {
+      // candidate pairs decided inside descents (the entry's own, decided
+      // again first, is counted already)
+      int32_t ndt;
+      (void)wave_excl_scan(deep ? nd - 1 : 0, &ndt);
+      td += ndt;
+    }
     int32_t Tm, Tp, Tq;
     const int32_t om = wave_excl_scan(m, &Tm);
     const int32_t op = wave_excl_scan(p, &Tp);
@@ -548,13 +593,14 @@ __device__ inline bool wave_walk(const TreeView& t, int32_t X, const WalkCell& c
       reserve(0, fo + Tm);
       reserve(1, no + Tp);
       reserve(2, B + Tq);
+      wave_sync();  // new region offsets in LDS before they are read
     }
     if (deep) {
       int64_t f = fo + om, g = no + op, bb = B + oq;
       traverse<EXT>(t, X, Y, [&](int d, int32_t Z) {
         if (d == kAccept) put_far(f++, Z);
         else if (d == kNear) put_near(g++, Z);
-        else put_split(bb++, Z);
+        else if (d == kSplitX) put_split(bb++, Z);
       });
     } else if (self) {
       if (p) put_near(no + op, X);
@@ -610,9 +656,10 @@ __global__ void __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(EXT ==
                                                     const int32_t* __restrict__ fy, const StageLayout* __restrict__ sl,
                                                     int64_t* __restrict__ km, int64_t* __restrict__ kp,
                                                     int64_t* __restrict__ kq, int32_t* __restrict__ kov,
-                                                    unsigned long long* __restrict__ nov, int32_t* __restrict__ gq,
-                                                    int32_t qcap, unsigned long long* dbg) {
+                                                    int64_t* __restrict__ kd, unsigned long long* __restrict__ nov,
+                                                    int32_t* __restrict__ gq, int32_t qcap, unsigned long long* dbg) {
   __shared__ int32_t queue[kBS / 64][kQ];
+  __shared__ int64_t regions[kBS / 64][3 * kRegions];
   const int lane = threadIdx.x & 63;
   // wave-uniform (readfirstlane): the cell's record and bookkeeping are
   // loaded once per wave into scalar registers
@@ -624,20 +671,21 @@ __global__ void __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(EXT ==
   const int64_t e0 = (k - cbase[i]) * chunk;
   const int32_t n = (int32_t)min<int64_t>(chunk, gcnt[i] - e0);
   const int64_t e = gbeg[i] + e0;
-  EmitDst dst{0, 0, 0, 0, nullptr, nullptr, nullptr, 0, sl, {}, {}, k};
+  EmitDst dst{0, 0, 0, 0, nullptr, nullptr, nullptr, 0, sl, {}, {}, k, regions[threadIdx.x >> 6]};
 #pragma unroll
   for (int w = 0; w < 3; ++w) {
     const int64_t lo = stage_lo(*sl, w, e, k);
     dst.win[w] = sl->win[w] + lo;
     dst.wcap[w] = stage_lo(*sl, w, e + n, k + 1) - lo;
   }
-  int64_t tm = 0, tp = 0, tq = 0;
+  int64_t tm = 0, tp = 0, tq = 0, td = 0;
   bool over;
   if (gq)
-    over = wave_walk<kStage, EXT>(t, X, cx, fy, e, n, gq + k * qcap, qcap, tm, tp, tq, dst, dbg);
+    over = wave_walk<kStage, EXT>(t, X, cx, fy, e, n, gq + k * qcap, qcap, tm, tp, tq, td, dst, dbg);
   else
-    over = wave_walk<kStage, EXT>(t, X, cx, fy, e, n, queue[threadIdx.x >> 6], kQ, tm, tp, tq, dst, dbg);
+    over = wave_walk<kStage, EXT>(t, X, cx, fy, e, n, queue[threadIdx.x >> 6], kQ, tm, tp, tq, td, dst, dbg);
   if (lane == 0) {
+    kd[k] = td;
     km[k] = tm;
     kp[k] = tp;
     kq[k] = tq;
@@ -704,7 +752,10 @@ __global__ void __launch_bounds__(kBS) k_walk_compact(TreeView t, int32_t c0, in
   auto src = [&](int w, int64_t j) {
     const int64_t lo = stage_lo(sl, w, e, k);
     const int64_t cap = stage_lo(sl, w, e + n, k + 1) - lo;
-    return j < cap ? sl.win[w][lo + j] : sl.spill[w][sl.ksec[3 * k + w] + (j - cap)];
+    if (j < cap) return sl.win[w][lo + j];
+    int64_t off;
+    const int r = spill_region(j - cap, spill_shift(cap), &off);
+    return sl.spill[w][sl.ksec[(3 * k + w) * kRegions + r] + off];
   };
   const int64_t nm = mex[k + 1] - mex[k], np = pex[k + 1] - pex[k], nq = qex[k + 1] - qex[k];
   int32_t* df = far_src + far_base + mex[k];
@@ -743,13 +794,13 @@ __global__ void __launch_bounds__(kBS) k_walk_emit(TreeView t, int32_t c0, int64
   const int64_t e0 = (k - cbase[i]) * chunk;
   const int32_t n = (int32_t)min<int64_t>(chunk, gcnt[i] - e0);
   const int64_t S = qex[cbase[i + 1]] - qex[cbase[i]];
-  int64_t tm = 0, tp = 0, tq = 0;
+  int64_t tm = 0, tp = 0, tq = 0, td = 0;
   EmitDst dst{far_base + mex[k], near_base + pex[k], nbase[i], S, far_src, near_src, fy_n,
-              qex[k] - qex[cbase[i]], nullptr, {}, {}, k};
+              qex[k] - qex[cbase[i]], nullptr, {}, {}, k, nullptr};
   if (gq)
-    wave_walk<kEmit, EXT>(t, X, cx, fy, gbeg[i] + e0, n, gq + k * qcap, qcap, tm, tp, tq, dst, nullptr);
+    wave_walk<kEmit, EXT>(t, X, cx, fy, gbeg[i] + e0, n, gq + k * qcap, qcap, tm, tp, tq, td, dst, nullptr);
   else
-    wave_walk<kEmit, EXT>(t, X, cx, fy, gbeg[i] + e0, n, queue[threadIdx.x >> 6], kQ, tm, tp, tq, dst, nullptr);
+    wave_walk<kEmit, EXT>(t, X, cx, fy, gbeg[i] + e0, n, queue[threadIdx.x >> 6], kQ, tm, tp, tq, td, dst, nullptr);
 }
 
 __global__ void k_walk_init(int64_t* gbeg, int32_t* gcnt, int32_t* fy) {
@@ -759,11 +810,12 @@ __global__ void k_walk_init(int64_t* gbeg, int32_t* gcnt, int32_t* fy) {
 }
 
 __global__ void k_gather_totals(const int64_t* mex, const int64_t* pex, const int64_t* qex, const int64_t* nbase,
-                                int64_t kmax, int32_t nl, int64_t* out) {
+                                const int64_t* kdex, int64_t kmax, int32_t nl, int64_t* out) {
   out[0] = mex[kmax];
   out[1] = pex[kmax];
   out[2] = nbase[nl];
   out[3] = qex[kmax];
+  out[5] = kdex[kmax];
 }
 
 }  // namespace
@@ -841,15 +893,19 @@ void walk_start(Ctx& c) {
   hipLaunchKernelGGL(k_walk_init, dim3(1), dim3(1), 0, c.stream, gbeg, gcnt, as<int32_t>(c.fy));
   AMFMM_HIP(hipGetLastError());
   c.frontier = 1;
+  c.walk_candidates = 0;
+  c.pass_launches = 0;
 }
 
 // Staging room of a level.  Expected terminal pairs per entry: those the
 // level produced the last time it was walked under the same rule (windows
 // 1.5x that), else the level above's in this walk (2.5x), else a default;
-// plus a slack per chunk.  Spill pools: 0.75x the windows.  The whole is held
+// plus a slack per chunk.  Spill pools: as large as the windows, plus a
+// minimal spill region for one chunk in 16.  The whole is held
 // within `limit` bytes (scaled down; below a quarter of the wanted size no
 // staging: every chunk with output is emitted by the second pass).  Returns
-// the bytes: windows, spill pools, then the spill offsets (3 int64 per chunk).
+// the bytes: the spill region offsets (3 kRegions int64 per chunk), then
+// windows and spill pools.
 static size_t stage_layout(Ctx& c, int lev, int64_t F, int64_t kn, const double* prev, size_t limit,
                            StageLayout& sl) {
   double r[3] = {4.0, 1.0, 2.0}, alpha = 1.0;
@@ -861,11 +917,12 @@ static size_t stage_layout(Ctx& c, int lev, int64_t F, int64_t kn, const double*
     for (int w = 0; w < 3; ++w) r[w] = prev[w];
     alpha = 2.5;
   }
-  constexpr double kSpill = 0.75;
+  constexpr double kSpill = 1.0;
   const int64_t slack[3] = {32, 8, 8};
-  const double offsets = 3.0 * sizeof(int64_t) * (double)kn;
+  const double offsets = 3.0 * kRegions * sizeof(int64_t) * (double)kn;
   double ints = 0.0;
-  for (int w = 0; w < 3; ++w) ints += (1.0 + kSpill) * (alpha * r[w] * (double)F + (double)(kn * slack[w]));
+  for (int w = 0; w < 3; ++w)
+    ints += (1.0 + kSpill) * (alpha * r[w] * (double)F + (double)(kn * slack[w])) + (double)(kn / 16 * kSpillMin);
   double scale = 1.0;
   if (ints * sizeof(int32_t) + offsets > (double)limit)
     scale = std::max(0.0, ((double)limit - offsets) / (ints * sizeof(int32_t)));
@@ -875,10 +932,10 @@ static size_t stage_layout(Ctx& c, int lev, int64_t F, int64_t kn, const double*
     sl.cap16[w] = (int64_t)std::ceil(16.0 * alpha * r[w] * scale);
     sl.slack[w] = (int64_t)((double)slack[w] * scale);
     const int64_t win = ((sl.cap16[w] * F) >> 4) + kn * sl.slack[w] + 1;
-    sl.spill_cap[w] = (int64_t)(kSpill * (double)win);
+    sl.spill_cap[w] = (int64_t)(kSpill * (double)win + scale * (double)(kn / 16 * kSpillMin));
     n += (size_t)(win + sl.spill_cap[w]);
   }
-  return sizeof(int32_t) * n + 3 * sizeof(int64_t) * (size_t)kn + 64;
+  return sizeof(int32_t) * n + 3 * kRegions * sizeof(int64_t) * (size_t)kn + 64;
 }
 
 __global__ void k_set_layout(StageLayout v, StageLayout* out) { *out = v; }
@@ -896,15 +953,16 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
     std::copy(key, key + 4, c.walk_ratio_key);
     c.walk_ratio.assign(3 * lo.size(), -1.0);
   }
-  // staging room: a third of the free device memory, at most 48 GiB
+  // staging room: a third of the free device memory, at most 64 GiB
   size_t fr = 0, totm = 0;
   if (hipMemGetInfo(&fr, &totm) != hipSuccess) {
     (void)hipGetLastError();
     fr = size_t(16) << 30;
   }
-  const size_t stage_limit = std::min<size_t>(fr / 3 + c.stage.cap, size_t(48) << 30);
+  const size_t stage_limit = std::min<size_t>(fr / 3 + c.stage.cap, size_t(64) << 30);
   double prev[3];
   bool have_prev = false;
+  int64_t cand = 0;  // candidate pairs, counted once the levels are done (a batch over budget is walked again)
   int64_t F = c.frontier;
   int64_t* tot_host = c.pinned;
   for (int lev = lev_first; lev <= lev_last && F > 0; ++lev) {
@@ -920,13 +978,14 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
     int32_t *gcnt, *gcnt_n;
     group_ptrs(c, c.grp_cur, &gbeg, &gcnt);
     group_ptrs(c, 1 - c.grp_cur, &gbeg_n, &gcnt_n);
-    int64_t* w = (int64_t*)ensure(c, c.scratch2, sizeof(int64_t) * (4 * L + 7 * K + 48));
+    int64_t* w = (int64_t*)ensure(c, c.scratch2, sizeof(int64_t) * (4 * L + 9 * K + 48));
     int64_t *nck = w, *cbase = nck + L, *ns = cbase + L, *nbase = ns + L;
     int64_t *km = nbase + L, *kp = km + K, *kq = kp + K, *mex = kq + K, *pex = mex + K, *qex = pex + K;
     int32_t* kov = (int32_t*)(qex + K);
-    // [0..3] totals, [4] chunks out of room, [5..7] spill used, [8..11] debug
-    // counters, [16..] the staging layout
-    int64_t* tot = qex + 2 * K;
+    int64_t *kd = qex + 2 * K, *kdex = kd + K;  // candidate pairs per chunk, and their scan
+    // [0..3] totals, [4] chunks out of room, [5] candidate pairs, [8..10] spill
+    // used, [12..15] debug counters, [16..] the staging layout
+    int64_t* tot = qex + 4 * K;
     const int32_t* fy = as<int32_t>(c.fy);
     hipLaunchKernelGGL(k_chunk_counts, dim3(blocks_for(nl, kBS)), dim3(kBS), 0, c.stream, nl, (const int32_t*)gcnt,
                        chunk, nck);
@@ -955,7 +1014,7 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
     {
       int64_t* st64 = (int64_t*)ensure(c, c.stage, stage_bytes);
       sl.ksec = st64;
-      int32_t* st = (int32_t*)(st64 + 3 * kn);
+      int32_t* st = (int32_t*)(st64 + 3 * kRegions * kn);
       for (int w = 0; w < 3; ++w) {
         sl.win[w] = st;
         st += ((sl.cap16[w] * F) >> 4) + kn * sl.slack[w] + 1;
@@ -964,10 +1023,10 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
       }
     }
     unsigned long long* nov = (unsigned long long*)(tot + 4);
-    sl.used = nov + 1;
-    unsigned long long* dbg = debug ? (unsigned long long*)(tot + 8) : nullptr;
+    sl.used = (unsigned long long*)(tot + 8);
+    unsigned long long* dbg = debug ? (unsigned long long*)(tot + 12) : nullptr;
     StageLayout* sl_dev = (StageLayout*)(tot + 16);
-    zero_u64(c, nov, debug ? 8 : 4);
+    zero_u64(c, nov, 12);
     hipLaunchKernelGGL(k_set_layout, dim3(1), dim3(1), 0, c.stream, sl, sl_dev);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (debug) {
@@ -975,17 +1034,21 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
       AMFMM_HIP(hipEventCreate(&e1));
       AMFMM_HIP(hipEventRecord(e0, c.stream));
     }
+    mark(c, kPhWalkPass);
     hipLaunchKernelGGL(ext == kExtLearned     ? k_walk_stage<kExtLearned>
                        : ext == kExtMultipole ? k_walk_stage<kExtMultipole>
                                               : k_walk_stage<kExtBase>,
                        dim3(kgrid), dim3(kBS), 0, c.stream, t, c0, kn, chunk, (const int32_t*)kcell,
                        (const int64_t*)cbase, (const int64_t*)gbeg, (const int32_t*)gcnt, fy,
-                       (const StageLayout*)sl_dev, km, kp, kq, kov, nov, gq, qcap, dbg);
+                       (const StageLayout*)sl_dev, km, kp, kq, kov, kd, nov, gq, qcap, dbg);
+    ++c.pass_launches;
+    mark(c, kPhWalk);
     AMFMM_HIP(hipGetLastError());
     if (debug) AMFMM_HIP(hipEventRecord(e1, c.stream));
     scan_i64(c, km, mex, kn);
     scan_i64(c, kp, pex, kn);
     scan_i64(c, kq, qex, kn);
+    scan_i64(c, kd, kdex, kn);
     hipLaunchKernelGGL(k_walk_cells, dim3(blocks_for(nl, kBS)), dim3(kBS), 0, c.stream, t, c0, nl, c0n,
                        (const int64_t*)cbase, (const int64_t*)mex, (const int64_t*)pex, (const int64_t*)qex, far_base,
                        near_base, (int64_t*)c.far_start.p, (int32_t*)c.far_count.p, (int64_t*)c.near_start.p,
@@ -995,11 +1058,12 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
     hipLaunchKernelGGL(k_walk_groups, dim3(blocks_for(nl, kBS)), dim3(kBS), 0, c.stream, t, c0, nl, c0n,
                        (const int64_t*)cbase, (const int64_t*)qex, (const int64_t*)nbase, gbeg_n, gcnt_n);
     hipLaunchKernelGGL(k_gather_totals, dim3(1), dim3(1), 0, c.stream, (const int64_t*)mex, (const int64_t*)pex,
-                       (const int64_t*)qex, (const int64_t*)nbase, kn, nl, tot);
+                       (const int64_t*)qex, (const int64_t*)nbase, (const int64_t*)kdex, kn, nl, tot);
     AMFMM_HIP(hipGetLastError());
-    AMFMM_HIP(hipMemcpyAsync(tot_host, tot, sizeof(int64_t) * 5, hipMemcpyDeviceToHost, c.stream));
+    AMFMM_HIP(hipMemcpyAsync(tot_host, tot, sizeof(int64_t) * 6, hipMemcpyDeviceToHost, c.stream));
     AMFMM_HIP(hipStreamSynchronize(c.stream));
     const int64_t mt = tot_host[0], pt = tot_host[1], Fn = tot_host[2], qt = tot_host[3], novh = tot_host[4];
+    cand += tot_host[5];
     if (debug) {
       unsigned long long h[4];
       AMFMM_HIP(hipMemcpy(h, dbg, sizeof(h), hipMemcpyDeviceToHost));
@@ -1049,6 +1113,7 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
     F = Fn;
   }
   c.frontier = F;
+  c.walk_candidates += cand;
   return F;
 }
 

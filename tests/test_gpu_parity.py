@@ -197,8 +197,9 @@ def test_batched_walk_matches_whole_walk(theta):
     part = amfmm.Solver(list_bytes=1 << 20)
     a2 = host4(part.solve_gravity(X, Y, Z, M, theta))
     c2 = part.get_counts()
-    assert c1["near_interactions"] == c2["near_interactions"] > 0
-    assert c1["far_evaluations"] == c2["far_evaluations"] > 0
+    for k in ("near_interactions", "far_evaluations", "walk_candidates"):
+        assert c1[k] == c2[k] > 0, k
+    assert c2["walk_pass_launches"] > c1["walk_pass_launches"]  # batches walk the lower levels again
     idx = W.sample_targets(len(x), 256, seed=99)
     _, _, gabs = orc.direct(x, y, z, m, idx)
     assert np.max(np.linalg.norm(a1[:3, idx] - a2[:3, idx], axis=0) / gabs) <= 1e-13
@@ -261,8 +262,8 @@ def test_multipole_criterion_batched_matches_whole():
         s.set_field_estimate(G)
         o = s.solve_gravity(X, Y, Z, M, 0.5)
         outs.append((host4(o), s.get_counts()))
-    for k in ("near_interactions", "far_evaluations"):
-        assert outs[0][1][k] == outs[1][1][k] > 0
+    for k in ("near_interactions", "far_evaluations", "walk_candidates"):
+        assert outs[0][1][k] == outs[1][1][k] > 0, k
     idx = W.sample_targets(len(x), 256, seed=99)
     _, _, gabs = orc.direct(x, y, z, m, idx)
     a0, a1 = outs[0][0][:3, idx], outs[1][0][:3, idx]
