@@ -4,11 +4,10 @@
 //
 // One wave per target leaf.  Each lane holds four targets in registers
 // (register blocking: one source load feeds four interactions) and a slice of
-// the sources; lanes = (target group g, slice s), slices a power of two so
-// that the partial sums of a group reduce with a fixed xor butterfly
-// (deterministic).  Source leaves that follow each other in particle order
-// are merged into one run; runs are read straight from the key-sorted double4
-// particle array (consecutive lanes read consecutive particles).
+// the sources; lanes = (target group g, slice s), 64 / groups slices per group
+// (any count: the partial sums of a group reduce over a fixed tree into its
+// first lane, deterministic).  The leaf's source entries are staged in LDS a
+// bufferful at a time, consecutive lanes copying consecutive particles.
 //
 // Mixed precision: targets and staged sources are FP32 offsets from the
 // target leaf's centre of mass (each difference taken in FP64, then rounded),
@@ -131,7 +130,7 @@ __global__ void __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(4))) k
   for (int32_t tb = b; tb < b + nt; tb += 64) {
     const int ntc = min(64, b + nt - tb);
     const int ng = (ntc + kTG - 1) / kTG;
-    const int nsl = pow2floor(64 / ng);
+    const int nsl = 64 / ng;  // slices per group: as many lanes as the groups leave
     const int g = lane / nsl, s = lane % nsl;
     const bool active = g < ng;
     double tx[kTG], ty[kTG], tz[kTG];
@@ -150,40 +149,53 @@ __global__ void __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(4))) k
       fx[q] = fy[q] = fz[q] = ph[q] = 0.0;
     }
     // The near list is consumed 64 entries at a time: every lane fetches one
-    // source leaf (index, first particle, count) with independent loads, an
-    // in-wave prefix sum places each leaf in this wave's LDS buffer, and
-    // every lane copies its own leaf.  Leaves are taken while they fit.
+    // source leaf (index, first particle, count), an in-wave prefix sum places
+    // each leaf in this wave's LDS buffer, and the wave copies them.  Leaves are
+    // taken while they fit.  The next round's entries are fetched while this
+    // round copies and computes.
     int32_t k = 0;
+    int32_t Yl = lane < nsc ? nsrc[st + lane] : -1;
+    int32_t bl = Yl >= 0 ? beg[Yl] : 0;
+    int32_t cl = Yl >= 0 ? cnt[Yl] : 0;
     while (k < nsc) {
-      const int32_t kk = k + lane;
-      const int32_t Yl = kk < nsc ? nsrc[st + kk] : -1;
-      const int32_t bl = Yl >= 0 ? beg[Yl] : 0;
-      const int32_t cl = Yl >= 0 ? cnt[Yl] : 0;
       const int32_t inc = wave_incl_scan(cl);  // inclusive prefix over lanes
       const uint64_t fits = __ballot(Yl >= 0 && inc <= cap);
       const int take = __popcll(fits);  // prefix is monotone: leading lanes fit
-      int fill;
+      const int adv = take > 0 ? take : 1;
+      const int32_t kn = k + adv + lane;
+      const int32_t Yn = kn < nsc ? nsrc[st + kn] : -1;
+      int fill = 0;
       if (take > 0) {
         fill = __shfl(inc, take - 1, 64);
         // Cooperative copy: buffer slot v belongs to the entry e with
         // end[e-1] <= v < end[e] (binary search over the lanes' prefix ends),
-        // so consecutive lanes copy consecutive particles of an entry.
+        // so consecutive lanes copy consecutive particles of an entry; two
+        // slots per lane and iteration, both loads in flight together.
         const int32_t endx = lane < take ? inc : INT32_MAX;
         const int32_t startx = inc - cl;
-        for (int32_t v0 = 0; v0 < fill; v0 += 64) {
-          const int32_t v = v0 + lane;
-          int e = 0;
+        for (int32_t v0 = 0; v0 < fill; v0 += 128) {
+          const int32_t va = v0 + lane, vb = va + 64;
+          int ea = 0, eb = 0;
 #pragma unroll
-          for (int st = 32; st >= 1; st >>= 1)
-            if (__shfl(endx, e + st - 1, 64) <= v) e += st;
-          const int32_t s0 = __shfl(startx, e, 64), b0 = __shfl(bl, e, 64);
-          if (v < fill) {
-            if (MIXED) buf32[v] = offset32(pos[b0 + v - s0], gx);
-            else buf[v] = pos[b0 + v - s0];
+          for (int sp = 32; sp >= 1; sp >>= 1) {
+            if (__shfl(endx, ea + sp - 1, 64) <= va) ea += sp;
+            if (__shfl(endx, eb + sp - 1, 64) <= vb) eb += sp;
+          }
+          const int32_t sa = __shfl(startx, ea, 64), ba = __shfl(bl, ea, 64);
+          const int32_t sb = __shfl(startx, eb, 64), bb = __shfl(bl, eb, 64);
+          double4 pa = make_double4(0.0, 0.0, 0.0, 0.0), pb = pa;
+          if (va < fill) pa = pos[ba + va - sa];
+          if (vb < fill) pb = pos[bb + vb - sb];
+          if (va < fill) {
+            if (MIXED) buf32[va] = offset32(pa, gx);
+            else buf[va] = pa;
+          }
+          if (vb < fill) {
+            if (MIXED) buf32[vb] = offset32(pb, gx);
+            else buf[vb] = pb;
           }
         }
         if (tb == b) nsrc_particles += fill;
-        k += take;
       } else {
         // a single leaf larger than the buffer (coincident points at the
         // deepest level): stream it in buffer-sized pieces
@@ -203,39 +215,55 @@ __global__ void __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(4))) k
           wave_sync();
         }
         if (tb == b) nsrc_particles += c0;
-        k += 1;
-        continue;
       }
-      wave_sync();
-      if (active) {
-        if (MIXED) near_tile_f32(buf32, fill, s, nsl, ux, uy, uz, fx, fy, fz, ph);
-        else near_tile(buf, fill, s, nsl, tx, ty, tz, fx, fy, fz, ph);
+      // the next round's extents load while this round computes
+      const int32_t bn = Yn >= 0 ? beg[Yn] : 0;
+      const int32_t cn = Yn >= 0 ? cnt[Yn] : 0;
+      if (take > 0) {
+        wave_sync();
+        if (active) {
+          if (MIXED) near_tile_f32(buf32, fill, s, nsl, ux, uy, uz, fx, fy, fz, ph);
+          else near_tile(buf, fill, s, nsl, tx, ty, tz, fx, fy, fz, ph);
+        }
+        wave_sync();
       }
-      wave_sync();
+      Yl = Yn;
+      bl = bn;
+      cl = cn;
+      k += adv;
     }
-    // sum the slices of each group (fixed butterfly)
-    for (int off = nsl >> 1; off > 0; off >>= 1) {
+    // sum the slices of each group into its first lane (a fixed tree: at
+    // step off, slice s adds slice s + off of its own group)
+    for (int off = nsl > 1 ? pow2floor(nsl - 1) : 0; off > 0; off >>= 1) {
+      const bool take = s + off < nsl;
 #pragma unroll
       for (int u = 0; u < kTG; ++u) {
-        fx[u] += __shfl_xor(fx[u], off, 64);
-        fy[u] += __shfl_xor(fy[u], off, 64);
-        fz[u] += __shfl_xor(fz[u], off, 64);
-        ph[u] += __shfl_xor(ph[u], off, 64);
-      }
-    }
-    // lane s < 4 of group g finishes target g*4 + s
-    const int t = g * kTG + s;
-    if (active && s < kTG && t < ntc) {
-      double sx = fx[0], sy = fy[0], sz = fz[0], sp = ph[0];
-#pragma unroll
-      for (int u = 1; u < kTG; ++u) {
-        if (s == u) {
-          sx = fx[u];
-          sy = fy[u];
-          sz = fz[u];
-          sp = ph[u];
+        const double vx = __shfl(fx[u], lane + off, 64), vy = __shfl(fy[u], lane + off, 64);
+        const double vz = __shfl(fz[u], lane + off, 64), vp = __shfl(ph[u], lane + off, 64);
+        if (take) {
+          fx[u] += vx;
+          fy[u] += vy;
+          fz[u] += vz;
+          ph[u] += vp;
         }
       }
+    }
+    // lane s < 4 of group g finishes target g*4 + s with the sums of the
+    // group's first lane
+    const int t = g * kTG + s;
+    double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
+#pragma unroll
+    for (int u = 0; u < kTG; ++u) {
+      const double vx = __shfl(fx[u], g * nsl, 64), vy = __shfl(fy[u], g * nsl, 64);
+      const double vz = __shfl(fz[u], g * nsl, 64), vp = __shfl(ph[u], g * nsl, 64);
+      if (s == u) {
+        sx = vx;
+        sy = vy;
+        sz = vz;
+        sp = vp;
+      }
+    }
+    if (active && s < kTG && t < ntc) {
       const double4 pt = pos[tb + t];  // reloaded: the mixed path keeps no FP64 copy
       const double x[3] = {pt.x - gx.x, pt.y - gx.y, pt.z - gx.z};
       double gl[3], phi;

@@ -748,7 +748,7 @@ __global__ void __launch_bounds__(kBS) k_walk_compact(TreeView t, int32_t c0, in
   const int64_t e0 = (k - cbase[i]) * chunk;
   const int64_t e = gbeg[i] + e0;
   const int64_t n = min<int64_t>(chunk, gcnt[i] - e0);
-  // source position j of list w: the window, then the spill region
+  // source position j of list w: the window, then the spill regions
   auto src = [&](int w, int64_t j) {
     const int64_t lo = stage_lo(sl, w, e, k);
     const int64_t cap = stage_lo(sl, w, e + n, k + 1) - lo;
@@ -757,11 +757,27 @@ __global__ void __launch_bounds__(kBS) k_walk_compact(TreeView t, int32_t c0, in
     const int r = spill_region(j - cap, spill_shift(cap), &off);
     return sl.spill[w][sl.ksec[(3 * k + w) * kRegions + r] + off];
   };
+  // list w to d: the window part with eight loads in flight per lane, then
+  // the spill part
+  auto copy = [&](int w, int32_t* __restrict__ d, int64_t cnt) {
+    const int64_t lo = stage_lo(sl, w, e, k);
+    const int64_t cap = stage_lo(sl, w, e + n, k + 1) - lo;
+    const int64_t nw = cnt < cap ? cnt : cap;
+    const int32_t* __restrict__ s = sl.win[w] + lo;
+    int64_t j = lane;
+    for (; j + 7 * 64 < nw; j += 8 * 64) {
+      int32_t v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = s[j + u * 64];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) d[j + u * 64] = v[u];
+    }
+    for (; j < nw; j += 64) d[j] = s[j];
+    for (j = nw + lane; j < cnt; j += 64) d[j] = src(w, j);
+  };
   const int64_t nm = mex[k + 1] - mex[k], np = pex[k + 1] - pex[k], nq = qex[k + 1] - qex[k];
-  int32_t* df = far_src + far_base + mex[k];
-  int32_t* dn = near_src + near_base + pex[k];
-  for (int64_t j = lane; j < nm; j += 64) df[j] = src(0, j);
-  for (int64_t j = lane; j < np; j += 64) dn[j] = src(1, j);
+  copy(0, far_src + far_base + mex[k], nm);
+  copy(1, near_src + near_base + pex[k], np);
   if (nq) {
     const int32_t nch = load_cell(t.rec, c0 + i).nch;
     const int64_t S = qex[cbase[i + 1]] - qex[cbase[i]];
