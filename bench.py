@@ -31,10 +31,14 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X vector FP64 (non-packed FP32 issues at the sam
 PEAK_HBM_GBS = 8000.0
 NEAR_FLOPS = 20  # per directed particle interaction (3 sub, 5 r^2, 1 rsqrt, 2 r^-3, 1 mass, 6 acc, 2 pot)
 # per directed far-field pair (cell-pair evaluation of eqs. 2-4 with the
-# correction of eq. 7 in closed form; counted from the kernel's arithmetic,
-# fma = 2): R (3) + coefficients (147 with a one-instruction FP32 rsqrt, 156
-# with the refined FP64 one) + correction (157, FP64)
-FAR_FLOPS = {"fp64": 3 + 156 + 157, "mixed": 3 + 147 + 157}
+# correction of eq. 7 or 8 in closed form; counted from the kernels'
+# arithmetic, fma = 2): R (3) + coefficients (147 with a one-instruction FP32
+# rsqrt, 156 with the refined FP64 one) + correction (FP64: TC 157 from full
+# octupoles, 128 from traceless ones in the mixed path; TCO 121; UC none)
+def far_flops(precision, variant):
+    coeff = 3 + (147 if precision == "mixed" else 156)
+    corr = {"UC": 0, "TC": 128 if precision == "mixed" else 157, "TCO": 121}[variant]
+    return coeff + corr
 WALK_BYTES = 64  # per candidate pair of the walk: one cell record read to decide it
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_plummer16m.json")
 # sources each kernel's code comes from (a traffic figure holds while they are unchanged)
@@ -219,8 +223,8 @@ def main():
                  "algorithmic": f"{WALK_BYTES} B (one cell record) x {counts['walk_candidates']} candidate pairs"},
         "far": {"kernel": "k_far (far field: eqs. 2-4 + correction per directed cell pair)", "bound": "alu",
                 "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS, "ms": phases["far"], "launches": counts["far_launches"],
-                "work": FAR_FLOPS[a.precision] * counts["far_evaluations"] / 1e12,
-                "algorithmic": f"{FAR_FLOPS[a.precision]} flop x {counts['far_evaluations']} directed pairs"},
+                "work": far_flops(a.precision, a.variant) * counts["far_evaluations"] / 1e12,
+                "algorithmic": f"{far_flops(a.precision, a.variant)} flop x {counts['far_evaluations']} directed pairs"},
         "near": {"kernel": "k_near (near field + evaluation at the particles)", "bound": "alu", "unit": "TFLOP/s",
                  "peak": PEAK_FP64_TFLOPS, "ms": phases["near+eval"], "launches": counts["near_launches"],
                  "work": NEAR_FLOPS * counts["near_interactions"] / 1e12,

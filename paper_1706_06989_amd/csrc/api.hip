@@ -67,7 +67,7 @@ static DevBuf* all_bufs(Ctx& c, int i) {
   DevBuf* v[] = {&c.pos4, &c.keys, &c.perm, &c.keys2, &c.perm2, &c.bbox, &c.scratch, &c.scratch2, &c.hist,
                  &c.c_begin, &c.c_count, &c.c_parent, &c.c_child0, &c.c_nchild, &c.leaves, &c.geo, &c.mom,
                  &c.msum, &c.loc, &c.far_start, &c.far_count, &c.far_src, &c.near_start, &c.near_count,
-                 &c.near_src, &c.fx, &c.fy, &c.fx2, &c.fy2, &c.fcnt, &c.grp, &c.walkrec, &c.fsave, &c.gsave, &c.counters, &c.gqueue, &c.stage, &c.gmin, &c.model, &c.mlp_tmp, &c.mlp_part,
+                 &c.near_src, &c.fx, &c.fy, &c.fx2, &c.fy2, &c.fcnt, &c.grp, &c.walkrec, &c.fsave, &c.gsave, &c.counters, &c.gqueue, &c.stage, &c.farrec, &c.gmin, &c.model, &c.mlp_tmp, &c.mlp_part,
                  &c.mlp_grad};
   const int nv = (int)(sizeof(v) / sizeof(v[0]));
   return i < nv ? v[i] : nullptr;
@@ -295,6 +295,7 @@ static int moments_impl(Ctx& c) {
   if (c.ev_used) --c.ev_used;  // continue the timeline of the tree build
   amfmm::mark(c, amfmm::kPhMoments);
   amfmm::upward_pass(c);
+  amfmm::far_prepare(c);
   amfmm::mark(c, amfmm::kPhEnd);
   return AMFMM_OK;
 }

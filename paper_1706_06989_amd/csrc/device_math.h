@@ -115,6 +115,52 @@ __device__ inline void far_correction(const double R[3], double MX, const double
   }
 }
 
+// The correction of eq. 7 (TC) from traceless octupoles: D_ijkl is traceless
+// in every pair of indices, so only the traceless part of Q = M_X,jkl M_Y -
+// M_X M_Y,jkl contributes, and with a traceless Q the closed form reduces to
+// t4 R_i (Q.RRR) + 3 t3 Q_ikl R_k R_l.  OXt, O3t: traceless octupoles (10
+// packed components); adds to F[3].
+__device__ inline void far_correction_traceless(const double R[3], double MX, const double OXt[10], double M,
+                                                const double O3t[10], double F[3]) {
+  const double r2 = fma(R[0], R[0], fma(R[1], R[1], R[2] * R[2]));
+  const double ri = rsqrt_f64(r2);
+  const double ri2 = ri * ri;
+  const double t3 = 15.0 * ((ri * ri2) * ri2) * ri2;
+  const double t4 = -7.0 * t3 * ri2;
+  const double RR[6] = {R[0] * R[0], R[0] * R[1], R[0] * R[2], R[1] * R[1], R[1] * R[2], R[2] * R[2]};
+  double Q[10];
+#pragma unroll
+  for (int u = 0; u < 10; ++u) Q[u] = fma(OXt[u], M, -MX * O3t[u]);
+  const double mult[6] = {1.0, 2.0, 2.0, 1.0, 2.0, 1.0};
+  double v[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) s = fma(mult[p] * Q[kT3[p][i]], RR[p], s);
+    v[i] = s;
+  }
+  const double s = fma(R[0], v[0], fma(R[1], v[1], R[2] * v[2]));
+#pragma unroll
+  for (int i = 0; i < 3; ++i) F[i] += fma(t4 * s, R[i], 3.0 * t3 * v[i]);
+}
+
+// traceless part of a packed symmetric octupole (xxx xxy xxz xyy xyz xzz yyy
+// yyz yzz zzz): T_jkl - (delta_jk u_l + delta_jl u_k + delta_kl u_j)/5, u_l = T_jjl
+__device__ inline void octupole_traceless(const double O[10], double T[10]) {
+  const double ux = O[0] + O[3] + O[5], uy = O[1] + O[6] + O[8], uz = O[2] + O[7] + O[9];
+  T[0] = O[0] - 0.6 * ux;
+  T[1] = O[1] - 0.2 * uy;
+  T[2] = O[2] - 0.2 * uz;
+  T[3] = O[3] - 0.2 * ux;
+  T[4] = O[4];
+  T[5] = O[5] - 0.2 * ux;
+  T[6] = O[6] - 0.6 * uy;
+  T[7] = O[7] - 0.2 * uz;
+  T[8] = O[8] - 0.2 * uy;
+  T[9] = O[9] - 0.6 * uz;
+}
+
 // Inclusive prefix sum over the 64 lanes with DPP row shifts and row
 // broadcasts (all lanes active): four shifts within each row of 16, then row
 // 0's total into row 1 and row 2's into row 3, then row 1's into rows 2, 3.

@@ -19,7 +19,11 @@
 // reduction (deterministic).  Mixed precision: R = Z_X - Z_Y is formed in FP64
 // and rounded, the coefficient terms are FP32 and each lane adds at most
 // kFarFlush of them in FP32 before an FP64 flush; the correction (which
-// cancels M_X,jkl M_Y against M_X M_Y,jkl) stays FP64.
+// cancels M_X,jkl M_Y against M_X M_Y,jkl) stays FP64.  For UC and TC the
+// mixed path reads each source from one 128-byte record (one cache line
+// instead of three): Z and M in FP64, the traceless octupole (7 components,
+// FP64; D_ijkl is traceless, so the correction needs no more) and the
+// quadrupole in FP32.
 #include "device_math.h"
 #include "internal.h"
 
@@ -37,6 +41,114 @@ __device__ inline double wave_sum(double v) {
 
 // sources per lane summed in FP32 before an FP64 flush (mixed path)
 constexpr int kFarFlush = 8;
+
+// far-field source record of the mixed UC/TC path: 128 bytes, one cache line
+struct alignas(128) FarRec {
+  double z[3], m;
+  double o[7];  // traceless octupole: xxx xxy xxz xyy xyz yyy yyz (xzz, yzz, zzz follow)
+  float q[6];   // quadrupole xx xy xz yy yz zz
+  float pad[4];
+};
+static_assert(sizeof(FarRec) == 128, "far record");
+
+__global__ void __launch_bounds__(kBS) k_pack_far(int32_t nc, const double4* __restrict__ geo,
+                                                  const double* __restrict__ mom, FarRec* __restrict__ rec) {
+  const int32_t c = blockIdx.x * kBS + threadIdx.x;
+  if (c >= nc) return;
+  const double4 g = geo[c];
+  const double* mo = mom + (int64_t)c * kMom;
+  double T[10];
+  octupole_traceless(mo + 7, T);
+  FarRec r;
+  r.z[0] = g.x;
+  r.z[1] = g.y;
+  r.z[2] = g.z;
+  r.m = mo[0];
+  r.o[0] = T[0];
+  r.o[1] = T[1];
+  r.o[2] = T[2];
+  r.o[3] = T[3];
+  r.o[4] = T[4];
+  r.o[5] = T[6];
+  r.o[6] = T[7];
+#pragma unroll
+  for (int u = 0; u < 6; ++u) r.q[u] = (float)mo[1 + u];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) r.pad[u] = 0.0f;
+  rec[c] = r;
+}
+
+// the full traceless octupole of a record
+__device__ inline void record_octupole(const double o[7], double T[10]) {
+  T[0] = o[0];
+  T[1] = o[1];
+  T[2] = o[2];
+  T[3] = o[3];
+  T[4] = o[4];
+  T[5] = -o[0] - o[3];
+  T[6] = o[5];
+  T[7] = o[6];
+  T[8] = -o[1] - o[5];
+  T[9] = -o[2] - o[6];
+}
+
+// Mixed UC/TC far field from the records (see k_far)
+template <int VARIANT>
+__global__ void __launch_bounds__(kBS) k_far_rec(int32_t c_lo, int32_t nc, const FarRec* __restrict__ rec,
+                                                 const int64_t* __restrict__ fstart,
+                                                 const int32_t* __restrict__ fcount,
+                                                 const int32_t* __restrict__ fsrc, double* __restrict__ loc) {
+  const int lane = threadIdx.x & 63;
+  const int32_t Xi = uniform((int32_t)(xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6)));
+  if (Xi >= nc) return;
+  const int32_t X = c_lo + Xi;
+  const int32_t cnt = fcount[X];
+  const int64_t st = fstart[X];
+  const FarRec& rx = rec[X];
+  const double gx[3] = {rx.z[0], rx.z[1], rx.z[2]};
+  const double MX = rx.m;
+  double OX[10];
+  if (VARIANT) record_octupole(rx.o, OX);
+  double acc[20], F[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int u = 0; u < 20; ++u) acc[u] = 0.0;
+  for (int64_t j0 = lane; j0 < cnt; j0 += 64 * kFarFlush) {
+    float a32[20];
+#pragma unroll
+    for (int u = 0; u < 20; ++u) a32[u] = 0.0f;
+    const int64_t j1 = j0 + 64 * kFarFlush < cnt ? j0 + 64 * kFarFlush : cnt;
+    for (int64_t j = j0; j < j1; j += 64) {
+      const FarRec& ry = rec[fsrc[st + j]];
+      const double R[3] = {gx[0] - ry.z[0], gx[1] - ry.z[1], gx[2] - ry.z[2]};
+      const double M = ry.m;
+      const float Rf[3] = {(float)R[0], (float)R[1], (float)R[2]};
+      float Q2f[6];
+#pragma unroll
+      for (int u = 0; u < 6; ++u) Q2f[u] = ry.q[u];
+      far_coeffs<float>(Rf, (float)M, Q2f, a32);
+      if (VARIANT) {
+        double O3[10];
+        record_octupole(ry.o, O3);
+        far_correction_traceless(R, MX, OX, M, O3, F);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 20; ++u) acc[u] += (double)a32[u];
+  }
+#pragma unroll
+  for (int u = 0; u < 20; ++u) acc[u] = wave_sum(acc[u]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) F[i] = wave_sum(F[i]);
+  if (lane == 0) {
+    double* o = loc + (int64_t)X * kLoc;
+    const double cf = -1.0 / (6.0 * MX);
+#pragma unroll
+    for (int u = 0; u < 20; ++u) o[u] = acc[u];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) o[20 + i] = VARIANT ? cf * F[i] : 0.0;
+    o[23] = 0.0;
+  }
+}
 
 template <int VARIANT, bool MIXED>
 __global__ void __launch_bounds__(kBS) k_far(int32_t c_lo, int32_t nc, const double4* __restrict__ geo, const double* __restrict__ mom,
@@ -169,12 +281,32 @@ void zero_u64(Ctx& c, unsigned long long* p, int n) {
   AMFMM_HIP(hipGetLastError());
 }
 
+static bool use_records(const Ctx& c) {
+  return c.opt.precision == AMFMM_MIXED && c.opt.variant != AMFMM_TCO;
+}
+
+void far_prepare(Ctx& c) {
+  if (!use_records(c) || c.ncells <= 0) return;
+  FarRec* rec = (FarRec*)ensure(c, c.farrec, sizeof(FarRec) * (size_t)c.ncells);
+  hipLaunchKernelGGL(k_pack_far, dim3(blocks_for(c.ncells, kBS)), dim3(kBS), 0, c.stream, c.ncells,
+                     (const double4*)c.geo.p, (const double*)c.mom.p, rec);
+  AMFMM_HIP(hipGetLastError());
+}
+
 void far_field(Ctx& c, int32_t c_lo, int32_t c_hi) {
   const int32_t nc = c_hi - c_lo;
   if (nc <= 0) return;
   double* loc = (double*)ensure_keep(c, c.loc, sizeof(double) * kLoc * (size_t)c.ncells,
                                      sizeof(double) * kLoc * (size_t)c.ncells);
   dim3 grid(blocks_for(nc, kWaves));
+  if (use_records(c)) {
+    ++c.far_launches;
+    hipLaunchKernelGGL(c.opt.variant == AMFMM_TC ? k_far_rec<AMFMM_TC> : k_far_rec<AMFMM_UC>, grid, dim3(kBS), 0,
+                       c.stream, c_lo, nc, (const FarRec*)c.farrec.p, (const int64_t*)c.far_start.p,
+                       (const int32_t*)c.far_count.p, (const int32_t*)c.far_src.p, loc);
+    AMFMM_HIP(hipGetLastError());
+    return;
+  }
   auto args = [&](auto kern) {
     hipLaunchKernelGGL(kern, grid, dim3(kBS), 0, c.stream, c_lo, nc, (const double4*)c.geo.p, (const double*)c.mom.p,
                        (const int64_t*)c.far_start.p, (const int32_t*)c.far_count.p, (const int32_t*)c.far_src.p, loc);

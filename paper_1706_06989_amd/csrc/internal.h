@@ -79,6 +79,7 @@ struct Ctx {
   // walk frontier
   DevBuf fx, fy, fx2, fy2, fcnt, grp, walkrec, fsave, gsave, counters, gqueue;
   DevBuf stage;  // walk: per-chunk staging windows of one level's terminal pairs
+  DevBuf farrec; // far field, mixed UC/TC: 128-byte source record per cell
   // walk: terminal pairs per frontier entry of every level (far, near, split-X
   // bases; -1 = unknown) from the last walk under the rule walk_ratio_key
   std::vector<double> walk_ratio;
@@ -164,6 +165,9 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
 void group_arrays(Ctx& c, int64_t** gbeg, int32_t** gcnt);  // current level's groups
 
 // ---- eval.hip ----
+// mixed precision, UC and TC: one 128-byte source record per cell for the far
+// field (after the moments)
+void far_prepare(Ctx& c);
 void far_field(Ctx& c, int32_t c_lo, int32_t c_hi);
 void push_down(Ctx& c, int32_t c_lo, int32_t c_hi);  // cells of one level
 // leaves != nullptr: the first `count` leaves of that list; else the leaves
