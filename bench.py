@@ -221,7 +221,8 @@ def main():
                  "ms": phases["walk-pass"], "launches": counts["walk_pass_launches"],
                  "work": WALK_BYTES * counts["walk_candidates"] / 1e9,
                  "algorithmic": f"{WALK_BYTES} B (one cell record) x {counts['walk_candidates']} candidate pairs"},
-        "far": {"kernel": "k_far (far field: eqs. 2-4 + correction per directed cell pair)", "bound": "alu",
+        "far": {"kernel": ("k_far_rec" if a.precision == "mixed" and a.variant != "TCO" else "k_far")
+                          + " (far field: eqs. 2-4 + correction per directed cell pair)", "bound": "alu",
                 "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS, "ms": phases["far"], "launches": counts["far_launches"],
                 "work": far_flops(a.precision, a.variant) * counts["far_evaluations"] / 1e12,
                 "algorithmic": f"{far_flops(a.precision, a.variant)} flop x {counts['far_evaluations']} directed pairs"},
