@@ -943,10 +943,14 @@ static size_t stage_layout(Ctx& c, int lev, int64_t F, int64_t kn, const double*
   if (ints * sizeof(int32_t) + offsets > (double)limit)
     scale = std::max(0.0, ((double)limit - offsets) / (ints * sizeof(int32_t)));
   if (scale < 0.25) scale = 0.0;
+  // AMFMM_WALK_WINDOWS (tests): a factor on the windows alone, to drive chunks
+  // into the spill regions (small factors) or the second pass (0)
+  double wf = 1.0;
+  if (const char* e = getenv("AMFMM_WALK_WINDOWS")) wf = std::max(0.0, std::min(1.0, atof(e)));
   size_t n = 0;
   for (int w = 0; w < 3; ++w) {
-    sl.cap16[w] = (int64_t)std::ceil(16.0 * alpha * r[w] * scale);
-    sl.slack[w] = (int64_t)((double)slack[w] * scale);
+    sl.cap16[w] = (int64_t)std::ceil(16.0 * alpha * r[w] * scale * wf);
+    sl.slack[w] = (int64_t)((double)slack[w] * scale * wf);
     const int64_t win = ((sl.cap16[w] * F) >> 4) + kn * sl.slack[w] + 1;
     sl.spill_cap[w] = (int64_t)(kSpill * (double)win + scale * (double)(kn / 16 * kSpillMin));
     n += (size_t)(win + sl.spill_cap[w]);
