@@ -60,12 +60,12 @@ def parse():
     p.add_argument("--pilot-theta", type=float, default=1.0,
                    help="opening angle of the pilot solve that gives the field estimate")
     p.add_argument("--criterion", choices=["geometric", "estimate", "learned", "multipole"], default="multipole")
-    p.add_argument("--eps", type=float, default=5e-8,
+    p.add_argument("--eps", type=float, default=6.5e-8,
                    help="error-estimate criterion: accepted pair error relative to the field scale")
     p.add_argument("--theta-max", type=float, default=0.5)
     p.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
     p.add_argument("--variant", choices=["UC", "TC", "TCO"], default="TC")
-    p.add_argument("--error-sample", type=int, default=4096)
+    p.add_argument("--error-sample", type=int, default=1 << 16)
     p.add_argument("--cpu-n", type=int, default=1 << 16, help="oracle sample size (0 = skip)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain device copy of known size (scale for HBM byte counters)")

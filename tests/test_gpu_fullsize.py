@@ -7,9 +7,9 @@
   accelerations against the oracle (FP64 1e-12 of gabs; mixed 1e-4 at worst
   and 2e-6 at the 99th percentile, the bounds of the mixed-precision tests).
 * Plummer 2^24 (seed 4) in the benchmark's configuration (pilot geometric
-  solve at theta 1.0 + multipole error-estimate solve, eps 5e-8, theta_max
+  solve at theta 1.0 + multipole error-estimate solve, eps 6.5e-8, theta_max
   0.5, mixed, TC): the oracle cannot walk 3e10 pairs, so properties that hold
-  at any size: p99 of the force error against direct summation at 4096
+  at any size: p99 of the force error against direct summation at 65536
   sampled targets below 1e-4, force and torque balance, and the mixed solve
   against the FP64 solve from the same field estimate (the same pairs) within
   the mixed-precision bound.
@@ -98,12 +98,12 @@ def test_plummer_2p24_benchmark_configuration():
     del x, y, z, m
     pilot = amfmm.Solver(precision=amfmm.MIXED)
     gx, gy, gz, _ = pilot.solve_gravity(X, Y, Z, M, 1.0, pot=False)
-    tg = torch.from_numpy(W.sample_targets(n, 4096, seed=99)).cuda()
+    tg = torch.from_numpy(W.sample_targets(n, 1 << 16, seed=99)).cuda()
     tx, ty, tz, _, _ = pilot.direct(X, Y, Z, M, tg, pot=False, gabs=False)
     T = torch.stack([tx, ty, tz])
     outs = {}
     for prec in (amfmm.MIXED, amfmm.FP64):
-        s = amfmm.Solver(precision=prec, criterion=amfmm.MULTIPOLE, error_tol=5e-8, theta_max=0.5)
+        s = amfmm.Solver(precision=prec, criterion=amfmm.MULTIPOLE, error_tol=6.5e-8, theta_max=0.5)
         s.set_field_estimate(gx, gy, gz)
         o = s.solve_gravity(X, Y, Z, M, 0.5, pot=False)
         A = torch.stack([o[0][tg], o[1][tg], o[2][tg]])
