@@ -1,21 +1,27 @@
 // Interaction selection (Sec. 2): symmetric dual walk under the opening
-// criterion |Z_A - Z_B| >= (R_A + R_B)/theta, organised by target cell.
+// criterion |Z_A - Z_B| >= (R_A + R_B)/theta, or an error-estimate criterion
+// (the error-based selection Sec. 2 cites), organised by target cell.
 //
 // The walk of cell pairs is reproduced pair for pair, but every visited pair
 // is held twice, once by each of its cells (directed entries (X, Y)), and the
-// frontier is processed one tree level of X at a time, grouped by X.  For an
-// entry (X, Y) a thread runs a depth-first descent into Y's subtree while the
-// symmetric split rule opens Y; each terminal pair ends as
+// frontier is processed one tree level of X at a time, grouped by X.  A wave
+// takes a chunk of X's entries and expands them breadth first (a work queue
+// in LDS or global memory; a lane descends a subtree alone when the queue is
+// full) while the symmetric split rule opens Y; each terminal pair ends as
 //   * a far-field entry X <- Y when accepted,
-//   * a near-field entry X <- Y when both are leaves,
+//   * a near-field entry X <- Y when both are leaves (or no cell below Y can
+//     be accepted with the leaf X: Y's whole subtree),
 //   * a "split X" base that hands (X_c, Y) to every child X_c of X.
 // A self entry (X, X) of a split cell hands (X_c, X_c') to every child for all
 // children X_c' (self included); of a leaf it becomes the near-field entry X<-X.
 // The decision on a pair depends only on the unordered pair (the criterion is
 // symmetric and the split rule picks the larger R_max, ties to the lower
 // index, and the non-leaf when one is a leaf), so both cells of a pair make
-// the same decision and every directed list comes out grouped by target with
-// no sort: count pass -> scans -> emit pass, deterministic.
+// the same decision.  One pass per level writes every chunk's terminal pairs
+// to staging room, scans of the per-chunk counts place them, and a copy
+// gives lists grouped by target with no sort (chunks that outgrew their room
+// are walked a second time straight into place); the result is
+// deterministic.
 //
 // Compiled with -ffp-contract=off: the criterion must round exactly as the
 // plain definition does.
