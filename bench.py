@@ -5,11 +5,11 @@ error-estimate criterion (default: the multipole estimate) a step is two
 amfmm_solve_gravity calls: a pilot solve with the geometric criterion
 (theta = 1.0) whose accelerations give every cell its field scale, then the
 solve whose pair selection keeps each pair's estimated error below eps times
-that scale.  Each solve covers
-validation, bounding cube, keys, sort, tree, upward pass, walk, far field,
-push-down, near field, evaluation at the particles and the unsort.  Outputs
-one JSON line.  The error of the timed configuration is measured outside the
-timed region against direct summation at a seeded sample of targets.
+that scale.  Each solve covers validation, bounding cube, keys, sort, tree,
+upward pass, walk, far field, push-down, near field, evaluation at the
+particles and the unsort.  Outputs one JSON line.  The error of the timed
+configuration is measured outside the timed region against direct summation
+at a seeded sample of 65536 targets.
 
 Workload: 16,777,216-particle Plummer sphere (scale radius 1, mass 1,
 truncated at 20, seed 4, equal masses), G = 1, n_crit = 25, TC variant,

@@ -160,7 +160,7 @@ class Solver:
 
     def set_field_estimate(self, gx, gy=None, gz=None):
         """Per-particle field estimates (CUDA float64, caller order) for the
-        error-estimate criterion: magnitudes (gx only) or the three
+        error-estimate criteria (ESTIMATE, MULTIPOLE, LEARNED): magnitudes (gx only) or the three
         components; None clears them.  The tensors are kept alive by the
         solver until replaced."""
         self._field = (gx, gy, gz)
