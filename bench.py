@@ -67,6 +67,9 @@ def parse():
     p.add_argument("--variant", choices=["UC", "TC", "TCO"], default="TC")
     p.add_argument("--error-sample", type=int, default=1 << 16)
     p.add_argument("--cpu-n", type=int, default=1 << 16, help="oracle sample size (0 = skip)")
+    p.add_argument("--plain-thetas", default="0.5,0.095",
+                   help="opening angles of the plain solve (FP64, geometric, same variant, no pilot) "
+                        "timed after the benchmark for the matched-error speedup; empty = skip")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain device copy of known size (scale for HBM byte counters)")
     return p.parse_args()
@@ -246,6 +249,38 @@ def main():
     roofline = roof(dominant)
     roofline["others"] = {n: roof(n) for n in kern if n != dominant}
 
+    # The plain solve (FP64 throughout, geometric criterion, no pilot) at the
+    # given opening angles, outside the timed region, each timed once after a
+    # warm-up: the largest angle whose p99 meets 1e-4 is the matched-error
+    # point the speedup is quoted against.
+    plain = None
+    thetas = [float(t) for t in a.plain_thetas.split(",") if t.strip()]
+    if thetas:
+        pilot.close()
+        solver.close()
+        del pout, out
+        torch.cuda.empty_cache()
+        ps = amfmm.Solver(variant=variant, precision=amfmm.FP64)
+        rows = []
+        for th in thetas:
+            ps.solve_gravity(X, Y, Z, M, th, pot=False)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            o = ps.solve_gravity(X, Y, Z, M, th, pot=False)
+            torch.cuda.synchronize()
+            pms = (time.perf_counter() - t1) * 1e3
+            pe = p_err(o)
+            del o
+            rows.append({"theta": th, "ms": round(pms, 3), "p99_rel_force_error": float(np.percentile(pe, 99))})
+            print(f"# plain fp64 theta={th}: {pms:.1f} ms", file=sys.stderr, flush=True)
+        ps.close()
+        ok = [r for r in rows if r["p99_rel_force_error"] <= 1e-4]
+        plain = {"precision": "fp64", "criterion": "geometric", "variant": a.variant, "rows": rows}
+        if ok:
+            best = max(ok, key=lambda r: r["theta"])
+            plain["matched_theta"] = best["theta"]
+            plain["speedup_at_matched_p99"] = round(best["ms"] / ms, 3)
+
     cpu = None
     if a.cpu_n > 0:
         cpu = cpu_baseline(a.cpu_n, a.pilot_theta if field else a.theta, a.criterion, a.eps, a.theta_max)
@@ -266,7 +301,7 @@ def main():
                    "meets_1e-4_p99": bool(np.percentile(eps, 99) <= 1e-4),
                    "force_balance": fbal, "torque_balance": tbal,
                    "phase_ms": {k: round(v, 3) for k, v in phases.items()}, "counts": counts},
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "plain_fp64": plain,
     }
     if a.copy_calibration:
         # 1 GiB read + 1 GiB written by one copy kernel per call
