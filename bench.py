@@ -115,12 +115,32 @@ def cpu_baseline(n, theta, criterion, eps, theta_max, seed=4):
         walk(eps, theta_max, np.linalg.norm(a, axis=0))
         t.evaluate(orc.TC)
     dt = time.perf_counter() - t0
+    # the cost of the correction in the oracle: its evaluation (far field,
+    # push-down, near field) of one geometric theta=0.5 walk of a 16384-particle
+    # sphere per variant, best of three
+    xs, ys, zs, ms = W.plummer(1 << 14, seed=seed)
+    tv = orc.Tree(xs, ys, zs, ms)
+    tv.compute_moments()
+    tv.walk(0.5)
+    best = {}
+    for name, v in (("UC", orc.UC), ("TC", orc.TC), ("TCO", orc.TCO)):
+        ts = []
+        for _ in range(3):
+            t1 = time.perf_counter()
+            tv.evaluate(v)
+            ts.append(time.perf_counter() - t1)
+        best[name] = min(ts)
     what = (f"pilot theta={theta} + {criterion} error-estimate solve eps={eps} theta_max={theta_max}"
             if criterion != "geometric" else f"theta={theta}")
     return {"value": n / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
             "sample": f"full oracle solve (tree, moments, walk, eqs. 2-4 at every particle, near "
                       f"field) of a {n}-particle Plummer sphere, same generator, {what}, TC, FP64, "
-                      f"single thread, {dt:.1f} s"}
+                      f"single thread, {dt:.1f} s",
+            "variant_cost": {"TC/UC": round(best["TC"] / best["UC"], 3),
+                             "TCO/UC": round(best["TCO"] / best["UC"], 3),
+                             "sample": "oracle evaluation (far field, push-down, near field) after one "
+                                       "geometric theta=0.5 walk of a 16384-particle Plummer sphere, FP64, "
+                                       "single thread, best of three per variant"}}
 
 
 def main():
