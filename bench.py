@@ -54,7 +54,9 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--n", type=int, default=1 << 24)
+    p.add_argument("--workload", choices=["plummer16m", "twoplummer16m", "twoplummer4m", "plummer1m"],
+                   default="plummer16m", help="synthetic input (generator, size and seed of the named workload)")
+    p.add_argument("--n", type=int, default=None, help="particles (default: the workload's size)")
     p.add_argument("--theta", type=float, default=0.5,
                    help="opening angle (geometric criterion; also the pilot solve)")
     p.add_argument("--pilot-theta", type=float, default=1.0,
@@ -82,7 +84,7 @@ def source_hash(kernel):
     return h.hexdigest()[:16]
 
 
-def traffic(kernel, config):
+def traffic(kernel, config, workload):
     """HBM bytes per launch of a kernel from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE, scaled by the copy calibration), or None when
     absent, taken on other sources of that kernel or on another configuration."""
@@ -93,19 +95,22 @@ def traffic(kernel, config):
     k = t.get("kernels", {}).get(kernel)
     if not k or k.get("source_hash") != source_hash(kernel) or t.get("config") != config:
         return None
+    if not str(t.get("workload", "")).startswith(workload + " "):
+        return None
     return k.get("bytes_per_launch")
 
 
-def cpu_baseline(n, theta, criterion, eps, theta_max, seed=4):
-    """The CPU oracle as it stands (single thread) on a smaller Plummer sphere
-    of the same generator and configuration: particles/s of its full solve
-    (with the error-estimate criterion: its own pilot solve, then the solve)."""
+def cpu_baseline(workload, n, theta, criterion, eps, theta_max):
+    """The CPU oracle as it stands (single thread) on a smaller sample of the
+    same workload (generator and seed) and configuration: particles/s of its
+    full solve (with an error-estimate criterion: its own pilot solve, then the
+    solve)."""
     import numpy as np
 
     from oracle import oracle as orc
     from paper_1706_06989_amd import workloads as W
 
-    x, y, z, m = W.plummer(n, seed=seed)
+    x, y, z, m = W.make(workload, n=n)
     t0 = time.perf_counter()
     a, _ = orc.solve(x, y, z, m, theta=theta, variant=orc.TC)
     if criterion != "geometric":
@@ -118,7 +123,7 @@ def cpu_baseline(n, theta, criterion, eps, theta_max, seed=4):
     # the cost of the correction in the oracle: its evaluation (far field,
     # push-down, near field) of one geometric theta=0.5 walk of a 16384-particle
     # sphere per variant, best of three
-    xs, ys, zs, ms = W.plummer(1 << 14, seed=seed)
+    xs, ys, zs, ms = W.make("plummer16m", n=1 << 14)
     tv = orc.Tree(xs, ys, zs, ms)
     tv.compute_moments()
     tv.walk(0.5)
@@ -134,7 +139,8 @@ def cpu_baseline(n, theta, criterion, eps, theta_max, seed=4):
             if criterion != "geometric" else f"theta={theta}")
     return {"value": n / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
             "sample": f"full oracle solve (tree, moments, walk, eqs. 2-4 at every particle, near "
-                      f"field) of a {n}-particle Plummer sphere, same generator, {what}, TC, FP64, "
+                      f"field) of {n} particles of the {workload} workload (same generator and seed), "
+                      f"{what}, TC, FP64, "
                       f"single thread, {dt:.1f} s",
             "variant_cost": {"TC/UC": round(best["TC"] / best["UC"], 3),
                              "TCO/UC": round(best["TCO"] / best["UC"], 3),
@@ -168,7 +174,10 @@ def main():
         model, losses = learned.train(f, lab)
         model_info = {"pairs": int(len(lab)), "loss": [losses[0], losses[-1]],
                       "train_s": round(time.perf_counter() - t0, 2)}
-    x, y, z, m = W.plummer(a.n, seed=4)
+    if a.n is None:
+        a.n = W.CONFIGS[a.workload]["n"]
+    x, y, z, m = W.make(a.workload, n=a.n)
+    workload = a.workload if a.n == W.CONFIGS[a.workload]["n"] else f"{a.workload}@{a.n}"
     X, Y, Z, M = (torch.from_numpy(v).to("cuda") for v in (x, y, z, m))
     del x, y, z, m
     crit = {"geometric": amfmm.GEOMETRIC, "estimate": amfmm.ESTIMATE, "learned": amfmm.LEARNED,
@@ -188,7 +197,7 @@ def main():
             pilot.solve_gravity(X, Y, Z, M, a.pilot_theta, out=pout)
         solver.solve_gravity(X, Y, Z, M, a.theta, out=out)
 
-    print(f"# bench: n={a.n} {a.criterion} theta={a.theta} eps={a.eps} {a.precision} {a.variant} "
+    print(f"# bench: {workload} n={a.n} {a.criterion} theta={a.theta} eps={a.eps} {a.precision} {a.variant} "
           f"warmup={a.warmup} steps={a.steps}", file=sys.stderr, flush=True)
     for i in range(a.warmup):
         step()
@@ -258,7 +267,7 @@ def main():
     def roof(name):
         k = kern[name]
         achieved = k["work"] / (k["ms"] * 1e-3)
-        tb = traffic(name, cfg_key)
+        tb = traffic(name, cfg_key, workload)
         launches = max(1, k["launches"])
         return {"kernel": k["kernel"], "bound": k["bound"], "achieved": round(achieved, 3), "peak": k["peak"],
                 "unit": k["unit"], "frac": round(achieved / k["peak"], 4), "traffic": tb,
@@ -303,14 +312,16 @@ def main():
 
     cpu = None
     if a.cpu_n > 0:
-        cpu = cpu_baseline(a.cpu_n, a.pilot_theta if field else a.theta, a.criterion, a.eps, a.theta_max)
+        cpu = cpu_baseline(a.workload, a.cpu_n, a.pilot_theta if field else a.theta, a.criterion, a.eps,
+                           a.theta_max)
 
     line = {
-        "metric": METRIC, "value": a.n / (ms * 1e-3), "unit": "particles/s", "n_gpus": 1,
+        "metric": METRIC if workload == "plummer16m" else f"particles/s full force solve, {workload}",
+        "value": a.n / (ms * 1e-3), "unit": "particles/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if a.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "plummer16m" if a.n == 1 << 24 else f"plummer{a.n}", "n": a.n,
+        "config": {"workload": workload, "n": a.n,
                    "criterion": a.criterion, "theta": a.theta,
                    "eps": a.eps if field else None, "theta_max": a.theta_max if field else None,
                    "pilot": pilot_info,
