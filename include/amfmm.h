@@ -140,7 +140,8 @@ int amfmm_solve_gravity(amfmm_ctx* ctx, int64_t n, const double* x, const double
 /* Direct summation at ntarget particles (device int64 indices; NULL = all n
  * particles in order): the exact sum that the method approximates (Sec. 3,
  * g_PP).  Coincident particles are skipped.  Outputs are device arrays of
- * ntarget doubles (pot and gabs may be NULL; gabs = G * sum_j m_j / r^2). */
+ * ntarget doubles (pot and gabs may be NULL; gabs = G * sum_j m_j / r^2); a
+ * target index outside [0, n) is read as no particle and gets NaN outputs. */
 int amfmm_direct(amfmm_ctx* ctx, int64_t n, const double* x, const double* y, const double* z,
                  const double* m, int64_t ntarget, const int64_t* targets, double* ax, double* ay,
                  double* az, double* pot, double* gabs);
@@ -174,11 +175,11 @@ int amfmm_balance(amfmm_ctx* ctx, int64_t n, const double* x, const double* y, c
 int amfmm_set_model(amfmm_ctx* ctx, const float* model);
 /* Features (8 floats per pair) and labels (log2 error factor, doubles) of np
  * cell pairs of the context's tree (after amfmm_compute_moments); pairs:
- * device int32, 2 per pair (distinct cells with distinct centres, else
- * AMFMM_E_INVALID is not detected: the caller passes pairs of a walk's far
- * field).  A label samples up to 64 particles of each cell (particle k of ns
+ * device int32, 2 per pair.  The two cells must be distinct with distinct
+ * centres, as in a walk's far field; that is not checked.  A label samples up to 64 particles of each cell (particle k of ns
  * is first + k N / ns) and evaluates the pair alone with the variant given
- * against direct summation over the other cell.  Outputs are device arrays. */
+ * against direct summation over the other cell.  Outputs are device arrays;
+ * a pair naming no cell of the tree gets NaN features or a NaN label. */
 int amfmm_pair_features(amfmm_ctx* ctx, int64_t np, const int32_t* pairs, float* feats);
 int amfmm_pair_labels(amfmm_ctx* ctx, int32_t variant, int64_t np, const int32_t* pairs, double* labels);
 /* FP32 inference exactly as the walk runs it: model (device, AMFMM_MLP_MODEL

@@ -100,20 +100,27 @@ class AmfmmError(RuntimeError):
         self.code = code
 
 
-def _dev(t, name):
-    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
-        raise TypeError(f"{name} must be a CUDA (ROCm) tensor")
-    if t.dtype != torch.float64 or not t.is_contiguous():
-        raise TypeError(f"{name} must be a contiguous float64 tensor")
-    return C.c_void_p(t.data_ptr())
+def _dev(t, name, n=None):
+    """Device pointer of a contiguous float64 CUDA tensor holding exactly n
+    elements (when n is given): the library reads n elements through it."""
+    return _devt(t, name, torch.float64, n)
 
 
-def _devt(t, name, dtype):
+def _devt(t, name, dtype, n=None):
     if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
         raise TypeError(f"{name} must be a CUDA (ROCm) tensor")
     if t.dtype != dtype or not t.is_contiguous():
         raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, {n} expected")
     return C.c_void_p(t.data_ptr())
+
+
+def _rows(t, name, width):
+    """Rows of a [rows, width] tensor (checked: the library reads rows x width)."""
+    if not isinstance(t, torch.Tensor) or t.dim() != 2 or t.shape[1] != width:
+        raise ValueError(f"{name} must be a [rows, {width}] tensor")
+    return t.shape[0]
 
 
 def _ptr(a, ctype):
@@ -179,14 +186,14 @@ class Solver:
 
     def pair_features(self, pairs):
         """pairs: CUDA int32 tensor [np, 2] of cells of the current tree."""
-        np_ = pairs.shape[0]
+        np_ = _rows(pairs, "pairs", 2)
         out = torch.empty((np_, 8), dtype=torch.float32, device=pairs.device)
         self._check(lib().amfmm_pair_features(self._h, np_, _devt(pairs, "pairs", torch.int32),
                                               _devt(out, "feats", torch.float32)))
         return out
 
     def pair_labels(self, pairs, variant=TC):
-        np_ = pairs.shape[0]
+        np_ = _rows(pairs, "pairs", 2)
         out = torch.empty(np_, dtype=torch.float64, device=pairs.device)
         self._check(lib().amfmm_pair_labels(self._h, variant, np_, _devt(pairs, "pairs", torch.int32),
                                             _devt(out, "labels", torch.float64)))
@@ -194,43 +201,45 @@ class Solver:
 
     def mlp_predict(self, model, feats):
         """model: CUDA float32 [MLP_MODEL]; feats: CUDA float32 [n, 8]."""
-        n = feats.shape[0]
+        n = _rows(feats, "feats", 8)
         y = torch.empty(n, dtype=torch.float32, device=feats.device)
-        self._check(lib().amfmm_mlp_predict(self._h, n, _devt(model, "model", torch.float32),
+        self._check(lib().amfmm_mlp_predict(self._h, n, _devt(model, "model", torch.float32, MLP_MODEL),
                                             _devt(feats, "feats", torch.float32), _devt(y, "y", torch.float32)))
         return y
 
     def mlp_grad(self, model, feats, labels, tau=0.9):
-        n = feats.shape[0]
+        n = _rows(feats, "feats", 8)
         g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=feats.device)
         loss = np.zeros(1)
-        self._check(lib().amfmm_mlp_grad(self._h, n, _devt(model, "model", torch.float32),
+        self._check(lib().amfmm_mlp_grad(self._h, n, _devt(model, "model", torch.float32, MLP_MODEL),
                                          _devt(feats, "feats", torch.float32),
-                                         _devt(labels, "labels", torch.float32), float(tau),
+                                         _devt(labels, "labels", torch.float32, n), float(tau),
                                          _devt(g, "grad", torch.float32), _ptr(loss, C.c_double)))
         return float(loss[0]), g
 
     def mlp_train(self, feats, labels, model, adam_m, adam_v, step0, steps, batch, lr, tau=0.9):
         """Adam steps on the pinball loss; model, adam_m, adam_v updated in place."""
-        n = feats.shape[0]
+        n = _rows(feats, "feats", 8)
         loss = np.zeros(1)
         self._check(lib().amfmm_mlp_train(self._h, n, _devt(feats, "feats", torch.float32),
-                                          _devt(labels, "labels", torch.float32),
-                                          _devt(model, "model", torch.float32),
-                                          _devt(adam_m, "adam_m", torch.float32),
-                                          _devt(adam_v, "adam_v", torch.float32), int(step0), int(steps),
-                                          int(batch), float(lr), float(tau), _ptr(loss, C.c_double)))
+                                          _devt(labels, "labels", torch.float32, n),
+                                          _devt(model, "model", torch.float32, MLP_MODEL),
+                                          _devt(adam_m, "adam_m", torch.float32, MLP_PARAMS),
+                                          _devt(adam_v, "adam_v", torch.float32, MLP_PARAMS), int(step0),
+                                          int(steps), int(batch), float(lr), float(tau), _ptr(loss, C.c_double)))
         return float(loss[0])
 
     def build_tree(self, x, y, z, m):
-        self.n = x.numel()
-        self._check(lib().amfmm_build_tree(self._h, self.n, _dev(x, "x"), _dev(y, "y"),
-                                           _dev(z, "z"), _dev(m, "m")))
+        n = x.numel()
+        self._check(lib().amfmm_build_tree(self._h, n, _dev(x, "x", n), _dev(y, "y", n),
+                                           _dev(z, "z", n), _dev(m, "m", n)))
+        self.n = n
 
     def compute_moments(self):
         self._check(lib().amfmm_compute_moments(self._h))
 
     def walk(self, theta):
+        self._check_field(self.n)
         self._check(lib().amfmm_walk(self._h, float(theta)))
 
     def _outputs(self, n, pot):
@@ -240,19 +249,28 @@ class Solver:
         return ax, ay, az, p
 
     def evaluate(self, out=None, pot=True):
-        ax, ay, az, p = out if out is not None else self._outputs(self.n, pot)
-        self._check(lib().amfmm_evaluate(self._h, _dev(ax, "ax"), _dev(ay, "ay"), _dev(az, "az"),
-                                         _dev(p, "pot") if p is not None else None))
+        n = self.n
+        ax, ay, az, p = out if out is not None else self._outputs(n, pot)
+        self._check_field(n)
+        self._check(lib().amfmm_evaluate(self._h, _dev(ax, "ax", n), _dev(ay, "ay", n), _dev(az, "az", n),
+                                         _dev(p, "pot", n) if p is not None else None))
         return ax, ay, az, p
+
+    def _check_field(self, n):
+        # the library reads n elements of each installed field estimate
+        for t, nm in zip(getattr(self, "_field", (None, None, None)), ("gx", "gy", "gz")):
+            if t is not None and t.numel() != n:
+                raise ValueError(f"field estimate {nm} has {t.numel()} elements, {n} expected")
 
     def solve_gravity(self, x, y, z, m, theta, out=None, pot=True):
         n = x.numel()
         ax, ay, az, p = out if out is not None else self._outputs(n, pot)
+        self._check_field(n)
+        args = (_dev(x, "x", n), _dev(y, "y", n), _dev(z, "z", n), _dev(m, "m", n), float(theta),
+                _dev(ax, "ax", n), _dev(ay, "ay", n), _dev(az, "az", n),
+                _dev(p, "pot", n) if p is not None else None)
         self.n = n
-        self._check(lib().amfmm_solve_gravity(self._h, n, _dev(x, "x"), _dev(y, "y"), _dev(z, "z"),
-                                              _dev(m, "m"), float(theta), _dev(ax, "ax"),
-                                              _dev(ay, "ay"), _dev(az, "az"),
-                                              _dev(p, "pot") if p is not None else None))
+        self._check(lib().amfmm_solve_gravity(self._h, n, *args))
         return ax, ay, az, p
 
     def direct(self, x, y, z, m, targets=None, pot=True, gabs=True):
@@ -260,20 +278,23 @@ class Solver:
         nt = n if targets is None else targets.numel()
         if targets is not None and (targets.dtype != torch.int64 or targets.device.type != "cuda"):
             raise TypeError("targets must be a CUDA int64 tensor")
+        if targets is not None and not targets.is_contiguous():
+            raise TypeError("targets must be contiguous")
         ax, ay, az, p = self._outputs(nt, pot)
         g = torch.empty(nt, dtype=torch.float64, device=x.device) if gabs else None
         tp = C.c_void_p(targets.data_ptr()) if targets is not None else None
-        self._check(lib().amfmm_direct(self._h, n, _dev(x, "x"), _dev(y, "y"), _dev(z, "z"),
-                                       _dev(m, "m"), nt, tp, _dev(ax, "ax"), _dev(ay, "ay"),
+        self._check(lib().amfmm_direct(self._h, n, _dev(x, "x", n), _dev(y, "y", n), _dev(z, "z", n),
+                                       _dev(m, "m", n), nt, tp, _dev(ax, "ax"), _dev(ay, "ay"),
                                        _dev(az, "az"), _dev(p, "pot") if p is not None else None,
                                        _dev(g, "gabs") if g is not None else None))
         return ax, ay, az, p, g
 
     def balance(self, x, y, z, m, ax, ay, az):
+        n = x.numel()
         out = np.zeros(2)
-        self._check(lib().amfmm_balance(self._h, x.numel(), _dev(x, "x"), _dev(y, "y"),
-                                        _dev(z, "z"), _dev(m, "m"), _dev(ax, "ax"),
-                                        _dev(ay, "ay"), _dev(az, "az"), _ptr(out, C.c_double)))
+        self._check(lib().amfmm_balance(self._h, n, _dev(x, "x", n), _dev(y, "y", n),
+                                        _dev(z, "z", n), _dev(m, "m", n), _dev(ax, "ax", n),
+                                        _dev(ay, "ay", n), _dev(az, "az", n), _ptr(out, C.c_double)))
         return float(out[0]), float(out[1])
 
     def get_counts(self):

@@ -42,12 +42,17 @@ __device__ inline PairSide side_of(const double4& g, const double* mo, int32_t n
   return PairSide{g.w, mo[0], quad_level(mo[0], g.w, mo + 1), n};
 }
 
-__global__ void __launch_bounds__(kBS) k_pair_features(int64_t np, const int32_t* __restrict__ pairs,
+__global__ void __launch_bounds__(kBS) k_pair_features(int64_t np, const int32_t* __restrict__ pairs, int32_t nc,
                                                        const double4* __restrict__ geo, const double* __restrict__ mom,
                                                        const int32_t* __restrict__ cnt, float* __restrict__ feats) {
   const int64_t k = (int64_t)blockIdx.x * kBS + threadIdx.x;
   if (k >= np) return;
   const int32_t a = pairs[2 * k], b = pairs[2 * k + 1];
+  if (a < 0 || a >= nc || b < 0 || b >= nc) {  // not a cell of the tree
+#pragma unroll
+    for (int i = 0; i < kFeat; ++i) feats[kFeat * k + i] = __builtin_nanf("");
+    return;
+  }
   const double4 ga = geo[a], gb = geo[b];
   const PairSide A = side_of(ga, mom + (int64_t)a * kMom, cnt[a]);
   const PairSide B = side_of(gb, mom + (int64_t)b * kMom, cnt[b]);
@@ -62,7 +67,7 @@ __global__ void __launch_bounds__(kBS) k_pair_features(int64_t np, const int32_t
 // with the correction of the variant), evaluated at up to 64 particles of T,
 // against the direct sum over S's particles.
 template <int VARIANT>
-__global__ void __launch_bounds__(kBS) k_pair_labels(int64_t np, const int32_t* __restrict__ pairs,
+__global__ void __launch_bounds__(kBS) k_pair_labels(int64_t np, const int32_t* __restrict__ pairs, int32_t nc,
                                                      const double4* __restrict__ geo, const double* __restrict__ mom,
                                                      const int32_t* __restrict__ beg, const int32_t* __restrict__ cnt,
                                                      const double4* __restrict__ pos, double* __restrict__ labels) {
@@ -70,6 +75,10 @@ __global__ void __launch_bounds__(kBS) k_pair_labels(int64_t np, const int32_t* 
   const int64_t k = (int64_t)blockIdx.x * (kBS / 64) + (threadIdx.x >> 6);
   if (k >= np) return;
   const int32_t pa = pairs[2 * k], pb = pairs[2 * k + 1];
+  if (pa < 0 || pa >= nc || pb < 0 || pb >= nc) {  // not a cell of the tree (wave-uniform)
+    if (lane == 0) labels[k] = __builtin_nan("");
+    return;
+  }
   const double d = centre_distance(geo[pa], geo[pb]);
   double S = 0.0;
   int total = 0;
@@ -341,7 +350,7 @@ void compute_pair_features(Ctx& c, int64_t np, const int32_t* pairs, float* feat
   check_pairs(c);
   if (np <= 0) return;
   hipLaunchKernelGGL(k_pair_features, dim3((unsigned)((np + kBS - 1) / kBS)), dim3(kBS), 0, c.stream, np, pairs,
-                     (const double4*)c.geo.p, (const double*)c.mom.p, as<int32_t>(c.c_count), feats);
+                     (int32_t)c.ncells, (const double4*)c.geo.p, (const double*)c.mom.p, as<int32_t>(c.c_count), feats);
   AMFMM_HIP(hipGetLastError());
 }
 
@@ -350,7 +359,7 @@ void compute_pair_labels(Ctx& c, int variant, int64_t np, const int32_t* pairs, 
   if (np <= 0) return;
   const dim3 grid((unsigned)((np + 3) / 4));
   auto launch = [&](auto kern) {
-    hipLaunchKernelGGL(kern, grid, dim3(kBS), 0, c.stream, np, pairs, (const double4*)c.geo.p,
+    hipLaunchKernelGGL(kern, grid, dim3(kBS), 0, c.stream, np, pairs, (int32_t)c.ncells, (const double4*)c.geo.p,
                        (const double*)c.mom.p, as<int32_t>(c.c_begin), as<int32_t>(c.c_count),
                        (const double4*)c.pos4.p, labels);
   };

@@ -71,6 +71,14 @@ def test_features_and_labels_match_oracle(name):
     assert np.max(np.abs(gl[big] - ol[big])) <= 1e-6
     assert np.all(gl[~big] < -25.0)
     say(f"  {len(pick)} pairs, labels {np.percentile(ol[big], [5, 50, 95])}, round-off level {np.sum(~big)}")
+    # pairs naming no cell of the tree come back as NaN, the others unchanged
+    nc = s.get_counts()["cells"]
+    odd = np.array([pick[0], [nc, pick[0][1]], [pick[1][0], -1], pick[1]], np.int32)
+    Po = torch.from_numpy(odd).to("cuda")
+    fo = s.pair_features(Po).cpu().numpy()
+    lo = s.pair_labels(Po, amfmm.TC).cpu().numpy()
+    assert np.all(np.isnan(fo[1:3])) and np.all(np.isnan(lo[1:3]))
+    assert np.array_equal(fo[[0, 3]], gf[:2]) and np.array_equal(lo[[0, 3]], gl[:2])
 
 
 def test_predict_bit_exact():

@@ -173,6 +173,20 @@ def test_error_paths():
     with pytest.raises(amfmm.AmfmmError) as e:
         s.solve_gravity(X, Y, Z, Mb, 0.5)
     assert e.value.code == amfmm.E_INVALID
+    # no particles; arrays of different lengths are refused before the call
+    e0 = torch.empty(0, dtype=torch.float64, device="cuda")
+    with pytest.raises(amfmm.AmfmmError) as e:
+        s.solve_gravity(e0, e0, e0, e0, 0.5)
+    assert e.value.code == amfmm.E_INVALID
+    with pytest.raises(ValueError):
+        s.solve_gravity(X, Y[:50], Z, M, 0.5)
+    with pytest.raises(ValueError):
+        s.solve_gravity(X, Y, Z, M, 0.5, out=s._outputs(99, True))
+    fe = amfmm.Solver(criterion=amfmm.MULTIPOLE, error_tol=1e-6, theta_max=0.5)
+    fe.set_field_estimate(torch.ones(99, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        fe.solve_gravity(X, Y, Z, M, 0.5)
+    fe.close()
     # a capped context reports out-of-memory instead of allocating
     small = amfmm.Solver(max_bytes=1 << 12)
     with pytest.raises(amfmm.AmfmmError) as e:
