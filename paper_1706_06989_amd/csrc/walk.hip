@@ -117,14 +117,18 @@ __device__ inline double multipole_bracket(double rt, double rs, int k2s, int k3
 
 template <int EXT>
 __device__ inline int decide(const TreeView& t, int32_t X, const WalkCell& a, int32_t Y, const WalkCell& b) {
+  // the learned and multipole kernels serve only their own mode: a constant
+  const int mode = EXT == kExtBase ? t.mode : EXT;
   const double dx = a.gx - b.gx, dy = a.gy - b.gy, dz = a.gz - b.gz;
   const double d2 = (dx * dx + dy * dy) + dz * dz;
   const double r = a.gw + b.gw;
-  if (t.mode == 0) {
-    const double d = sqrt(d2);
+  // one root per pair, shared by the acceptance tests and the leaf rule below
+  // (lanes of a wave take both paths)
+  const double d = sqrt(d2);
+  if (mode == 0) {
     const double rhs = r / t.theta;
     if (d > 0.0 && d >= rhs) return kAccept;
-  } else if (EXT == kExtBase || t.mode == 1) {
+  } else if (EXT == kExtBase || mode == 1) {
     // The force error of a quadrupole-order pair scales as M_other r^3 / d^5
     // with r = R_A + R_B; accept when that estimate stays below eps times the
     // field scale of each cell (both cells: a symmetric decision) and r <=
@@ -140,7 +144,6 @@ __device__ inline int decide(const TreeView& t, int32_t X, const WalkCell& a, in
     // mode 3: (P_A d + Q_A) M_B <= eps s_A d^6 and the same for B, in product
     // form (one root, no division)
     if (d2 > 0.0 && r * r <= t.theta_max2 * d2) {
-      const double d = sqrt(d2);
       const double d6 = (d2 * d2) * d2;
       const double ea = multipole_bracket(a.gw, b.gw, b.k2, b.k3, d) * b.m;
       const double eb = multipole_bracket(b.gw, a.gw, a.k2, a.k3, d) * a.m;
@@ -148,7 +151,6 @@ __device__ inline int decide(const TreeView& t, int32_t X, const WalkCell& a, in
     }
   } else {
     // mode 2: the network decides where the estimate is close to the bound
-    const double d = sqrt(d2);
     if (d > 0.0 && r <= t.theta_max * d) {
       const PairSide A{a.gw, a.m, a.qlev, a.count}, B{b.gw, b.m, b.qlev, b.count};
       if (learned_accept(t.model, t.eps, t.min_work, d, A, a.gmin, B, b.gmin)) return kAccept;
@@ -162,10 +164,9 @@ __device__ inline int decide(const TreeView& t, int32_t X, const WalkCell& a, in
     // leaf X and the walk would pair X with every leaf under Y: record Y once
     // as a near-field source (its whole particle range).  The margin makes the
     // test safe against rounding of d and of the centres.
-    const double cut = t.mode == 0 ? t.theta : t.theta_max;
-    const double d = sqrt(d2);
+    const double cut = mode == 0 ? t.theta : t.theta_max;
     if ((d + b.gw) * (1.0 + 1e-12) + t.abs_tol < a.gw / cut) return kNear;
-    if (t.mode != 0) {
+    if (mode != 0) {
       // Error-estimate modes: a cell Y' below Y has d' <= d + R_Y, mass at
       // least the smallest leaf mass m below Y, and R_X + R_Y' >= R_X, so its
       // estimate e' M_Y' = (R_X + R_Y')^3 M_Y' / d'^5 is at least
@@ -176,7 +177,7 @@ __device__ inline int decide(const TreeView& t, int32_t X, const WalkCell& a, in
       // a whole.
       const double D = (d + b.gw + t.abs_tol) * (1.0 + 1e-9);
       const double D2 = D * D;
-      const double lim = (t.mode == 2 ? kGateHi : 1.0) * t.eps * a.gmin;
+      const double lim = (mode == 2 ? kGateHi : 1.0) * t.eps * a.gmin;
       if ((a.gw * a.gw * a.gw) * t.mmin[Y] > lim * (D2 * D2 * D)) return kNear;
     }
     return kSplitY;
