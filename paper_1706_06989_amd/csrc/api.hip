@@ -556,6 +556,7 @@ int amfmm_balance(amfmm_ctx* ctx, int64_t n, const double* x, const double* y, c
                   const double* m, const double* ax, const double* ay, const double* az, double* out) {
   return guarded(ctx, [&](Ctx& c) -> int {
     if (n < 1 || !out) return fail(c, AMFMM_E_INVALID, "bad arguments");
+    if (!x || !y || !z || !m || !ax || !ay || !az) return fail(c, AMFMM_E_INVALID, "null pointer");
     amfmm::balance(c, n, x, y, z, m, ax, ay, az, out);
     return AMFMM_OK;
   });
