@@ -381,6 +381,11 @@ __device__ inline int32_t wave_excl_scan(int32_t v, int32_t* total) {
   return inc - v;
 }
 
+// set bits of a wave mask in the lanes below this one
+__device__ inline int32_t lanes_below(uint64_t mask) {
+  return (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
 __device__ inline int64_t wave_sum64(int64_t v) {
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
@@ -592,10 +597,22 @@ __device__ inline bool wave_walk(const TreeView& t, int32_t X, const WalkCell& c
       (void)wave_excl_scan(deep ? nd - 1 : 0, &ndt);
       td += ndt;
     }
-    int32_t Tm, Tp, Tq;
-    const int32_t om = wave_excl_scan(m, &Tm);
-    const int32_t op = wave_excl_scan(p, &Tp);
-    const int32_t oq = wave_excl_scan(q, &Tq);
+    int32_t Tm, Tp, Tq, om, op, oq;
+    if (__ballot(deep || self) == 0) {
+      // no descent and no self pair: every lane holds at most one terminal
+      // pair, so the offsets are counts of lanes below
+      const uint64_t bm = __ballot(m != 0), bp = __ballot(p != 0), bq = __ballot(q != 0);
+      om = lanes_below(bm);
+      op = lanes_below(bp);
+      oq = lanes_below(bq);
+      Tm = __popcll(bm);
+      Tp = __popcll(bp);
+      Tq = __popcll(bq);
+    } else {
+      om = wave_excl_scan(m, &Tm);
+      op = wave_excl_scan(p, &Tp);
+      oq = wave_excl_scan(q, &Tq);
+    }
     if (PASS == kStage) {
       reserve(0, fo + Tm);
       reserve(1, no + Tp);
