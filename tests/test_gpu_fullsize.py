@@ -117,3 +117,31 @@ def test_plummer_2p24_benchmark_configuration():
     d = np.linalg.norm(outs[amfmm.MIXED] - outs[amfmm.FP64], axis=0) / np.linalg.norm(outs[amfmm.FP64], axis=0)
     say(f"  mixed against FP64 (same pairs): p99 {np.percentile(d, 99):.2e}, max {d.max():.2e}")
     assert np.percentile(d, 99) <= 2e-6 and d.max() <= 1e-4
+
+
+def test_two_plummer_2p24_multipole_meets_target():
+    """The two-sphere 2^24 workload (seed 5) in the benchmark's configuration
+    (mixed, TC, geometric pilot at theta 1.0, multipole estimate eps 6.5e-8,
+    theta_max 0.5): p99 relative force error at most 1e-4 over 65536 sampled
+    targets against direct summation, both balances at FP32 round-off."""
+    n = 1 << 24
+    x, y, z, m = W.two_plummer(n, seed=5)
+    say("full size: two plummer spheres 2^24, benchmark configuration")
+    X, Y, Z, M = to_dev(x, y, z, m)
+    del x, y, z, m
+    pilot = amfmm.Solver(precision=amfmm.MIXED)
+    gx, gy, gz, _ = pilot.solve_gravity(X, Y, Z, M, 1.0, pot=False)
+    tg = torch.from_numpy(W.sample_targets(n, 1 << 16, seed=99)).cuda()
+    tx, ty, tz, _, _ = pilot.direct(X, Y, Z, M, tg, pot=False, gabs=False)
+    T = torch.stack([tx, ty, tz])
+    s = amfmm.Solver(precision=amfmm.MIXED, criterion=amfmm.MULTIPOLE, error_tol=6.5e-8, theta_max=0.5)
+    s.set_field_estimate(gx, gy, gz)
+    o = s.solve_gravity(X, Y, Z, M, 0.5, pot=False)
+    A = torch.stack([o[0][tg], o[1][tg], o[2][tg]])
+    e = (torch.linalg.norm(A - T, dim=0) / torch.linalg.norm(T, dim=0)).cpu().numpy()
+    fb, tb = s.balance(X, Y, Z, M, o[0], o[1], o[2])
+    say(f"  p99 {np.percentile(e, 99):.3e}, max {e.max():.3e}, balances {fb:.1e} {tb:.1e}")
+    assert np.percentile(e, 99) <= 1e-4
+    assert fb <= 1e-7 and tb <= 1e-7
+    s.close()
+    pilot.close()
