@@ -459,6 +459,7 @@ struct EmitDst {
   int64_t wcap[3];
   int64_t chunk;
   int64_t* lreg;  // this wave's spill region offsets in LDS (3 x kRegions)
+  int wsh;        // spill_shift of window w in bits 8w..8w+7
 };
 
 enum : int { kStage = 0, kEmit = 1 };
@@ -489,7 +490,7 @@ __device__ inline bool wave_walk(const TreeView& t, int32_t X, const WalkCell& c
         dst.win[w][f] = v;
       } else {
         int64_t off;
-        const int j = spill_region(f - dst.wcap[w], spill_shift(dst.wcap[w]), &off);
+        const int j = spill_region(f - dst.wcap[w], (dst.wsh >> (8 * w)) & 0xff, &off);
         dst.sl->spill[w][dst.lreg[w * kRegions + j] + off] = v;
       }
     }
@@ -512,7 +513,7 @@ __device__ inline bool wave_walk(const TreeView& t, int32_t X, const WalkCell& c
   // STAGE: room for positions below `end` of list w
   auto reserve = [&](int w, int64_t end) {
     const int64_t cap = dst.wcap[w];
-    const int sh = spill_shift(cap);
+    const int sh = (dst.wsh >> (8 * w)) & 0xff;
     while (!ovf && end > cap + ((((int64_t)1 << nreg[w]) - 1) << sh)) {
       if (nreg[w] == kRegions) {
         ovf = true;
@@ -701,6 +702,7 @@ __global__ void __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(EXT ==
     const int64_t lo = stage_lo(*sl, w, e, k);
     dst.win[w] = sl->win[w] + lo;
     dst.wcap[w] = stage_lo(*sl, w, e + n, k + 1) - lo;
+    dst.wsh |= spill_shift(dst.wcap[w]) << (8 * w);
   }
   int64_t tm = 0, tp = 0, tq = 0, td = 0;
   bool over;
