@@ -774,13 +774,11 @@ __global__ void __launch_bounds__(kBS) k_walk_compact(TreeView t, int32_t c0, in
   const int64_t e0 = (k - cbase[i]) * chunk;
   const int64_t e = gbeg[i] + e0;
   const int64_t n = min<int64_t>(chunk, gcnt[i] - e0);
-  // source position j of list w: the window, then the spill regions
-  auto src = [&](int w, int64_t j) {
-    const int64_t lo = stage_lo(sl, w, e, k);
-    const int64_t cap = stage_lo(sl, w, e + n, k + 1) - lo;
-    if (j < cap) return sl.win[w][lo + j];
+  // source position j >= cap of list w (window capacity cap, spill shift sh):
+  // the spill regions
+  auto spilled = [&](int w, int64_t j, int64_t cap, int sh) {
     int64_t off;
-    const int r = spill_region(j - cap, spill_shift(cap), &off);
+    const int r = spill_region(j - cap, sh, &off);
     return sl.spill[w][sl.ksec[(3 * k + w) * kRegions + r] + off];
   };
   // list w to d: the window part with eight loads in flight per lane, then
@@ -799,7 +797,10 @@ __global__ void __launch_bounds__(kBS) k_walk_compact(TreeView t, int32_t c0, in
       for (int u = 0; u < 8; ++u) d[j + u * 64] = v[u];
     }
     for (; j < nw; j += 64) d[j] = s[j];
-    for (j = nw + lane; j < cnt; j += 64) d[j] = src(w, j);
+    if (cnt > cap) {
+      const int sh = spill_shift(cap);
+      for (j = nw + lane; j < cnt; j += 64) d[j] = spilled(w, j, cap, sh);
+    }
   };
   const int64_t nm = mex[k + 1] - mex[k], np = pex[k + 1] - pex[k], nq = qex[k + 1] - qex[k];
   copy(0, far_src + far_base + mex[k], nm);
@@ -808,8 +809,11 @@ __global__ void __launch_bounds__(kBS) k_walk_compact(TreeView t, int32_t c0, in
     const int32_t nch = load_cell(t.rec, c0 + i).nch;
     const int64_t S = qex[cbase[i + 1]] - qex[cbase[i]];
     int32_t* dq = fy_n + nbase[i] + (qex[k] - qex[cbase[i]]);
+    const int64_t lo = stage_lo(sl, 2, e, k);
+    const int64_t cap = stage_lo(sl, 2, e + n, k + 1) - lo;
+    const int sh = spill_shift(cap);
     for (int64_t j = lane; j < nq; j += 64) {
-      const int32_t v = src(2, j);
+      const int32_t v = j < cap ? sl.win[2][lo + j] : spilled(2, j, cap, sh);
       for (int32_t r = 0; r < nch; ++r) dq[r * S + j] = v;
     }
   }
