@@ -62,7 +62,7 @@ def parse():
     p.add_argument("--pilot-theta", type=float, default=1.0,
                    help="opening angle of the pilot solve that gives the field estimate")
     p.add_argument("--criterion", choices=["geometric", "estimate", "learned", "multipole"], default="multipole")
-    p.add_argument("--eps", type=float, default=6.5e-8,
+    p.add_argument("--eps", type=float, default=8e-8,
                    help="error-estimate criterion: accepted pair error relative to the field scale")
     p.add_argument("--theta-max", type=float, default=0.5)
     p.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
