@@ -11,9 +11,20 @@ particles and the unsort.  Outputs one JSON line.  The error of the timed
 configuration is measured outside the timed region against direct summation
 at a seeded sample of 65536 targets.
 
-Workload: 16,777,216-particle Plummer sphere (scale radius 1, mass 1,
-truncated at 20, seed 4, equal masses), G = 1, n_crit = 25, TC variant,
-mixed precision (FP32 pair terms, FP64 accumulation and correction).
+Workload (default): 16,777,216-particle Plummer sphere (scale radius 1, mass
+1, truncated at 20, seed 4, equal masses), G = 1, n_crit = 25, TC variant,
+mixed precision (FP32 pair terms, FP64 accumulation and correction);
+--workload picks another synthetic input of the same generators.  Default
+steps: 10 timed after 3 warm-ups.
+
+Beside the contract's fields the line carries: `roofline` (the kernel with
+the most time in the step, the other two large kernels under `others`,
+measured HBM bytes per launch from the committed counter summary when its
+sources and configuration match), `cpu_baseline` (the CPU oracle on a smaller
+sample of the same workload, and its UC/TC/TCO evaluation cost),
+`plain_fp64` (the plain solve, FP64 and geometric, at the --plain-thetas
+angles, with the speedup at the largest angle that meets p99 1e-4) and the
+median of the per-step HIP-event totals.
 """
 import argparse
 import hashlib
