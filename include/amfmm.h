@@ -201,6 +201,12 @@ int amfmm_mlp_train(amfmm_ctx* ctx, int64_t n, const float* feats, const float* 
                     float* adam_m, float* adam_v, int64_t step0, int32_t steps, int32_t batch, double lr,
                     double tau, double* last_loss);
 
+/* Environment (read by the library, for tests and diagnosis only):
+ *   AMFMM_WALK_WINDOWS=f  scales the walk's staging windows by f in [0, 1]
+ *                         (small values force the spill and re-walk paths);
+ *   AMFMM_DEBUG_WALK      prints per-level walk statistics to stderr (adds a
+ *                         synchronisation per level). */
+
 /* ---- introspection (host buffers owned by the caller; synchronising) ---- */
 /* counts[0..11] = cells, depth, far-field pairs, near-field pairs (unordered,
  * as amfmm_get_lists returns them), leaves, particles, near-field particle
