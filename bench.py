@@ -148,7 +148,14 @@ def cpu_baseline(workload, n, theta, criterion, eps, theta_max):
         best[name] = min(ts)
     what = (f"pilot theta={theta} + {criterion} error-estimate solve eps={eps} theta_max={theta_max}"
             if criterion != "geometric" else f"theta={theta}")
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": n / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
+            "host": {"nproc": os.cpu_count(), "cpu_model": model},
             "sample": f"full oracle solve (tree, moments, walk, eqs. 2-4 at every particle, near "
                       f"field) of {n} particles of the {workload} workload (same generator and seed), "
                       f"{what}, TC, FP64, "
