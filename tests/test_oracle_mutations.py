@@ -77,6 +77,12 @@ MUTATIONS = {
     "multipole_octupole_not_traceless": ("double w = mo.M3[i][j][k] - (v[i] * kdelta(j, k) + v[j] * kdelta(i, k) + v[k] * kdelta(i, j)) / 5.0;",
                                          "double w = mo.M3[i][j][k];"),
     "multipole_no_target_truncation": ("kMw1 * (rt2 * rt);", "0.0 * (rt2 * rt);"),
+    "multipole_quadrupole_not_traceless": ("double v = mo.M2[i][j] - (i == j ? tr / 3.0 : 0.0);",
+                                           "double v = mo.M2[i][j];"),
+    "multipole_level_truncates": ("double k = std::floor(kMq * (norm / den) + 0.5);",
+                                  "double k = std::floor(kMq * (norm / den));"),
+    "multipole_source_terms_swapped": ("double Q = kMw4 * (rs2 * rs2) + kMw5 * (rt2 * rt2);",
+                                       "double Q = kMw5 * (rs2 * rs2) + kMw4 * (rt2 * rt2);"),
     "self_walk_skips_pairs": ("for (int32_t b = a + 1; b < C.child0 + C.nchild; ++b) walk_pair(t, a, b);",
                               "for (int32_t b = a + 2; b < C.child0 + C.nchild; ++b) walk_pair(t, a, b);"),
 }
