@@ -50,7 +50,7 @@ def _plummer_radii(rng, n, a=1.0, rtrunc=PLUMMER_RTRUNC):
 
 
 def _plummer_points(rng, n, a=1.0):
-    r = _plummer_radii(rng, n, a)
+    r = _plummer_radii(rng, n, a, PLUMMER_RTRUNC * a)  # truncated at 20 scale radii
     c = rng.uniform(-1.0, 1.0, n)
     p = rng.uniform(0.0, 2.0 * np.pi, n)
     s = np.sqrt(1.0 - c * c)
