@@ -15,6 +15,8 @@ import pytest
 from oracle import oracle as orc
 from paper_1706_06989_amd import workloads as W
 
+from .walk_check import check_walk
+
 W1, W2, W3, W4, W5 = 1.159, 3.73, 0.967, 0.232, 2.68  # the calibrated weights (see oracle.cpp)
 KQ = 128.0
 
@@ -109,6 +111,54 @@ def test_multipole_walk_covers_pairs_and_meets_estimate(eps, tmax):
         assert estimate(RA, RB, k2[B], k3[B], d, mo[B, 0]) <= eps * s[A] * (1 + 1e-9)
         assert estimate(RB, RA, k2[A], k3[A], d, mo[A, 0]) <= eps * s[B] * (1 + 1e-9)
     assert len(m2l) > 0
+
+
+def multipole_accept(mo, k2, k3, s, eps, tmax):
+    """The multipole estimate's decision from this file's own formula; pairs
+    within 1e-9 (relative) of a bound may go either way (None): the oracle
+    evaluates the same bound in another operation order."""
+    def side(lhs, rhs):
+        if lhs <= rhs * (1 - 1e-9):
+            return True
+        if lhs >= rhs * (1 + 1e-9):
+            return False
+        return None
+
+    def accept(a, b):
+        d = float(np.linalg.norm(mo[a, 1:4] - mo[b, 1:4]))
+        if d == 0.0:
+            return False
+        RA, RB = mo[a, 4], mo[b, 4]
+        v = [side(RA + RB, tmax * d),
+             side(estimate(RA, RB, k2[b], k3[b], d, mo[b, 0]), eps * s[a]),
+             side(estimate(RB, RA, k2[a], k3[a], d, mo[a, 0]), eps * s[b])]
+        if False in v:
+            return False
+        return True if all(v) else None
+
+    return accept
+
+
+@pytest.mark.parametrize("eps,tmax", [(1e-3, 0.7), (1e-5, 0.5)])
+def test_multipole_walk_is_complete(eps, tmax):
+    """No pair the estimate accepts is split, and no leaf pair it accepts goes
+    to the near field (bottom-up check of the walk, see walk_check); a walk at
+    a 1.25 times smaller tolerance fails the same check."""
+    x, y, z, m = W.two_plummer(800, seed=17)
+    a, _, _ = orc.direct(x, y, z, m)
+    gmag = np.linalg.norm(a, axis=0)
+    t = orc.Tree(x, y, z, m, n_crit=8)
+    t.compute_moments()
+    mo = t.moments()
+    k2, k3 = levels_from_particles(t, x, y, z, m)
+    acc = multipole_accept(mo, k2, k3, field_scale(t, gmag), eps, tmax)
+    t.walk_multipole(eps, tmax, gmag)
+    m2l, p2p = t.lists()
+    check_walk(t.cells(), mo, m2l, p2p, acc)
+    t.walk_multipole(eps / 1.25, tmax, gmag)
+    m2l_c, p2p_c = t.lists()
+    with pytest.raises(AssertionError):
+        check_walk(t.cells(), mo, m2l_c, p2p_c, acc)
 
 
 def test_multipole_tolerance_controls_error():

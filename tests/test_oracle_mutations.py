@@ -47,6 +47,7 @@ MUTATIONS = {
     "octupole_transposed": ("mo.M3[i][j][k] += mu * xv[i] * xv[j] * xv[k];",
                             "mo.M3[i][j][k] += mu * xv[i] * xv[j] * xv[j];"),
     "criterion_one_radius": ("double rhs = (A.Rmax + B.Rmax) / t.theta;", "double rhs = (A.Rmax) / t.theta;"),
+    "criterion_stricter": ("double rhs = (A.Rmax + B.Rmax) / t.theta;", "double rhs = 1.25 * (A.Rmax + B.Rmax) / t.theta;"),
     "key_bits_swapped": ("key |= ((q[0] >> b) & 1) << (3 * b + 2);", "key |= ((q[0] >> b) & 1) << (3 * b + 1);"),
     "split_at_ncrit": ("if (!(cur.count > n_crit && lev < max_level)) continue;",
                        "if (!(cur.count >= n_crit && lev < max_level)) continue;"),
@@ -71,6 +72,8 @@ MUTATIONS = {
                               "f[5] = (float)((double)(qa - qb) / 64.0);"),
     "multipole_one_sided": ("return ea <= (t.eps * t.fscale[a]) * d6 && eb <= (t.eps * t.fscale[b]) * d6;",
                             "return ea <= (t.eps * t.fscale[a]) * d6;"),
+    "multipole_stricter": ("return ea <= (t.eps * t.fscale[a]) * d6 && eb <= (t.eps * t.fscale[b]) * d6;",
+                           "return 1.25 * ea <= (t.eps * t.fscale[a]) * d6 && 1.25 * eb <= (t.eps * t.fscale[b]) * d6;"),
     "multipole_power_of_d": ("double d6 = (d2 * d2) * d2;", "double d6 = (d2 * d2) * d;"),
     "multipole_extents_swapped": ("double ea = multipole_bracket(A.Rmax, B.Rmax, t.k2[b], t.k3[b], d) * B.M;",
                                   "double ea = multipole_bracket(B.Rmax, A.Rmax, t.k2[b], t.k3[b], d) * B.M;"),

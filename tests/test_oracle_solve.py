@@ -13,6 +13,8 @@ import pytest
 from oracle import oracle as orc
 from paper_1706_06989_amd import workloads as W
 
+from .walk_check import check_walk, geometric_accept
+
 
 def test_single_leaf_equals_direct_sum():
     x, y, z, m = W.uniform_cube(25, seed=3)
@@ -68,6 +70,26 @@ def test_every_particle_pair_covered_once(theta):
     for a, b in m2l:
         d = np.linalg.norm(mo[a, 1:4] - mo[b, 1:4])
         assert d >= (mo[a, 4] + mo[b, 4]) / theta
+
+
+@pytest.mark.parametrize("theta", [0.3, 0.7, 1.0])
+def test_walk_is_complete(theta):
+    """The lists hold exactly the walk's terminal pairs: no pair is split that
+    the criterion accepts, and no leaf pair that it accepts goes to the near
+    field (checked bottom-up, see walk_check)."""
+    x, y, z, m = W.two_plummer(700, seed=6)
+    t = orc.Tree(x, y, z, m, n_crit=8)
+    t.compute_moments()
+    t.walk(theta)
+    m2l, p2p = t.lists()
+    mo = t.moments()
+    check_walk(t.cells(), mo, m2l, p2p, geometric_accept(mo, theta))
+    # the lists of a walk 1.25 times more conservative than the criterion
+    # (a covering, self-consistent walk at a smaller angle) fail the check
+    t.walk(theta / 1.25)
+    m2l_c, p2p_c = t.lists()
+    with pytest.raises(AssertionError):
+        check_walk(t.cells(), mo, m2l_c, p2p_c, geometric_accept(mo, theta))
 
 
 @pytest.fixture(scope="module")
