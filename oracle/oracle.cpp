@@ -34,6 +34,9 @@
 #include <numeric>
 #include <utility>
 #include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 namespace {
 
@@ -1164,6 +1167,103 @@ int32_t orc_evaluate_sample(orc_tree* t, int32_t variant, double G, int64_t ns, 
     if (pot) pot[q] = G * ph;
   }
   return ORC_OK;
+}
+
+int32_t orc_evaluate_targets(orc_tree* t, int32_t variant, double G, double* ax, double* ay,
+                             double* az, double* pot) {
+  if (!t->have_lists) return ORC_E_STATE;
+  if (variant < ORC_UC || variant > ORC_TCO) return ORC_E_INVALID;
+  int64_t n = t->n;
+  int64_t nc = (int64_t)t->cells.size();
+  std::vector<double> gx(n, 0.0), gy(n, 0.0), gz(n, 0.0), ph(n, 0.0);
+  // the partners of every cell, in list order
+  std::vector<std::vector<int32_t>> far(nc), near(nc);
+  for (const auto& pr : t->m2l) {
+    far[pr.first].push_back(pr.second);
+    far[pr.second].push_back(pr.first);
+  }
+  for (const auto& pr : t->p2p) {
+    near[pr.first].push_back(pr.second);
+    if (pr.first != pr.second) near[pr.second].push_back(pr.first);
+  }
+  // far field, one level at a time: the lower index of a pair is the field
+  // cell of eq. 3, the higher that of eq. 4 (as in orc_evaluate)
+  int32_t depth = orc_depth(t);
+  for (int32_t lev = 0; lev <= depth; ++lev) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t ci = 0; ci < nc; ++ci) {
+      const Cell& C = t->cells[ci];
+      if (C.level != lev) continue;
+      const Moments& own = t->mom[ci];
+      for (int32_t other : far[ci]) {
+        int32_t a = std::min((int32_t)ci, other), b = std::max((int32_t)ci, other);
+        PairTerms pt;
+        pair_terms(t->mom[a], t->mom[b], variant, pt);
+        for (int64_t p = C.begin; p < C.begin + C.count; ++p) {
+          double xv[3] = {t->x[p] - own.Z[0], t->y[p] - own.Z[1], t->z[p] - own.Z[2]};
+          double g[3];
+          if (ci == a) {
+            eq3_accel(pt.g, t->mom[b], xv, g);
+            gx[p] += g[0] + pt.Fc[0] / own.M;
+            gy[p] += g[1] + pt.Fc[1] / own.M;
+            gz[p] += g[2] + pt.Fc[2] / own.M;
+            ph[p] += eq2_pot_A(pt.g, t->mom[b], xv);
+          } else {
+            eq4_accel(pt.g, t->mom[a], xv, g);
+            gx[p] += g[0] - pt.Fc[0] / own.M;
+            gy[p] += g[1] - pt.Fc[1] / own.M;
+            gz[p] += g[2] - pt.Fc[2] / own.M;
+            ph[p] += eq2_pot_B(pt.g, t->mom[a], xv);
+          }
+        }
+      }
+    }
+  }
+  // near field: every leaf sums its partners' particles onto its own
+  int64_t skipped = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : skipped)
+  for (int64_t ci = 0; ci < nc; ++ci) {
+    const Cell& C = t->cells[ci];
+    if (!is_leaf(C)) continue;
+    for (int32_t other : near[ci]) {
+      const Cell& O = t->cells[other];
+      for (int64_t i = C.begin; i < C.begin + C.count; ++i) {
+        for (int64_t j = O.begin; j < O.begin + O.count; ++j) {
+          double dx = t->x[j] - t->x[i];
+          double dy = t->y[j] - t->y[i];
+          double dz = t->z[j] - t->z[i];
+          double r2 = (dx * dx + dy * dy) + dz * dz;
+          if (r2 == 0.0) {
+            if (j != i) ++skipped;
+            continue;
+          }
+          double r = std::sqrt(r2);
+          double r3 = r2 * r;
+          gx[i] += t->m[j] * dx / r3;
+          gy[i] += t->m[j] * dy / r3;
+          gz[i] += t->m[j] * dz / r3;
+          ph[i] -= t->m[j] / r;
+        }
+      }
+    }
+  }
+  t->coincident = skipped / 2;  // each coincident pair was seen from both sides
+  for (int64_t s = 0; s < n; ++s) {
+    int64_t i = t->perm[s];
+    ax[i] = G * gx[s];
+    ay[i] = G * gy[s];
+    az[i] = G * gz[s];
+    if (pot) pot[i] = G * ph[s];
+  }
+  return ORC_OK;
+}
+
+int32_t orc_num_threads(void) {
+#ifdef _OPENMP
+  return (int32_t)omp_get_max_threads();
+#else
+  return 1;
+#endif
 }
 
 int64_t orc_num_coincident(const orc_tree* t) { return t->coincident; }

@@ -95,6 +95,17 @@ int32_t orc_evaluate(orc_tree* t, int32_t variant, double G, double* ax, double*
  * walk.  Outputs are per sample entry. */
 int32_t orc_evaluate_sample(orc_tree* t, int32_t variant, double G, int64_t ns, const int64_t* idx,
                             double* ax, double* ay, double* az, double* pot);
+/* The same evaluation organised by target, for timing on many cores: the far
+ * pairs of every cell are applied to its own particles one tree level at a
+ * time (cells of a level hold disjoint particles), the near field of every
+ * leaf is summed over its own particles only.  Each particle's sums run in an
+ * order fixed by the lists, so the result does not depend on the number of
+ * threads (OpenMP when built with it; serial otherwise).  Equal to
+ * orc_evaluate up to summation order. */
+int32_t orc_evaluate_targets(orc_tree* t, int32_t variant, double G, double* ax, double* ay,
+                             double* az, double* pot);
+/* threads orc_evaluate_targets runs on (1 in a build without OpenMP) */
+int32_t orc_num_threads(void);
 /* number of particle pairs skipped because they coincide (r == 0, i != j) */
 int64_t orc_num_coincident(const orc_tree* t);
 

@@ -55,6 +55,10 @@ def lib():
         L.orc_get_lists.argtypes = [P, i32, i32]
         L.orc_evaluate.restype = C.c_int32
         L.orc_evaluate.argtypes = [P, C.c_int32, C.c_double, d, d, d, d]
+        L.orc_evaluate_targets.restype = C.c_int32
+        L.orc_evaluate_targets.argtypes = [P, C.c_int32, C.c_double, d, d, d, d]
+        L.orc_num_threads.restype = C.c_int32
+        L.orc_num_threads.argtypes = []
         L.orc_evaluate_sample.restype = C.c_int32
         L.orc_evaluate_sample.argtypes = [P, C.c_int32, C.c_double, C.c_int64, i64, d, d, d, d]
         L.orc_num_coincident.restype = C.c_int64
@@ -233,6 +237,16 @@ class Tree:
             raise OracleError(st)
         return np.stack([ax, ay, az]), pot
 
+    def evaluate_targets(self, variant=TC, G=1.0):
+        """The same evaluation organised by target (all host cores in the
+        OpenMP build); equal to evaluate() up to summation order."""
+        n = self.n
+        ax, ay, az, pot = (np.zeros(n) for _ in range(4))
+        st = lib().orc_evaluate_targets(self._t, variant, float(G), _d(ax), _d(ay), _d(az), _d(pot))
+        if st:
+            raise OracleError(st)
+        return np.stack([ax, ay, az]), pot
+
     def evaluate_sample(self, idx, variant=TC, G=1.0):
         """Same evaluation at the caller indices idx only."""
         idx = np.ascontiguousarray(idx, dtype=np.int64)
@@ -248,6 +262,20 @@ class Tree:
     @property
     def coincident(self):
         return lib().orc_num_coincident(self._t)
+
+
+def num_threads():
+    """Threads the loaded oracle library's target-ordered evaluation uses."""
+    return lib().orc_num_threads()
+
+
+def use_openmp_build():
+    """Load the OpenMP build of the oracle in place of the serial one (the
+    benchmark's CPU baseline; call before any other oracle call)."""
+    from .build import ensure_built_omp
+    global _lib
+    if _lib is None:
+        os.environ["AMFMM_ORACLE_LIB"] = ensure_built_omp()
 
 
 def solve(x, y, z, m, theta=0.5, n_crit=25, variant=TC, G=1.0):

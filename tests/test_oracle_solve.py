@@ -200,3 +200,46 @@ def test_sampled_evaluation_matches_full():
         _, _, gabs = orc.direct(x, y, z, m, idx)
         assert np.max(np.linalg.norm(s - a[:, idx], axis=0) / gabs) <= 1e-14
         assert np.max(np.abs(q - p[idx]) / np.abs(p[idx])) <= 1e-14
+
+
+def test_target_ordered_evaluation_matches():
+    """The target-ordered evaluation (the CPU baseline's, on all cores in the
+    OpenMP build) equals the pair-ordered one up to summation order, and the
+    OpenMP build gives the serial build's result bit for bit."""
+    import os
+    import subprocess
+    import sys
+
+    x, y, z, m = W.two_plummer(3000, seed=8)
+    x = np.concatenate([x, x[:3]])  # coincident points: counted once per pair
+    y = np.concatenate([y, y[:3]])
+    z = np.concatenate([z, z[:3]])
+    m = np.full(len(x), 1.0 / len(x))
+    t = orc.Tree(x, y, z, m, n_crit=12)
+    t.compute_moments()
+    t.walk(0.6)
+    _, _, gabs = orc.direct(x, y, z, m)
+    for v in (orc.UC, orc.TC, orc.TCO):
+        a, p = t.evaluate(v)
+        c1 = t.coincident
+        b, q = t.evaluate_targets(v)
+        assert t.coincident == c1 == 3
+        assert np.max(np.linalg.norm(a - b, axis=0) / gabs) <= 1e-14
+        assert np.max(np.abs(p - q) / np.abs(p)) <= 1e-14
+    from oracle.build import ensure_built_omp
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys, numpy as np; sys.path.insert(0, %r)\n"
+            "from oracle import oracle as orc\nfrom paper_1706_06989_amd import workloads as W\n"
+            "x, y, z, m = W.two_plummer(3000, seed=8)\n"
+            "t = orc.Tree(x, y, z, m, n_crit=12); t.compute_moments(); t.walk(0.6)\n"
+            "a, p = t.evaluate_targets(orc.TC)\n"
+            "sys.stdout.buffer.write(np.concatenate([a.ravel(), p]).tobytes())\n" % root)
+    outs = []
+    for lib in (None, ensure_built_omp()):
+        env = dict(os.environ, OMP_NUM_THREADS="4")
+        env.pop("AMFMM_ORACLE_LIB", None)
+        if lib:
+            env["AMFMM_ORACLE_LIB"] = lib
+        outs.append(subprocess.run([sys.executable, "-c", code], env=env, capture_output=True,
+                                   check=True).stdout)
+    assert len(outs[0]) == 8 * 4 * 3000 and outs[0] == outs[1]
