@@ -23,8 +23,10 @@ measured HBM bytes per launch from the committed counter summary when its
 sources and configuration match), `cpu_baseline` (the CPU oracle on a smaller
 sample of the same workload, and its UC/TC/TCO evaluation cost),
 `plain_fp64` (the plain solve, FP64 and geometric, at the --plain-thetas
-angles, with the speedup at the largest angle that meets p99 1e-4) and the
-median of the per-step HIP-event totals.
+angles, with the speedup at the largest angle that meets p99 1e-4),
+`mixed_geometric` (the mixed-precision geometric solve at --theta against the
+FP64 one: times, errors, residuals) and the median of the per-step HIP-event
+totals.
 """
 import argparse
 import hashlib
@@ -310,7 +312,34 @@ def main():
     # given opening angles, outside the timed region, each timed once after a
     # warm-up: the largest angle whose p99 meets 1e-4 is the matched-error
     # point the speedup is quoted against.
+    def mixed_against_fp64(o64, ms64, th):
+        """The mixed-precision geometric solve at angle th (the same pairs as
+        the FP64 solve o64): its time, its error against direct summation and
+        against the FP64 solve at the sampled targets, and its residuals."""
+        pm = amfmm.Solver(variant=variant, precision=amfmm.MIXED)
+        pm.solve_gravity(X, Y, Z, M, th, pot=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        om = pm.solve_gravity(X, Y, Z, M, th, pot=False)
+        torch.cuda.synchronize()
+        mms = (time.perf_counter() - t1) * 1e3
+        em = p_err(om)
+        A64 = torch.stack([o64[0][idx], o64[1][idx], o64[2][idx]])
+        Am = torch.stack([om[0][idx], om[1][idx], om[2][idx]])
+        d = (torch.linalg.norm(Am - A64, dim=0) / torch.linalg.norm(A64, dim=0)).cpu().numpy()
+        fb, tb = pm.balance(X, Y, Z, M, om[0], om[1], om[2])
+        fb64, tb64 = pm.balance(X, Y, Z, M, o64[0], o64[1], o64[2])
+        pm.close()
+        print(f"# mixed geometric theta={th}: {mms:.1f} ms", file=sys.stderr, flush=True)
+        return {"criterion": "geometric", "theta": th, "variant": a.variant, "fp64_ms": round(ms64, 3),
+                "mixed_ms": round(mms, 3), "speedup": round(ms64 / mms, 3),
+                "mixed_p99_rel_force_error": float(np.percentile(em, 99)),
+                "mixed_vs_fp64_p99": float(np.percentile(d, 99)), "mixed_vs_fp64_max": float(d.max()),
+                "mixed_force_balance": fb, "mixed_torque_balance": tb,
+                "fp64_force_balance": fb64, "fp64_torque_balance": tb64}
+
     plain = None
+    mixed_geo = None
     thetas = [float(t) for t in a.plain_thetas.split(",") if t.strip()]
     if thetas:
         pilot.close()
@@ -327,9 +356,11 @@ def main():
             torch.cuda.synchronize()
             pms = (time.perf_counter() - t1) * 1e3
             pe = p_err(o)
-            del o
             rows.append({"theta": th, "ms": round(pms, 3), "p99_rel_force_error": float(np.percentile(pe, 99))})
             print(f"# plain fp64 theta={th}: {pms:.1f} ms", file=sys.stderr, flush=True)
+            if th == a.theta and mixed_geo is None:
+                mixed_geo = mixed_against_fp64(o, pms, th)
+            del o
         ps.close()
         ok = [r for r in rows if r["p99_rel_force_error"] <= 1e-4]
         plain = {"precision": "fp64", "criterion": "geometric", "variant": a.variant, "rows": rows}
@@ -361,7 +392,7 @@ def main():
                    "meets_1e-4_p99": bool(np.percentile(eps, 99) <= 1e-4),
                    "force_balance": fbal, "torque_balance": tbal,
                    "phase_ms": {k: round(v, 3) for k, v in phases.items()}, "counts": counts},
-        "roofline": roofline, "cpu_baseline": cpu, "plain_fp64": plain,
+        "roofline": roofline, "cpu_baseline": cpu, "plain_fp64": plain, "mixed_geometric": mixed_geo,
     }
     if a.copy_calibration:
         # 1 GiB read + 1 GiB written by one copy kernel per call

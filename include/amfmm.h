@@ -36,10 +36,15 @@ typedef enum { AMFMM_UC = 0, AMFMM_TC = 1, AMFMM_TCO = 2 } amfmm_variant;
 
 /* Arithmetic of the near field and of the far-field coefficients.
  * FP64: everything in double precision.
- * MIXED: pair terms in FP32 on offsets taken relative to cell centres (the
- * centre-to-centre vector formed in FP64), summed per particle into FP64 with
- * compensated (two-sum) accumulation; centres of mass, the moment reduction
- * and the correction of eq. 7/8 stay in FP64. */
+ * MIXED: near-field pair terms and far-field coefficient terms in FP32, on
+ * offsets taken relative to cell centres (each offset and the centre-to-centre
+ * vector formed in FP64, then rounded).  Per-particle near-field sums are
+ * compensated FP64 sums: blocks of at most 16 FP32 terms are added to an FP64
+ * accumulator with TwoSum, the rounding errors collected in a compensation
+ * term added back at the end.  Far-field coefficients are summed per cell in
+ * FP32 blocks of at most 8 terms added to FP64.  Centres of mass, the moment
+ * reduction, the correction of eq. 7/8, the push-down and the evaluation at
+ * the particles stay in FP64. */
 typedef enum { AMFMM_FP64 = 0, AMFMM_MIXED = 1 } amfmm_precision;
 
 /* Accept/open decision of the walk.

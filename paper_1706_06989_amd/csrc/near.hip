@@ -12,10 +12,13 @@
 // Mixed precision: targets and staged sources are FP32 offsets from the
 // target leaf's centre of mass (each difference taken in FP64, then rounded),
 // the pair terms are FP32 (hardware reciprocal square root), and each lane's
-// FP32 sums run over at most kFlush sources before they are added to FP64
-// accumulators; the tile sums enter FP64 exactly, so the FP64 accumulator
-// carries what an FP32 compensation term would.  Slices, L2P and the output
-// stay FP64.
+// FP32 sums run over at most kFlush sources before they are flushed into a
+// compensated FP64 sum per target and component: an FP64 accumulator plus the
+// rounding error of every addition to it (TwoSum, Knuth), collected in an
+// FP32 compensation term (the errors are below 2^-53 of the sum, so FP32
+// holds them to far below FP64 resolution).  The slices of a target are
+// reduced the same way; the compensation is added back once, before L2P.
+// L2P and the output stay FP64.
 #include "device_math.h"
 #include "internal.h"
 
@@ -38,10 +41,23 @@ __device__ inline int pow2floor(int v) { return 1 << (31 - __builtin_clz(v)); }
 
 constexpr int kFlush = 16;  // FP32 terms per lane and target before an FP64 flush
 
+// s + b = s' + e exactly (TwoSum: six operations, no condition on the
+// magnitudes; the library is built without contraction, so no step fuses);
+// s <- s', the rounding error e goes to the compensation term c
+__device__ inline void comp_add(double& s, float& c, double b) {
+  const double t = s + b;
+  const double bp = t - s;
+  const double e = (s - (t - bp)) + (b - bp);
+  s = t;
+  c += (float)e;
+}
+
 // FP32 interactions of this lane's targets (offsets t*) with sources
-// buf[s], buf[s+nsl], ...; partial sums flushed into the FP64 accumulators
+// buf[s], buf[s+nsl], ...; partial sums flushed into the compensated FP64
+// sums (f*, compensation terms c*)
 __device__ inline void near_tile_f32(const float4* buf, int fill, int s, int nsl, const float* tx, const float* ty,
-                                     const float* tz, double* fx, double* fy, double* fz, double* ph) {
+                                     const float* tz, double* fx, double* fy, double* fz, double* ph, float* cx,
+                                     float* cy, float* cz, float* cp) {
   for (int j0 = s; j0 < fill; j0 += kFlush * nsl) {
     const int j1 = min(fill, j0 + kFlush * nsl);
     float gx[kTG], gy[kTG], gz[kTG], gp[kTG];
@@ -65,10 +81,10 @@ __device__ inline void near_tile_f32(const float4* buf, int fill, int s, int nsl
     }
 #pragma unroll
     for (int u = 0; u < kTG; ++u) {
-      fx[u] += (double)gx[u];
-      fy[u] += (double)gy[u];
-      fz[u] += (double)gz[u];
-      ph[u] += (double)gp[u];
+      comp_add(fx[u], cx[u], (double)gx[u]);
+      comp_add(fy[u], cy[u], (double)gy[u]);
+      comp_add(fz[u], cz[u], (double)gz[u]);
+      comp_add(ph[u], cp[u], (double)gp[u]);
     }
   }
 }
@@ -136,8 +152,10 @@ __global__ void __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(4))) k
     double tx[kTG], ty[kTG], tz[kTG];
     float ux[kTG], uy[kTG], uz[kTG];  // mixed: FP32 offsets from the leaf centre
     double fx[kTG], fy[kTG], fz[kTG], ph[kTG];
+    float cx[kTG], cy[kTG], cz[kTG], cp[kTG];  // mixed: compensation terms
 #pragma unroll
     for (int q = 0; q < kTG; ++q) {
+      cx[q] = cy[q] = cz[q] = cp[q] = 0.0f;
       const int t = g * kTG + q;
       const double4 p = pos[tb + ((active && t < ntc) ? t : 0)];
       tx[q] = p.x;
@@ -209,7 +227,7 @@ __global__ void __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(4))) k
           }
           wave_sync();
           if (active) {
-            if (MIXED) near_tile_f32(buf32, part, s, nsl, ux, uy, uz, fx, fy, fz, ph);
+            if (MIXED) near_tile_f32(buf32, part, s, nsl, ux, uy, uz, fx, fy, fz, ph, cx, cy, cz, cp);
             else near_tile(buf, part, s, nsl, tx, ty, tz, fx, fy, fz, ph);
           }
           wave_sync();
@@ -222,7 +240,7 @@ __global__ void __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(4))) k
       if (take > 0) {
         wave_sync();
         if (active) {
-          if (MIXED) near_tile_f32(buf32, fill, s, nsl, ux, uy, uz, fx, fy, fz, ph);
+          if (MIXED) near_tile_f32(buf32, fill, s, nsl, ux, uy, uz, fx, fy, fz, ph, cx, cy, cz, cp);
           else near_tile(buf, fill, s, nsl, tx, ty, tz, fx, fy, fz, ph);
         }
         wave_sync();
@@ -240,12 +258,35 @@ __global__ void __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(4))) k
       for (int u = 0; u < kTG; ++u) {
         const double vx = __shfl(fx[u], lane + off, 64), vy = __shfl(fy[u], lane + off, 64);
         const double vz = __shfl(fz[u], lane + off, 64), vp = __shfl(ph[u], lane + off, 64);
-        if (take) {
+        if (MIXED) {
+          const float wx = __shfl(cx[u], lane + off, 64), wy = __shfl(cy[u], lane + off, 64);
+          const float wz = __shfl(cz[u], lane + off, 64), wp = __shfl(cp[u], lane + off, 64);
+          if (take) {
+            comp_add(fx[u], cx[u], vx);
+            comp_add(fy[u], cy[u], vy);
+            comp_add(fz[u], cz[u], vz);
+            comp_add(ph[u], cp[u], vp);
+            cx[u] += wx;
+            cy[u] += wy;
+            cz[u] += wz;
+            cp[u] += wp;
+          }
+        } else if (take) {
           fx[u] += vx;
           fy[u] += vy;
           fz[u] += vz;
           ph[u] += vp;
         }
+      }
+    }
+    if (MIXED) {
+      // the compensated sums, rounded once to FP64
+#pragma unroll
+      for (int u = 0; u < kTG; ++u) {
+        fx[u] += (double)cx[u];
+        fy[u] += (double)cy[u];
+        fz[u] += (double)cz[u];
+        ph[u] += (double)cp[u];
       }
     }
     // lane s < 4 of group g finishes target g*4 + s with the sums of the

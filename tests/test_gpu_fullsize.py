@@ -3,9 +3,15 @@
 * Plummer 2^20 (seed 2), FP64, theta = 0.5: tree and both interaction lists
   bit for bit against the oracle, accelerations at 256 sampled particles
   (evaluated one by one by the oracle) to 1e-12 of gabs, balances at round-off.
-* Two Plummer spheres 2^22 (seed 3), theta = 0.5, FP64 and mixed: sampled
-  accelerations against the oracle (FP64 1e-12 of gabs; mixed 1e-4 at worst
-  and 2e-6 at the 99th percentile, the bounds of the mixed-precision tests).
+* Plummer 2^20 with the multipole error estimate (the benchmark's criterion)
+  at a tolerance the oracle can walk: lists bit for bit, sampled accelerations
+  in FP64 and mixed precision.
+* Two Plummer spheres 2^22 (seed 3), theta = 0.35, 0.5 and 0.7, FP64 and
+  mixed: sampled accelerations against the oracle (FP64 1e-12 of gabs; mixed
+  1e-4 at worst and 2e-6 at the 99th percentile, the bounds of the
+  mixed-precision tests).
+* Plummer 2^24 (seed 4), geometric theta = 0.5: mixed against FP64 (the same
+  pairs), both against direct summation, residuals and wall times.
 * Plummer 2^24 (seed 4) in the benchmark's configuration (pilot geometric
   solve at theta 1.0 + multipole error-estimate solve, eps 8e-8, theta_max
   0.5, mixed, TC): the oracle cannot walk 3e10 pairs, so properties that hold
@@ -64,20 +70,23 @@ def test_plummer_2p20_fp64_against_oracle():
     assert fb <= 1e-13 and tb <= 1e-13, (fb, tb)
 
 
-def test_two_plummer_2p22_fp64_and_mixed_against_oracle():
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("theta", [0.35, 0.5, 0.7])
+def test_two_plummer_2p22_fp64_and_mixed_against_oracle(theta):
     n = 1 << 22
     x, y, z, m = W.two_plummer(n, seed=3)
-    say("full size: two plummer 2^22")
+    say(f"full size: two plummer 2^22, theta {theta}")
     X, Y, Z, M = to_dev(x, y, z, m)
     t = orc.Tree(x, y, z, m)
     t.compute_moments()
-    t.walk(0.5)
+    t.walk(theta)
     idx = W.sample_targets(n, 256, seed=99)
     oa, _ = t.evaluate_sample(idx)
+    del t
     _, _, gabs = orc.direct(x, y, z, m, idx)
     for prec in (amfmm.FP64, amfmm.MIXED):
         s = amfmm.Solver(precision=prec)
-        o = s.solve_gravity(X, Y, Z, M, 0.5, pot=False)
+        o = s.solve_gravity(X, Y, Z, M, theta, pot=False)
         err = np.linalg.norm(host(o)[:, idx] - oa, axis=0) / gabs
         fb, tb = s.balance(X, Y, Z, M, o[0], o[1], o[2])
         say(f"  precision {prec}: sampled max err/gabs {err.max():.2e}, p99 {np.percentile(err, 99):.2e}; "
@@ -88,6 +97,96 @@ def test_two_plummer_2p22_fp64_and_mixed_against_oracle():
         else:
             assert err.max() <= 1e-4 and np.percentile(err, 99) <= 2e-6
             assert fb <= 1e-7 and tb <= 1e-7
+
+
+@pytest.mark.timeout(600)
+def test_plummer_2p20_multipole_against_oracle():
+    """The benchmark's criterion (the multipole error estimate) at 2^20 (seed
+    2) with a field input both sides share (the analytic field magnitude of
+    the Plummer sphere): lists bit for bit against the oracle's walk, and
+    accelerations and potentials at 256 sampled particles (evaluated one by one
+    by the oracle) in FP64 (1e-12 of gabs) and mixed precision (the
+    mixed-precision bounds)."""
+    n = 1 << 20
+    eps, tmax = 1e-5, 0.5
+    x, y, z, m = W.plummer(n, seed=2)
+    r = np.sqrt(x * x + y * y + z * z)
+    gmag = r / (r * r + 1.0) ** 1.5
+    say(f"full size: plummer 2^20, multipole estimate eps {eps} theta_max {tmax}")
+    X, Y, Z, M = to_dev(x, y, z, m)
+    G, = to_dev(gmag)
+    t = orc.Tree(x, y, z, m)
+    t.compute_moments()
+    t.walk_multipole(eps, tmax, gmag)
+    ofar, onear = t.lists()
+    idx = W.sample_targets(n, 256, seed=99)
+    oa, op = t.evaluate_sample(idx)
+    del t
+    _, _, gabs = orc.direct(x, y, z, m, idx)
+    for prec in (amfmm.FP64, amfmm.MIXED):
+        s = amfmm.Solver(precision=prec, criterion=amfmm.MULTIPOLE, error_tol=eps, theta_max=tmax)
+        s.set_field_estimate(G)
+        s.build_tree(X, Y, Z, M)
+        s.compute_moments()
+        s.walk(0.5)
+        if prec == amfmm.FP64:
+            far, near = s.get_lists()
+            say(f"  lists: {len(far)} far, {len(near)} near")
+            assert np.array_equal(far, ofar) and np.array_equal(near, onear)
+            del far, near
+        ax, ay, az, p = s.evaluate()
+        err = np.linalg.norm(host((ax, ay, az))[:, idx] - oa, axis=0) / gabs
+        perr = np.abs(p.cpu().numpy()[idx] - op) / np.abs(op)
+        fb, tb = s.balance(X, Y, Z, M, ax, ay, az)
+        say(f"  precision {prec}: sampled max err/gabs {err.max():.2e}, p99 {np.percentile(err, 99):.2e}; "
+            f"potential max {perr.max():.2e}; balances {fb:.1e} {tb:.1e}")
+        if prec == amfmm.FP64:
+            assert err.max() <= 1e-12 and perr.max() <= 1e-12
+            assert fb <= 1e-13 and tb <= 1e-13
+        else:
+            assert err.max() <= 1e-4 and np.percentile(err, 99) <= 2e-6
+            assert np.percentile(perr, 99) <= 1e-6
+            assert fb <= 1e-7 and tb <= 1e-7
+        s.close()
+
+
+def test_plummer_2p24_mixed_geometric():
+    """The mixed-precision configuration at scale (Plummer 2^24, seed 4,
+    geometric theta 0.5, TC): FP32 bulk against the FP64 solve of the same
+    pairs at 65536 sampled targets, both against direct summation, the
+    torque and force residuals, and the wall time of both solves."""
+    n = 1 << 24
+    x, y, z, m = W.plummer(n, seed=4)
+    say("full size: plummer 2^24, geometric theta 0.5, mixed against FP64")
+    X, Y, Z, M = to_dev(x, y, z, m)
+    del x, y, z, m
+    tg = torch.from_numpy(W.sample_targets(n, 1 << 16, seed=99)).cuda()
+    res = {}
+    for prec in (amfmm.FP64, amfmm.MIXED):
+        s = amfmm.Solver(precision=prec)
+        s.solve_gravity(X, Y, Z, M, 0.5, pot=False)  # warm-up (allocation)
+        o = s.solve_gravity(X, Y, Z, M, 0.5, pot=False)
+        ms = s.get_phase_times()["total"]
+        if prec == amfmm.FP64:
+            tx, ty, tz, _, _ = s.direct(X, Y, Z, M, tg, pot=False, gabs=False)
+            T = torch.stack([tx, ty, tz])
+        A = torch.stack([o[0][tg], o[1][tg], o[2][tg]])
+        e = (torch.linalg.norm(A - T, dim=0) / torch.linalg.norm(T, dim=0)).cpu().numpy()
+        fb, tb = s.balance(X, Y, Z, M, o[0], o[1], o[2])
+        res[prec] = (A.cpu().numpy(), ms)
+        say(f"  precision {prec}: {ms:.1f} ms, p99 vs direct {np.percentile(e, 99):.3e}, "
+            f"balances {fb:.1e} {tb:.1e}")
+        if prec == amfmm.FP64:
+            assert fb <= 1e-13 and tb <= 1e-13
+        else:
+            assert fb <= 1e-7 and tb <= 1e-7
+        s.close()
+        del o
+    a64, am = res[amfmm.FP64][0], res[amfmm.MIXED][0]
+    d = np.linalg.norm(am - a64, axis=0) / np.linalg.norm(a64, axis=0)
+    say(f"  mixed against FP64 (same pairs): p99 {np.percentile(d, 99):.2e}, max {d.max():.2e}; "
+        f"time ratio {res[amfmm.FP64][1] / res[amfmm.MIXED][1]:.2f}")
+    assert np.percentile(d, 99) <= 2e-6 and d.max() <= 1e-4
 
 
 def test_plummer_2p24_benchmark_configuration():
