@@ -142,6 +142,28 @@ int amfmm_solve_gravity(amfmm_ctx* ctx, int64_t n, const double* x, const double
                         const double* z, const double* m, double theta, double* ax, double* ay,
                         double* az, double* pot);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as amfmm_solve_gravity (same arguments, outputs to rounding: a cell's
+ * pairs may be summed in another order), with every scratch buffer carved from
+ * one static device array of 256 MiB that the library holds on each device it
+ * runs on until the process ends.  It calls no hipMalloc, hipFree or other
+ * allocating routine and records no timing events.  n may be at most 2^18
+ * (else AMFMM_E_INVALID); a solve whose scratch (particles, cells, interaction
+ * lists, walk staging) would outgrow the array returns AMFMM_E_OOM: near that
+ * size, small opening angles or tight error tolerances can (the geometric
+ * theta = 0.5 solve of 2^18 particles fits).  The context's own
+ * buffers are set aside for the call: afterwards it holds no tree, lists or
+ * phase times (introspection returns AMFMM_E_STATE) and the next
+ * amfmm_solve_gravity proceeds as before.  Every call on a device shares that
+ * device's array and leaves its contents behind: calls that overlap on one
+ * device (other contexts or streams) race and must be serialised by the caller;
+ * calls on one stream are ordered by it.  The context must be used on the
+ * device it was created on. */
+int amfmm_solve_gravity_noalloc(amfmm_ctx* ctx, int64_t n, const double* x, const double* y,
+                                const double* z, const double* m, double theta, double* ax,
+                                double* ay, double* az, double* pot);
+
 /* Direct summation at ntarget particles (device int64 indices; NULL = all n
  * particles in order): the exact sum that the method approximates (Sec. 3,
  * g_PP).  Coincident particles are skipped.  Outputs are device arrays of

@@ -57,6 +57,7 @@ def lib():
         "amfmm_walk": (C.c_int, [P, C.c_double]),
         "amfmm_evaluate": (C.c_int, [P, pd, pd, pd, pd]),
         "amfmm_solve_gravity": (C.c_int, [P, i64, pd, pd, pd, pd, C.c_double, pd, pd, pd, pd]),
+        "amfmm_solve_gravity_noalloc": (C.c_int, [P, i64, pd, pd, pd, pd, C.c_double, pd, pd, pd, pd]),
         "amfmm_direct": (C.c_int, [P, i64, pd, pd, pd, pd, i64, pd, pd, pd, pd, pd, pd]),
         "amfmm_balance": (C.c_int, [P, i64, pd, pd, pd, pd, pd, pd, pd, d]),
         "amfmm_get_counts": (C.c_int, [P, C.POINTER(C.c_int64)]),
@@ -88,7 +89,7 @@ def lib():
 EXPORTED = ["amfmm_default_options", "amfmm_create", "amfmm_destroy", "amfmm_set_stream",
             "amfmm_set_field_estimate",
             "amfmm_build_tree", "amfmm_compute_moments", "amfmm_walk", "amfmm_evaluate",
-            "amfmm_solve_gravity", "amfmm_direct", "amfmm_balance", "amfmm_get_counts",
+            "amfmm_solve_gravity", "amfmm_solve_gravity_noalloc", "amfmm_direct", "amfmm_balance", "amfmm_get_counts",
             "amfmm_get_tree", "amfmm_get_moments", "amfmm_get_lists", "amfmm_get_phase_times",
             "amfmm_set_model", "amfmm_pair_features", "amfmm_pair_labels", "amfmm_mlp_predict",
             "amfmm_mlp_grad", "amfmm_mlp_train", "amfmm_status_string", "amfmm_last_error"]
@@ -271,6 +272,20 @@ class Solver:
                 _dev(p, "pot", n) if p is not None else None)
         self.n = n
         self._check(lib().amfmm_solve_gravity(self._h, n, *args))
+        return ax, ay, az, p
+
+    def solve_gravity_noalloc(self, x, y, z, m, theta, out):
+        """amfmm_solve_gravity_noalloc: the solve without device allocation
+        (scratch in the library's static array); out = (ax, ay, az, pot or
+        None), preallocated by the caller."""
+        n = x.numel()
+        ax, ay, az, p = out
+        self._check_field(n)
+        args = (_dev(x, "x", n), _dev(y, "y", n), _dev(z, "z", n), _dev(m, "m", n), float(theta),
+                _dev(ax, "ax", n), _dev(ay, "ay", n), _dev(az, "az", n),
+                _dev(p, "pot", n) if p is not None else None)
+        self.n = n
+        self._check(lib().amfmm_solve_gravity_noalloc(self._h, n, *args))
         return ax, ay, az, p
 
     def direct(self, x, y, z, m, targets=None, pot=True, gabs=True):

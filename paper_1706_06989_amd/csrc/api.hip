@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <utility>
 
 #include "internal.h"
@@ -14,16 +15,65 @@ struct amfmm_ctx {
 
 namespace amfmm {
 
+static bool in_arena(const Ctx& c, const void* p) {
+  return c.arena && (const char*)p >= c.arena && (const char*)p < c.arena + c.arena_cap;
+}
+
+constexpr size_t kArenaAlign = 256;
+
+// give an arena block back, merged with free neighbours
+static void arena_release(Ctx& c, size_t off, size_t bytes) {
+  auto next = c.arena_free.lower_bound(off);
+  if (next != c.arena_free.end() && off + bytes == next->first) {
+    bytes += next->second;
+    next = c.arena_free.erase(next);
+  }
+  if (next != c.arena_free.begin()) {
+    auto prev = std::prev(next);
+    if (prev->first + prev->second == off) {
+      prev->second += bytes;
+      return;
+    }
+  }
+  c.arena_free.emplace(off, bytes);
+}
+
 static void release(Ctx& c, DevBuf& b) {
   if (b.p) {
-    (void)hipFree(b.p);
-    c.bytes -= b.cap;
+    if (in_arena(c, b.p)) {
+      arena_release(c, (size_t)((char*)b.p - c.arena), b.cap);
+    } else {
+      (void)hipFree(b.p);
+      c.bytes -= b.cap;
+    }
     b.p = nullptr;
     b.cap = 0;
   }
 }
 
+// an arena block of `bytes` (a multiple of kArenaAlign): the first free block
+// that holds it
+static void* arena_alloc(Ctx& c, size_t bytes) {
+  for (auto it = c.arena_free.begin(); it != c.arena_free.end(); ++it) {
+    if (it->second < bytes) continue;
+    const size_t off = it->first, rest = it->second - bytes;
+    c.arena_free.erase(it);
+    if (rest) c.arena_free.emplace(off + bytes, rest);
+    return c.arena + off;
+  }
+  size_t largest = 0, total = 0;
+  for (const auto& f : c.arena_free) {
+    largest = std::max(largest, f.second);
+    total += f.second;
+  }
+  throw Error(AMFMM_E_OOM, "allocation-free solve: its scratch needs more than the " +
+                               std::to_string(c.arena_cap >> 20) + " MiB static array (request of " +
+                               std::to_string(bytes) + " bytes; " + std::to_string(total) + " bytes free, " +
+                               "largest block " + std::to_string(largest) + ")");
+}
+
 static void* alloc(Ctx& c, size_t bytes) {
+  if (c.arena) return arena_alloc(c, bytes);
   if (c.opt.max_bytes > 0 && (int64_t)(c.bytes + bytes) > c.opt.max_bytes)
     throw Error(AMFMM_E_OOM, "device scratch would exceed max_bytes (" + std::to_string(c.bytes + bytes) + " bytes)");
   void* p = nullptr;
@@ -36,11 +86,28 @@ static void* alloc(Ctx& c, size_t bytes) {
   return p;
 }
 
+size_t free_device_bytes(Ctx& c) {
+  if (c.arena) {
+    size_t largest = 0;
+    for (const auto& f : c.arena_free) largest = std::max(largest, f.second);
+    return largest;
+  }
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    (void)hipGetLastError();
+    fr = size_t(16) << 30;
+  }
+  return fr;
+}
+
 void* ensure(Ctx& c, DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 8;
   if (b.cap >= bytes) return b.p;
   release(c, b);
+  // headroom for regrowth, except in the arena (exact blocks: buffers sized
+  // from the free space would otherwise outgrow it)
   size_t want = bytes + bytes / 4;
+  if (c.arena) want = (bytes + kArenaAlign - 1) & ~(kArenaAlign - 1);
   b.p = alloc(c, want);
   b.cap = want;
   return b.p;
@@ -50,6 +117,21 @@ void* ensure_keep(Ctx& c, DevBuf& b, size_t bytes, size_t keep) {
   if (bytes == 0) bytes = 8;
   if (b.cap >= bytes) return b.p;
   size_t want = bytes + bytes / 4;
+  if (c.arena) {
+    want = (want + kArenaAlign - 1) & ~(kArenaAlign - 1);
+    // an arena block followed by a large enough free block grows in place
+    if (b.p && in_arena(c, b.p)) {
+      const size_t end = (size_t)((char*)b.p - c.arena) + b.cap, more = want - b.cap;
+      auto it = c.arena_free.find(end);
+      if (it != c.arena_free.end() && it->second >= more) {
+        const size_t rest = it->second - more;
+        c.arena_free.erase(it);
+        if (rest) c.arena_free.emplace(end + more, rest);
+        b.cap = want;
+        return b.p;
+      }
+    }
+  }
   void* p = alloc(c, want);
   if (b.p && keep) AMFMM_HIP(hipMemcpyAsync(p, b.p, std::min(keep, b.cap), hipMemcpyDeviceToDevice, c.stream));
   if (b.p) {
@@ -74,6 +156,7 @@ static DevBuf* all_bufs(Ctx& c, int i) {
 }
 
 void mark(Ctx& c, int phase) {
+  if (c.arena) return;  // the allocation-free solve creates no events
   if (c.ev_used == c.ev_pool.size()) {
     hipEvent_t e;
     AMFMM_HIP(hipEventCreate(&e));
@@ -83,6 +166,36 @@ void mark(Ctx& c, int phase) {
   AMFMM_HIP(hipEventRecord(c.ev_pool[c.ev_used], c.stream));
   c.ev_phase[c.ev_used] = phase;
   ++c.ev_used;
+}
+
+// Scratch of the allocation-free solve: one array in the library's code
+// object, so every device the library runs on holds its own copy of it until
+// the process ends.  Host code never passes the array's name to a kernel or a
+// copy: it looks up each device's copy once (hipGetSymbolAddress with that
+// device current, in amfmm_create) and uses that address.
+constexpr size_t kNoAllocBytes = size_t(256) << 20;
+constexpr int64_t kNoAllocMaxN = int64_t(1) << 18;
+__device__ __align__(256) char scratch[kNoAllocBytes];
+
+static std::mutex g_scratch_mu;
+static std::vector<char*> g_scratch_ptr;  // per device; nullptr until looked up
+
+// The device address of the scratch array on `device`, which must be the
+// current device: looked up on the first call for that device.
+static char* device_scratch(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize((size_t)device + 1, nullptr);
+  if (!g_scratch_ptr[(size_t)device]) {
+    char* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      throw Error(AMFMM_E_HIP, std::string("hipGetSymbolAddress of the allocation-free scratch failed: ") +
+                                   hipGetErrorString(e));
+    }
+    g_scratch_ptr[(size_t)device] = ptr;
+  }
+  return g_scratch_ptr[(size_t)device];
 }
 
 }  // namespace amfmm
@@ -160,6 +273,13 @@ int amfmm_create(const amfmm_options* opt, void* stream, amfmm_ctx** out) {
     return AMFMM_E_HIP;
   }
   if (hipHostMalloc((void**)&ctx->c.pinned, 8 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
+    delete ctx;
+    return AMFMM_E_HIP;
+  }
+  try {
+    (void)amfmm::device_scratch(ctx->c.device);  // the allocation-free solve's array on this device
+  } catch (const Error&) {
+    (void)hipHostFree(ctx->c.pinned);
     delete ctx;
     return AMFMM_E_HIP;
   }
@@ -360,14 +480,12 @@ static double list_bytes_per_particle(double theta) {
 
 static size_t list_budget(Ctx& c) {
   if (c.opt.list_bytes > 0) return (size_t)c.opt.list_bytes;
-  size_t fr = 0, tot = 0;
-  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
-    (void)hipGetLastError();
-    fr = size_t(16) << 30;
-  }
-  size_t b = std::min<size_t>(fr / 3, size_t(48) << 30);
+  const size_t fr = amfmm::free_device_bytes(c);
+  // a quarter of the largest free arena block: a list that grows is copied,
+  // so its old and new blocks coexist for a moment
+  size_t b = std::min<size_t>(c.arena ? fr / 4 : fr / 3, size_t(48) << 30);
   if (c.opt.max_bytes > 0) b = std::min<size_t>(b, (size_t)c.opt.max_bytes / 2);
-  return std::max<size_t>(b, size_t(64) << 20);
+  return c.arena ? b : std::max<size_t>(b, size_t(64) << 20);
 }
 
 // Walk and evaluation one batch of subtrees at a time, so that the lists of
@@ -496,9 +614,9 @@ int amfmm_evaluate(amfmm_ctx* ctx, double* ax, double* ay, double* az, double* p
   return guarded(ctx, [&](Ctx& c) -> int { return evaluate_impl(c, ax, ay, az, pot); });
 }
 
-int amfmm_solve_gravity(amfmm_ctx* ctx, int64_t n, const double* x, const double* y, const double* z,
-                        const double* m, double theta, double* ax, double* ay, double* az, double* pot) {
-  return guarded(ctx, [&](Ctx& c) -> int {
+static int solve_impl(Ctx& c, int64_t n, const double* x, const double* y, const double* z, const double* m,
+                      double theta, double* ax, double* ay, double* az, double* pot) {
+  {
     if (!(theta > 0.0 && theta <= 1.0)) return fail(c, AMFMM_E_INVALID, "theta must lie in (0, 1]");
     if (!ax || !ay || !az) return fail(c, AMFMM_E_INVALID, "null output pointer");
     int st = build_tree_impl(c, n, x, y, z, m);
@@ -537,6 +655,61 @@ int amfmm_solve_gravity(amfmm_ctx* ctx, int64_t n, const double* x, const double
     c.hint_mode = c.opt.criterion;
     c.hint_tol = c.opt.error_tol;
     return AMFMM_OK;
+  }
+}
+
+int amfmm_solve_gravity(amfmm_ctx* ctx, int64_t n, const double* x, const double* y, const double* z,
+                        const double* m, double theta, double* ax, double* ay, double* az, double* pot) {
+  return guarded(ctx, [&](Ctx& c) -> int { return solve_impl(c, n, x, y, z, m, theta, ax, ay, az, pot); });
+}
+
+// The solve with every device buffer carved from this device's scratch array.
+// The context's own buffers, batch hints and timing are set aside for the
+// call and restored after it (so its tree, lists and phase times are not
+// kept: introspection calls see no tree afterwards); the learned model stays
+// in place (read only).
+int amfmm_solve_gravity_noalloc(amfmm_ctx* ctx, int64_t n, const double* x, const double* y, const double* z,
+                                const double* m, double theta, double* ax, double* ay, double* az, double* pot) {
+  return guarded(ctx, [&](Ctx& c) -> int {
+    if (n > amfmm::kNoAllocMaxN)
+      return fail(c, AMFMM_E_INVALID, "allocation-free solve: n exceeds its maximum of 2^18 particles");
+    if (c.arena) return fail(c, AMFMM_E_STATE, "allocation-free solve already running on this context");
+    struct Saved {
+      Ctx& c;
+      std::vector<amfmm::DevBuf> bufs;
+      int64_t batch_hint, hint_n, batch_fail;
+      double hint_theta, hint_tol;
+      int hint_mode;
+      explicit Saved(Ctx& cc)
+          : c(cc), batch_hint(cc.batch_hint), hint_n(cc.hint_n), batch_fail(cc.batch_fail),
+            hint_theta(cc.hint_theta), hint_tol(cc.hint_tol), hint_mode(cc.hint_mode) {
+        for (int i = 0; amfmm::DevBuf* b = amfmm::all_bufs(c, i); ++i) {
+          bufs.push_back(*b);
+          if (b != &c.model) *b = amfmm::DevBuf{};
+        }
+        c.hint_n = 0;
+      }
+      ~Saved() {
+        for (int i = 0; amfmm::DevBuf* b = amfmm::all_bufs(c, i); ++i) *b = bufs[(size_t)i];
+        c.arena = nullptr;
+        c.arena_cap = 0;
+        c.arena_free.clear();
+        c.have_tree = c.have_moments = c.have_lists = false;
+        c.near_pairs_valid = false;
+        c.batch_hint = batch_hint;
+        c.hint_n = hint_n;
+        c.batch_fail = batch_fail;
+        c.hint_theta = hint_theta;
+        c.hint_tol = hint_tol;
+        c.hint_mode = hint_mode;
+      }
+    } saved(c);
+    c.arena = amfmm::device_scratch(c.device);
+    c.arena_cap = amfmm::kNoAllocBytes;
+    c.arena_free.clear();
+    c.arena_free.emplace(0, amfmm::kNoAllocBytes);
+    c.ev_used = 0;
+    return solve_impl(c, n, x, y, z, m, theta, ax, ay, az, pot);
   });
 }
 

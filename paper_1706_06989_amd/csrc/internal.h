@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -118,7 +119,18 @@ struct Ctx {
   std::vector<hipEvent_t> ev_pool;
   std::vector<int> ev_phase;
   size_t ev_used = 0;
+  // allocation-free solve: while arena is set, every device buffer is carved
+  // from [arena, arena + arena_cap) (a static device array) instead of being
+  // allocated (first fit over the free blocks, released blocks merged with
+  // their neighbours), and no timing events are recorded
+  char* arena = nullptr;
+  size_t arena_cap = 0;
+  std::map<size_t, size_t> arena_free;  // offset -> bytes of each free block
 };
+
+// device bytes a solve may still take in one buffer: the free device memory,
+// or the largest free block of the arena in an allocation-free solve
+size_t free_device_bytes(Ctx& c);
 
 // allocate (grow-only) a device buffer of at least `bytes`; contents are lost on growth
 void* ensure(Ctx& c, DevBuf& b, size_t bytes);

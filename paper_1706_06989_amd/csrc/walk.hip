@@ -995,7 +995,8 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
   TreeView t{(const WalkRec*)c.walkrec.p, c.theta, c.walk_abs_tol, c.walk_mode, c.opt.error_tol,
              c.opt.theta_max, c.opt.theta_max * c.opt.theta_max, (const float*)c.model.p, c.opt.learned_min_work,
              c.walk_mode != 0 ? (const double*)c.gmin.p + 3 * (size_t)c.ncells : nullptr};
-  static const bool debug = getenv("AMFMM_DEBUG_WALK") != nullptr;
+  static const bool debug_env = getenv("AMFMM_DEBUG_WALK") != nullptr;
+  const bool debug = debug_env && !c.arena;  // no events in an allocation-free solve
   const int ext = c.walk_mode == 2 ? kExtLearned : (c.walk_mode == 3 ? kExtMultipole : kExtBase);
   // per-level ratios of terminal pairs to entries, kept while the rule stays the same
   const double key[4] = {(double)c.walk_mode, c.theta, c.opt.error_tol, c.opt.theta_max};
@@ -1004,12 +1005,12 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
     c.walk_ratio.assign(3 * lo.size(), -1.0);
   }
   // staging room: a third of the free device memory, at most 64 GiB
-  size_t fr = 0, totm = 0;
-  if (hipMemGetInfo(&fr, &totm) != hipSuccess) {
-    (void)hipGetLastError();
-    fr = size_t(16) << 30;
-  }
-  const size_t stage_limit = std::min<size_t>(fr / 3 + c.stage.cap, size_t(64) << 30);
+  const size_t fr = free_device_bytes(c);
+  // (the staging buffer of an earlier walk is given back when it grows; in an
+  // arena its block need not join the largest free one)
+  const size_t stage_limit = std::min<size_t>(fr / 3 + (c.arena ? 0 : c.stage.cap), size_t(64) << 30);
+  // global work queues: at most kGlobalQueueBytes, an eighth of an arena
+  const int64_t queue_limit = c.arena ? (int64_t)(fr / 8) : kGlobalQueueBytes;
   double prev[3];
   bool have_prev = false;
   int64_t cand = 0;  // candidate pairs, counted once the levels are done (a batch over budget is walked again)
@@ -1053,8 +1054,8 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
     int32_t qcap = kQ;
     {
       int64_t g = kGlobalQueueMax;
-      while (g > 4 * kQ && (int64_t)sizeof(int32_t) * g * kn > kGlobalQueueBytes) g >>= 1;
-      if ((int64_t)sizeof(int32_t) * g * kn <= kGlobalQueueBytes) {
+      while (g > 4 * kQ && (int64_t)sizeof(int32_t) * g * kn > queue_limit) g >>= 1;
+      if ((int64_t)sizeof(int32_t) * g * kn <= queue_limit) {
         qcap = (int32_t)g;
         gq = (int32_t*)ensure(c, c.gqueue, sizeof(int32_t) * (size_t)kn * qcap);
       }
