@@ -52,8 +52,20 @@ def far_flops(precision, variant):
     coeff = 3 + (147 if precision == "mixed" else 156)
     corr = {"UC": 0, "TC": 128 if precision == "mixed" else 157, "TCO": 121}[variant]
     return coeff + corr
-WALK_BYTES = 64  # per candidate pair of the walk: one cell record read to decide it
+
+
+# per unordered far-field pair in the paper's symmetric form (eqs. 3 and 4 share
+# one evaluation of D): R (3) + the D tensors (68 with the FP32 rsqrt, 77 with
+# the refined FP64 one) + the coefficients of both cells (2 x 79) + the
+# correction once (as above)
+def far_flops_symmetric(precision, variant):
+    corr = {"UC": 0, "TC": 128 if precision == "mixed" else 157, "TCO": 121}[variant]
+    return 3 + (68 if precision == "mixed" else 77) + 2 * 79 + corr
+
+
+WALK_BYTES = 64  # per decision of the walk: one cell record read to decide it
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_plummer16m.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_plummer16m.json")
 # sources each kernel's code comes from (a traffic figure holds while they are unchanged)
 KERNEL_SOURCES = {
     "walk": ("walk.hip", "device_math.h", "learned.h", "internal.h"),
@@ -111,6 +123,24 @@ def traffic(kernel, config, workload):
     if not str(t.get("workload", "")).startswith(workload + " "):
         return None
     return k.get("bytes_per_launch")
+
+
+def counters(kernel, config, workload):
+    """Instruction and L2 counters per launch of a kernel from the committed
+    summary, or None when absent, taken on other sources or another
+    configuration."""
+    try:
+        t = json.load(open(COUNTERS_FILE))
+    except (OSError, ValueError):
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    if not k or k.get("source_hash") != source_hash(kernel) or t.get("config") != config:
+        return None
+    if not str(t.get("workload", "")).startswith(workload + " "):
+        return None
+    return {"valu_issue_frac": round(k["valu_issue_frac"], 3), "l2_hit": round(k["l2_hit"], 3),
+            "fp64_tflops": round(k["fp64_tflops"], 3), "fp32_tflops": round(k["fp32_tflops"], 3),
+            "avg_ms": round(k["avg_ms"], 3)}
 
 
 def cpu_baseline(workload, n, theta, criterion, eps, theta_max):
@@ -277,17 +307,24 @@ def main():
     # launch duration.
     cfg_key = {"n": a.n, "criterion": a.criterion, "eps": a.eps if field else None,
                "theta": a.theta, "precision": a.precision, "variant": a.variant}
+    # The method decides each unordered cell pair once (the dual walk); the
+    # kernel decides it from both cells (directed candidates), and takes each
+    # cell's self pair once: unordered decisions = (candidates - cells) / 2 + cells.
+    decisions = (counts["walk_candidates"] - counts["cells"]) // 2 + counts["cells"]
+    fsym = far_flops_symmetric(a.precision, a.variant)
     kern = {
-        "walk": {"kernel": "k_walk_stage (the walk's one pass: a decision per candidate pair, terminal pairs "
+        "walk": {"kernel": "k_walk_stage (the walk's one pass: the decisions on the cell pairs, terminal pairs "
                            "staged)", "bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM_GBS,
                  "ms": phases["walk-pass"], "launches": counts["walk_pass_launches"],
-                 "work": WALK_BYTES * counts["walk_candidates"] / 1e9,
-                 "algorithmic": f"{WALK_BYTES} B (one cell record) x {counts['walk_candidates']} candidate pairs"},
+                 "work": WALK_BYTES * decisions / 1e9,
+                 "algorithmic": f"{WALK_BYTES} B (one cell record) x {decisions} unordered pair decisions "
+                                f"({counts['walk_candidates']} directed candidates)"},
         "far": {"kernel": ("k_far_rec" if a.precision == "mixed" and a.variant != "TCO" else "k_far")
-                          + " (far field: eqs. 2-4 + correction per directed cell pair)", "bound": "alu",
+                          + " (far field: eqs. 2-4 + correction, evaluated per directed cell pair)", "bound": "alu",
                 "unit": "TFLOP/s", "peak": PEAK_FP64_TFLOPS, "ms": phases["far"], "launches": counts["far_launches"],
-                "work": far_flops(a.precision, a.variant) * counts["far_evaluations"] / 1e12,
-                "algorithmic": f"{far_flops(a.precision, a.variant)} flop x {counts['far_evaluations']} directed pairs"},
+                "work": fsym * (counts["far_evaluations"] // 2) / 1e12,
+                "algorithmic": f"{fsym} flop (symmetric form: D and the correction once, both cells' coefficients) "
+                               f"x {counts['far_evaluations'] // 2} unordered pairs"},
         "near": {"kernel": "k_near (near field + evaluation at the particles)", "bound": "alu", "unit": "TFLOP/s",
                  "peak": PEAK_FP64_TFLOPS, "ms": phases["near+eval"], "launches": counts["near_launches"],
                  "work": NEAR_FLOPS * counts["near_interactions"] / 1e12,
@@ -299,10 +336,18 @@ def main():
         achieved = k["work"] / (k["ms"] * 1e-3)
         tb = traffic(name, cfg_key, workload)
         launches = max(1, k["launches"])
-        return {"kernel": k["kernel"], "bound": k["bound"], "achieved": round(achieved, 3), "peak": k["peak"],
-                "unit": k["unit"], "frac": round(achieved / k["peak"], 4), "traffic": tb,
-                "algorithmic": k["algorithmic"] + f" per step over {k['launches']} launches",
-                "avg_launch_ms": round(k["ms"] / launches, 3), "step_ms": round(k["ms"], 3)}
+        r = {"kernel": k["kernel"], "bound": k["bound"], "achieved": round(achieved, 3), "peak": k["peak"],
+             "unit": k["unit"], "frac": round(achieved / k["peak"], 4), "traffic": tb,
+             "algorithmic": k["algorithmic"] + f" per step over {k['launches']} launches",
+             "avg_launch_ms": round(k["ms"] / launches, 3), "step_ms": round(k["ms"], 3)}
+        cn = counters(name, cfg_key, workload)
+        if cn is not None:
+            # measured beside the model: HBM bytes per launch over its duration,
+            # VALU issue (wave instructions x 4 cycles over the SIMD-cycles), L2 hits
+            if tb is not None:
+                cn["hbm_frac"] = round(tb / (k["ms"] / launches * 1e-3) / (PEAK_HBM_GBS * 1e9), 4)
+        r["counters"] = cn
+        return r
 
     dominant = max(kern, key=lambda n: kern[n]["ms"])
     roofline = roof(dominant)
@@ -356,7 +401,11 @@ def main():
             torch.cuda.synchronize()
             pms = (time.perf_counter() - t1) * 1e3
             pe = p_err(o)
-            rows.append({"theta": th, "ms": round(pms, 3), "p99_rel_force_error": float(np.percentile(pe, 99))})
+            # the FP64 near field of this solve against FP64 peak (20 flop per directed interaction)
+            pph, pc = ps.get_phase_times(), ps.get_counts()
+            nfrac = NEAR_FLOPS * pc["near_interactions"] / (pph["near+eval"] * 1e-3) / (PEAK_FP64_TFLOPS * 1e12)
+            rows.append({"theta": th, "ms": round(pms, 3), "p99_rel_force_error": float(np.percentile(pe, 99)),
+                         "near_ms": round(pph["near+eval"], 3), "near_fp64_frac": round(nfrac, 4)})
             print(f"# plain fp64 theta={th}: {pms:.1f} ms", file=sys.stderr, flush=True)
             if th == a.theta and mixed_geo is None:
                 mixed_geo = mixed_against_fp64(o, pms, th)
