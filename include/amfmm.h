@@ -91,12 +91,20 @@ typedef struct {
                                this (default 4096); smaller pairs, where a network
                                evaluation costs more than the work it can save,
                                take the analytic estimate q^3 <= u */
+  double softening;   /* Plummer softening length eps >= 0 of the Green's function
+                         g = -1/sqrt(R^2 + eps^2) (Sec. 4: the correction holds for
+                         any g of the distance alone): the far-field derivatives, the
+                         correction, the near field and amfmm_direct use it; 0 (the
+                         default) is the plain -1/R.  Pairs at r = 0 are skipped
+                         either way.  The walk's criteria and the learned features and
+                         labels do not depend on it. */
 } amfmm_options;
 
 typedef struct amfmm_ctx amfmm_ctx;
 
 /* Fills *opt with n_crit = 25, TC, FP64, geometric, G = 1, error_tol = 1e-4,
- * theta_max = 1, max_bytes = 0, list_bytes = 0, learned_min_work = 4096. */
+ * theta_max = 1, max_bytes = 0, list_bytes = 0, learned_min_work = 4096,
+ * softening = 0. */
 int amfmm_default_options(amfmm_options* opt);
 
 /* Creates a context bound to hip_stream (a hipStream_t; NULL = null stream)
@@ -141,6 +149,21 @@ int amfmm_evaluate(amfmm_ctx* ctx, double* ax, double* ay, double* az, double* p
 int amfmm_solve_gravity(amfmm_ctx* ctx, int64_t n, const double* x, const double* y,
                         const double* z, const double* m, double theta, double* ax, double* ay,
                         double* az, double* pot);
+
+/* Time integration with the solver's forces (Sec. 1 and Sec. 4: the torque
+ * correction conserves angular momentum when every particle takes the same
+ * time step): `steps` kick-drift-kick leapfrog steps of dt,
+ *   v += (dt/2) a;  x += dt v;  a = solve(x);  v += (dt/2) a,
+ * in place on the device arrays x, y, z, vx, vy, vz (n doubles each, caller
+ * order) with the masses m, the opening angle theta and the context's
+ * options (variant, precision, criterion, field estimate).  On entry ax, ay,
+ * az must hold the accelerations at x, y, z (as amfmm_solve_gravity returns
+ * them); on return they hold those at the new positions.  The positions are
+ * validated at every solve (a non-finite position stops the integration with
+ * AMFMM_E_NONFINITE after the steps already taken).  steps >= 0, dt finite. */
+int amfmm_leapfrog(amfmm_ctx* ctx, int64_t n, double* x, double* y, double* z, double* vx, double* vy,
+                   double* vz, const double* m, double theta, double dt, int32_t steps, double* ax,
+                   double* ay, double* az);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same

@@ -83,6 +83,7 @@ struct orc_tree {
   std::vector<int> k2, k3;     // mode 3: quantised traceless quadrupole and octupole norms
   std::vector<std::pair<int32_t, int32_t>> m2l, p2p;
   int64_t coincident = 0;
+  double eps2 = 0.0;  // Plummer softening length squared (0: the plain 1/R)
 };
 
 namespace {
@@ -169,6 +170,44 @@ void greens(const double R[3], Greens& g, bool want4) {
         }
 }
 
+// The same derivatives for the softened Green's function g = -1/sqrt(R^2 +
+// eps^2) (Sec. 4: the correction holds for any g that depends on R only).
+// For any such g, with f_k = (1/R d/dR)^k g (here f_k = (-1)^(k+1)
+// (2k-1)!! s^-(2k+1)/2, s = R^2 + eps^2), the derivatives are sums over the
+// ways to pair up indices: D_i = f1 R_i, D_ij = f1 d_ij + f2 R_i R_j,
+// D_ijk = f2 (d_ij R_k + d_jk R_i + d_ki R_j) + f3 R_i R_j R_k, and
+// D_ijkl = f2 (three dd) + f3 (six dRR) + f4 RRRR; at eps = 0 they are the
+// printed tensors.  D'_ijkl keeps the d_i. terms, as in eq. 8.
+void greens_softened(const double R[3], double eps2, Greens& g, bool want4) {
+  double s = ((R[0] * R[0] + R[1] * R[1]) + R[2] * R[2]) + eps2;
+  double rs = std::sqrt(s);
+  double f0 = -1.0 / rs;
+  double f1 = 1.0 / (s * rs);
+  double f2 = -3.0 * f1 / s;
+  double f3 = -5.0 * f2 / s;
+  double f4 = -7.0 * f3 / s;
+  g.D0 = f0;
+  for (int i = 0; i < 3; ++i) g.D1[i] = f1 * R[i];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) g.D2[i][j] = f1 * kdelta(i, j) + f2 * R[i] * R[j];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k)
+        g.D3[i][j][k] = f2 * (kdelta(i, j) * R[k] + kdelta(j, k) * R[i] + kdelta(k, i) * R[j]) +
+                        f3 * R[i] * R[j] * R[k];
+  if (!want4) return;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l) {
+          double dd = kdelta(i, j) * kdelta(k, l) + kdelta(i, k) * kdelta(j, l) + kdelta(i, l) * kdelta(j, k);
+          double di = kdelta(i, j) * R[k] * R[l] + kdelta(i, k) * R[j] * R[l] + kdelta(i, l) * R[j] * R[k];
+          double dr = kdelta(j, k) * R[i] * R[l] + kdelta(j, l) * R[i] * R[k] + kdelta(k, l) * R[i] * R[j];
+          g.D4[i][j][k][l] = f2 * dd + f3 * (di + dr) + f4 * R[i] * R[j] * R[k] * R[l];
+          g.D4p[i][j][k][l] = f2 * dd + f3 * di;
+        }
+}
+
 // --------------------------------------------------------------- moments ---
 // M2_ij = sum mu x_i x_j and M3_ijk = sum mu x_i x_j x_k with x = X - Z, summed
 // over the particles [b, b+cnt) of the sorted arrays (eq. quad and the
@@ -203,9 +242,12 @@ struct PairTerms {
   double Fc[3];  // correction force of the variant (zero for UC)
 };
 
-void pair_terms(const Moments& A, const Moments& B, int variant, PairTerms& pt) {
+void pair_terms(const Moments& A, const Moments& B, int variant, PairTerms& pt, double eps2 = 0.0) {
   double R[3] = {A.Z[0] - B.Z[0], A.Z[1] - B.Z[1], A.Z[2] - B.Z[2]};
-  greens(R, pt.g, variant != ORC_UC);
+  if (eps2 > 0.0)
+    greens_softened(R, eps2, pt.g, variant != ORC_UC);
+  else
+    greens(R, pt.g, variant != ORC_UC);
   for (int i = 0; i < 3; ++i) pt.Fc[i] = 0.0;
   if (variant == ORC_UC) return;
   // eq. 7 / eq. 8: F_c,i = -(1/6) (M_A,jkl M_B - M_A M_B,jkl) D_ijkl
@@ -1029,7 +1071,7 @@ int32_t orc_evaluate(orc_tree* t, int32_t variant, double G, double* ax, double*
     const Moments& A = t->mom[pr.first];
     const Moments& B = t->mom[pr.second];
     PairTerms pt;
-    pair_terms(A, B, variant, pt);
+    pair_terms(A, B, variant, pt, t->eps2);
     for (int64_t p = CA.begin; p < CA.begin + CA.count; ++p) {
       double xv[3] = {t->x[p] - A.Z[0], t->y[p] - A.Z[1], t->z[p] - A.Z[2]};
       double g[3];
@@ -1066,8 +1108,9 @@ int32_t orc_evaluate(orc_tree* t, int32_t variant, double G, double* ax, double*
           ++t->coincident;
           continue;
         }
-        double r = std::sqrt(r2);
-        double r3 = r2 * r;
+        double s2 = r2 + t->eps2;  // softened distance squared
+        double r = std::sqrt(s2);
+        double r3 = s2 * r;
         // acceleration on i towards j and on j towards i
         gx[i] += t->m[j] * dx / r3;
         gy[i] += t->m[j] * dy / r3;
@@ -1129,7 +1172,7 @@ int32_t orc_evaluate_sample(orc_tree* t, int32_t variant, double G, int64_t ns, 
         // field cell of eq. 3 and the higher that of eq. 4
         int32_t a = std::min(cell, other), b = std::max(cell, other);
         PairTerms pt;
-        pair_terms(t->mom[a], t->mom[b], variant, pt);
+        pair_terms(t->mom[a], t->mom[b], variant, pt, t->eps2);
         const Moments& own = t->mom[cell];
         double xv[3] = {t->x[p] - own.Z[0], t->y[p] - own.Z[1], t->z[p] - own.Z[2]};
         double gg[3];
@@ -1153,8 +1196,9 @@ int32_t orc_evaluate_sample(orc_tree* t, int32_t variant, double G, int64_t ns, 
         double dz = t->z[j] - t->z[p];
         double r2 = (dx * dx + dy * dy) + dz * dz;
         if (r2 == 0.0) continue;
-        double r = std::sqrt(r2);
-        double r3 = r2 * r;
+        double s2 = r2 + t->eps2;
+        double r = std::sqrt(s2);
+        double r3 = s2 * r;
         g[0] += t->m[j] * dx / r3;
         g[1] += t->m[j] * dy / r3;
         g[2] += t->m[j] * dz / r3;
@@ -1198,7 +1242,7 @@ int32_t orc_evaluate_targets(orc_tree* t, int32_t variant, double G, double* ax,
       for (int32_t other : far[ci]) {
         int32_t a = std::min((int32_t)ci, other), b = std::max((int32_t)ci, other);
         PairTerms pt;
-        pair_terms(t->mom[a], t->mom[b], variant, pt);
+        pair_terms(t->mom[a], t->mom[b], variant, pt, t->eps2);
         for (int64_t p = C.begin; p < C.begin + C.count; ++p) {
           double xv[3] = {t->x[p] - own.Z[0], t->y[p] - own.Z[1], t->z[p] - own.Z[2]};
           double g[3];
@@ -1237,8 +1281,9 @@ int32_t orc_evaluate_targets(orc_tree* t, int32_t variant, double G, double* ax,
             if (j != i) ++skipped;
             continue;
           }
-          double r = std::sqrt(r2);
-          double r3 = r2 * r;
+          double s2 = r2 + t->eps2;
+          double r = std::sqrt(s2);
+          double r3 = s2 * r;
           gx[i] += t->m[j] * dx / r3;
           gy[i] += t->m[j] * dy / r3;
           gz[i] += t->m[j] * dz / r3;
@@ -1285,7 +1330,14 @@ int32_t orc_solve(int64_t n, const double* x, const double* y, const double* z, 
 int32_t orc_direct(int64_t n, const double* x, const double* y, const double* z, const double* m,
                    int64_t ntarget, const int64_t* targets, double G, double* ax, double* ay,
                    double* az, double* pot, double* gabs) {
-  if (n < 1 || ntarget < 0) return ORC_E_INVALID;
+  return orc_direct_softened(n, x, y, z, m, ntarget, targets, G, 0.0, ax, ay, az, pot, gabs);
+}
+
+int32_t orc_direct_softened(int64_t n, const double* x, const double* y, const double* z, const double* m,
+                            int64_t ntarget, const int64_t* targets, double G, double eps, double* ax,
+                            double* ay, double* az, double* pot, double* gabs) {
+  if (n < 1 || ntarget < 0 || !(eps >= 0.0)) return ORC_E_INVALID;
+  double eps2 = eps * eps;
   for (int64_t q = 0; q < ntarget; ++q) {
     int64_t i = targets ? targets[q] : q;
     if (i < 0 || i >= n) return ORC_E_INVALID;
@@ -1296,13 +1348,14 @@ int32_t orc_direct(int64_t n, const double* x, const double* y, const double* z,
       double dz = z[j] - z[i];
       double r2 = (dx * dx + dy * dy) + dz * dz;
       if (r2 == 0.0) continue;
-      double r = std::sqrt(r2);
-      double r3 = r2 * r;
+      double s2 = r2 + eps2;
+      double r = std::sqrt(s2);
+      double r3 = s2 * r;
       sx += m[j] * dx / r3;
       sy += m[j] * dy / r3;
       sz += m[j] * dz / r3;
       sp -= m[j] / r;
-      sa += m[j] / r2;
+      sa += m[j] / s2;
     }
     ax[q] = G * sx;
     ay[q] = G * sy;
@@ -1311,6 +1364,24 @@ int32_t orc_direct(int64_t n, const double* x, const double* y, const double* z,
     if (gabs) gabs[q] = G * sa;
   }
   return ORC_OK;
+}
+
+int32_t orc_set_softening(orc_tree* t, double eps) {
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return ORC_E_INVALID;
+  t->eps2 = eps * eps;
+  return ORC_OK;
+}
+
+void orc_greens_softened(const double* R3, double eps, double* D0, double* D1, double* D2, double* D3,
+                         double* D4, double* D4p) {
+  Greens g;
+  greens_softened(R3, eps * eps, g, true);
+  *D0 = g.D0;
+  std::memcpy(D1, g.D1, sizeof(g.D1));
+  std::memcpy(D2, g.D2, sizeof(g.D2));
+  std::memcpy(D3, g.D3, sizeof(g.D3));
+  std::memcpy(D4, g.D4, sizeof(g.D4));
+  std::memcpy(D4p, g.D4p, sizeof(g.D4p));
 }
 
 void orc_greens(const double* R3, double* D0, double* D1, double* D2, double* D3, double* D4,

@@ -106,6 +106,11 @@ int32_t orc_evaluate_targets(orc_tree* t, int32_t variant, double G, double* ax,
                              double* az, double* pot);
 /* threads orc_evaluate_targets runs on (1 in a build without OpenMP) */
 int32_t orc_num_threads(void);
+/* Plummer softening of the Green's function, g = -1/sqrt(R^2 + eps^2) (Sec. 4:
+ * the correction carries over to any g of R alone), for the far field (the
+ * derivatives of the softened g), the near field and every later evaluation
+ * of the tree; eps = 0 restores -1/R.  Pairs at r = 0 are still skipped. */
+int32_t orc_set_softening(orc_tree* t, double eps);
 /* number of particle pairs skipped because they coincide (r == 0, i != j) */
 int64_t orc_num_coincident(const orc_tree* t);
 
@@ -121,11 +126,19 @@ int32_t orc_solve(int64_t n, const double* x, const double* y, const double* z, 
 int32_t orc_direct(int64_t n, const double* x, const double* y, const double* z, const double* m,
                    int64_t ntarget, const int64_t* targets, double G, double* ax, double* ay,
                    double* az, double* pot, double* gabs);
+/* The same with the softened Green's function (eps >= 0; gabs = sum_j m_j /
+ * (r^2 + eps^2)). */
+int32_t orc_direct_softened(int64_t n, const double* x, const double* y, const double* z, const double* m,
+                            int64_t ntarget, const int64_t* targets, double G, double eps, double* ax,
+                            double* ay, double* az, double* pot, double* gabs);
 
 /* Building blocks exposed for the pins. */
 /* full tensors: D0[1], D1[3], D2[9], D3[27], D4[81], D4p[81] at R (Sec. 2) */
 void orc_greens(const double* R3, double* D0, double* D1, double* D2, double* D3, double* D4,
                 double* D4p);
+/* the same tensors of the softened g = -1/sqrt(R^2 + eps^2) */
+void orc_greens_softened(const double* R3, double eps, double* D0, double* D1, double* D2, double* D3,
+                         double* D4, double* D4p);
 /* Moments of one cluster (as one cell): out21 as in orc_get_moments. */
 void orc_cluster_moments(int64_t n, const double* x, const double* y, const double* z,
                          const double* m, double* out21);

@@ -70,6 +70,12 @@ def lib():
         L.orc_direct.argtypes = [C.c_int64, d, d, d, d, C.c_int64, i64, C.c_double,
                                  d, d, d, d, d]
         L.orc_greens.argtypes = [d, d, d, d, d, d, d]
+        L.orc_greens_softened.argtypes = [d, C.c_double, d, d, d, d, d, d]
+        L.orc_set_softening.restype = C.c_int32
+        L.orc_set_softening.argtypes = [P, C.c_double]
+        L.orc_direct_softened.restype = C.c_int32
+        L.orc_direct_softened.argtypes = [C.c_int64, d, d, d, d, C.c_int64, i64, C.c_double, C.c_double,
+                                          d, d, d, d, d]
         L.orc_cluster_moments.argtypes = [C.c_int64, d, d, d, d, d]
         L.orc_pair_far.argtypes = [C.c_int64, d, d, d, d, C.c_int64, d, d, d, d, C.c_int32,
                                    d, d, d, d]
@@ -109,7 +115,7 @@ class OracleError(RuntimeError):
 class Tree:
     """Octree of the oracle: build (a1-a4), moments (a5), walk (a6), evaluate."""
 
-    def __init__(self, x, y, z, m, n_crit=25, max_level=MAX_LEVEL):
+    def __init__(self, x, y, z, m, n_crit=25, max_level=MAX_LEVEL, softening=0.0):
         self._keep = [_f64(v) for v in (x, y, z, m)]
         x, y, z, m = self._keep
         st = C.c_int32(0)
@@ -118,6 +124,14 @@ class Tree:
                                        C.byref(st))
         if not self._t:
             raise OracleError(st.value)
+        if softening:
+            self.set_softening(softening)
+
+    def set_softening(self, eps):
+        """Plummer softening length of every later evaluation (0 = plain 1/R)."""
+        st = lib().orc_set_softening(self._t, float(eps))
+        if st:
+            raise OracleError(st)
 
     def __del__(self):
         if getattr(self, "_t", None):
@@ -278,8 +292,14 @@ def use_openmp_build():
         os.environ["AMFMM_ORACLE_LIB"] = ensure_built_omp()
 
 
-def solve(x, y, z, m, theta=0.5, n_crit=25, variant=TC, G=1.0):
+def solve(x, y, z, m, theta=0.5, n_crit=25, variant=TC, G=1.0, softening=0.0):
     """Whole FMM solve; returns (acc[3,n], pot[n]) in caller order."""
+    if softening:
+        t = Tree(x, y, z, m, n_crit=n_crit, softening=softening)
+        t.compute_moments()
+        t.walk(theta)
+        a, p = t.evaluate(variant, G)
+        return a, p
     x, y, z, m = (_f64(v) for v in (x, y, z, m))
     n = len(x)
     ax, ay, az, pot = (np.zeros(n) for _ in range(4))
@@ -290,8 +310,29 @@ def solve(x, y, z, m, theta=0.5, n_crit=25, variant=TC, G=1.0):
     return np.stack([ax, ay, az]), pot
 
 
-def direct(x, y, z, m, targets=None, G=1.0):
-    """Exact direct sum; returns (acc[3,t], pot[t], gabs[t]) for the targets."""
+def leapfrog(x, y, z, vx, vy, vz, m, theta, dt, steps, n_crit=25, variant=TC, G=1.0, acc=None, softening=0.0):
+    """Uniform-step kick-drift-kick leapfrog with the oracle's forces (Sec. 1
+    and Sec. 4 ask for one time step for every particle): per step
+    v += (dt/2) a, x += dt v, a = solve(x), v += (dt/2) a.  acc: the
+    accelerations at the starting positions ([3, n]; solved when None).
+    Returns the new (x, y, z, vx, vy, vz, acc) as float64 copies."""
+    pos = np.stack([_f64(x), _f64(y), _f64(z)]).copy()
+    vel = np.stack([_f64(vx), _f64(vy), _f64(vz)]).copy()
+    m = _f64(m)
+    if acc is None:
+        acc, _ = solve(pos[0], pos[1], pos[2], m, theta, n_crit, variant, G, softening)
+    acc = np.array(acc, dtype=np.float64)
+    for _ in range(steps):
+        vel += (0.5 * dt) * acc
+        pos += dt * vel
+        acc, _ = solve(pos[0], pos[1], pos[2], m, theta, n_crit, variant, G, softening)
+        vel += (0.5 * dt) * acc
+    return pos[0], pos[1], pos[2], vel[0], vel[1], vel[2], acc
+
+
+def direct(x, y, z, m, targets=None, G=1.0, softening=0.0):
+    """Exact direct sum; returns (acc[3,t], pot[t], gabs[t]) for the targets
+    (softened Green's function when softening > 0)."""
     x, y, z, m = (_f64(v) for v in (x, y, z, m))
     n = len(x)
     if targets is None:
@@ -302,11 +343,24 @@ def direct(x, y, z, m, targets=None, G=1.0):
         nt = len(targets)
         tp = targets.ctypes.data_as(C.POINTER(C.c_int64))
     ax, ay, az, pot, gabs = (np.zeros(nt) for _ in range(5))
-    st = lib().orc_direct(n, _d(x), _d(y), _d(z), _d(m), nt, tp, float(G), _d(ax), _d(ay),
-                          _d(az), _d(pot), _d(gabs))
+    st = lib().orc_direct_softened(n, _d(x), _d(y), _d(z), _d(m), nt, tp, float(G), float(softening),
+                                   _d(ax), _d(ay), _d(az), _d(pot), _d(gabs))
     if st:
         raise OracleError(st)
     return np.stack([ax, ay, az]), pot, gabs
+
+
+def greens_softened(R, eps):
+    """D0..D4 and D'_ijkl of the softened g = -1/sqrt(R^2 + eps^2) as full tensors."""
+    R = _f64(R)
+    D0 = np.zeros(1)
+    D1 = np.zeros(3)
+    D2 = np.zeros((3, 3))
+    D3 = np.zeros((3, 3, 3))
+    D4 = np.zeros((3, 3, 3, 3))
+    D4p = np.zeros((3, 3, 3, 3))
+    lib().orc_greens_softened(_d(R), float(eps), _d(D0), _d(D1), _d(D2), _d(D3), _d(D4), _d(D4p))
+    return D0[0], D1, D2, D3, D4, D4p
 
 
 def greens(R):

@@ -28,7 +28,7 @@ class amfmm_options(C.Structure):
     _fields_ = [("n_crit", C.c_int32), ("variant", C.c_int32), ("precision", C.c_int32),
                 ("criterion", C.c_int32), ("G", C.c_double), ("error_tol", C.c_double),
                 ("theta_max", C.c_double), ("max_bytes", C.c_int64), ("list_bytes", C.c_int64),
-                ("learned_min_work", C.c_int64)]
+                ("learned_min_work", C.c_int64), ("softening", C.c_double)]
 
 
 _lib = None
@@ -58,6 +58,8 @@ def lib():
         "amfmm_evaluate": (C.c_int, [P, pd, pd, pd, pd]),
         "amfmm_solve_gravity": (C.c_int, [P, i64, pd, pd, pd, pd, C.c_double, pd, pd, pd, pd]),
         "amfmm_solve_gravity_noalloc": (C.c_int, [P, i64, pd, pd, pd, pd, C.c_double, pd, pd, pd, pd]),
+        "amfmm_leapfrog": (C.c_int, [P, i64, pd, pd, pd, pd, pd, pd, pd, C.c_double, C.c_double, i32,
+                                     pd, pd, pd]),
         "amfmm_direct": (C.c_int, [P, i64, pd, pd, pd, pd, i64, pd, pd, pd, pd, pd, pd]),
         "amfmm_balance": (C.c_int, [P, i64, pd, pd, pd, pd, pd, pd, pd, d]),
         "amfmm_get_counts": (C.c_int, [P, C.POINTER(C.c_int64)]),
@@ -89,7 +91,7 @@ def lib():
 EXPORTED = ["amfmm_default_options", "amfmm_create", "amfmm_destroy", "amfmm_set_stream",
             "amfmm_set_field_estimate",
             "amfmm_build_tree", "amfmm_compute_moments", "amfmm_walk", "amfmm_evaluate",
-            "amfmm_solve_gravity", "amfmm_solve_gravity_noalloc", "amfmm_direct", "amfmm_balance", "amfmm_get_counts",
+            "amfmm_solve_gravity", "amfmm_solve_gravity_noalloc", "amfmm_leapfrog", "amfmm_direct", "amfmm_balance", "amfmm_get_counts",
             "amfmm_get_tree", "amfmm_get_moments", "amfmm_get_lists", "amfmm_get_phase_times",
             "amfmm_set_model", "amfmm_pair_features", "amfmm_pair_labels", "amfmm_mlp_predict",
             "amfmm_mlp_grad", "amfmm_mlp_train", "amfmm_status_string", "amfmm_last_error"]
@@ -133,7 +135,7 @@ class Solver:
 
     def __init__(self, n_crit=25, variant=TC, precision=FP64, criterion=GEOMETRIC, G=1.0,
                  error_tol=1e-4, theta_max=1.0, max_bytes=0, list_bytes=0, learned_min_work=4096,
-                 stream=None):
+                 stream=None, softening=0.0):
         L = lib()
         o = amfmm_options()
         L.amfmm_default_options(C.byref(o))
@@ -141,6 +143,7 @@ class Solver:
         o.G, o.error_tol, o.theta_max, o.max_bytes = G, error_tol, theta_max, max_bytes
         o.list_bytes = list_bytes
         o.learned_min_work = learned_min_work
+        o.softening = softening
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = C.c_void_p()
         st = L.amfmm_create(C.byref(o), C.c_void_p(self.stream.cuda_stream), C.byref(h))
@@ -287,6 +290,20 @@ class Solver:
         self.n = n
         self._check(lib().amfmm_solve_gravity_noalloc(self._h, n, *args))
         return ax, ay, az, p
+
+    def leapfrog(self, x, y, z, vx, vy, vz, m, theta, dt, steps, acc):
+        """amfmm_leapfrog: `steps` kick-drift-kick steps of dt in place on the
+        positions and velocities; acc = (ax, ay, az) holds the accelerations at
+        the positions on entry and at the new ones on return."""
+        n = x.numel()
+        ax, ay, az = acc
+        self._check_field(n)
+        self._check(lib().amfmm_leapfrog(self._h, n, _dev(x, "x", n), _dev(y, "y", n), _dev(z, "z", n),
+                                         _dev(vx, "vx", n), _dev(vy, "vy", n), _dev(vz, "vz", n),
+                                         _dev(m, "m", n), float(theta), float(dt), int(steps),
+                                         _dev(ax, "ax", n), _dev(ay, "ay", n), _dev(az, "az", n)))
+        self.n = n
+        return acc
 
     def direct(self, x, y, z, m, targets=None, pot=True, gabs=True):
         n = x.numel()

@@ -246,6 +246,7 @@ int amfmm_default_options(amfmm_options* o) {
   o->learned_min_work = 4096;
   o->max_bytes = 0;
   o->list_bytes = 0;
+  o->softening = 0.0;
   return AMFMM_OK;
 }
 
@@ -255,6 +256,7 @@ static int check_options(const amfmm_options* o) {
   if (o->precision != AMFMM_FP64 && o->precision != AMFMM_MIXED) return AMFMM_E_INVALID;
   if (o->criterion < AMFMM_GEOMETRIC || o->criterion > AMFMM_MULTIPOLE) return AMFMM_E_INVALID;
   if (!(o->G == o->G) || o->max_bytes < 0 || o->list_bytes < 0 || o->learned_min_work < 0) return AMFMM_E_INVALID;
+  if (!(o->softening >= 0.0) || !std::isfinite(o->softening)) return AMFMM_E_INVALID;
   return AMFMM_OK;
 }
 
@@ -661,6 +663,24 @@ static int solve_impl(Ctx& c, int64_t n, const double* x, const double* y, const
 int amfmm_solve_gravity(amfmm_ctx* ctx, int64_t n, const double* x, const double* y, const double* z,
                         const double* m, double theta, double* ax, double* ay, double* az, double* pot) {
   return guarded(ctx, [&](Ctx& c) -> int { return solve_impl(c, n, x, y, z, m, theta, ax, ay, az, pot); });
+}
+
+int amfmm_leapfrog(amfmm_ctx* ctx, int64_t n, double* x, double* y, double* z, double* vx, double* vy, double* vz,
+                   const double* m, double theta, double dt, int32_t steps, double* ax, double* ay, double* az) {
+  return guarded(ctx, [&](Ctx& c) -> int {
+    if (!vx || !vy || !vz || !ax || !ay || !az) return fail(c, AMFMM_E_INVALID, "null pointer");
+    if (steps < 0 || !std::isfinite(dt)) return fail(c, AMFMM_E_INVALID, "bad steps or dt");
+    if (!(theta > 0.0 && theta <= 1.0)) return fail(c, AMFMM_E_INVALID, "theta must lie in (0, 1]");
+    if (n < 1 || n >= (int64_t)INT32_MAX) return fail(c, AMFMM_E_INVALID, "n must be in [1, 2^31)");
+    for (int32_t s = 0; s < steps; ++s) {
+      amfmm::kick(c, n, 0.5 * dt, ax, ay, az, vx, vy, vz);
+      amfmm::drift(c, n, dt, vx, vy, vz, x, y, z);
+      const int st = solve_impl(c, n, x, y, z, m, theta, ax, ay, az, nullptr);
+      if (st) return st;
+      amfmm::kick(c, n, 0.5 * dt, ax, ay, az, vx, vy, vz);
+    }
+    return AMFMM_OK;
+  });
 }
 
 // The solve with every device buffer carved from this device's scratch array.

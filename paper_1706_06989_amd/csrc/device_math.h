@@ -32,10 +32,13 @@ __device__ inline double rsqrt_f64_1nr(double r2) {
 
 // Far-field coefficients of one source (moments M, quadrupole Q2) at R:
 // acc[0] C, acc[1..3] C_k, acc[4..9] C_kl, acc[10..19] C_klm (packed).
-// T = double (FP64 path) or float (mixed path).
+// T = double (FP64 path) or float (mixed path).  The D tensors are written as
+// sums over index pairings of the radial factors t_k = (1/R d/dR)^k g, which
+// holds for any g of the distance alone: eps2 > 0 gives the softened g =
+// -1/sqrt(R^2 + eps2) (Sec. 4), eps2 = 0 the plain -1/R (adding zero is exact).
 template <typename T>
-__device__ inline void far_coeffs(const T R[3], T M, const T Q2[6], T* acc) {
-  const T r2 = fma(R[0], R[0], fma(R[1], R[1], R[2] * R[2]));
+__device__ inline void far_coeffs(const T R[3], T M, const T Q2[6], T* acc, T eps2) {
+  const T r2 = fma(R[0], R[0], fma(R[1], R[1], R[2] * R[2])) + eps2;
   T ri;
   if constexpr (sizeof(T) == 8) ri = rsqrt_f64(r2);
   else ri = __builtin_amdgcn_rsqf(r2);
@@ -78,11 +81,12 @@ __device__ inline void far_coeffs(const T R[3], T M, const T Q2[6], T* acc) {
 }
 
 // Q_jkl D_ijkl (TC) or Q_jkl D'_ijkl (TCO) of the correction, FP64, with
-// Q = M_X,jkl M_Y - M_X M_Y,jkl; adds to F[3]
+// Q = M_X,jkl M_Y - M_X M_Y,jkl; adds to F[3].  In the radial-factor form of
+// far_coeffs (softened for eps2 > 0).
 template <int VARIANT>
 __device__ inline void far_correction(const double R[3], double MX, const double OX[10], double M, const double O3[10],
-                                      double F[3]) {
-  const double r2 = fma(R[0], R[0], fma(R[1], R[1], R[2] * R[2]));
+                                      double F[3], double eps2) {
+  const double r2 = fma(R[0], R[0], fma(R[1], R[1], R[2] * R[2])) + eps2;
   const double ri = rsqrt_f64(r2);
   const double ri2 = ri * ri;
   const double t2 = -3.0 * (ri * ri2) * ri2;
@@ -115,7 +119,8 @@ __device__ inline void far_correction(const double R[3], double MX, const double
   }
 }
 
-// The correction of eq. 7 (TC) from traceless octupoles: D_ijkl is traceless
+// The correction of eq. 7 (TC) from traceless octupoles (plain -1/R only: the
+// softened D_ijkl is not traceless): D_ijkl is traceless
 // in every pair of indices, so only the traceless part of Q = M_X,jkl M_Y -
 // M_X M_Y,jkl contributes, and with a traceless Q the closed form reduces to
 // t4 R_i (Q.RRR) + 3 t3 Q_ikl R_k R_l.  OXt, O3t: traceless octupoles (10

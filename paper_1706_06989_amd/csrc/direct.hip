@@ -14,7 +14,7 @@ constexpr int kBS = 256;
 __global__ void __launch_bounds__(kBS) k_direct(int64_t n, const double* __restrict__ x, const double* __restrict__ y,
                                                 const double* __restrict__ z, const double* __restrict__ m,
                                                 int64_t nt, const int64_t* __restrict__ tg, int64_t chunk,
-                                                double* __restrict__ part) {
+                                                double* __restrict__ part, double eps2) {
   __shared__ double4 tile[kBS];
   const int64_t q = (int64_t)blockIdx.x * kBS + threadIdx.x;
   int64_t i = q < nt ? (tg ? tg[q] : q) : 0;
@@ -31,7 +31,7 @@ __global__ void __launch_bounds__(kBS) k_direct(int64_t n, const double* __restr
       const double4 s = tile[k];
       const double dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
       const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-      double w = rsqrt_f64(r2);
+      double w = rsqrt_f64(r2 + eps2);  // softened for eps2 > 0 (Sec. 4)
       w = r2 > 0.0 ? w : 0.0;
       const double mw = s.w * w;
       const double mw3 = mw * w * w;
@@ -166,7 +166,7 @@ void direct_sum(Ctx& c, int64_t n, const double* x, const double* y, const doubl
   nchunk = (n + chunk - 1) / chunk;
   double* part = (double*)ensure(c, c.scratch2, sizeof(double) * 5 * (size_t)(nchunk * ntarget));
   hipLaunchKernelGGL(k_direct, dim3((unsigned)tblocks, (unsigned)nchunk), dim3(kBS), 0, c.stream, n, x, y, z, m,
-                     ntarget, targets, chunk, part);
+                     ntarget, targets, chunk, part, c.opt.softening * c.opt.softening);
   hipLaunchKernelGGL(k_direct_sum, dim3((unsigned)tblocks), dim3(kBS), 0, c.stream, n, ntarget, targets,
                      (int)nchunk, (const double*)part, c.opt.G, ax, ay, az, pot, gabs);
   AMFMM_HIP(hipGetLastError());

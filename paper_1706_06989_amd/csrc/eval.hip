@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(kBS) k_far_rec(int32_t c_lo, int32_t nc, const
       float Q2f[6];
 #pragma unroll
       for (int u = 0; u < 6; ++u) Q2f[u] = ry.q[u];
-      far_coeffs<float>(Rf, (float)M, Q2f, a32);
+      far_coeffs<float>(Rf, (float)M, Q2f, a32, 0.0f);
       if (VARIANT) {
         double O3[10];
         record_octupole(ry.o, O3);
@@ -153,7 +153,7 @@ __global__ void __launch_bounds__(kBS) k_far_rec(int32_t c_lo, int32_t nc, const
 template <int VARIANT, bool MIXED>
 __global__ void __launch_bounds__(kBS) k_far(int32_t c_lo, int32_t nc, const double4* __restrict__ geo, const double* __restrict__ mom,
                                              const int64_t* __restrict__ fstart, const int32_t* __restrict__ fcount,
-                                             const int32_t* __restrict__ fsrc, double* __restrict__ loc) {
+                                             const int32_t* __restrict__ fsrc, double* __restrict__ loc, double eps2) {
   const int lane = threadIdx.x & 63;
   const int32_t Xi = uniform((int32_t)(xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6)));
   if (Xi >= nc) return;
@@ -186,18 +186,18 @@ __global__ void __launch_bounds__(kBS) k_far(int32_t c_lo, int32_t nc, const dou
         float Q2f[6];
 #pragma unroll
         for (int u = 0; u < 6; ++u) Q2f[u] = (float)my[1 + u];
-        far_coeffs<float>(Rf, (float)M, Q2f, a32);
+        far_coeffs<float>(Rf, (float)M, Q2f, a32, (float)eps2);
       } else {
         double Q2[6];
 #pragma unroll
         for (int u = 0; u < 6; ++u) Q2[u] = my[1 + u];
-        far_coeffs<double>(R, M, Q2, acc);
+        far_coeffs<double>(R, M, Q2, acc, eps2);
       }
       if (VARIANT) {
         double O3[10];
 #pragma unroll
         for (int u = 0; u < 10; ++u) O3[u] = my[7 + u];
-        far_correction<VARIANT>(R, MX, OX, M, O3, F);
+        far_correction<VARIANT>(R, MX, OX, M, O3, F, eps2);
       }
     }
     if (MIXED) {
@@ -281,8 +281,10 @@ void zero_u64(Ctx& c, unsigned long long* p, int n) {
   AMFMM_HIP(hipGetLastError());
 }
 
+// the 128-byte records carry traceless octupoles, enough for the correction
+// of the plain -1/R only (mixed UC and TC)
 static bool use_records(const Ctx& c) {
-  return c.opt.precision == AMFMM_MIXED && c.opt.variant != AMFMM_TCO;
+  return c.opt.precision == AMFMM_MIXED && c.opt.variant != AMFMM_TCO && c.opt.softening == 0.0;
 }
 
 void far_prepare(Ctx& c) {
@@ -309,7 +311,8 @@ void far_field(Ctx& c, int32_t c_lo, int32_t c_hi) {
   }
   auto args = [&](auto kern) {
     hipLaunchKernelGGL(kern, grid, dim3(kBS), 0, c.stream, c_lo, nc, (const double4*)c.geo.p, (const double*)c.mom.p,
-                       (const int64_t*)c.far_start.p, (const int32_t*)c.far_count.p, (const int32_t*)c.far_src.p, loc);
+                       (const int64_t*)c.far_start.p, (const int32_t*)c.far_count.p, (const int32_t*)c.far_src.p, loc,
+                       c.opt.softening * c.opt.softening);
   };
   ++c.far_launches;
   const bool mixed = c.opt.precision == AMFMM_MIXED;

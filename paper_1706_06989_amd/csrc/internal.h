@@ -203,6 +203,13 @@ double mlp_grad(Ctx& c, int64_t n, const float* model, const float* feats, const
 double mlp_train(Ctx& c, int64_t n, const float* feats, const float* labels, float* model, float* am, float* av,
                  int64_t step0, int32_t steps, int32_t batch, double lr, double tau);
 
+// ---- integrate.hip ----
+// v += h a and x += dt v over n particles (device SoA arrays)
+void kick(Ctx& c, int64_t n, double h, const double* ax, const double* ay, const double* az, double* vx, double* vy,
+          double* vz);
+void drift(Ctx& c, int64_t n, double dt, const double* vx, const double* vy, const double* vz, double* x, double* y,
+           double* z);
+
 // ---- direct.hip ----
 void direct_sum(Ctx& c, int64_t n, const double* x, const double* y, const double* z,
                 const double* m, int64_t ntarget, const int64_t* targets, double* ax, double* ay,

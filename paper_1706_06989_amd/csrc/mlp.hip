@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(kBS) k_pair_labels(int64_t np, const int32_t* 
 #pragma unroll
     for (int u = 0; u < kLoc; ++u) L[u] = 0.0;
     const double Q2[6] = {ms[1], ms[2], ms[3], ms[4], ms[5], ms[6]};
-    far_coeffs<double>(R, ms[0], Q2, L);
+    far_coeffs<double>(R, ms[0], Q2, L, 0.0);
     if (VARIANT != AMFMM_UC) {
       double OX[10], O3[10], F[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(kBS) k_pair_labels(int64_t np, const int32_t* 
         OX[u] = mt[7 + u];
         O3[u] = ms[7 + u];
       }
-      far_correction<VARIANT>(R, mt[0], OX, ms[0], O3, F);
+      far_correction<VARIANT>(R, mt[0], OX, ms[0], O3, F, 0.0);
       const double cf = -1.0 / (6.0 * mt[0]);
 #pragma unroll
       for (int i = 0; i < 3; ++i) L[20 + i] = cf * F[i];

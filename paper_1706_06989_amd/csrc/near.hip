@@ -54,10 +54,12 @@ __device__ inline void comp_add(double& s, float& c, double b) {
 
 // FP32 interactions of this lane's targets (offsets t*) with sources
 // buf[s], buf[s+nsl], ...; partial sums flushed into the compensated FP64
-// sums (f*, compensation terms c*)
+// sums (f*, compensation terms c*).  SOFT: the softened kernel, 1/(r^2 +
+// eps2)^{1/2} and ^{3/2} (Sec. 4); pairs at r = 0 are skipped either way.
+template <bool SOFT>
 __device__ inline void near_tile_f32(const float4* buf, int fill, int s, int nsl, const float* tx, const float* ty,
                                      const float* tz, double* fx, double* fy, double* fz, double* ph, float* cx,
-                                     float* cy, float* cz, float* cp) {
+                                     float* cy, float* cz, float* cp, float eps2) {
   for (int j0 = s; j0 < fill; j0 += kFlush * nsl) {
     const int j1 = min(fill, j0 + kFlush * nsl);
     float gx[kTG], gy[kTG], gz[kTG], gp[kTG];
@@ -69,7 +71,7 @@ __device__ inline void near_tile_f32(const float4* buf, int fill, int s, int nsl
       for (int u = 0; u < kTG; ++u) {
         const float dx = q.x - tx[u], dy = q.y - ty[u], dz = q.z - tz[u];
         const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        float y = __builtin_amdgcn_rsqf(r2);
+        float y = __builtin_amdgcn_rsqf(SOFT ? r2 + eps2 : r2);
         y = r2 > 0.0f ? y : 0.0f;
         const float my = q.w * y;
         const float my3 = my * (y * y);
@@ -90,15 +92,16 @@ __device__ inline void near_tile_f32(const float4* buf, int fill, int s, int nsl
 }
 
 // interactions of this lane's kTG targets with sources buf[s], buf[s+nsl], ...
+template <bool SOFT>
 __device__ inline void near_tile(const double4* buf, int fill, int s, int nsl, const double* tx, const double* ty,
-                                 const double* tz, double* fx, double* fy, double* fz, double* ph) {
+                                 const double* tz, double* fx, double* fy, double* fz, double* ph, double eps2) {
   for (int j = s; j < fill; j += nsl) {
     const double4 q = buf[j];
 #pragma unroll
     for (int u = 0; u < kTG; ++u) {
       const double dx = q.x - tx[u], dy = q.y - ty[u], dz = q.z - tz[u];
       const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-      double y = rsqrt_f64_1nr(r2);
+      double y = rsqrt_f64_1nr(SOFT ? r2 + eps2 : r2);
       y = r2 > 0.0 ? y : 0.0;
       const double my = q.w * y;
       const double my3 = my * (y * y);
@@ -116,7 +119,7 @@ __device__ inline float4 offset32(const double4 p, const double4 c) {
 }
 
 // leaves == nullptr: the targets are the leaves among cells [c_lo, c_lo + nleaves)
-template <bool MIXED>
+template <bool MIXED, bool SOFT>
 __global__ void __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(4))) k_near(int32_t nleaves, const int32_t* __restrict__ leaves, int32_t c_lo,
                                               const int32_t* __restrict__ nch,
                                               const int32_t* __restrict__ beg, const int32_t* __restrict__ cnt,
@@ -125,7 +128,7 @@ __global__ void __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(4))) k
                                               const int32_t* __restrict__ ncount, const int32_t* __restrict__ nsrc,
                                               const int32_t* __restrict__ perm, double G, double* __restrict__ ax,
                                               double* __restrict__ ay, double* __restrict__ az, double* __restrict__ pot,
-                                              unsigned long long* __restrict__ inter) {
+                                              unsigned long long* __restrict__ inter, double eps2) {
   const int lane = threadIdx.x & 63;
   const int32_t li = uniform((int32_t)(xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6)));
   if (li >= nleaves) return;
@@ -227,8 +230,8 @@ __global__ void __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(4))) k
           }
           wave_sync();
           if (active) {
-            if (MIXED) near_tile_f32(buf32, part, s, nsl, ux, uy, uz, fx, fy, fz, ph, cx, cy, cz, cp);
-            else near_tile(buf, part, s, nsl, tx, ty, tz, fx, fy, fz, ph);
+            if (MIXED) near_tile_f32<SOFT>(buf32, part, s, nsl, ux, uy, uz, fx, fy, fz, ph, cx, cy, cz, cp, (float)eps2);
+            else near_tile<SOFT>(buf, part, s, nsl, tx, ty, tz, fx, fy, fz, ph, eps2);
           }
           wave_sync();
         }
@@ -240,8 +243,8 @@ __global__ void __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(4))) k
       if (take > 0) {
         wave_sync();
         if (active) {
-          if (MIXED) near_tile_f32(buf32, fill, s, nsl, ux, uy, uz, fx, fy, fz, ph, cx, cy, cz, cp);
-          else near_tile(buf, fill, s, nsl, tx, ty, tz, fx, fy, fz, ph);
+          if (MIXED) near_tile_f32<SOFT>(buf32, fill, s, nsl, ux, uy, uz, fx, fy, fz, ph, cx, cy, cz, cp, (float)eps2);
+          else near_tile<SOFT>(buf, fill, s, nsl, tx, ty, tz, fx, fy, fz, ph, eps2);
         }
         wave_sync();
       }
@@ -325,12 +328,14 @@ void near_field(Ctx& c, const int32_t* leaves, int32_t c_lo, int32_t count, doub
                 double* pot) {
   if (count <= 0) return;
   ++c.near_launches;
-  auto kern = c.opt.precision == AMFMM_MIXED ? k_near<true> : k_near<false>;
+  const bool mixed = c.opt.precision == AMFMM_MIXED, soft = c.opt.softening > 0.0;
+  auto kern = mixed ? (soft ? k_near<true, true> : k_near<true, false>)
+                    : (soft ? k_near<false, true> : k_near<false, false>);
   hipLaunchKernelGGL(kern, dim3(blocks_for(count, kWaves)), dim3(kBS), 0, c.stream, count, leaves, c_lo,
                      as<int32_t>(c.c_nchild), as<int32_t>(c.c_begin), as<int32_t>(c.c_count), (const double4*)c.pos4.p,
                      (const double4*)c.geo.p, (const double*)c.loc.p, (const int64_t*)c.near_start.p,
                      (const int32_t*)c.near_count.p, (const int32_t*)c.near_src.p, as<int32_t>(c.perm), c.opt.G, ax,
-                     ay, az, pot, (unsigned long long*)c.counters.p);
+                     ay, az, pot, (unsigned long long*)c.counters.p, c.opt.softening * c.opt.softening);
   AMFMM_HIP(hipGetLastError());
 }
 

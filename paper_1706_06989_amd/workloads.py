@@ -84,6 +84,58 @@ def two_plummer(n, seed=3, a=1.0, a2=None):
     return x, y, z, _equal_masses(n)
 
 
+def _plummer_speeds(rng, r, mass, a):
+    """Speeds of an isotropic Plummer sphere in equilibrium (G = 1) at radii r:
+    q v_esc(r), v_esc^2 = 2 mass / sqrt(r^2 + a^2), with q drawn from the
+    density q^2 (1 - q^2)^{7/2} on [0, 1] by rejection under the constant 0.1
+    (Aarseth, Henon & Wielen 1974)."""
+    q = np.empty(len(r))
+    todo = np.arange(len(r))
+    while len(todo):
+        x = rng.random(len(todo))
+        y = 0.1 * rng.random(len(todo))
+        ok = y < x * x * (1.0 - x * x) ** 3.5
+        q[todo[ok]] = x[ok]
+        todo = todo[~ok]
+    return q * np.sqrt(2.0 * mass / np.sqrt(r * r + a * a))
+
+
+def _isotropic(rng, v):
+    c = rng.uniform(-1.0, 1.0, len(v))
+    p = rng.uniform(0.0, 2.0 * np.pi, len(v))
+    s = np.sqrt(1.0 - c * c)
+    return v * s * np.cos(p), v * s * np.sin(p), v * c
+
+
+def two_plummer_binary(n, seed=7, a=1.0):
+    """Positions and velocities of a bound binary: the two spheres of
+    ``two_plummer`` (same seed stream for the positions), each given isotropic
+    equilibrium velocities about its own centre, the two centres on a circular
+    orbit about their common centre of mass in the x-y plane (separation 3a,
+    angular speed sqrt(M / (3a)^3)).  Returns (x, y, z, m, vx, vy, vz); the
+    orbital period is 2 pi / sqrt(M / (3a)^3), about 32.6 for a = 1, M = 1."""
+    x, y, z, m = two_plummer(n, seed=seed, a=a)
+    n2 = n // 3
+    n1 = n - n2
+    rng = np.random.default_rng(seed + 1000)
+    vel = []
+    for lo, hi, cx in ((0, n1, -a), (n1, n, 2.0 * a)):
+        r = np.sqrt((x[lo:hi] - cx) ** 2 + y[lo:hi] ** 2 + z[lo:hi] ** 2)
+        vel.append(_isotropic(rng, _plummer_speeds(rng, r, m[lo:hi].sum(), a)))
+    vx, vy, vz = (np.concatenate([vel[0][k], vel[1][k]]) for k in range(3))
+    m1, m2 = m[:n1].sum(), m[n1:].sum()
+    d = 3.0 * a
+    w = np.sqrt((m1 + m2) / d**3)
+    com = (m1 * -a + m2 * 2.0 * a) / (m1 + m2)
+    cx = np.concatenate([np.full(n1, -a), np.full(n2, 2.0 * a)])
+    vy += w * (cx - com)
+    # no net momentum
+    vx -= np.average(vx, weights=m)
+    vy -= np.average(vy, weights=m)
+    vz -= np.average(vz, weights=m)
+    return x, y, z, m, vx, vy, vz
+
+
 # The five workloads the solver is specified on (sizes, seeds, shapes).
 CONFIGS = {
     "uniform4k": dict(gen=uniform_cube, n=4096, seed=1),

@@ -31,6 +31,8 @@ def pins_for(name):
         return ["tests/test_oracle_multipole.py"]
     if name.split("_")[0] in ("learned", "label", "grad", "plog2", "bf16", "feature"):
         return LEARNED_PINS
+    if name.startswith("soft_"):
+        return ["tests/test_oracle_softening.py"]
     return CORE_PINS
 
 MUTATIONS = {
@@ -86,6 +88,10 @@ MUTATIONS = {
                                   "double k = std::floor(kMq * (norm / den));"),
     "multipole_source_terms_swapped": ("double Q = kMw4 * (rs2 * rs2) + kMw5 * (rt2 * rt2);",
                                        "double Q = kMw5 * (rs2 * rs2) + kMw4 * (rt2 * rt2);"),
+    "soft_f3_coefficient": ("double f3 = -5.0 * f2 / s;", "double f3 = -3.0 * f2 / s;"),
+    "soft_direct_unsoftened": ("      double s2 = r2 + eps2;", "      double s2 = r2;"),
+    "soft_D4_missing_terms": ("g.D4[i][j][k][l] = f2 * dd + f3 * (di + dr) + f4 * R[i] * R[j] * R[k] * R[l];",
+                              "g.D4[i][j][k][l] = f2 * dd + f3 * di + f4 * R[i] * R[j] * R[k] * R[l];"),
     "self_walk_skips_pairs": ("for (int32_t b = a + 1; b < C.child0 + C.nchild; ++b) walk_pair(t, a, b);",
                               "for (int32_t b = a + 2; b < C.child0 + C.nchild; ++b) walk_pair(t, a, b);"),
 }
