@@ -226,7 +226,7 @@ def main():
         # trained on the GPU before the timed region (library kernels)
         from paper_1706_06989_amd import learned
         t0 = time.perf_counter()
-        f, lab = learned.training_set(n_plummer=1 << 20)
+        f, lab = learned.training_set()
         model, losses = learned.train(f, lab)
         model_info = {"pairs": int(len(lab)), "loss": [losses[0], losses[-1]],
                       "train_s": round(time.perf_counter() - t0, 2)}

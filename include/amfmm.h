@@ -54,13 +54,14 @@ typedef enum { AMFMM_FP64 = 0, AMFMM_MIXED = 1 } amfmm_precision;
  *   (per cell: the smallest field estimate over its particles, at least 0.1
  *   times their mean), a pair is accepted when q <= theta_max and
  *   q^3 M_B / d^2 <= error_tol s_A and q^3 M_A / d^2 <= error_tol s_B.
- * LEARNED: as ESTIMATE, but for pairs with N_A N_B >= learned_min_work the
- *   analytic error factor q^3 is replaced by the network's prediction f
- *   (amfmm_set_model) where q^3 lies within [u/4, 16 u] of the allowed factor
- *   u = min(error_tol s_A d^2 / M_B, error_tol s_B d^2 / M_A); below the band
- *   the pair is accepted, above it opened.  Smaller pairs, and pairs whose
- *   features fall outside the model's training range, are accepted when
- *   q^3 <= u (the analytic factor).
+ * LEARNED: MULTIPOLE (below), with a network (amfmm_set_model) deciding the
+ *   pairs whose estimate lies near the bound: with rho the larger of
+ *   e_A / (error_tol s_A) and e_B / (error_tol s_B), rho <= 1/4 accepts and
+ *   rho > 2 opens; in between, for pairs with N_A N_B >= learned_min_work and
+ *   features inside the model's training range, the network predicts log2 of
+ *   the ratio of the method's error to the estimate and the pair is accepted
+ *   when that prediction is at most -plog2(rho) (the error then predicted
+ *   stays within error_tol s); other pairs take the MULTIPOLE decision rho <= 1.
  * MULTIPOLE: an error-estimate criterion from the parts a third-order
  *   expansion drops: with k2, k3 the Frobenius norms of the source's traceless
  *   quadrupole and octupole in units of M R_max^2 and M R_max^3 (held to the
@@ -88,9 +89,9 @@ typedef struct {
                          fit, amfmm_solve_gravity walks and evaluates the tree
                          in batches of subtrees, with identical results */
   int64_t learned_min_work; /* LEARNED: the network decides pairs with N_A N_B >=
-                               this (default 4096); smaller pairs, where a network
-                               evaluation costs more than the work it can save,
-                               take the analytic estimate q^3 <= u */
+                               this (default 262144); smaller pairs, where a network
+                               evaluation (about 9 kFLOP) costs more than the work
+                               it can save, take the multipole estimate's decision */
   double softening;   /* Plummer softening length eps >= 0 of the Green's function
                          g = -1/sqrt(R^2 + eps^2) (Sec. 4: the correction holds for
                          any g of the distance alone): the far-field derivatives, the
@@ -103,7 +104,7 @@ typedef struct {
 typedef struct amfmm_ctx amfmm_ctx;
 
 /* Fills *opt with n_crit = 25, TC, FP64, geometric, G = 1, error_tol = 1e-4,
- * theta_max = 1, max_bytes = 0, list_bytes = 0, learned_min_work = 4096,
+ * theta_max = 1, max_bytes = 0, list_bytes = 0, learned_min_work = 262144,
  * softening = 0. */
 int amfmm_default_options(amfmm_options* opt);
 
@@ -111,7 +112,7 @@ int amfmm_default_options(amfmm_options* opt);
  * on the current device.  The context owns all scratch. */
 int amfmm_create(const amfmm_options* opt, void* hip_stream, amfmm_ctx** out);
 int amfmm_destroy(amfmm_ctx* ctx);
-/* Per-particle field estimates for the ESTIMATE and LEARNED criteria, e.g. the
+/* Per-particle field estimates for the ESTIMATE, LEARNED and MULTIPOLE criteria, e.g. the
  * accelerations of the previous time step or of a cheaper solve: device
  * pointers to n doubles in caller order, either the three components (gx, gy,
  * gz) or magnitudes in gx with gy = gz = NULL.  The arrays are read during the
@@ -211,12 +212,13 @@ int amfmm_balance(amfmm_ctx* ctx, int64_t n, const double* x, const double* y, c
  * a[8], b[8], and the training range of the raw features, lo[8], hi[8].
  * Inference rounds weights, inputs and hidden activations to BF16 and sums
  * in FP32 (fused multiply-adds in index order).  Its output is the predicted
- * log2 of a pair's error factor: the rms over the pair's particles of
- * |g_pair - g_direct| / (M_other / d^2).  Features of a pair (A, B), d the
- * centre distance, all symmetric: (R_A+R_B)/d, plog2 of it, |R_A-R_B|/(R_A+R_B),
- * |M_A-M_B|/(M_A+M_B), (k_A+k_B)/128, |k_A-k_B|/64 with k = floor(64
- * ||M_ij||_F / (M R_max^2) + 1/2), plog2(N_A N_B), |plog2 N_A - plog2 N_B| (counts
- * saturated at 1024), where plog2(2^e (1+f)) = e + f. */
+ * log2 of the ratio, for the worse of the pair's two cells, of the largest
+ * error |g_pair - g_direct| over the cell's particles to the multipole
+ * estimate of that cell's error.  Features of a pair (A, B), d the centre
+ * distance, all symmetric: (R_A+R_B)/d, |R_A-R_B|/(R_A+R_B), (k2_A+k2_B)/256,
+ * |k2_A-k2_B|/128, (k3_A+k3_B)/256, |k3_A-k3_B|/128 (the traceless norm levels
+ * of MULTIPOLE), |M_A-M_B|/(M_A+M_B), plog2(N_A N_B) (counts saturated at
+ * 1024), where plog2(2^e (1+f)) = e + f. */
 #define AMFMM_MLP_PARAMS 4801
 #define AMFMM_MLP_MODEL 4833
 
@@ -226,10 +228,14 @@ int amfmm_set_model(amfmm_ctx* ctx, const float* model);
 /* Features (8 floats per pair) and labels (log2 error factor, doubles) of np
  * cell pairs of the context's tree (after amfmm_compute_moments); pairs:
  * device int32, 2 per pair.  The two cells must be distinct with distinct
- * centres, as in a walk's far field; that is not checked.  A label samples up to 64 particles of each cell (particle k of ns
- * is first + k N / ns) and evaluates the pair alone with the variant given
- * against direct summation over the other cell.  Outputs are device arrays;
- * a pair naming no cell of the tree gets NaN features or a NaN label. */
+ * centres, as in a walk's far field; that is not checked.  A label samples up
+ * to 64 particles of each cell (particle k of ns is first + k N / ns),
+ * evaluates the pair alone with the variant given against direct summation
+ * over the other cell, and is log2 of the larger of the two cells' ratios
+ * (largest sampled error over the multipole estimate); a cell whose estimate
+ * is zero (a point mass: exact) is left out, -inf when both are.  Outputs are
+ * device arrays; a pair naming no cell of the tree gets NaN features or a NaN
+ * label. */
 int amfmm_pair_features(amfmm_ctx* ctx, int64_t np, const int32_t* pairs, float* feats);
 int amfmm_pair_labels(amfmm_ctx* ctx, int32_t variant, int64_t np, const int32_t* pairs, double* labels);
 /* FP32 inference exactly as the walk runs it: model (device, AMFMM_MLP_MODEL

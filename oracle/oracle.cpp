@@ -78,9 +78,8 @@ struct orc_tree {
   double eps = 0.0, theta_max = 1.0;
   std::vector<double> fscale;  // per-cell field scale (modes 1 and 2)
   std::vector<float> model;    // mode 2: network and feature normalisation
-  std::vector<int> qlev;       // mode 2: quantised quadrupole norm per cell
   int64_t min_work = 0;        // mode 2: least N_A N_B for which the network decides
-  std::vector<int> k2, k3;     // mode 3: quantised traceless quadrupole and octupole norms
+  std::vector<int> k2, k3;     // modes 2, 3: quantised traceless quadrupole and octupole norms
   std::vector<std::pair<int32_t, int32_t>> m2l, p2p;
   int64_t coincident = 0;
   double eps2 = 0.0;  // Plummer softening length squared (0: the plain 1/R)
@@ -342,13 +341,14 @@ double eq2_pot_B(const Greens& g, const Moments& A, const double y[3]) {
 }
 
 // ------------------------------------------------- learned pair selection ---
-// Not in the paper: a network predicts the force error of an accepted pair
-// (the role of an error-estimating pair selection, cited in Sec. 2).  Every
-// quantity below is defined so that a GPU implementation can reproduce the
-// decision bit for bit: features use only IEEE-rounded operations on values
-// both sides hold identically (centres, radii, masses, counts) plus a
-// quadrupole norm quantised to 1/64 of M R_max^2; the network runs in FP32
-// with fused multiply-adds in a fixed order on BF16-rounded weights.
+// Not in the paper: a network predicts how far the force error the method
+// makes on an accepted pair lies from the multipole error estimate (below;
+// both take the role of the error-estimating pair selection cited in Sec.
+// 2).  Every quantity below is defined so that a GPU implementation can
+// reproduce the decision bit for bit: features use only IEEE-rounded
+// operations on values both sides hold identically (centres, radii, masses,
+// counts) and the traceless norm levels quantised to 1/128; the network runs
+// in FP32 with fused multiply-adds in a fixed order on BF16-rounded weights.
 //
 // Model layout (floats): W1[64][8], b1[64], W2[64][64], b2[64], w3[64], b3,
 // then the feature normalisation x = fma(f, a, b) (a[8], b[8]) and the
@@ -379,37 +379,22 @@ double plog2(double x) {
   return (double)(e - 1) + (2.0 * m - 1.0);
 }
 
-// ||M_ij||_F / (M R_max^2) lies in [0, 1] (1 for a cell whose particles lie
-// on a line through Z at equal distance, e.g. two equal masses); quantised to
-// the nearest multiple of 1/64, so that such exact values sit mid-bin where
-// the rounding of M_ij cannot move them across a bin boundary
-int quad_level(const Moments& mo) {
-  double s = 0.0;
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) s += mo.M2[i][j] * mo.M2[i][j];
-  double den = mo.M * (mo.Rmax * mo.Rmax);
-  if (!(den > 0.0)) return 0;
-  double k = std::floor(64.0 * (std::sqrt(s) / den) + 0.5);
-  if (k < 0.0) return 0;
-  if (k > 64.0) return 64;
-  return (int)k;
-}
-
-// the eight features of an unordered pair (each symmetric in A and B)
-void pair_features(double d, const Moments& A, const Moments& B, int qa, int qb, int64_t na, int64_t nb,
-                   float f[kFeat]) {
+// the eight features of an unordered pair (each symmetric in A and B); k2, k3
+// are the traceless norm levels of the multipole estimate (0..128)
+void pair_features(double d, const Moments& A, const Moments& B, int k2a, int k3a, int k2b, int k3b, int64_t na,
+                   int64_t nb, float f[kFeat]) {
   double r = A.Rmax + B.Rmax;
-  f[0] = (float)(r / d);                                        // (R_A + R_B) / d
-  f[1] = (float)plog2(r / d);                                   // its logarithm
-  f[2] = (float)(r > 0.0 ? std::fabs(A.Rmax - B.Rmax) / r : 0.0);  // size asymmetry
-  f[3] = (float)(std::fabs(A.M - B.M) / (A.M + B.M));          // mass asymmetry
-  f[4] = (float)((double)(qa + qb) / 128.0);                    // mean quadrupole level
-  f[5] = (float)((double)std::abs(qa - qb) / 64.0);             // its asymmetry
+  f[0] = (float)(r / d);                                           // (R_A + R_B) / d
+  f[1] = (float)(r > 0.0 ? std::fabs(A.Rmax - B.Rmax) / r : 0.0);  // size asymmetry
+  f[2] = (float)((double)(k2a + k2b) / 256.0);                     // mean quadrupole level
+  f[3] = (float)((double)std::abs(k2a - k2b) / 128.0);             // its asymmetry
+  f[4] = (float)((double)(k3a + k3b) / 256.0);                     // mean octupole level
+  f[5] = (float)((double)std::abs(k3a - k3b) / 128.0);             // its asymmetry
+  f[6] = (float)(std::fabs(A.M - B.M) / (A.M + B.M));             // mass asymmetry
   // particle counts, saturated at kCountCap: beyond it a cell behaves as a
   // continuum and the count carries no information about the error
   double ca = (double)std::min<int64_t>(na, kCountCap), cb = (double)std::min<int64_t>(nb, kCountCap);
-  f[6] = (float)plog2(ca * cb);
-  f[7] = (float)std::fabs(plog2(ca) - plog2(cb));
+  f[7] = (float)plog2(ca * cb);
 }
 
 double pair_distance(const Moments& A, const Moments& B) {
@@ -538,26 +523,33 @@ bool accept(const orc_tree& t, int32_t a, int32_t b) {
     double wa = t.eps * t.fscale[a], wb = t.eps * t.fscale[b];
     return r6 * (B.M * B.M) <= (wa * wa) * d10 && r6 * (A.M * A.M) <= (wb * wb) * d10;
   }
-  if (!(d > 0.0 && r <= t.theta_max * d)) return false;
-  double q = r / d;
-  // Learned: the error of the pair on A is f M_B / d^2 with f the predicted
-  // error factor; accept when f <= u = min over both cells of eps s d^2 / M.
-  // Where the analytic factor q^3 sits far from u the network is not asked:
-  // q^3 <= u/4 accepts, q^3 > 16 u opens.  Small pairs and pairs whose
-  // features fall outside the training range take the analytic factor.
-  double u = std::min((t.eps * t.fscale[a]) * (d * d) / B.M, (t.eps * t.fscale[b]) * (d * d) / A.M);
-  double q3 = q * q * q;
-  if (q3 <= 0.25 * u) return true;
-  if (q3 > 16.0 * u) return false;
-  // small pairs (a network evaluation would cost more than the work it saves)
-  // take the analytic factor
-  if (t.cells[a].count * t.cells[b].count < t.min_work) return q3 <= u;
+  // mode 2, learned: the multipole estimate (as mode 3), with the network
+  // deciding where it lies near the allowed error.  With rho the larger of
+  // e / (eps s d^6) over the two cells: rho <= 1/4 accepts, rho > 2 opens
+  // (eps scaled by powers of two, exactly); pairs with N_A N_B
+  // below min_work or features outside the training range take rho <= 1;
+  // the others are accepted when the predicted log2 ratio of the method's
+  // error to the estimate is at most -plog2(rho).
+  double d2 = (dx * dx + dy * dy) + dz * dz;
+  if (!(d2 > 0.0 && r * r <= (t.theta_max * t.theta_max) * d2)) return false;
+  double dl = std::sqrt(d2);
+  double d6 = (d2 * d2) * d2;
+  double ea = multipole_bracket(A.Rmax, B.Rmax, t.k2[b], t.k3[b], dl) * B.M;
+  double eb = multipole_bracket(B.Rmax, A.Rmax, t.k2[a], t.k3[a], dl) * A.M;
+  double sa = t.fscale[a], sb = t.fscale[b];
+  double lo = 0.25 * t.eps, hi = 2.0 * t.eps;
+  if (ea <= (lo * sa) * d6 && eb <= (lo * sb) * d6) return true;
+  if (!(ea <= (hi * sa) * d6 && eb <= (hi * sb) * d6)) return false;
+  bool plain = ea <= (t.eps * sa) * d6 && eb <= (t.eps * sb) * d6;
+  if (t.cells[a].count * t.cells[b].count < t.min_work) return plain;
   float f[kFeat];
-  pair_features(d, A, B, t.qlev[a], t.qlev[b], t.cells[a].count, t.cells[b].count, f);
+  pair_features(dl, A, B, t.k2[a], t.k3[a], t.k2[b], t.k3[b], t.cells[a].count, t.cells[b].count, f);
   const float* P = t.model.data();
   for (int i = 0; i < kFeat; ++i)
-    if (!(f[i] >= P[kLo + i] && f[i] <= P[kHi + i])) return q3 <= u;
-  return mlp_infer(P, f) <= (float)plog2(u);
+    if (!(f[i] >= P[kLo + i] && f[i] <= P[kHi + i])) return plain;
+  double ra = ea / ((t.eps * sa) * d6), rb = eb / ((t.eps * sb) * d6);
+  double rho = std::max(ra, rb);
+  return mlp_infer(P, f) <= (float)(-plog2(rho));
 }
 
 void walk_pair(orc_tree& t, int32_t a, int32_t b) {
@@ -821,6 +813,18 @@ void set_field_scales(orc_tree* t, const double* gmag) {
     t->fscale[ci] = std::max(gmin[ci], 0.1 * (gsum[ci] / (double)t->cells[ci].count));
 }
 
+// traceless quadrupole and octupole norm levels of every cell (modes 2 and 3)
+void set_norm_levels(orc_tree* t) {
+  size_t nc = t->cells.size();
+  t->k2.resize(nc);
+  t->k3.resize(nc);
+  for (size_t c = 0; c < nc; ++c) {
+    const Moments& mo = t->mom[c];
+    t->k2[c] = norm_level(traceless_norm2(mo), mo.M, mo.Rmax, 2);
+    t->k3[c] = norm_level(traceless_norm3(mo), mo.M, mo.Rmax, 3);
+  }
+}
+
 void run_walk(orc_tree* t) {
   t->m2l.clear();
   t->p2p.clear();
@@ -848,14 +852,7 @@ int32_t orc_walk_multipole(orc_tree* t, double eps, double theta_max, const doub
   if (!(eps > 0.0) || !(theta_max > 0.0 && theta_max <= 1.0) || !gmag) return ORC_E_INVALID;
   if (!t->have_moments) return ORC_E_STATE;
   set_field_scales(t, gmag);
-  size_t nc = t->cells.size();
-  t->k2.resize(nc);
-  t->k3.resize(nc);
-  for (size_t c = 0; c < nc; ++c) {
-    const Moments& mo = t->mom[c];
-    t->k2[c] = norm_level(traceless_norm2(mo), mo.M, mo.Rmax, 2);
-    t->k3[c] = norm_level(traceless_norm3(mo), mo.M, mo.Rmax, 3);
-  }
+  set_norm_levels(t);
   t->mode = 3;
   t->eps = eps;
   t->theta_max = theta_max;
@@ -879,8 +876,7 @@ int32_t orc_walk_learned(orc_tree* t, double eps, double theta_max, double theta
   if (!t->have_moments) return ORC_E_STATE;
   set_field_scales(t, gmag);
   t->model.assign(model, model + kModel);
-  t->qlev.resize(t->cells.size());
-  for (size_t c = 0; c < t->cells.size(); ++c) t->qlev[c] = quad_level(t->mom[c]);
+  set_norm_levels(t);
   t->mode = 2;
   t->min_work = min_work;
   t->eps = eps;
@@ -891,22 +887,27 @@ int32_t orc_walk_learned(orc_tree* t, double eps, double theta_max, double theta
 }
 
 void orc_pair_features(const orc_tree* t, int64_t np, const int32_t* pairs, float* feats) {
-  std::vector<int> q(t->cells.size());
-  for (size_t c = 0; c < t->cells.size(); ++c) q[c] = quad_level(t->mom[c]);
+  size_t nc = t->cells.size();
+  std::vector<int> k2(nc), k3(nc);
+  for (size_t c = 0; c < nc; ++c) {
+    k2[c] = norm_level(traceless_norm2(t->mom[c]), t->mom[c].M, t->mom[c].Rmax, 2);
+    k3[c] = norm_level(traceless_norm3(t->mom[c]), t->mom[c].M, t->mom[c].Rmax, 3);
+  }
   for (int64_t k = 0; k < np; ++k) {
     int32_t a = pairs[2 * k], b = pairs[2 * k + 1];
     const Moments& A = t->mom[a];
     const Moments& B = t->mom[b];
-    pair_features(pair_distance(A, B), A, B, q[a], q[b], t->cells[a].count, t->cells[b].count,
+    pair_features(pair_distance(A, B), A, B, k2[a], k3[a], k2[b], k3[b], t->cells[a].count, t->cells[b].count,
                   feats + kFeat * k);
   }
 }
 
-// Label of a pair: log2 of the rms, over up to 64 sampled particles of each
-// cell, of |g_pair - g_direct| / (M_other / d^2), where g_pair is the method's
-// acceleration from the other cell alone (eq. 3 about the own centre, with the
-// correction of the variant) and g_direct the direct sum over the other
-// cell's particles.  Particle k of ns samples of a cell is begin + k N / ns.
+// Label of a pair: for each cell T (the other S) the method's acceleration of
+// the pair alone at up to kLabelSample particles of T (eq. 3 about Z_T plus
+// the correction of the variant) against the direct sum over S; the largest
+// error over those particles divided by the multipole estimate of the error
+// on T.  The label is log2 of the larger ratio of the two cells; a cell whose
+// estimate is zero (a point mass: exact) is left out, -inf when both are.
 int32_t orc_pair_labels(const orc_tree* t, int32_t variant, int64_t np, const int32_t* pairs,
                         double* labels) {
   if (!t->have_moments) return ORC_E_STATE;
@@ -917,8 +918,7 @@ int32_t orc_pair_labels(const orc_tree* t, int32_t variant, int64_t np, const in
     if (a < 0 || b < 0 || a >= nc || b >= nc || a == b) return ORC_E_INVALID;
     double d = pair_distance(t->mom[a], t->mom[b]);
     if (!(d > 0.0)) return ORC_E_INVALID;
-    double sum = 0.0;
-    int64_t cnt = 0;
+    double worst = -INFINITY;
     for (int side = 0; side < 2; ++side) {
       int32_t ct = side ? b : a, cs = side ? a : b;
       const Cell& T = t->cells[ct];
@@ -928,6 +928,7 @@ int32_t orc_pair_labels(const orc_tree* t, int32_t variant, int64_t np, const in
       PairTerms pt;
       pair_terms(MT, MS, variant, pt);  // R = Z_T - Z_S: T is the field cell of eq. 3
       int64_t ns = std::min<int64_t>(T.count, kLabelSample);
+      double E = 0.0;
       for (int64_t s = 0; s < ns; ++s) {
         int64_t p = T.begin + (s * T.count) / ns;
         double xv[3] = {t->x[p] - MT.Z[0], t->y[p] - MT.Z[1], t->z[p] - MT.Z[2]};
@@ -946,12 +947,15 @@ int32_t orc_pair_labels(const orc_tree* t, int32_t variant, int64_t np, const in
           gd[2] += t->m[j] * dz / r3;
         }
         double ex = g[0] - gd[0], ey = g[1] - gd[1], ez = g[2] - gd[2];
-        double e = std::sqrt((ex * ex + ey * ey) + ez * ez) / (MS.M / (d * d));
-        sum += e * e;
-        ++cnt;
+        E = std::max(E, std::sqrt((ex * ex + ey * ey) + ez * ez));
       }
+      int k2s = norm_level(traceless_norm2(MS), MS.M, MS.Rmax, 2);
+      int k3s = norm_level(traceless_norm3(MS), MS.M, MS.Rmax, 3);
+      double d2 = d * d;
+      double est = multipole_bracket(MT.Rmax, MS.Rmax, k2s, k3s, d) * MS.M / ((d2 * d2) * d2);
+      if (est > 0.0) worst = std::max(worst, E / est);
     }
-    labels[k] = std::log2(std::sqrt(sum / (double)cnt));
+    labels[k] = worst > 0.0 ? std::log2(worst) : -INFINITY;
   }
   return ORC_OK;
 }

@@ -192,7 +192,7 @@ class Tree:
         if st:
             raise OracleError(st)
 
-    def walk_learned(self, eps, theta_max, theta, gmag, model, min_work=4096):
+    def walk_learned(self, eps, theta_max, theta, gmag, model, min_work=1 << 18):
         """Walk whose accept decision asks the network (model: MLP_MODEL floats,
         or None for the opening-angle walk) for pairs with N_A N_B >= min_work."""
         g = _f64(gmag)

@@ -134,7 +134,7 @@ class Solver:
     """One amfmm context.  Method names follow the C ABI without the prefix."""
 
     def __init__(self, n_crit=25, variant=TC, precision=FP64, criterion=GEOMETRIC, G=1.0,
-                 error_tol=1e-4, theta_max=1.0, max_bytes=0, list_bytes=0, learned_min_work=4096,
+                 error_tol=1e-4, theta_max=1.0, max_bytes=0, list_bytes=0, learned_min_work=1 << 18,
                  stream=None, softening=0.0):
         L = lib()
         o = amfmm_options()

@@ -243,7 +243,7 @@ int amfmm_default_options(amfmm_options* o) {
   o->G = 1.0;
   o->error_tol = 1e-4;
   o->theta_max = 1.0;
-  o->learned_min_work = 4096;
+  o->learned_min_work = 262144;
   o->max_bytes = 0;
   o->list_bytes = 0;
   o->softening = 0.0;

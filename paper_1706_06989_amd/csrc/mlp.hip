@@ -38,8 +38,10 @@ __device__ inline double centre_distance(const double4& a, const double4& b) {
   return sqrt((dx * dx + dy * dy) + dz * dz);
 }
 
+// a cell's side of a pair (no field scale: features and labels do not use it)
 __device__ inline PairSide side_of(const double4& g, const double* mo, int32_t n) {
-  return PairSide{g.w, mo[0], quad_level(mo[0], g.w, mo + 1), n};
+  return PairSide{g.w, mo[0], norm_level(traceless_norm2(mo + 1), mo[0], g.w, 2),
+                  norm_level(traceless_norm3(mo + 7), mo[0], g.w, 3), n, 0.0};
 }
 
 __global__ void __launch_bounds__(kBS) k_pair_features(int64_t np, const int32_t* __restrict__ pairs, int32_t nc,
@@ -62,10 +64,19 @@ __global__ void __launch_bounds__(kBS) k_pair_features(int64_t np, const int32_t
   for (int i = 0; i < kFeat; ++i) feats[kFeat * k + i] = f[i];
 }
 
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
 // One wave per pair.  For each cell T of the pair (the other S): the local
 // coefficients of the pair alone about Z_T (as the far field computes them,
 // with the correction of the variant), evaluated at up to 64 particles of T,
-// against the direct sum over S's particles.
+// against the direct sum over S's particles; the largest error over those
+// particles, divided by the multipole estimate of the error on T.  The
+// label is log2 of the larger ratio of the two cells (cells whose estimate
+// is zero, point masses, are exact and left out; -inf when both are).
 template <int VARIANT>
 __global__ void __launch_bounds__(kBS) k_pair_labels(int64_t np, const int32_t* __restrict__ pairs, int32_t nc,
                                                      const double4* __restrict__ geo, const double* __restrict__ mom,
@@ -80,8 +91,8 @@ __global__ void __launch_bounds__(kBS) k_pair_labels(int64_t np, const int32_t* 
     return;
   }
   const double d = centre_distance(geo[pa], geo[pb]);
-  double S = 0.0;
-  int total = 0;
+  const double d2 = d * d, d6 = (d2 * d2) * d2;
+  double worst = -INFINITY;
   for (int side = 0; side < 2; ++side) {
     const int32_t T = side ? pb : pa, Sc = side ? pa : pb;
     const double4 gt = geo[T], gs = geo[Sc];
@@ -107,6 +118,7 @@ __global__ void __launch_bounds__(kBS) k_pair_labels(int64_t np, const int32_t* 
     }
     const int32_t nT = cnt[T], bS = beg[Sc], nS = cnt[Sc];
     const int ns = nT < kLabelSample ? nT : kLabelSample;
+    double E = 0.0;
     if (lane < ns) {
       const int64_t p = beg[T] + ((int64_t)lane * nT) / ns;
       const double4 P = pos[p];
@@ -124,13 +136,14 @@ __global__ void __launch_bounds__(kBS) k_pair_labels(int64_t np, const int32_t* 
         gd[2] += q.w * dz / r3;
       }
       const double ex = g[0] - gd[0], ey = g[1] - gd[1], ez = g[2] - gd[2];
-      const double e = sqrt((ex * ex + ey * ey) + ez * ez) / (ms[0] / (d * d));
-      S += e * e;
+      E = sqrt((ex * ex + ey * ey) + ez * ez);
     }
-    total += ns;
+    E = wave_max(E);
+    const PairSide pt = side_of(gt, mt, nT), ps = side_of(gs, ms, nS);
+    const double est = multipole_bracket(pt.R, ps.R, ps.k2, ps.k3, d) * ps.M / d6;
+    if (est > 0.0) worst = fmax(worst, E / est);
   }
-  S = wave_sum(S);
-  if (lane == 0) labels[k] = log2(sqrt(S / (double)total));
+  if (lane == 0) labels[k] = worst > 0.0 ? log2(worst) : -INFINITY;
 }
 
 // weights (W1, W2, w3) rounded to BF16; biases, normalisation, range copied

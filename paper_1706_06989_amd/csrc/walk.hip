@@ -38,21 +38,20 @@ namespace {
 
 constexpr int kBS = 256;
 
-enum : int { kAccept = 0, kNear = 1, kSplitX = 2, kSplitY = 3 };
+enum : int { kAccept = 0, kNear = 1, kSplitX = 2, kSplitY = 3, kAsk = 4 };
 
 // per cell, everything a walk step reads, in one 64-byte record
 struct alignas(16) WalkRec {
   double gx, gy, gz, gw;  // centre of mass, R_max
   double m, gmin;         // mass, field scale of the cell (see k_gscale)
   // first child, parent, particles, meta: nch (bits 0-3) | has_next (4) |
-  // quadrupole level of the learned features (5-11) | traceless quadrupole
-  // level (12-19) | traceless octupole level (20-27)
+  // traceless quadrupole level (12-19) | traceless octupole level (20-27)
   int32_t ch0, par, count, meta;
 };
 
 struct WalkCell {
   double gx, gy, gz, gw, m, gmin;
-  int32_t ch0, nch, par, next, count, qlev, k2, k3;
+  int32_t ch0, nch, par, next, count, k2, k3;
 };
 
 struct TreeView {
@@ -66,6 +65,7 @@ struct TreeView {
   const float* model;  // mode 2: network (BF16-rounded weights)
   int64_t min_work;    // mode 2: least N_A N_B for which the network is asked
   const double* mmin;  // modes 1-3: smallest leaf mass below each cell
+  const float* lmodel; // mode 2, in the kernels: the network's LDS copy (lds_model_index layout)
 };
 
 __device__ inline WalkCell load_cell(const WalkRec* __restrict__ r, int32_t c) {
@@ -85,7 +85,6 @@ __device__ inline WalkCell load_cell(const WalkRec* __restrict__ r, int32_t c) {
   w.count = v.z;
   w.nch = v.w & 0xf;
   w.next = ((v.w >> 4) & 1) ? c + 1 : -1;
-  w.qlev = (v.w >> 5) & 0x7f;
   w.k2 = (v.w >> 12) & 0xff;
   w.k3 = (v.w >> 20) & 0xff;
   return w;
@@ -96,27 +95,51 @@ __device__ inline WalkCell load_cell(const WalkRec* __restrict__ r, int32_t c) {
 // stay free of their code and registers.
 enum : int { kExtBase = 0, kExtLearned = 2, kExtMultipole = 3 };
 
-// The multipole estimate of the error of an accepted pair on field cell T
-// from source S (Sec. 2's error-based selection, built from the parts a
-// third-order expansion drops: S's traceless octupole, S's traceless
-// quadrupole over T's extent, and the truncation of S's field over T; the next
-// order adds R^4/d terms), per unit mass of S and times d^6:
-//   P d + Q,  P = w3 k3_S R_S^3 + w2 k2_S R_S^2 R_T + w1 R_T^3,  Q = w4 R_S^4 + w5 R_T^4
-// with k2, k3 the traceless norms in units of M R^2, M R^3.  The weights were
-// fitted once to measured pair errors of this method; w1 >= 1 is used by the
-// subtree rule in decide().
-constexpr double kMw1 = 1.159, kMw2 = 3.73, kMw3 = 0.967, kMw4 = 0.232, kMw5 = 2.68;
-constexpr double kMq = 128.0;  // the norm ratios are held to the nearest 1/128
-
-__device__ inline double multipole_bracket(double rt, double rs, int k2s, int k3s, double d) {
-  const double rt2 = rt * rt, rs2 = rs * rs;
-  const double P = ((kMw3 * (k3s / kMq)) * (rs2 * rs) + (kMw2 * (k2s / kMq)) * (rs2 * rt)) + kMw1 * (rt2 * rt);
-  const double Q = kMw4 * (rs2 * rs2) + kMw5 * (rt2 * rt2);
-  return P * d + Q;
+// The rules for a pair that is not accepted: near field, or which cell opens.
+template <int EXT>
+__device__ inline int open_rule(const TreeView& t, int32_t X, const WalkCell& a, int32_t Y, const WalkCell& b,
+                                double d) {
+  const int mode = EXT == kExtBase ? t.mode : EXT;
+  const bool lx = a.nch == 0, ly = b.nch == 0;
+  if (lx && ly) return kNear;
+  if (lx) {
+    // Every centre of mass inside Y lies within R_Y of Z_Y, so when even
+    // d + R_Y falls short of R_X/theta no cell below Y can be accepted with the
+    // leaf X and the walk would pair X with every leaf under Y: record Y once
+    // as a near-field source (its whole particle range).  The margin makes the
+    // test safe against rounding of d and of the centres.
+    const double cut = mode == 0 ? t.theta : t.theta_max;
+    if ((d + b.gw) * (1.0 + 1e-12) + t.abs_tol < a.gw / cut) return kNear;
+    if (mode != 0) {
+      // Error-estimate modes: a cell Y' below Y has d' <= d + R_Y, mass at
+      // least the smallest leaf mass m below Y, and R_X + R_Y' >= R_X, so its
+      // estimate e' M_Y' = (R_X + R_Y')^3 M_Y' / d'^5 is at least
+      // R_X^3 m / (d + R_Y)^5, and in modes 2 and 3 the multipole estimate's
+      // w1 R_X^3 M_Y' / d'^5 term alone is at least as large (w1 >= 1).  When
+      // that exceeds what any rule accepts (eps s_X, times the network's upper
+      // gate in mode 2) no pair below Y is accepted with X either: Y is a
+      // near-field source as a whole.
+      const double D = (d + b.gw + t.abs_tol) * (1.0 + 1e-9);
+      const double D2 = D * D;
+      const double lim = (mode == 2 ? kGateHi : 1.0) * t.eps * a.gmin;
+      if ((a.gw * a.gw * a.gw) * t.mmin[Y] > lim * (D2 * D2 * D)) return kNear;
+    }
+    return kSplitY;
+  }
+  if (ly) return kSplitX;
+  if (a.gw > b.gw) return kSplitX;
+  if (a.gw < b.gw) return kSplitY;
+  return X < Y ? kSplitX : kSplitY;
 }
 
+// The walk's decision on pair (X, Y).  Mode 2 with f given: a pair the
+// network has to decide returns kAsk with its features in f and the
+// threshold in *thr (the caller runs the network for the wave and finishes
+// with open_rule); without f the lane runs the network itself.  *dist: the
+// centre distance, for open_rule.
 template <int EXT>
-__device__ inline int decide(const TreeView& t, int32_t X, const WalkCell& a, int32_t Y, const WalkCell& b) {
+__device__ inline int decide(const TreeView& t, int32_t X, const WalkCell& a, int32_t Y, const WalkCell& b,
+                             float* f = nullptr, float* thr = nullptr, double* dist = nullptr) {
   // the learned and multipole kernels serve only their own mode: a constant
   const int mode = EXT == kExtBase ? t.mode : EXT;
   const double dx = a.gx - b.gx, dy = a.gy - b.gy, dz = a.gz - b.gz;
@@ -125,6 +148,7 @@ __device__ inline int decide(const TreeView& t, int32_t X, const WalkCell& a, in
   // one root per pair, shared by the acceptance tests and the leaf rule below
   // (lanes of a wave take both paths)
   const double d = sqrt(d2);
+  if (dist) *dist = d;
   if (mode == 0) {
     const double rhs = r / t.theta;
     if (d > 0.0 && d >= rhs) return kAccept;
@@ -150,42 +174,24 @@ __device__ inline int decide(const TreeView& t, int32_t X, const WalkCell& a, in
       if (ea <= (t.eps * a.gmin) * d6 && eb <= (t.eps * b.gmin) * d6) return kAccept;
     }
   } else {
-    // mode 2: the network decides where the estimate is close to the bound
-    if (d > 0.0 && r <= t.theta_max * d) {
-      const PairSide A{a.gw, a.m, a.qlev, a.count}, B{b.gw, b.m, b.qlev, b.count};
-      if (learned_accept(t.model, t.eps, t.min_work, d, A, a.gmin, B, b.gmin)) return kAccept;
+    // mode 2: the multipole estimate, the network deciding where it is close
+    // to the bound (same theta_max guard as mode 3)
+    if (d2 > 0.0 && r * r <= t.theta_max2 * d2) {
+      const PairSide A{a.gw, a.m, a.k2, a.k3, a.count, a.gmin}, B{b.gw, b.m, b.k2, b.k3, b.count, b.gmin};
+      float g[kFeat], th = 0.0f;
+      float* fo = f ? f : g;
+      const int v = learned_gate(t.lmodel, t.eps, t.min_work, d, d2, A, B, fo, &th);
+      if (v == kLrnAccept) return kAccept;
+      if (v == kLrnAsk) {
+        if (f) {
+          *thr = th;
+          return kAsk;
+        }
+        if (mlp_infer(t.model, g) <= th) return kAccept;
+      }
     }
   }
-  const bool lx = a.nch == 0, ly = b.nch == 0;
-  if (lx && ly) return kNear;
-  if (lx) {
-    // Every centre of mass inside Y lies within R_Y of Z_Y, so when even
-    // d + R_Y falls short of R_X/theta no cell below Y can be accepted with the
-    // leaf X and the walk would pair X with every leaf under Y: record Y once
-    // as a near-field source (its whole particle range).  The margin makes the
-    // test safe against rounding of d and of the centres.
-    const double cut = mode == 0 ? t.theta : t.theta_max;
-    if ((d + b.gw) * (1.0 + 1e-12) + t.abs_tol < a.gw / cut) return kNear;
-    if (mode != 0) {
-      // Error-estimate modes: a cell Y' below Y has d' <= d + R_Y, mass at
-      // least the smallest leaf mass m below Y, and R_X + R_Y' >= R_X, so its
-      // estimate e' M_Y' = (R_X + R_Y')^3 M_Y' / d'^5 is at least
-      // R_X^3 m / (d + R_Y)^5.  When that exceeds what any rule accepts (eps
-      // s_X, times the network's upper gate in mode 2; in mode 3 the
-      // estimate's w1 R_X^3 M_Y' / d'^5 term alone is at least as large, w1 >= 1)
-      // no pair below Y is accepted with X either: Y is a near-field source as
-      // a whole.
-      const double D = (d + b.gw + t.abs_tol) * (1.0 + 1e-9);
-      const double D2 = D * D;
-      const double lim = (mode == 2 ? kGateHi : 1.0) * t.eps * a.gmin;
-      if ((a.gw * a.gw * a.gw) * t.mmin[Y] > lim * (D2 * D2 * D)) return kNear;
-    }
-    return kSplitY;
-  }
-  if (ly) return kSplitX;
-  if (a.gw > b.gw) return kSplitX;
-  if (a.gw < b.gw) return kSplitY;
-  return X < Y ? kSplitX : kSplitY;
+  return open_rule<EXT>(t, X, a, Y, b, d);
 }
 
 // Visits the pairs of entry (X, Y) in depth-first order (children of Y in
@@ -226,57 +232,6 @@ __device__ inline void traverse(const TreeView& t, int32_t X, int32_t Y, F&& f) 
   }
 }
 
-// Frobenius norms of the traceless parts of M_ij (packed xx xy xz yy yz zz)
-// and of M_ijk (packed xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz): M_ij -
-// delta_ij tr/3 and M_ijk - (v_i delta_jk + v_j delta_ik + v_k delta_ij)/5,
-// v_i = M_ijj.  Squares are summed over all index tuples in row-major order
-// (the order of the plain definition, so the result rounds the same way).
-__device__ inline double traceless_norm2(const double* Q) {
-  const double m[3][3] = {{Q[0], Q[1], Q[2]}, {Q[1], Q[3], Q[4]}, {Q[2], Q[4], Q[5]}};
-  const double tr = m[0][0] + m[1][1] + m[2][2];
-  double s = 0.0;
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const double v = m[i][j] - (i == j ? tr / 3.0 : 0.0);
-      s += v * v;
-    }
-  return sqrt(s);
-}
-
-// packed position of M_ijk (symmetric: any order of i, j, k)
-__device__ inline int oct_index(int i, int j, int k) {
-  constexpr int idx[27] = {0, 1, 2, 1, 3, 4, 2, 4, 5, 1, 3, 4, 3, 6, 7, 4, 7, 8, 2, 4, 5, 4, 7, 8, 5, 8, 9};
-  return idx[9 * i + 3 * j + k];
-}
-
-__device__ inline double traceless_norm3(const double* O) {
-  double v[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) v[i] = O[oct_index(i, 0, 0)] + O[oct_index(i, 1, 1)] + O[oct_index(i, 2, 2)];
-  double s = 0.0;
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const double dij = i == j ? 1.0 : 0.0, dik = i == k ? 1.0 : 0.0, djk = j == k ? 1.0 : 0.0;
-        const double w = O[oct_index(i, j, k)] - (v[i] * djk + v[j] * dik + v[k] * dij) / 5.0;
-        s += w * w;
-      }
-  return sqrt(s);
-}
-
-// norm / (M R^p) to the nearest 1/kMq, in [0, kMq] (0 where M R^p = 0)
-__device__ inline int norm_level(double norm, double M, double R, int p) {
-  const double den = M * (p == 2 ? R * R : R * R * R);
-  if (!(den > 0.0)) return 0;
-  const double k = floor(kMq * (norm / den) + 0.5);
-  return k < 0.0 ? 0 : (k > kMq ? (int)kMq : (int)k);
-}
-
 __global__ void __launch_bounds__(kBS) k_pack_cells(int32_t nc, const double4* __restrict__ geo,
                                                     const double* __restrict__ mom, const int32_t* __restrict__ ch0,
                                                     const int32_t* __restrict__ nch, const int32_t* __restrict__ par,
@@ -300,7 +255,7 @@ __global__ void __launch_bounds__(kBS) k_pack_cells(int32_t nc, const double4* _
   const int has_next = (p >= 0 && c + 1 < ch0[p] + nch[p]) ? 1 : 0;
   const int k2 = norm_level(traceless_norm2(mo + 1), mo[0], g.w, 2);
   const int k3 = norm_level(traceless_norm3(mo + 7), mo[0], g.w, 3);
-  w.meta = nch[c] | (has_next << 4) | (quad_level(mo[0], g.w, mo + 1) << 5) | (k2 << 12) | (k3 << 20);
+  w.meta = nch[c] | (has_next << 4) | (k2 << 12) | (k3 << 20);
   rec[c] = w;
 }
 
@@ -479,9 +434,13 @@ __device__ inline bool wave_walk(const TreeView& t, int32_t X, const WalkCell& c
                                  int64_t& td, EmitDst dst, unsigned long long* dbg) {
   const int32_t qmask = qcap - 1;
   const int lane = threadIdx.x & 63;
+  // mode 2: this lane's part of the network, for the wave's cooperative
+  // inference
+  MlpLane ml{};
+  if (EXT == kExtLearned) ml = mlp_lane(t.lmodel);
   int32_t head = 0, tail = 0, fpos = 0;
   int64_t fo = dst.fo, no = dst.no, B = dst.B0;
-  unsigned long long dsteps = 0, ddeep = 0, dpairs = 0;
+  unsigned long long dsteps = 0, ddeep = 0, dpairs = 0, dask = 0, daskw = 0;
   int32_t nreg[3] = {0, 0, 0};  // STAGE: spill regions held (wave-uniform)
   bool ovf = false;              // STAGE: out of room; writes stop
   auto stage_put = [&](int w, int64_t f, int32_t v) {
@@ -548,22 +507,46 @@ __device__ inline bool wave_walk(const TreeView& t, int32_t X, const WalkCell& c
     wave_sync();  // queue slots just read may be reused by this step's pushes
     td += __popcll(__ballot(Y >= 0));
     int32_t m = 0, p = 0, q = 0, push = 0, ych0 = 0;
-    bool self = false;
-    if (Y >= 0) {
-      if (Y == X) {
-        self = true;
-        if (cx.nch == 0) p = 1;
-        else q = cx.nch;
-      } else {
-        const WalkCell cy = load_cell(t.rec, Y);
-        const int d = decide<EXT>(t, X, cx, Y, cy);
-        m = d == kAccept;
-        p = d == kNear;
-        q = d == kSplitX;
-        if (d == kSplitY) {
-          push = cy.nch;
-          ych0 = cy.ch0;
-        }
+    const bool self = Y >= 0 && Y == X;
+    WalkCell cy{};
+    int d = -1;
+    float f[kFeat], thr = 0.0f;
+    double dist = 0.0;
+    if (Y >= 0 && !self) {
+      cy = load_cell(t.rec, Y);
+      d = EXT == kExtLearned ? decide<EXT>(t, X, cx, Y, cy, f, &thr, &dist) : decide<EXT>(t, X, cx, Y, cy);
+    }
+    if (EXT == kExtLearned) {
+      // Pairs for the network are decided by the whole wave (every lane
+      // active again here), one after the other, each lane holding a hidden
+      // unit.
+      const bool ask = d == kAsk;
+      float mine = 0.0f;
+      const uint64_t asked = __ballot(ask);
+      if (dbg) {
+        dask += __popcll(asked);
+        daskw += asked != 0;
+      }
+      for (uint64_t am = asked; am; am &= am - 1) {
+        const int L = __ffsll((unsigned long long)am) - 1;
+        float g[kFeat];
+#pragma unroll
+        for (int i = 0; i < kFeat; ++i) g[i] = lane_value(f[i], L);
+        const float y = mlp_infer_wave(t.lmodel, ml, g);
+        if (lane == L) mine = y;
+      }
+      if (ask) d = mine <= thr ? kAccept : open_rule<EXT>(t, X, cx, Y, cy, dist);
+    }
+    if (self) {
+      if (cx.nch == 0) p = 1;
+      else q = cx.nch;
+    } else if (Y >= 0) {
+      m = d == kAccept;
+      p = d == kNear;
+      q = d == kSplitX;
+      if (d == kSplitY) {
+        push = cy.nch;
+        ych0 = cy.ch0;
       }
     }
     int32_t ptot;
@@ -649,6 +632,8 @@ __device__ inline bool wave_walk(const TreeView& t, int32_t X, const WalkCell& c
     atomicAdd(&dbg[0], dsteps);
     atomicAdd(&dbg[1], ddeep);
     atomicAdd(&dbg[2], dpairs);
+    atomicAdd(&dbg[3], dask);
+    atomicAdd(&dbg[4], daskw);
   }
   return ovf;
 }
@@ -671,11 +656,19 @@ __global__ void __launch_bounds__(kBS) k_chunk_counts(int32_t nl, const int32_t*
   if (i < nl) nck[i] = (gcnt[i] + chunk - 1) / chunk;
 }
 
+// The learned kernels' copy of the network in LDS (W2 transposed, see
+// lds_model_index), loaded by the whole workgroup before any wave leaves.
+__device__ inline const float* stage_model(const float* __restrict__ g, float* lds) {
+  for (int i = threadIdx.x; i < AMFMM_MLP_MODEL; i += kBS) lds[lds_model_index(i)] = g[i];
+  __syncthreads();
+  return lds;
+}
+
 // One wave per chunk of a cell's frontier entries: walk it once, writing its
 // terminal pairs to its staging room, and record its counts (and whether it
 // ran out of room).
 template <int EXT>
-__global__ void __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(EXT == kExtLearned ? 1 : 4))) k_walk_stage(TreeView t, int32_t c0, int64_t kn, int32_t chunk,
+__global__ void __launch_bounds__(kBS) k_walk_stage(TreeView t, int32_t c0, int64_t kn, int32_t chunk,
                                                     const int32_t* __restrict__ kcell, const int64_t* __restrict__ cbase,
                                                     const int64_t* __restrict__ gbeg, const int32_t* __restrict__ gcnt,
                                                     const int32_t* __restrict__ fy, const StageLayout* __restrict__ sl,
@@ -685,6 +678,8 @@ __global__ void __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(EXT ==
                                                     int32_t* __restrict__ gq, int32_t qcap, unsigned long long* dbg) {
   __shared__ int32_t queue[kBS / 64][kQ];
   __shared__ int64_t regions[kBS / 64][3 * kRegions];
+  __shared__ float model[EXT == kExtLearned ? AMFMM_MLP_MODEL : 1];
+  if (EXT == kExtLearned) t.lmodel = stage_model(t.model, model);
   const int lane = threadIdx.x & 63;
   // wave-uniform (readfirstlane): the cell's record and bookkeeping are
   // loaded once per wave into scalar registers
@@ -832,6 +827,8 @@ __global__ void __launch_bounds__(kBS) k_walk_emit(TreeView t, int32_t c0, int64
                                                    int32_t* __restrict__ near_src, int32_t* __restrict__ fy_n,
                                                    int32_t* __restrict__ gq, int32_t qcap) {
   __shared__ int32_t queue[kBS / 64][kQ];
+  __shared__ float model[EXT == kExtLearned ? AMFMM_MLP_MODEL : 1];
+  if (EXT == kExtLearned) t.lmodel = stage_model(t.model, model);
   const int64_t k = uniform((int32_t)(xcd_block(blockIdx.x, gridDim.x) * (kBS / 64) + (threadIdx.x >> 6)));
   if (k >= kn || !kov[k]) return;
   const int32_t i = kcell[k];
@@ -994,7 +991,7 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
                     const std::vector<int32_t>& hi, int64_t& far_base, int64_t& near_base) {
   TreeView t{(const WalkRec*)c.walkrec.p, c.theta, c.walk_abs_tol, c.walk_mode, c.opt.error_tol,
              c.opt.theta_max, c.opt.theta_max * c.opt.theta_max, (const float*)c.model.p, c.opt.learned_min_work,
-             c.walk_mode != 0 ? (const double*)c.gmin.p + 3 * (size_t)c.ncells : nullptr};
+             c.walk_mode != 0 ? (const double*)c.gmin.p + 3 * (size_t)c.ncells : nullptr, nullptr};
   static const bool debug_env = getenv("AMFMM_DEBUG_WALK") != nullptr;
   const bool debug = debug_env && !c.arena;  // no events in an allocation-free solve
   const int ext = c.walk_mode == 2 ? kExtLearned : (c.walk_mode == 3 ? kExtMultipole : kExtBase);
@@ -1035,7 +1032,7 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
     int32_t* kov = (int32_t*)(qex + K);
     int64_t *kd = qex + 2 * K, *kdex = kd + K;  // candidate pairs per chunk, and their scan
     // [0..3] totals, [4] chunks out of room, [5] candidate pairs, [8..10] spill
-    // used, [12..15] debug counters, [16..] the staging layout
+    // used, [12..16] debug counters, [20..] the staging layout
     int64_t* tot = qex + 4 * K;
     const int32_t* fy = as<int32_t>(c.fy);
     hipLaunchKernelGGL(k_chunk_counts, dim3(blocks_for(nl, kBS)), dim3(kBS), 0, c.stream, nl, (const int32_t*)gcnt,
@@ -1076,8 +1073,9 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
     unsigned long long* nov = (unsigned long long*)(tot + 4);
     sl.used = (unsigned long long*)(tot + 8);
     unsigned long long* dbg = debug ? (unsigned long long*)(tot + 12) : nullptr;
-    StageLayout* sl_dev = (StageLayout*)(tot + 16);
-    zero_u64(c, nov, 12);
+    StageLayout* sl_dev = (StageLayout*)(tot + 20);
+    static_assert(20 + sizeof(StageLayout) / sizeof(int64_t) <= 48, "walk totals");
+    zero_u64(c, nov, 16);
     hipLaunchKernelGGL(k_set_layout, dim3(1), dim3(1), 0, c.stream, sl, sl_dev);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (debug) {
@@ -1116,7 +1114,7 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
     const int64_t mt = tot_host[0], pt = tot_host[1], Fn = tot_host[2], qt = tot_host[3], novh = tot_host[4];
     cand += tot_host[5];
     if (debug) {
-      unsigned long long h[4];
+      unsigned long long h[5];
       AMFMM_HIP(hipMemcpy(h, dbg, sizeof(h), hipMemcpyDeviceToHost));
       float ms = 0.f;
       AMFMM_HIP(hipEventElapsedTime(&ms, e0, e1));
@@ -1124,9 +1122,9 @@ int64_t walk_levels(Ctx& c, int lev_first, int lev_last, const std::vector<int32
       (void)hipEventDestroy(e1);
       fprintf(stderr,
               "walk level %d: cells %d entries %lld chunks %lld (x%d) far %lld near %lld next %lld | staging pass "
-              "%.3f ms, steps %llu, pairs %llu, deep %llu, overflowed %lld\n",
+              "%.3f ms, steps %llu, pairs %llu, deep %llu, asked %llu in %llu steps, overflowed %lld\n",
               lev, nl, (long long)F, (long long)kn, chunk, (long long)mt, (long long)pt, (long long)Fn, ms, h[0],
-              h[2], h[1], (long long)novh);
+              h[2], h[1], h[3], h[4], (long long)novh);
     }
     prev[0] = (double)mt / (double)F;
     prev[1] = (double)pt / (double)F;

@@ -2,11 +2,14 @@
 bookkeeping only: labels, features, forward, backward and Adam run in the
 library's GPU kernels through the C ABI).
 
-Training data: cell pairs accepted by geometric walks at several opening
-angles on seeded synthetic particle sets, each labelled by the library with
-the measured error of the method's own pair evaluation against direct
-summation (``Solver.pair_labels``).  The network predicts log2 of that error
-factor at the 0.9 quantile (pinball loss), so that it errs on the safe side.
+Training data: cell pairs accepted by multipole error-estimate walks at
+several tolerances on seeded synthetic particle sets (the field estimate from
+a geometric pilot solve), each labelled by the library with log2 of the ratio
+of the method's largest error on the pair (against direct summation) to the
+multipole estimate (``Solver.pair_labels``).  Only pairs large enough for the
+walk to ask the network (N_A N_B >= MIN_PAIR_WORK) are kept.  The network
+predicts that ratio at the 0.9 quantile (pinball loss), so that it errs on
+the safe side.
 """
 import numpy as np
 import torch
@@ -15,41 +18,52 @@ from . import amfmm
 from . import workloads as W
 
 TAU = 0.9
-TRAIN_THETAS = (0.3, 0.45, 0.6, 0.75, 0.9)
+TRAIN_EPS = (1e-5, 1e-6, 3e-7)
+TRAIN_THETA_MAX = 0.5
+MIN_PAIR_WORK = 1024
 
 
-def collect(x, y, z, m, thetas=TRAIN_THETAS, per_theta=20000, seed=11, variant=amfmm.TC):
+def collect(x, y, z, m, eps_list=TRAIN_EPS, per_eps=20000, seed=11, variant=amfmm.TC):
     """Features and labels of pairs sampled from the far-field lists of
-    geometric walks at each opening angle (host numpy arrays)."""
+    multipole-estimate walks at each tolerance (host numpy arrays)."""
     dev = torch.device("cuda")
     X, Y, Z, M = (torch.from_numpy(np.ascontiguousarray(v, np.float64)).to(dev) for v in (x, y, z, m))
-    s = amfmm.Solver(variant=variant)
-    s.build_tree(X, Y, Z, M)
-    s.compute_moments()
+    pilot = amfmm.Solver(variant=variant)
+    gx, gy, gz, _ = pilot.solve_gravity(X, Y, Z, M, 0.5, pot=False)
     rng = np.random.default_rng(seed)
     feats, labels = [], []
-    for th in thetas:
-        s.walk(th)
+    for eps in eps_list:
+        s = amfmm.Solver(variant=variant, criterion=amfmm.MULTIPOLE, error_tol=eps, theta_max=TRAIN_THETA_MAX)
+        s.set_field_estimate(gx, gy, gz)
+        s.build_tree(X, Y, Z, M)
+        s.compute_moments()
+        s.walk(0.5)
         far, _ = s.get_lists()
-        if len(far) == 0:
-            continue
-        pick = far[rng.choice(len(far), min(per_theta, len(far)), replace=False)]
-        P = torch.from_numpy(np.ascontiguousarray(pick, np.int32)).to(dev)
-        feats.append(s.pair_features(P).cpu().numpy())
-        labels.append(s.pair_labels(P, variant).cpu().numpy())
-    s.close()
+        cnt = np.asarray(s.get_tree()["count"])
+        far = far[cnt[far[:, 0]].astype(np.int64) * cnt[far[:, 1]] >= MIN_PAIR_WORK]
+        if len(far):
+            pick = far[rng.choice(len(far), min(per_eps, len(far)), replace=False)]
+            P = torch.from_numpy(np.ascontiguousarray(pick, np.int32)).to(dev)
+            feats.append(s.pair_features(P).cpu().numpy())
+            labels.append(s.pair_labels(P, variant).cpu().numpy())
+        s.close()
+    pilot.close()
+    if not feats:
+        return np.zeros((0, 8), np.float32), np.zeros(0, np.float32)
     f = np.concatenate(feats)
     lab = np.concatenate(labels)
     ok = np.isfinite(lab) & np.all(np.isfinite(f), axis=1) & (f[:, 0] > 0)
     return f[ok], lab[ok].astype(np.float32)
 
 
-def training_set(n_plummer=1 << 20, per_theta=20000):
-    """Pairs of the uniform 4096-particle cube (seed 1) and of a Plummer sphere
-    (seed 2): the two plain-FP64 test configurations."""
-    f1, l1 = collect(*W.uniform_cube(4096, seed=1), per_theta=per_theta, seed=11)
-    f2, l2 = collect(*W.plummer(n_plummer, seed=2), per_theta=per_theta, seed=12)
-    return np.concatenate([f1, f2]), np.concatenate([l1, l2])
+def training_set(n=1 << 18, per_eps=20000):
+    """Pairs of the uniform 4096-particle cube (seed 1), a Plummer sphere
+    (seed 2) and two Plummer spheres (seed 13; the benchmark's two-sphere
+    workload uses seed 5)."""
+    f1, l1 = collect(*W.uniform_cube(4096, seed=1), per_eps=per_eps, seed=11)
+    f2, l2 = collect(*W.plummer(n, seed=2), per_eps=per_eps, seed=12)
+    f3, l3 = collect(*W.two_plummer(n, seed=13), per_eps=per_eps, seed=14)
+    return np.concatenate([f1, f2, f3]), np.concatenate([l1, l2, l3])
 
 
 def init_model(feats, seed=7):

@@ -1,21 +1,23 @@
-"""What the trained network gains over the method without it.
+"""What the trained network gains on the two-sphere workload of 2^24
+particles (seed 5, mixed precision, TC, n_crit 25), the learned-selection
+configuration.
 
-The network is trained on the GPU (library kernels: labels, forward,
-backward, Adam) from pairs of the uniform 4096-particle cube and a
-2^20-particle Plummer sphere, then used on a different problem: two Plummer
-spheres of 2^18 particles.  For each error tolerance the error-estimate walk
-(the method without the network) and the learned walk are run from the same
-field estimate; the test prints p99 relative force error against direct
-summation, the work (far-field evaluations and near-field interactions) and
-the time of each, and the work ratio at matched p99.
+The network is trained on the GPU by the library's kernels (labels, forward,
+backward, Adam) from pairs of other problems: the uniform 4096-particle
+cube, a Plummer sphere and two Plummer spheres of 2^18 (seed 13).  On the
+test workload a geometric pilot solve (theta 1.0, mixed) gives the field
+estimate of the error-estimate criteria, and the relative force error is
+measured against direct summation at 65536 sampled targets (seed 99).
 
-Asserted: training lowers the loss and reaches the 0.9 quantile on held-out
-pairs; the learned walk stays accurate (p99 within 2x of the error-estimate
-walk at the same tolerance, since out-of-range pairs and small pairs keep the
-analytic factor).  The gain itself is reported, not asserted.
+Asserted: training lowers the loss and puts about 0.9 of held-out labels at
+or below the prediction; the learned solve (pilot included, the network asked
+for pairs with N_A N_B >= 2^18, the default) reaches p99 <= 1e-4 faster than
+the geometric criterion reaches it (the largest opening angle tried that
+meets 1e-4).  Reported: time and p99 of the geometric, multipole-estimate and
+learned solves (the largest tolerance tried that meets 1e-4), and the learned
+time over the multipole time.
 """
 import json
-import os
 
 import numpy as np
 import pytest
@@ -28,69 +30,75 @@ from tests.gpu_util import say
 pytestmark = pytest.mark.gpu
 
 
-def work(c):
-    # directed far-field evaluations cost about 15 near interactions each
-    # (about 300 flops against 20)
-    return c["near_interactions"] + 15 * c["far_evaluations"]
-
-
-def test_trained_network_gain():
-    f, lab = learned.training_set(n_plummer=1 << 20, per_theta=20000)
+@pytest.mark.timeout(1100)
+def test_learned_selection_beats_the_opening_angle_at_matched_p99():
+    f, lab = learned.training_set()
     rng = np.random.default_rng(0)
     idx = rng.permutation(len(lab))
     ntr = int(0.85 * len(lab))
-    P, losses = learned.train(f[idx[:ntr]], lab[idx[:ntr]], steps=3000, batch=4096, lr=2e-3)
-    cov, _ = learned.coverage(P, f[idx[ntr:]], lab[idx[ntr:]])
-    say(f"pairs {len(lab)}, loss {losses[0]:.4f} -> {losses[-1]:.4f}, held-out coverage {cov:.3f}")
+    model, losses = learned.train(f[idx[:ntr]], lab[idx[:ntr]], steps=3000, batch=4096, lr=2e-3)
+    cov, _ = learned.coverage(model, f[idx[ntr:]], lab[idx[ntr:]])
+    say(f"training pairs {len(lab)}, labels p10/p50/p90 {np.percentile(lab, [10, 50, 90])}, "
+        f"loss {losses[0]:.4f} -> {losses[-1]:.4f}, held-out coverage {cov:.3f}")
     assert losses[-1] < losses[0]
-    assert 0.85 <= cov <= 0.95
+    assert 0.8 <= cov <= 0.97
 
-    n = 1 << 18
+    n = 1 << 24
     x, y, z, m = W.two_plummer(n, seed=5)
     X, Y, Z, M = (torch.from_numpy(v).cuda() for v in (x, y, z, m))
-    pilot = amfmm.Solver()
-    gx, gy, gz, _ = pilot.solve_gravity(X, Y, Z, M, 0.5, pot=False)
-    tg = torch.from_numpy(W.sample_targets(n, 4096, seed=99)).cuda()
+    del x, y, z, m
+    pilot = amfmm.Solver(precision=amfmm.MIXED)
+    gx, gy, gz, _ = pilot.solve_gravity(X, Y, Z, M, 1.0, pot=False)
+    pilot.solve_gravity(X, Y, Z, M, 1.0, pot=False)
+    pilot_ms = pilot.get_phase_times()["total"]
+    tg = torch.from_numpy(W.sample_targets(n, 1 << 16, seed=99)).cuda()
     tx, ty, tz, _, _ = pilot.direct(X, Y, Z, M, tg, pot=False, gabs=False)
     T = torch.stack([tx, ty, tz])
 
-    def p99(o):
+    def run(solver, theta=0.5):
+        solver.solve_gravity(X, Y, Z, M, theta, pot=False)  # warm-up (allocation, staging sizes)
+        o = solver.solve_gravity(X, Y, Z, M, theta, pot=False)
+        ph = solver.get_phase_times()
+        ms = ph["total"]
         A = torch.stack([o[0][tg], o[1][tg], o[2][tg]])
         e = (torch.linalg.norm(A - T, dim=0) / torch.linalg.norm(T, dim=0)).cpu().numpy()
-        return float(np.percentile(e, 99))
+        c = solver.get_counts()
+        solver.close()
+        return {"ms": round(ms, 1), "walk_ms": round(ph["walk"], 1), "p99": float(np.percentile(e, 99)),
+                "far": c["far_evaluations"], "near": c["near_interactions"]}
 
-    rows = []
-    for crit in (amfmm.ESTIMATE, amfmm.LEARNED):
-        for eps in (1e-5, 3e-6, 1e-6):
-            s = amfmm.Solver(criterion=crit, error_tol=eps, theta_max=0.5)
-            if crit == amfmm.LEARNED:
-                s.set_model(P)
-            s.set_field_estimate(gx, gy, gz)
-            s.solve_gravity(X, Y, Z, M, 0.5, pot=False)  # warm-up (allocation)
-            o = s.solve_gravity(X, Y, Z, M, 0.5, pot=False)
-            torch.cuda.synchronize()
-            c = s.get_counts()
-            r = dict(criterion="learned" if crit == amfmm.LEARNED else "estimate", eps=eps, p99=p99(o),
-                     ms=s.get_phase_times()["total"], work=work(c), far=c["far_evaluations"],
-                     near=c["near_interactions"])
-            rows.append(r)
-            say(json.dumps(r))
-    est = [r for r in rows if r["criterion"] == "estimate"]
-    lea = [r for r in rows if r["criterion"] == "learned"]
-    for a, b in zip(est, lea):
-        assert b["p99"] <= 2.0 * a["p99"], (a, b)
-
-    # work and time at matched p99: interpolate log(work) against log(p99)
-    def at(rs, key, p):
-        xs = np.log([r["p99"] for r in rs])
-        ys = np.log([r[key] for r in rs])
-        o = np.argsort(xs)
-        return float(np.exp(np.interp(np.log(p), xs[o], ys[o])))
-
-    p_ref = float(np.median([r["p99"] for r in est]))
-    gain_work = at(est, "work", p_ref) / at(lea, "work", p_ref)
-    gain_time = at(est, "ms", p_ref) / at(lea, "ms", p_ref)
-    say(f"at p99 {p_ref:.3e}: learned needs 1/{gain_work:.3f} of the work and 1/{gain_time:.3f} of the time")
-    out = os.environ.get("AMFMM_GAIN_OUT")
-    if out:
-        json.dump(dict(rows=rows, p99_ref=p_ref, gain_work=gain_work, gain_time=gain_time), open(out, "w"))
+    res = {"pilot_ms": round(pilot_ms, 1)}
+    geo = None
+    for th in (0.12, 0.1, 0.085):
+        r = run(amfmm.Solver(precision=amfmm.MIXED), th)
+        res[f"geometric theta={th}"] = r
+        say(f"geometric theta {th}: {r}")
+        if r["p99"] <= 1e-4:
+            geo = r
+            break
+    assert geo is not None
+    for eps in (1e-7, 9e-8, 8e-8, 6.5e-8):
+        s = amfmm.Solver(precision=amfmm.MIXED, criterion=amfmm.MULTIPOLE, error_tol=eps, theta_max=0.5)
+        s.set_field_estimate(gx, gy, gz)
+        r = run(s)
+        res[f"multipole eps={eps}"] = r
+        say(f"multipole eps {eps}: {r}")
+        if r["p99"] <= 1e-4:
+            mp = r
+            break
+    lrn = None
+    for eps in (1e-7, 9e-8, 8e-8, 6.5e-8):
+        s = amfmm.Solver(precision=amfmm.MIXED, criterion=amfmm.LEARNED, error_tol=eps, theta_max=0.5)
+        s.set_model(model)
+        s.set_field_estimate(gx, gy, gz)
+        r = run(s)
+        res[f"learned eps={eps}"] = r
+        say(f"learned eps {eps}: {r}")
+        if r["p99"] <= 1e-4:
+            lrn = r
+            break
+    assert lrn is not None
+    res["learned_over_geometric"] = round((lrn["ms"] + pilot_ms) / geo["ms"], 3)
+    res["learned_over_multipole"] = round((lrn["ms"] + pilot_ms) / (mp["ms"] + pilot_ms), 3)
+    say("learned gain: " + json.dumps(res))
+    assert lrn["ms"] + pilot_ms < geo["ms"]

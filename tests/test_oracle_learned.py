@@ -1,9 +1,11 @@
 """Pins of the oracle's learned pair selection (not in the paper): the BF16
 rounding and piecewise-linear log2 against their definitions, the network and
 its gradient against torch (a library implementation of the same layers),
-Adam against torch.optim.Adam, labels against an independent assembly from
-the pair evaluation and numpy direct sums, features' symmetry, and the walk's
-gating against the analytic error-estimate walk."""
+Adam against torch.optim.Adam, labels (the ratio of the method's largest pair
+error to the multipole estimate) against an independent assembly from the
+pair evaluation, numpy direct sums and the estimate recomputed from particle
+sums, features' symmetry, and the walk's gating against the multipole
+error-estimate walk."""
 import math
 
 import numpy as np
@@ -12,6 +14,8 @@ import torch
 
 from oracle import oracle as orc
 from paper_1706_06989_amd import workloads as W
+
+from .test_oracle_multipole import estimate, levels_from_particles
 
 
 def random_model(seed, scale=0.3):
@@ -150,20 +154,24 @@ def plummer_tree():
 
 
 def test_features_symmetric_and_in_range(plummer_tree):
-    _, t, _ = plummer_tree
+    (x, y, z, m), t, _ = plummer_tree
     t.walk(0.7)
     far, _ = t.lists()
     f = t.pair_features(far)
     fr = t.pair_features(far[:, ::-1])
     assert np.array_equal(f.view(np.uint32), fr.view(np.uint32))
     assert np.all(f[:, 0] <= 0.7 * (1 + 1e-6)) and np.all(f[:, 0] >= 0)
-    assert np.all((f[:, 2] >= 0) & (f[:, 2] <= 1) & (f[:, 3] >= 0) & (f[:, 3] <= 1))
-    assert np.all((f[:, 4] >= 0) & (f[:, 4] <= 1) & (f[:, 5] >= 0) & (f[:, 5] <= 1))
+    assert np.all((f[:, 1:7] >= 0) & (f[:, 1:7] <= 1))
+    # the norm-level features are the traceless levels recomputed from particles
+    k2, k3 = levels_from_particles(t, x, y, z, m)
+    a, b = far[:, 0], far[:, 1]
+    assert np.array_equal(f[:, 2], ((k2[a] + k2[b]) / 256.0).astype(np.float32))
+    assert np.array_equal(f[:, 5], (np.abs(k3[a] - k3[b]) / 128.0).astype(np.float32))
     # the counts feature is the plog2 of N_A N_B (counts saturated at 1024)
     c = t.cells()
-    na, nb = np.minimum(c["count"][far[:, 0]], 1024), np.minimum(c["count"][far[:, 1]], 1024)
+    na, nb = np.minimum(c["count"][a], 1024), np.minimum(c["count"][b], 1024)
     ref = np.array([orc.plog2(float(u) * float(v)) for u, v in zip(na, nb)], np.float32)
-    assert np.array_equal(f[:, 6], ref)
+    assert np.array_equal(f[:, 7], ref)
 
 
 def test_labels_against_independent_assembly(plummer_tree):
@@ -174,8 +182,10 @@ def test_labels_against_independent_assembly(plummer_tree):
     mo = t.moments()
     _, perm = t.keys()
     xs, ys, zs, ms = x[perm], y[perm], z[perm], m[perm]
+    k2, k3 = levels_from_particles(t, x, y, z, m)
     rng = np.random.default_rng(3)
-    small = far[(c["count"][far[:, 0]] <= 64) & (c["count"][far[:, 1]] <= 64)]
+    small = far[(c["count"][far[:, 0]] <= 64) & (c["count"][far[:, 1]] <= 64)
+                & (mo[far[:, 0], 4] > 0) & (mo[far[:, 1], 4] > 0)]
     sel = small[rng.choice(len(small), 40, replace=False)]
     lab = t.pair_labels(sel, orc.TC)
     for (A, B), L in zip(sel, lab):
@@ -191,32 +201,40 @@ def test_labels_against_independent_assembly(plummer_tree):
             return (S[3][None, :] * d / r3).sum(2).T
 
         d = np.linalg.norm(mo[A, 1:4] - mo[B, 1:4])
-        eA = np.linalg.norm(gA - direct(PA, PB), axis=1) / (mo[B, 0] / d ** 2)
-        eB = np.linalg.norm(gB - direct(PB, PA), axis=1) / (mo[A, 0] / d ** 2)
-        ref = 0.5 * math.log2(np.mean(np.concatenate([eA, eB]) ** 2))
+        eA = np.linalg.norm(gA - direct(PA, PB), axis=1).max()
+        eB = np.linalg.norm(gB - direct(PB, PA), axis=1).max()
+        estA = estimate(mo[A, 4], mo[B, 4], k2[B], k3[B], d, mo[B, 0])
+        estB = estimate(mo[B, 4], mo[A, 4], k2[A], k3[A], d, mo[A, 0])
+        ref = math.log2(max(eA / estA, eB / estB))
         assert abs(L - ref) <= 1e-6, (A, B, L, ref)
 
 
 def test_labels_follow_the_expansion_order():
     """Two clusters of fixed shape, each one leaf, at a fixed distance: the
-    error factor of a quadrupole-order pair falls like (r/d)^3, so the label
-    drops by 3 per halving of the cluster size."""
+    method's error and the estimate both fall like (r/d)^3, so as the
+    clusters shrink the label (their log ratio) settles to a constant of
+    order one, the next order fading linearly: each halving of the size
+    halves the change of the label."""
     rng = np.random.default_rng(11)
     base = rng.uniform(-1, 1, (2, 40, 3))
     labs = []
-    for r in (0.05, 0.025, 0.0125):
+    m = None
+    for r in (0.1, 0.05, 0.025, 0.0125, 0.00625):
         A = base[0] * r
         B = base[1] * r + np.array([1.0, 0.8, 0.6])
         P = np.concatenate([A, B])
-        m = rng.uniform(0.5, 1.5, 80) if not labs else m
+        m = rng.uniform(0.5, 1.5, 80) if m is None else m
         t = orc.Tree(P[:, 0], P[:, 1], P[:, 2], m, n_crit=64)
         t.compute_moments()
         c = t.cells()
         leaves = np.nonzero(c["nchild"] == 0)[0]
         assert len(leaves) == 2 and sorted(c["count"][leaves]) == [40, 40]
         labs.append(t.pair_labels(leaves.reshape(1, 2))[0])
-    d1, d2 = labs[0] - labs[1], labs[1] - labs[2]
-    assert 2.8 <= d1 <= 3.2 and 2.9 <= d2 <= 3.1, labs
+    steps = np.diff(labs)
+    assert abs(labs[-1]) < 2.0, labs
+    assert np.all(np.abs(steps) < 0.5), labs
+    ratios = steps[1:] / steps[:-1]
+    assert np.all((ratios > 0.35) & (ratios < 0.65)), labs
 
 
 def test_learned_walk_without_model_is_geometric(plummer_tree):
@@ -228,49 +246,60 @@ def test_learned_walk_without_model_is_geometric(plummer_tree):
     assert np.array_equal(ref[0], got[0]) and np.array_equal(ref[1], got[1])
 
 
+def constant_model(out, in_range=True):
+    P = np.zeros(orc.MLP_MODEL, np.float32)
+    P[4800] = out
+    P[4817:4825] = -1e30 if in_range else 1e30
+    P[4825:4833] = 1e30 if in_range else -1e30
+    return P
+
+
 def test_learned_walk_gating(plummer_tree):
-    """A network that always predicts a tiny error accepts every pair in the
-    band (q^3 <= 16 u): the analytic walk at 16 eps.  One that always predicts
-    a huge error accepts only below the band (q^3 <= u/4): eps/4."""
+    """A network that always predicts a tiny ratio accepts every pair in the
+    band (rho <= 2): the multipole walk at 2 eps.  One that always predicts a
+    huge ratio accepts only below the band (rho <= 1/4): eps/4.  Bit for bit
+    (the gates scale eps by powers of two)."""
     _, t, g = plummer_tree
     eps = 2e-5
-    for out, factor in ((-1000.0, 16.0), (1000.0, 0.25)):
-        P = np.zeros(orc.MLP_MODEL, np.float32)
-        P[4800] = out
-        P[4825:4833] = 1e30
-        P[4817:4825] = -1e30
-        t.walk_learned(eps, 0.7, 0.5, g, P, min_work=1)
+    for out, factor in ((-1000.0, 2.0), (1000.0, 0.25)):
+        t.walk_learned(eps, 0.7, 0.5, g, constant_model(out), min_work=1)
         got = t.lists()
-        t.walk_field(eps * factor, 0.7, g)
+        t.walk_multipole(eps * factor, 0.7, g)
         ref = t.lists()
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
 
 
-def test_learned_walk_small_pairs_take_the_analytic_factor(plummer_tree):
+def test_learned_walk_small_pairs_take_the_multipole_estimate(plummer_tree):
     """With min_work above every N_A N_B the network is never asked: the
-    decision is q^3 <= u, the analytic error-estimate walk."""
+    decision is rho <= 1, the multipole error-estimate walk."""
     _, t, g = plummer_tree
-    P = np.zeros(orc.MLP_MODEL, np.float32)
-    P[4800] = -1000.0
-    P[4825:4833] = 1e30
-    P[4817:4825] = -1e30
-    t.walk_learned(2e-5, 0.7, 0.5, g, P, min_work=1 << 40)
+    t.walk_learned(2e-5, 0.7, 0.5, g, constant_model(-1000.0), min_work=1 << 40)
     got = t.lists()
-    t.walk_field(2e-5, 0.7, g)
+    t.walk_multipole(2e-5, 0.7, g)
     ref = t.lists()
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
 
 
-def test_learned_walk_out_of_range_takes_the_analytic_factor(plummer_tree):
-    """With an empty training range every band pair takes the analytic factor:
-    the error-estimate walk."""
+def test_learned_walk_out_of_range_takes_the_multipole_estimate(plummer_tree):
+    """With an empty training range every band pair takes rho <= 1: the
+    multipole error-estimate walk."""
     _, t, g = plummer_tree
-    P = np.zeros(orc.MLP_MODEL, np.float32)
-    P[4800] = -1000.0
-    P[4817:4825] = 1e30
-    P[4825:4833] = -1e30
-    t.walk_learned(2e-5, 0.7, 0.4, g, P, min_work=1)
+    t.walk_learned(2e-5, 0.7, 0.4, g, constant_model(-1000.0, in_range=False), min_work=1)
     got = t.lists()
-    t.walk_field(2e-5, 0.7, g)
+    t.walk_multipole(2e-5, 0.7, g)
     ref = t.lists()
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+
+
+def test_learned_walk_follows_the_prediction(plummer_tree):
+    """A constant integer prediction c (log2 of the error ratio) accepts a band
+    pair when plog2(rho) <= -c, i.e. rho <= 2^-c (plog2 is exact at powers of
+    two): the multipole walk at the tolerance eps 2^-c."""
+    _, t, g = plummer_tree
+    eps = 2e-5
+    for c in (2.0, 1.0, 0.0, -1.0):
+        t.walk_learned(eps, 0.7, 0.5, g, constant_model(c), min_work=1)
+        got = t.lists()
+        t.walk_multipole(eps * 2.0 ** -c, 0.7, g)
+        ref = t.lists()
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), c

@@ -60,23 +60,27 @@ MUTATIONS = {
     "field_cube_not_sixth": ("double r6 = (r2 * r2) * r2;", "double r6 = r2 * r2;"),
     "field_scale_no_floor": ("std::max(gmin[ci], 0.1 * (gsum[ci] / (double)t->cells[ci].count))",
                              "std::max(gmin[ci], 1.0 * (gsum[ci] / (double)t->cells[ci].count))"),
-    "learned_gate_low": ("if (q3 <= 0.25 * u) return true;", "if (q3 <= 1.0 * u) return true;"),
-    "learned_small_pairs_accept_all": ("if (t.cells[a].count * t.cells[b].count < t.min_work) return q3 <= u;",
+    "learned_gate_low": ("double lo = 0.25 * t.eps, hi = 2.0 * t.eps;", "double lo = 0.5 * t.eps, hi = 2.0 * t.eps;"),
+    "learned_small_pairs_accept_all": ("if (t.cells[a].count * t.cells[b].count < t.min_work) return plain;",
                                        "if (t.cells[a].count * t.cells[b].count < t.min_work) return true;"),
-    "learned_one_cell": ("double u = std::min((t.eps * t.fscale[a]) * (d * d) / B.M, (t.eps * t.fscale[b]) * (d * d) / A.M);",
-                         "double u = (t.eps * t.fscale[a]) * (d * d) / B.M;"),
-    "label_own_mass": ("double e = std::sqrt((ex * ex + ey * ey) + ez * ez) / (MS.M / (d * d));",
-                       "double e = std::sqrt((ex * ex + ey * ey) + ez * ez) / (MT.M / (d * d));"),
+    "learned_one_cell": ("bool plain = ea <= (t.eps * sa) * d6 && eb <= (t.eps * sb) * d6;",
+                         "bool plain = ea <= (t.eps * sa) * d6;"),
+    "learned_rho_sign": ("return mlp_infer(P, f) <= (float)(-plog2(rho));",
+                         "return mlp_infer(P, f) <= (float)(plog2(rho));"),
+    "label_mean_not_max": ("E = std::max(E, std::sqrt((ex * ex + ey * ey) + ez * ez));",
+                           "E += std::sqrt((ex * ex + ey * ey) + ez * ez) / (double)ns;"),
+    "label_estimate_own_moments": ("int k2s = norm_level(traceless_norm2(MS), MS.M, MS.Rmax, 2);",
+                                   "int k2s = norm_level(traceless_norm2(MT), MT.M, MT.Rmax, 2);"),
     "grad_no_relu_mask": ("double dz1 = z1[j] > 0.0 ? dh : 0.0;", "double dz1 = dh;"),
     "plog2_off_by_one": ("return (double)(e - 1) + (2.0 * m - 1.0);", "return (double)(e) + (2.0 * m - 1.0);"),
     "bf16_truncates": ("u += 0x7FFFu + ((u >> 16) & 1u);", "u += 0u;"),
-    "feature_antisymmetric": ("f[5] = (float)((double)std::abs(qa - qb) / 64.0);",
-                              "f[5] = (float)((double)(qa - qb) / 64.0);"),
+    "feature_antisymmetric": ("f[3] = (float)((double)std::abs(k2a - k2b) / 128.0);",
+                              "f[3] = (float)((double)(k2a - k2b) / 128.0);"),
     "multipole_one_sided": ("return ea <= (t.eps * t.fscale[a]) * d6 && eb <= (t.eps * t.fscale[b]) * d6;",
                             "return ea <= (t.eps * t.fscale[a]) * d6;"),
     "multipole_stricter": ("return ea <= (t.eps * t.fscale[a]) * d6 && eb <= (t.eps * t.fscale[b]) * d6;",
                            "return 1.25 * ea <= (t.eps * t.fscale[a]) * d6 && 1.25 * eb <= (t.eps * t.fscale[b]) * d6;"),
-    "multipole_power_of_d": ("double d6 = (d2 * d2) * d2;", "double d6 = (d2 * d2) * d;"),
+    "multipole_power_of_d": ("    double d6 = (d2 * d2) * d2;", "    double d6 = (d2 * d2) * d;"),
     "multipole_extents_swapped": ("double ea = multipole_bracket(A.Rmax, B.Rmax, t.k2[b], t.k3[b], d) * B.M;",
                                   "double ea = multipole_bracket(B.Rmax, A.Rmax, t.k2[b], t.k3[b], d) * B.M;"),
     "multipole_octupole_not_traceless": ("double w = mo.M3[i][j][k] - (v[i] * kdelta(j, k) + v[j] * kdelta(i, k) + v[k] * kdelta(i, j)) / 5.0;",
