@@ -39,7 +39,7 @@ typedef enum { AMFMM_UC = 0, AMFMM_TC = 1, AMFMM_TCO = 2 } amfmm_variant;
  * MIXED: near-field pair terms and far-field coefficient terms in FP32, on
  * offsets taken relative to cell centres (each offset and the centre-to-centre
  * vector formed in FP64, then rounded).  Per-particle near-field sums are
- * compensated FP64 sums: blocks of at most 16 FP32 terms are added to an FP64
+ * compensated FP64 sums: blocks of at most 32 FP32 terms are added to an FP64
  * accumulator with TwoSum, the rounding errors collected in a compensation
  * term added back at the end.  Far-field coefficients are summed per cell in
  * FP32 blocks of at most 8 terms added to FP64.  Centres of mass, the moment
