@@ -433,9 +433,10 @@ float mlp_infer(const float* P, const float f[kFeat]) {
 // M R^3 and M R^2 (quantised to 1/128, rounded to nearest), the estimate is
 //   e_A = ((w3 k3_B R_B^3 + w2 k2_B R_B^2 R_A + w1 R_A^3) d + w4 R_B^4 + w5 R_A^4) M_B / d^6
 // with weights calibrated on measured pair errors of this method (the largest
-// error over A's particles; least squares in log space over accepted pairs of
-// a 65536-particle Plummer sphere at opening angles 0.4, 0.6, 0.8).
-constexpr double kMw1 = 1.159, kMw2 = 3.73, kMw3 = 0.967, kMw4 = 0.232, kMw5 = 2.68;
+// error over A's particles; least squares in log space over the accepted
+// pairs of geometric walks of a 65536-particle Plummer sphere at opening
+// angles 0.4, 0.6, 0.8), as fit_multipole.py beside this file computes them.
+constexpr double kMw1 = 1.326, kMw2 = 4.095, kMw3 = 0.285, kMw4 = 0.1416, kMw5 = 1.618;
 constexpr double kMq = 128.0;  // quantisation of the norm ratios
 
 // traceless part of M_ij: M_ij - delta_ij tr/3; of M_ijk: M_ijk - (v_i
@@ -902,53 +903,89 @@ void orc_pair_features(const orc_tree* t, int64_t np, const int32_t* pairs, floa
   }
 }
 
-// Label of a pair: for each cell T (the other S) the method's acceleration of
-// the pair alone at up to kLabelSample particles of T (eq. 3 about Z_T plus
-// the correction of the variant) against the direct sum over S; the largest
-// error over those particles divided by the multipole estimate of the error
-// on T.  The label is log2 of the larger ratio of the two cells; a cell whose
-// estimate is zero (a point mass: exact) is left out, -inf when both are.
-int32_t orc_pair_labels(const orc_tree* t, int32_t variant, int64_t np, const int32_t* pairs,
-                        double* labels) {
+// The method's largest error on field cell T from the pair (T, S) alone: the
+// acceleration of eq. 3 about Z_T plus the correction of the variant at up to
+// kLabelSample particles of T (evenly spread over T's range) against the
+// direct sum over S's particles.
+static double pair_side_error(const orc_tree* t, int32_t ct, int32_t cs, int32_t variant) {
+  const Cell& T = t->cells[ct];
+  const Cell& S = t->cells[cs];
+  const Moments& MT = t->mom[ct];
+  const Moments& MS = t->mom[cs];
+  PairTerms pt;
+  pair_terms(MT, MS, variant, pt);  // R = Z_T - Z_S: T is the field cell of eq. 3
+  int64_t ns = std::min<int64_t>(T.count, kLabelSample);
+  double E = 0.0;
+  for (int64_t s = 0; s < ns; ++s) {
+    int64_t p = T.begin + (s * T.count) / ns;
+    double xv[3] = {t->x[p] - MT.Z[0], t->y[p] - MT.Z[1], t->z[p] - MT.Z[2]};
+    double g[3];
+    eq3_accel(pt.g, MS, xv, g);
+    for (int dd = 0; dd < 3; ++dd) g[dd] += pt.Fc[dd] / MT.M;
+    double gd[3] = {0.0, 0.0, 0.0};
+    for (int64_t j = S.begin; j < S.begin + S.count; ++j) {
+      double dx = t->x[j] - t->x[p];
+      double dy = t->y[j] - t->y[p];
+      double dz = t->z[j] - t->z[p];
+      double r2 = (dx * dx + dy * dy) + dz * dz;
+      double r3 = r2 * std::sqrt(r2);
+      gd[0] += t->m[j] * dx / r3;
+      gd[1] += t->m[j] * dy / r3;
+      gd[2] += t->m[j] * dz / r3;
+    }
+    double ex = g[0] - gd[0], ey = g[1] - gd[1], ez = g[2] - gd[2];
+    E = std::max(E, std::sqrt((ex * ex + ey * ey) + ez * ez));
+  }
+  return E;
+}
+
+static int32_t check_pairs(const orc_tree* t, int32_t variant, int64_t np, const int32_t* pairs) {
   if (!t->have_moments) return ORC_E_STATE;
   if (variant < ORC_UC || variant > ORC_TCO) return ORC_E_INVALID;
   int64_t nc = (int64_t)t->cells.size();
   for (int64_t k = 0; k < np; ++k) {
     int32_t a = pairs[2 * k], b = pairs[2 * k + 1];
     if (a < 0 || b < 0 || a >= nc || b >= nc || a == b) return ORC_E_INVALID;
+    if (!(pair_distance(t->mom[a], t->mom[b]) > 0.0)) return ORC_E_INVALID;
+  }
+  return ORC_OK;
+}
+
+void orc_multipole_weights(double* w) {
+  w[0] = kMw1;
+  w[1] = kMw2;
+  w[2] = kMw3;
+  w[3] = kMw4;
+  w[4] = kMw5;
+}
+
+int32_t orc_pair_errors(const orc_tree* t, int32_t variant, int64_t np, const int32_t* pairs, double* err) {
+  int32_t st = check_pairs(t, variant, np, pairs);
+  if (st != ORC_OK) return st;
+  for (int64_t k = 0; k < np; ++k) {
+    err[2 * k] = pair_side_error(t, pairs[2 * k], pairs[2 * k + 1], variant);
+    err[2 * k + 1] = pair_side_error(t, pairs[2 * k + 1], pairs[2 * k], variant);
+  }
+  return ORC_OK;
+}
+
+// Label of a pair: for each cell T (the other S) the largest error of the
+// pair on T (pair_side_error) divided by the multipole estimate of the error
+// on T.  The label is log2 of the larger ratio of the two cells; a cell whose
+// estimate is zero (a point mass: exact) is left out, -inf when both are.
+int32_t orc_pair_labels(const orc_tree* t, int32_t variant, int64_t np, const int32_t* pairs,
+                        double* labels) {
+  int32_t st = check_pairs(t, variant, np, pairs);
+  if (st != ORC_OK) return st;
+  for (int64_t k = 0; k < np; ++k) {
+    int32_t a = pairs[2 * k], b = pairs[2 * k + 1];
     double d = pair_distance(t->mom[a], t->mom[b]);
-    if (!(d > 0.0)) return ORC_E_INVALID;
     double worst = -INFINITY;
     for (int side = 0; side < 2; ++side) {
       int32_t ct = side ? b : a, cs = side ? a : b;
-      const Cell& T = t->cells[ct];
-      const Cell& S = t->cells[cs];
       const Moments& MT = t->mom[ct];
       const Moments& MS = t->mom[cs];
-      PairTerms pt;
-      pair_terms(MT, MS, variant, pt);  // R = Z_T - Z_S: T is the field cell of eq. 3
-      int64_t ns = std::min<int64_t>(T.count, kLabelSample);
-      double E = 0.0;
-      for (int64_t s = 0; s < ns; ++s) {
-        int64_t p = T.begin + (s * T.count) / ns;
-        double xv[3] = {t->x[p] - MT.Z[0], t->y[p] - MT.Z[1], t->z[p] - MT.Z[2]};
-        double g[3];
-        eq3_accel(pt.g, MS, xv, g);
-        for (int dd = 0; dd < 3; ++dd) g[dd] += pt.Fc[dd] / MT.M;
-        double gd[3] = {0.0, 0.0, 0.0};
-        for (int64_t j = S.begin; j < S.begin + S.count; ++j) {
-          double dx = t->x[j] - t->x[p];
-          double dy = t->y[j] - t->y[p];
-          double dz = t->z[j] - t->z[p];
-          double r2 = (dx * dx + dy * dy) + dz * dz;
-          double r3 = r2 * std::sqrt(r2);
-          gd[0] += t->m[j] * dx / r3;
-          gd[1] += t->m[j] * dy / r3;
-          gd[2] += t->m[j] * dz / r3;
-        }
-        double ex = g[0] - gd[0], ey = g[1] - gd[1], ez = g[2] - gd[2];
-        E = std::max(E, std::sqrt((ex * ex + ey * ey) + ez * ez));
-      }
+      double E = pair_side_error(t, ct, cs, variant);
       int k2s = norm_level(traceless_norm2(MS), MS.M, MS.Rmax, 2);
       int k3s = norm_level(traceless_norm3(MS), MS.M, MS.Rmax, 3);
       double d2 = d * d;

@@ -156,17 +156,25 @@ void orc_pair_far(int64_t nA, const double* xa, const double* ya, const double* 
  * ORC_MLP_PARAMS entries. */
 #define ORC_MLP_PARAMS 4801
 #define ORC_MLP_MODEL 4833
-/* Walk whose accept decision asks the network (error factor against eps times
- * the field scale of each cell, as orc_walk_field) for pairs with N_A N_B >=
- * min_work and features inside the training range; other pairs take the
- * analytic factor q^3.  model == NULL gives the opening-angle walk with theta. */
+/* Walk on the multipole estimate (as orc_walk_multipole) whose accept
+ * decision asks the network where the estimate lies near the bound (rho in
+ * (1/4, 2], rho the larger of e / (eps s d^6) over the two cells) for pairs
+ * with N_A N_B >= min_work and features inside the training range; below the
+ * band pairs are accepted, above it opened, other pairs in it take rho <= 1.
+ * model == NULL gives the opening-angle walk with theta. */
 int32_t orc_walk_learned(orc_tree* t, double eps, double theta_max, double theta, const double* gmag,
                          const float* model, int64_t min_work);
 /* Features (8 floats per pair) and labels (log2 error factor) of cell pairs
- * (a, b), 2 int32 per pair; labels need moments and a != b, d > 0. */
+ * (a, b), 2 int32 per pair; labels need moments and a != b, d > 0.
+ * orc_pair_errors: the method's largest error from the pair alone on a
+ * (err[2k]) and on b (err[2k+1]), the measurements behind the labels and the
+ * fit of the multipole estimate's weights. */
 void orc_pair_features(const orc_tree* t, int64_t np, const int32_t* pairs, float* feats);
 int32_t orc_pair_labels(const orc_tree* t, int32_t variant, int64_t np, const int32_t* pairs,
                         double* labels);
+int32_t orc_pair_errors(const orc_tree* t, int32_t variant, int64_t np, const int32_t* pairs, double* err);
+/* The multipole estimate's weights w1..w5 (5 doubles). */
+void orc_multipole_weights(double* w);
 /* BF16 rounding (nearest, ties to even) and the piecewise-linear log2 that
  * the features and the decision use. */
 float orc_bf16_round(float v);

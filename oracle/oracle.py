@@ -85,6 +85,9 @@ def lib():
         L.orc_pair_features.argtypes = [P, C.c_int64, i32, f]
         L.orc_pair_labels.restype = C.c_int32
         L.orc_pair_labels.argtypes = [P, C.c_int32, C.c_int64, i32, d]
+        L.orc_pair_errors.restype = C.c_int32
+        L.orc_pair_errors.argtypes = [P, C.c_int32, C.c_int64, i32, d]
+        L.orc_multipole_weights.argtypes = [d]
         L.orc_bf16_round.restype = C.c_float
         L.orc_bf16_round.argtypes = [C.c_float]
         L.orc_plog2.restype = C.c_double
@@ -110,6 +113,13 @@ class OracleError(RuntimeError):
     def __init__(self, code):
         super().__init__(f"oracle status {code}")
         self.code = code
+
+
+def multipole_weights():
+    """The multipole error estimate's weights (w1..w5)."""
+    w = np.zeros(5)
+    lib().orc_multipole_weights(_d(w))
+    return w
 
 
 class Tree:
@@ -215,6 +225,17 @@ class Tree:
         pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
         out = np.zeros(len(pairs))
         st = lib().orc_pair_labels(self._t, variant, len(pairs), pairs.ctypes.data_as(C.POINTER(C.c_int32)),
+                                   _d(out))
+        if st:
+            raise OracleError(st)
+        return out
+
+    def pair_errors(self, pairs, variant=TC):
+        """The method's largest error from each pair alone on its first and
+        on its second cell (n x 2)."""
+        pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+        out = np.zeros((len(pairs), 2))
+        st = lib().orc_pair_errors(self._t, variant, len(pairs), pairs.ctypes.data_as(C.POINTER(C.c_int32)),
                                    _d(out))
         if st:
             raise OracleError(st)
