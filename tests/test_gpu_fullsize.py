@@ -13,7 +13,7 @@
 * Plummer 2^24 (seed 4), geometric theta = 0.5: mixed against FP64 (the same
   pairs), both against direct summation, residuals and wall times.
 * Plummer 2^24 (seed 4) in the benchmark's configuration (pilot geometric
-  solve at theta 1.0 + multipole error-estimate solve, eps 8e-8, theta_max
+  solve at theta 1.0 + multipole error-estimate solve, eps 9e-8, theta_max
   0.5, mixed, TC): the oracle cannot walk 3e10 pairs, so properties that hold
   at any size: p99 of the force error against direct summation at 65536
   sampled targets below 1e-4, force and torque balance, and the mixed solve
@@ -202,7 +202,7 @@ def test_plummer_2p24_benchmark_configuration():
     T = torch.stack([tx, ty, tz])
     outs = {}
     for prec in (amfmm.MIXED, amfmm.FP64):
-        s = amfmm.Solver(precision=prec, criterion=amfmm.MULTIPOLE, error_tol=8e-8, theta_max=0.5)
+        s = amfmm.Solver(precision=prec, criterion=amfmm.MULTIPOLE, error_tol=9e-8, theta_max=0.5)
         s.set_field_estimate(gx, gy, gz)
         o = s.solve_gravity(X, Y, Z, M, 0.5, pot=False)
         A = torch.stack([o[0][tg], o[1][tg], o[2][tg]])
@@ -220,7 +220,7 @@ def test_plummer_2p24_benchmark_configuration():
 
 def test_two_plummer_2p24_multipole_meets_target():
     """The two-sphere 2^24 workload (seed 5) in the benchmark's configuration
-    (mixed, TC, geometric pilot at theta 1.0, multipole estimate eps 8e-8,
+    (mixed, TC, geometric pilot at theta 1.0, multipole estimate eps 9e-8,
     theta_max 0.5): p99 relative force error at most 1e-4 over 65536 sampled
     targets against direct summation, both balances at FP32 round-off."""
     n = 1 << 24
@@ -233,7 +233,7 @@ def test_two_plummer_2p24_multipole_meets_target():
     tg = torch.from_numpy(W.sample_targets(n, 1 << 16, seed=99)).cuda()
     tx, ty, tz, _, _ = pilot.direct(X, Y, Z, M, tg, pot=False, gabs=False)
     T = torch.stack([tx, ty, tz])
-    s = amfmm.Solver(precision=amfmm.MIXED, criterion=amfmm.MULTIPOLE, error_tol=8e-8, theta_max=0.5)
+    s = amfmm.Solver(precision=amfmm.MIXED, criterion=amfmm.MULTIPOLE, error_tol=9e-8, theta_max=0.5)
     s.set_field_estimate(gx, gy, gz)
     o = s.solve_gravity(X, Y, Z, M, 0.5, pot=False)
     A = torch.stack([o[0][tg], o[1][tg], o[2][tg]])
