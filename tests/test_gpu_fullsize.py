@@ -6,6 +6,8 @@
 * Plummer 2^20 with the multipole error estimate (the benchmark's criterion)
   at a tolerance the oracle can walk: lists bit for bit, sampled accelerations
   in FP64 and mixed precision.
+* Plummer 2^20 with the learned criterion (a random network, the default
+  min_work): lists bit for bit.
 * Two Plummer spheres 2^22 (seed 3), theta = 0.35, 0.5 and 0.7, FP64 and
   mixed: sampled accelerations against the oracle (FP64 1e-12 of gabs; mixed
   1e-4 at worst and 2e-6 at the 99th percentile, the bounds of the
@@ -148,6 +150,44 @@ def test_plummer_2p20_multipole_against_oracle():
             assert np.percentile(perr, 99) <= 1e-6
             assert fb <= 1e-7 and tb <= 1e-7
         s.close()
+
+
+def test_plummer_2p20_learned_lists_against_oracle():
+    """The learned criterion at 2^20 (seed 2), the network asked for pairs with
+    N_A N_B >= 2^18 (the default), eps 1e-5, theta_max 0.5, the analytic field
+    magnitude on both sides and a random network (seed 10, normalised on a
+    sample of the geometric walk's pairs): both lists bit for bit against the
+    oracle's walk; the network's decisions differ from the multipole rule's on
+    about a million pairs, so both sides' inference is exercised."""
+    from tests.test_gpu_learned import random_model
+
+    n = 1 << 20
+    eps, tmax, mw = 1e-5, 0.5, 1 << 18
+    x, y, z, m = W.plummer(n, seed=2)
+    r = np.sqrt(x * x + y * y + z * z)
+    gmag = r / (r * r + 1.0) ** 1.5
+    say(f"full size: plummer 2^20, learned eps {eps} theta_max {tmax} min_work {mw}")
+    t = orc.Tree(x, y, z, m)
+    t.compute_moments()
+    t.walk(0.8)
+    far0, _ = t.lists()
+    sample = far0[np.random.default_rng(0).choice(len(far0), 20000, replace=False)]
+    P = random_model(10, t.pair_features(sample), 0.0)
+    t.walk_learned(eps, tmax, 0.5, gmag, P, mw)
+    ofar, onear = t.lists()
+    X, Y, Z, M = to_dev(x, y, z, m)
+    G, = to_dev(gmag)
+    s = amfmm.Solver(criterion=amfmm.LEARNED, error_tol=eps, theta_max=tmax, learned_min_work=mw)
+    s.set_model(P)
+    s.set_field_estimate(G)
+    s.build_tree(X, Y, Z, M)
+    s.compute_moments()
+    s.walk(0.5)
+    far, near = s.get_lists()
+    say(f"  far pairs {len(far)}, near pairs {len(near)}")
+    assert np.array_equal(far, ofar)
+    assert np.array_equal(near, onear)
+    s.close()
 
 
 def test_plummer_2p24_mixed_geometric():
