@@ -33,6 +33,7 @@
 #include <cstring>
 #include <numeric>
 #include <utility>
+#include <array>
 #include <vector>
 #ifdef _OPENMP
 #include <omp.h>
@@ -56,6 +57,7 @@ struct Moments {
   double Rmax = 0.0;
   double M2[3][3] = {};     // sum mu x_i x_j about Z
   double M3[3][3][3] = {};  // sum mu x_i x_j x_k about Z
+  std::vector<double> mono; // expansion order P != 3: sum mu x^alpha about Z, |alpha| <= P
 };
 
 }  // namespace
@@ -83,6 +85,8 @@ struct orc_tree {
   std::vector<std::pair<int32_t, int32_t>> m2l, p2p;
   int64_t coincident = 0;
   double eps2 = 0.0;  // Plummer softening length squared (0: the plain 1/R)
+  int order = 3;         // expansion order P (appendix)
+  bool general = false;  // the appendix's general form (always at P != 3; at P = 3 on request)
 };
 
 namespace {
@@ -232,6 +236,178 @@ void moments_about(const orc_tree& t, int64_t b, int64_t cnt, Moments& mo) {
   mo.Rmax = std::sqrt(r2max);
 }
 
+// ------------------------------------------------ general expansion order ---
+// The appendix's expansion to order P, written with multi-indices alpha =
+// (a, b, c) (x^alpha = x^a y^b z^c, alpha! = a! b! c!): a full tensor index
+// tuple with a ones, b twos and c threes stands for alpha, and a sum over all
+// tuples of order n is a sum over |alpha| = n weighted by n!/alpha!.
+constexpr int kMaxOrder = 6;  // P <= 6: derivatives up to order 7
+
+struct MultiIndexTable {
+  std::vector<std::array<int, 3>> e;  // exponents, graded by order
+  std::vector<int> order;
+  std::vector<double> fact;           // alpha!
+  int id[kMaxOrder + 2][kMaxOrder + 2][kMaxOrder + 2];
+  int count[kMaxOrder + 3];           // multi-indices of order < n
+  MultiIndexTable() {
+    for (int n = 0; n <= kMaxOrder + 1; ++n) {
+      count[n] = (int)e.size();
+      for (int a = n; a >= 0; --a)
+        for (int b = n - a; b >= 0; --b) {
+          int c = n - a - b;
+          id[a][b][c] = (int)e.size();
+          e.push_back({a, b, c});
+          order.push_back(n);
+          double f = 1.0;
+          for (int k = 2; k <= a; ++k) f *= k;
+          for (int k = 2; k <= b; ++k) f *= k;
+          for (int k = 2; k <= c; ++k) f *= k;
+          fact.push_back(f);
+        }
+    }
+    count[kMaxOrder + 2] = (int)e.size();
+  }
+  int of(int a, int b, int c) const { return id[a][b][c]; }
+};
+const MultiIndexTable kMI;
+
+double power(double v, int k) {
+  double r = 1.0;
+  for (int i = 0; i < k; ++i) r *= v;
+  return r;
+}
+
+// D_gamma = d^gamma g(R) for |gamma| <= nmax, g = -1/sqrt(R^2 + eps2) (the
+// plain -1/R at eps2 = 0).  For any g of R alone, with f_k = (1/R d/dR)^k g
+// (f_0 = -s^-1/2, f_{k+1} = -(2k+1) f_k / s, s = R^2 + eps2), the derivative is
+// a sum over the ways to pair up equal indices: pairing b_i of the gamma_i
+// indices of direction i (gamma_i! / (b_i! (gamma_i - 2 b_i)! 2^b_i) ways)
+// leaves R_i^(gamma_i - 2 b_i) and the factor f_(|gamma| - |b|).  At order
+// <= 4 this is the tensors of greens() and greens_softened().
+void greens_general(const double R[3], double eps2, int nmax, std::vector<double>& D) {
+  double s = ((R[0] * R[0] + R[1] * R[1]) + R[2] * R[2]) + eps2;
+  double f[kMaxOrder + 2];
+  f[0] = -1.0 / std::sqrt(s);
+  for (int k = 0; k + 1 <= nmax; ++k) f[k + 1] = -(2.0 * k + 1.0) * f[k] / s;
+  D.assign(kMI.count[nmax + 1], 0.0);
+  for (int g = 0; g < kMI.count[nmax + 1]; ++g) {
+    const auto& ge = kMI.e[g];
+    double sum = 0.0;
+    for (int b0 = 0; 2 * b0 <= ge[0]; ++b0)
+      for (int b1 = 0; 2 * b1 <= ge[1]; ++b1)
+        for (int b2 = 0; 2 * b2 <= ge[2]; ++b2) {
+          int b[3] = {b0, b1, b2};
+          double c = 1.0;
+          for (int i = 0; i < 3; ++i) {
+            double ways = 1.0;
+            for (int k = 2; k <= ge[i]; ++k) ways *= k;
+            for (int k = 2; k <= b[i]; ++k) ways /= k;
+            for (int k = 2; k <= ge[i] - 2 * b[i]; ++k) ways /= k;
+            ways /= power(2.0, b[i]);
+            c *= ways * power(R[i], ge[i] - 2 * b[i]);
+          }
+          sum += f[kMI.order[g] - (b0 + b1 + b2)] * c;
+        }
+    D[g] = sum;
+  }
+}
+
+// x^alpha for every |alpha| <= n
+void monomials(const double x[3], int n, std::vector<double>& out) {
+  out.assign(kMI.count[n + 1], 0.0);
+  for (int g = 0; g < kMI.count[n + 1]; ++g)
+    out[g] = power(x[0], kMI.e[g][0]) * power(x[1], kMI.e[g][1]) * power(x[2], kMI.e[g][2]);
+}
+
+// M_alpha = sum mu x^alpha about Z, |alpha| <= P, of the particles [b, b+cnt)
+void moments_general(const orc_tree& t, int64_t b, int64_t cnt, int P, Moments& mo) {
+  mo.mono.assign(kMI.count[P + 1], 0.0);
+  std::vector<double> xm;
+  for (int64_t p = b; p < b + cnt; ++p) {
+    double xv[3] = {t.x[p] - mo.Z[0], t.y[p] - mo.Z[1], t.z[p] - mo.Z[2]};
+    monomials(xv, P, xm);
+    for (size_t g = 0; g < xm.size(); ++g) mo.mono[g] += t.m[p] * xm[g];
+  }
+}
+
+// One accepted pair (a, b) at order P, R = Z_a - Z_b.  With G(R + x - y)
+// expanded in both offsets, the potential at offset x from Z_a due to b is
+// sum_alpha x^alpha/alpha! La_alpha, La_alpha = sum_beta (-1)^|beta|/beta!
+// D_(alpha+beta) M_b,beta over |alpha| + |beta| <= P, and at offset y from
+// Z_b due to a the same with Lb_alpha = (-1)^|alpha| sum_beta 1/beta!
+// D_(alpha+beta) M_a,beta (D(-R) = (-1)^n D(R)).  Dipole terms (|beta| = 1,
+// zero about the centre of mass) and the constant |alpha| = 0, |beta| = P
+// are dropped, as at P = 3.  The acceleration is minus the gradient.  The
+// correction (TC): F_c,k = -sum_n (-1)^n sum_{|alpha| = P-n, |beta| = n}
+// M_a,alpha M_b,beta D_(alpha+beta+e_k) / (alpha! beta!), the appendix's
+// corrective force (its expansion carries (-1)^n on the source offsets, so
+// its D is taken at this R) in this sign convention: at P = 3 it is eq. 7,
+// -(1/6)(M_a,jkl M_b - M_a M_b,jkl) D_ijkl.  +F_c/M_a on a's particles and
+// -F_c/M_b on b's.
+struct GeneralPair {
+  std::vector<double> La, Lb;
+  double Fc[3];
+};
+
+void general_pair(const Moments& A, const Moments& B, int variant, int P, double eps2, GeneralPair& gp) {
+  double R[3] = {A.Z[0] - B.Z[0], A.Z[1] - B.Z[1], A.Z[2] - B.Z[2]};
+  std::vector<double> D;
+  greens_general(R, eps2, P + 1, D);
+  int nl = kMI.count[P + 1];
+  gp.La.assign(nl, 0.0);
+  gp.Lb.assign(nl, 0.0);
+  for (int al = 0; al < nl; ++al) {
+    const auto& ae = kMI.e[al];
+    for (int be = 0; be < nl; ++be) {
+      int na = kMI.order[al], nb = kMI.order[be];
+      if (na + nb > P || nb == 1 || (na == 0 && nb == P)) continue;
+      const auto& bexp = kMI.e[be];
+      double Dab = D[kMI.of(ae[0] + bexp[0], ae[1] + bexp[1], ae[2] + bexp[2])];
+      double sb = (nb % 2) ? -1.0 : 1.0;
+      gp.La[al] += sb / kMI.fact[be] * Dab * B.mono[be];
+      gp.Lb[al] += 1.0 / kMI.fact[be] * Dab * A.mono[be];
+    }
+    if (kMI.order[al] % 2) gp.Lb[al] = -gp.Lb[al];
+  }
+  for (int k = 0; k < 3; ++k) gp.Fc[k] = 0.0;
+  if (variant == ORC_UC) return;
+  for (int k = 0; k < 3; ++k) {
+    double s = 0.0;
+    for (int n = 0; n <= P; ++n) {
+      if (n == 1 || P - n == 1) continue;
+      double sn = (n % 2) ? -1.0 : 1.0;
+      for (int al = kMI.count[P - n]; al < kMI.count[P - n + 1]; ++al)
+        for (int be = kMI.count[n]; be < kMI.count[n + 1]; ++be) {
+          const auto& ae = kMI.e[al];
+          const auto& bexp = kMI.e[be];
+          int g[3] = {ae[0] + bexp[0], ae[1] + bexp[1], ae[2] + bexp[2]};
+          g[k] += 1;
+          s += sn * A.mono[al] * B.mono[be] * D[kMI.of(g[0], g[1], g[2])] / (kMI.fact[al] * kMI.fact[be]);
+        }
+    }
+    gp.Fc[k] = -s;
+  }
+}
+
+// acceleration (minus the gradient) and potential of a local expansion L of
+// order P at offset x
+void general_local_at(const std::vector<double>& L, int P, const double x[3], double g[3], double& phi) {
+  std::vector<double> xm;
+  monomials(x, P, xm);
+  phi = 0.0;
+  for (int al = 0; al < kMI.count[P + 1]; ++al) phi += xm[al] / kMI.fact[al] * L[al];
+  for (int k = 0; k < 3; ++k) {
+    double s = 0.0;
+    for (int al = 0; al < kMI.count[P]; ++al) {
+      const auto& ae = kMI.e[al];
+      int e[3] = {ae[0], ae[1], ae[2]};
+      e[k] += 1;
+      s += xm[al] / kMI.fact[al] * L[kMI.of(e[0], e[1], e[2])];
+    }
+    g[k] = -s;
+  }
+}
+
 // ------------------------------------------------------------- far field ---
 // One accepted pair, R = Z_A - Z_B.  Eq. 3 (field in A) and eq. 4 (field in B)
 // with dipole terms dropped; eq. 2 for the potential in A and its mirror image
@@ -338,6 +514,51 @@ double eq2_pot_B(const Greens& g, const Moments& A, const double y[3]) {
       for (int k = 0; k < 3; ++k) s3 += y[i] * y[j] * y[k] * A.M * g.D3[i][j][k];
     }
   return p + 0.5 * s2 - (1.0 / 6.0) * s3;
+}
+
+// The far-field terms of one accepted pair (a, b) at the tree's order: the
+// printed equations at P = 3 (a the field cell of eq. 3, b that of eq. 4),
+// the general form otherwise (or when asked for at P = 3).
+struct PairField {
+  int P;
+  bool general;
+  PairTerms pt;
+  GeneralPair gp;
+};
+
+void pair_field(const orc_tree& t, int32_t a, int32_t b, int variant, PairField& pf) {
+  pf.P = t.general ? t.order : 3;
+  pf.general = t.general;
+  if (!t.general)
+    pair_terms(t.mom[a], t.mom[b], variant, pf.pt, t.eps2);
+  else
+    general_pair(t.mom[a], t.mom[b], variant, t.order, t.eps2, pf.gp);
+}
+
+// acceleration (the correction included) and potential at offset v from the
+// centre of a (side 0) or of b (side 1)
+void pair_field_at(const orc_tree& t, const PairField& pf, int32_t a, int32_t b, int side, const double v[3],
+                   double g[3], double& phi) {
+  const Moments& A = t.mom[a];
+  const Moments& B = t.mom[b];
+  double gg[3];
+  if (!pf.general) {
+    if (side == 0) {
+      eq3_accel(pf.pt.g, B, v, gg);
+      for (int d = 0; d < 3; ++d) g[d] = gg[d] + pf.pt.Fc[d] / A.M;
+      phi = eq2_pot_A(pf.pt.g, B, v);
+    } else {
+      eq4_accel(pf.pt.g, A, v, gg);
+      for (int d = 0; d < 3; ++d) g[d] = gg[d] - pf.pt.Fc[d] / B.M;
+      phi = eq2_pot_B(pf.pt.g, A, v);
+    }
+  } else if (side == 0) {
+    general_local_at(pf.gp.La, pf.P, v, gg, phi);
+    for (int d = 0; d < 3; ++d) g[d] = gg[d] + pf.gp.Fc[d] / A.M;
+  } else {
+    general_local_at(pf.gp.Lb, pf.P, v, gg, phi);
+    for (int d = 0; d < 3; ++d) g[d] = gg[d] - pf.gp.Fc[d] / B.M;
+  }
 }
 
 // ------------------------------------------------- learned pair selection ---
@@ -760,8 +981,10 @@ int32_t orc_compute_moments(orc_tree* t) {
     for (int d = 0; d < 3; ++d) mo.Z[d] = mo.S[d] / mo.M;
   }
   // higher moments and R_max directly from the particles of each cell
-  for (size_t ci = 0; ci < nc; ++ci)
+  for (size_t ci = 0; ci < nc; ++ci) {
     moments_about(*t, t->cells[ci].begin, t->cells[ci].count, t->mom[ci]);
+    if (t->general) moments_general(*t, t->cells[ci].begin, t->cells[ci].count, t->order, t->mom[ci]);
+  }
   t->have_moments = true;
   t->have_lists = false;
   return ORC_OK;
@@ -1103,6 +1326,7 @@ int32_t orc_evaluate(orc_tree* t, int32_t variant, double G, double* ax, double*
                      double* pot) {
   if (!t->have_lists) return ORC_E_STATE;
   if (variant < ORC_UC || variant > ORC_TCO) return ORC_E_INVALID;
+  if (variant == ORC_TCO && t->general) return ORC_E_INVALID;  // eq. 8's tensor is printed for P = 3 only
   int64_t n = t->n;
   std::vector<double> gx(n, 0.0), gy(n, 0.0), gz(n, 0.0), ph(n, 0.0);
   // far field: every accepted pair, at every particle of both cells
@@ -1111,25 +1335,25 @@ int32_t orc_evaluate(orc_tree* t, int32_t variant, double G, double* ax, double*
     const Cell& CB = t->cells[pr.second];
     const Moments& A = t->mom[pr.first];
     const Moments& B = t->mom[pr.second];
-    PairTerms pt;
-    pair_terms(A, B, variant, pt, t->eps2);
+    PairField pf;
+    pair_field(*t, pr.first, pr.second, variant, pf);
     for (int64_t p = CA.begin; p < CA.begin + CA.count; ++p) {
       double xv[3] = {t->x[p] - A.Z[0], t->y[p] - A.Z[1], t->z[p] - A.Z[2]};
-      double g[3];
-      eq3_accel(pt.g, B, xv, g);
-      gx[p] += g[0] + pt.Fc[0] / A.M;
-      gy[p] += g[1] + pt.Fc[1] / A.M;
-      gz[p] += g[2] + pt.Fc[2] / A.M;
-      ph[p] += eq2_pot_A(pt.g, B, xv);
+      double g[3], phi;
+      pair_field_at(*t, pf, pr.first, pr.second, 0, xv, g, phi);
+      gx[p] += g[0];
+      gy[p] += g[1];
+      gz[p] += g[2];
+      ph[p] += phi;
     }
     for (int64_t p = CB.begin; p < CB.begin + CB.count; ++p) {
       double yv[3] = {t->x[p] - B.Z[0], t->y[p] - B.Z[1], t->z[p] - B.Z[2]};
-      double g[3];
-      eq4_accel(pt.g, A, yv, g);
-      gx[p] += g[0] - pt.Fc[0] / B.M;
-      gy[p] += g[1] - pt.Fc[1] / B.M;
-      gz[p] += g[2] - pt.Fc[2] / B.M;
-      ph[p] += eq2_pot_B(pt.g, A, yv);
+      double g[3], phi;
+      pair_field_at(*t, pf, pr.first, pr.second, 1, yv, g, phi);
+      gx[p] += g[0];
+      gy[p] += g[1];
+      gz[p] += g[2];
+      ph[p] += phi;
     }
   }
   // near field: every particle pair of every non-accepted leaf pair, once
@@ -1178,6 +1402,7 @@ int32_t orc_evaluate_sample(orc_tree* t, int32_t variant, double G, int64_t ns, 
                             double* ax, double* ay, double* az, double* pot) {
   if (!t->have_lists) return ORC_E_STATE;
   if (variant < ORC_UC || variant > ORC_TCO) return ORC_E_INVALID;
+  if (variant == ORC_TCO && t->general) return ORC_E_INVALID;  // eq. 8's tensor is printed for P = 3 only
   int64_t n = t->n;
   // caller index -> sorted position, cell -> partners of each list
   std::vector<int64_t> pos(n);
@@ -1212,20 +1437,14 @@ int32_t orc_evaluate_sample(orc_tree* t, int32_t variant, double G, int64_t ns, 
         // the pair is stored once as (lower, higher); the lower index is the
         // field cell of eq. 3 and the higher that of eq. 4
         int32_t a = std::min(cell, other), b = std::max(cell, other);
-        PairTerms pt;
-        pair_terms(t->mom[a], t->mom[b], variant, pt, t->eps2);
+        PairField pf;
+        pair_field(*t, a, b, variant, pf);
         const Moments& own = t->mom[cell];
         double xv[3] = {t->x[p] - own.Z[0], t->y[p] - own.Z[1], t->z[p] - own.Z[2]};
-        double gg[3];
-        if (cell == a) {
-          eq3_accel(pt.g, t->mom[b], xv, gg);
-          for (int d = 0; d < 3; ++d) g[d] += gg[d] + pt.Fc[d] / own.M;
-          ph += eq2_pot_A(pt.g, t->mom[b], xv);
-        } else {
-          eq4_accel(pt.g, t->mom[a], xv, gg);
-          for (int d = 0; d < 3; ++d) g[d] += gg[d] - pt.Fc[d] / own.M;
-          ph += eq2_pot_B(pt.g, t->mom[a], xv);
-        }
+        double gg[3], phi;
+        pair_field_at(*t, pf, a, b, cell == a ? 0 : 1, xv, gg, phi);
+        for (int d = 0; d < 3; ++d) g[d] += gg[d];
+        ph += phi;
       }
     }
     int32_t leaf = chain.back();
@@ -1258,6 +1477,7 @@ int32_t orc_evaluate_targets(orc_tree* t, int32_t variant, double G, double* ax,
                              double* az, double* pot) {
   if (!t->have_lists) return ORC_E_STATE;
   if (variant < ORC_UC || variant > ORC_TCO) return ORC_E_INVALID;
+  if (variant == ORC_TCO && t->general) return ORC_E_INVALID;  // eq. 8's tensor is printed for P = 3 only
   int64_t n = t->n;
   int64_t nc = (int64_t)t->cells.size();
   std::vector<double> gx(n, 0.0), gy(n, 0.0), gz(n, 0.0), ph(n, 0.0);
@@ -1282,24 +1502,16 @@ int32_t orc_evaluate_targets(orc_tree* t, int32_t variant, double G, double* ax,
       const Moments& own = t->mom[ci];
       for (int32_t other : far[ci]) {
         int32_t a = std::min((int32_t)ci, other), b = std::max((int32_t)ci, other);
-        PairTerms pt;
-        pair_terms(t->mom[a], t->mom[b], variant, pt, t->eps2);
+        PairField pf;
+        pair_field(*t, a, b, variant, pf);
         for (int64_t p = C.begin; p < C.begin + C.count; ++p) {
           double xv[3] = {t->x[p] - own.Z[0], t->y[p] - own.Z[1], t->z[p] - own.Z[2]};
-          double g[3];
-          if (ci == a) {
-            eq3_accel(pt.g, t->mom[b], xv, g);
-            gx[p] += g[0] + pt.Fc[0] / own.M;
-            gy[p] += g[1] + pt.Fc[1] / own.M;
-            gz[p] += g[2] + pt.Fc[2] / own.M;
-            ph[p] += eq2_pot_A(pt.g, t->mom[b], xv);
-          } else {
-            eq4_accel(pt.g, t->mom[a], xv, g);
-            gx[p] += g[0] - pt.Fc[0] / own.M;
-            gy[p] += g[1] - pt.Fc[1] / own.M;
-            gz[p] += g[2] - pt.Fc[2] / own.M;
-            ph[p] += eq2_pot_B(pt.g, t->mom[a], xv);
-          }
+          double g[3], phi;
+          pair_field_at(*t, pf, a, b, ci == a ? 0 : 1, xv, g, phi);
+          gx[p] += g[0];
+          gy[p] += g[1];
+          gz[p] += g[2];
+          ph[p] += phi;
         }
       }
     }
@@ -1407,6 +1619,31 @@ int32_t orc_direct_softened(int64_t n, const double* x, const double* y, const d
   return ORC_OK;
 }
 
+int32_t orc_set_order_form(orc_tree* t, int32_t P, int32_t general) {
+  if (P < 2 || P > kMaxOrder || (P != 3 && !general)) return ORC_E_INVALID;
+  t->order = P;
+  t->general = general != 0;
+  if (t->have_moments && t->general)
+    for (size_t ci = 0; ci < t->cells.size(); ++ci)
+      moments_general(*t, t->cells[ci].begin, t->cells[ci].count, P, t->mom[ci]);
+  return ORC_OK;
+}
+
+int32_t orc_set_order(orc_tree* t, int32_t P) { return orc_set_order_form(t, P, P != 3); }
+
+int32_t orc_num_multi_indices(int32_t n) { return n < 0 || n > kMaxOrder + 1 ? 0 : kMI.count[n + 1]; }
+
+void orc_multi_indices(int32_t n, int32_t* exps) {
+  for (int g = 0; g < kMI.count[n + 1]; ++g)
+    for (int i = 0; i < 3; ++i) exps[3 * g + i] = kMI.e[g][i];
+}
+
+void orc_greens_general(const double* R3, double eps, int32_t n, double* D) {
+  std::vector<double> v;
+  greens_general(R3, eps * eps, n, v);
+  std::copy(v.begin(), v.end(), D);
+}
+
 int32_t orc_set_softening(orc_tree* t, double eps) {
   if (!(eps >= 0.0) || !std::isfinite(eps)) return ORC_E_INVALID;
   t->eps2 = eps * eps;
@@ -1455,55 +1692,63 @@ void orc_cluster_moments(int64_t n, const double* x, const double* y, const doub
   orc_free(t);
 }
 
+void orc_pair_far_order(int32_t order, int32_t general, int64_t nA, const double* xa, const double* ya, const double* za,
+                        const double* ma, int64_t nB, const double* xb, const double* yb, const double* zb,
+                        const double* mb, int32_t variant, double* gA, double* phiA, double* gB, double* phiB) {
+  // the two clusters as cells 0 and 1 of one tree, particles in caller order
+  orc_tree t;
+  t.n = nA + nB;
+  t.order = order;
+  t.general = general != 0 || order != 3;
+  t.x.assign(xa, xa + nA);
+  t.y.assign(ya, ya + nA);
+  t.z.assign(za, za + nA);
+  t.m.assign(ma, ma + nA);
+  t.x.insert(t.x.end(), xb, xb + nB);
+  t.y.insert(t.y.end(), yb, yb + nB);
+  t.z.insert(t.z.end(), zb, zb + nB);
+  t.m.insert(t.m.end(), mb, mb + nB);
+  t.cells.push_back(Cell{0, 0, nA, -1, -1, 0, 0});
+  t.cells.push_back(Cell{0, nA, nB, -1, -1, 0, 0});
+  for (int c = 0; c < 2; ++c) {
+    const Cell& C = t.cells[c];
+    Moments mo;
+    for (int64_t p = C.begin; p < C.begin + C.count; ++p) {
+      mo.M += t.m[p];
+      mo.S[0] += t.m[p] * t.x[p];
+      mo.S[1] += t.m[p] * t.y[p];
+      mo.S[2] += t.m[p] * t.z[p];
+    }
+    for (int d = 0; d < 3; ++d) mo.Z[d] = mo.S[d] / mo.M;
+    moments_about(t, C.begin, C.count, mo);
+    if (t.general) moments_general(t, C.begin, C.count, order, mo);
+    t.mom.push_back(mo);
+  }
+  const Moments& A = t.mom[0];
+  const Moments& B = t.mom[1];
+  PairField pf;
+  pair_field(t, 0, 1, variant, pf);
+  for (int64_t p = 0; p < nA; ++p) {
+    double xv[3] = {xa[p] - A.Z[0], ya[p] - A.Z[1], za[p] - A.Z[2]};
+    double g[3], phi;
+    pair_field_at(t, pf, 0, 1, 0, xv, g, phi);
+    for (int d = 0; d < 3; ++d) gA[3 * p + d] = g[d];
+    if (phiA) phiA[p] = phi;
+  }
+  for (int64_t p = 0; p < nB; ++p) {
+    double yv[3] = {xb[p] - B.Z[0], yb[p] - B.Z[1], zb[p] - B.Z[2]};
+    double g[3], phi;
+    pair_field_at(t, pf, 0, 1, 1, yv, g, phi);
+    for (int d = 0; d < 3; ++d) gB[3 * p + d] = g[d];
+    if (phiB) phiB[p] = phi;
+  }
+}
+
 void orc_pair_far(int64_t nA, const double* xa, const double* ya, const double* za,
                   const double* ma, int64_t nB, const double* xb, const double* yb,
                   const double* zb, const double* mb, int32_t variant, double* gA, double* phiA,
                   double* gB, double* phiB) {
-  // moments of each cluster as one cell, particles in caller order
-  auto cluster = [](int64_t n, const double* x, const double* y, const double* z,
-                    const double* m) {
-    orc_tree* t = new orc_tree();
-    t->n = n;
-    t->x.assign(x, x + n);
-    t->y.assign(y, y + n);
-    t->z.assign(z, z + n);
-    t->m.assign(m, m + n);
-    Cell c{0, 0, n, -1, -1, 0, 0};
-    t->cells.push_back(c);
-    Moments mo;
-    for (int64_t p = 0; p < n; ++p) {
-      mo.M += m[p];
-      mo.S[0] += m[p] * x[p];
-      mo.S[1] += m[p] * y[p];
-      mo.S[2] += m[p] * z[p];
-    }
-    for (int d = 0; d < 3; ++d) mo.Z[d] = mo.S[d] / mo.M;
-    moments_about(*t, 0, n, mo);
-    t->mom.push_back(mo);
-    return t;
-  };
-  orc_tree* ta = cluster(nA, xa, ya, za, ma);
-  orc_tree* tb = cluster(nB, xb, yb, zb, mb);
-  const Moments& A = ta->mom[0];
-  const Moments& B = tb->mom[0];
-  PairTerms pt;
-  pair_terms(A, B, variant, pt);
-  for (int64_t p = 0; p < nA; ++p) {
-    double xv[3] = {xa[p] - A.Z[0], ya[p] - A.Z[1], za[p] - A.Z[2]};
-    double g[3];
-    eq3_accel(pt.g, B, xv, g);
-    for (int d = 0; d < 3; ++d) gA[3 * p + d] = g[d] + pt.Fc[d] / A.M;
-    if (phiA) phiA[p] = eq2_pot_A(pt.g, B, xv);
-  }
-  for (int64_t p = 0; p < nB; ++p) {
-    double yv[3] = {xb[p] - B.Z[0], yb[p] - B.Z[1], zb[p] - B.Z[2]};
-    double g[3];
-    eq4_accel(pt.g, A, yv, g);
-    for (int d = 0; d < 3; ++d) gB[3 * p + d] = g[d] - pt.Fc[d] / B.M;
-    if (phiB) phiB[p] = eq2_pot_B(pt.g, A, yv);
-  }
-  delete ta;
-  delete tb;
+  orc_pair_far_order(3, 0, nA, xa, ya, za, ma, nB, xb, yb, zb, mb, variant, gA, phiA, gB, phiB);
 }
 
 }  // extern "C"

@@ -149,6 +149,25 @@ void orc_pair_far(int64_t nA, const double* xa, const double* ya, const double* 
                   const double* ma, int64_t nB, const double* xb, const double* yb,
                   const double* zb, const double* mb, int32_t variant, double* gA, double* phiA,
                   double* gB, double* phiB);
+/* The same at expansion order P (the appendix's general form when general
+ * != 0 or P != 3; P = 3 otherwise is orc_pair_far; TCO only in the printed
+ * form). */
+void orc_pair_far_order(int32_t order, int32_t general, int64_t nA, const double* xa, const double* ya, const double* za,
+                        const double* ma, int64_t nB, const double* xb, const double* yb, const double* zb,
+                        const double* mb, int32_t variant, double* gA, double* phiA, double* gB, double* phiB);
+/* Expansion order P of the tree's evaluation (2 <= P <= 6; default 3, the
+ * printed equations; other orders use the appendix's general expansion and
+ * correction, UC and TC only).  Recomputes the moments it needs. */
+int32_t orc_set_order(orc_tree* t, int32_t P);
+/* The same with the form chosen: general != 0 evaluates the appendix's
+ * general form also at P = 3 (a check of it against the printed equations). */
+int32_t orc_set_order_form(orc_tree* t, int32_t P, int32_t general);
+/* Multi-indices (a, b, c) of order <= n in the graded order the general form
+ * uses (count, then 3 ints each), and D_alpha(R) of the softened Green's
+ * function (eps = 0: -1/R) for |alpha| <= n in that order. */
+int32_t orc_num_multi_indices(int32_t n);
+void orc_multi_indices(int32_t n, int32_t* exps);
+void orc_greens_general(const double* R3, double eps, int32_t n, double* D);
 
 /* ---- learned pair selection (not in the paper; see the notes in oracle.cpp) ----
  * Model: ORC_MLP_MODEL floats (network, then feature normalisation a[8], b[8]

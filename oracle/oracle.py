@@ -73,6 +73,16 @@ def lib():
         L.orc_greens_softened.argtypes = [d, C.c_double, d, d, d, d, d, d]
         L.orc_set_softening.restype = C.c_int32
         L.orc_set_softening.argtypes = [P, C.c_double]
+        L.orc_set_order.restype = C.c_int32
+        L.orc_set_order.argtypes = [P, C.c_int32]
+        L.orc_set_order_form.restype = C.c_int32
+        L.orc_set_order_form.argtypes = [P, C.c_int32, C.c_int32]
+        L.orc_num_multi_indices.restype = C.c_int32
+        L.orc_num_multi_indices.argtypes = [C.c_int32]
+        L.orc_multi_indices.argtypes = [C.c_int32, i32]
+        L.orc_greens_general.argtypes = [d, C.c_double, C.c_int32, d]
+        L.orc_pair_far_order.argtypes = [C.c_int32, C.c_int32, C.c_int64, d, d, d, d, C.c_int64, d, d, d, d, C.c_int32,
+                                         d, d, d, d]
         L.orc_direct_softened.restype = C.c_int32
         L.orc_direct_softened.argtypes = [C.c_int64, d, d, d, d, C.c_int64, i64, C.c_double, C.c_double,
                                           d, d, d, d, d]
@@ -125,7 +135,7 @@ def multipole_weights():
 class Tree:
     """Octree of the oracle: build (a1-a4), moments (a5), walk (a6), evaluate."""
 
-    def __init__(self, x, y, z, m, n_crit=25, max_level=MAX_LEVEL, softening=0.0):
+    def __init__(self, x, y, z, m, n_crit=25, max_level=MAX_LEVEL, softening=0.0, order=3):
         self._keep = [_f64(v) for v in (x, y, z, m)]
         x, y, z, m = self._keep
         st = C.c_int32(0)
@@ -136,6 +146,17 @@ class Tree:
             raise OracleError(st.value)
         if softening:
             self.set_softening(softening)
+        if order != 3:
+            self.set_order(order)
+
+    def set_order(self, P, general=None):
+        """Expansion order P of every later evaluation (3: the printed
+        equations; others, or general=True: the appendix's general form, UC
+        and TC)."""
+        g = (P != 3) if general is None else bool(general)
+        st = lib().orc_set_order_form(self._t, int(P), int(g))
+        if st:
+            raise OracleError(st)
 
     def set_softening(self, eps):
         """Plummer softening length of every later evaluation (0 = plain 1/R)."""
@@ -313,10 +334,10 @@ def use_openmp_build():
         os.environ["AMFMM_ORACLE_LIB"] = ensure_built_omp()
 
 
-def solve(x, y, z, m, theta=0.5, n_crit=25, variant=TC, G=1.0, softening=0.0):
+def solve(x, y, z, m, theta=0.5, n_crit=25, variant=TC, G=1.0, softening=0.0, order=3):
     """Whole FMM solve; returns (acc[3,n], pot[n]) in caller order."""
-    if softening:
-        t = Tree(x, y, z, m, n_crit=n_crit, softening=softening)
+    if softening or order != 3:
+        t = Tree(x, y, z, m, n_crit=n_crit, softening=softening, order=order)
         t.compute_moments()
         t.walk(theta)
         a, p = t.evaluate(variant, G)
@@ -448,7 +469,23 @@ def cluster_moments(x, y, z, m):
     return out
 
 
-def pair_far(A, B, variant=TC):
+def multi_indices(n):
+    """Multi-indices (a, b, c) of order <= n, graded ([k, 3] int array)."""
+    k = lib().orc_num_multi_indices(int(n))
+    out = np.zeros((k, 3), np.int32)
+    lib().orc_multi_indices(int(n), out.ctypes.data_as(C.POINTER(C.c_int32)))
+    return out
+
+
+def greens_general(R, n, eps=0.0):
+    """D_alpha(R) for |alpha| <= n in the order of multi_indices(n)."""
+    R = _f64(R)
+    out = np.zeros(lib().orc_num_multi_indices(int(n)))
+    lib().orc_greens_general(_d(R), float(eps), int(n), _d(out))
+    return out
+
+
+def pair_far(A, B, variant=TC, order=3, general=False):
     """A, B: (x, y, z, m) tuples.  Far-field accelerations [n,3] and potentials."""
     xa, ya, za, ma = (_f64(v) for v in A)
     xb, yb, zb, mb = (_f64(v) for v in B)
@@ -457,8 +494,8 @@ def pair_far(A, B, variant=TC):
     gB = np.zeros((nb, 3))
     pA = np.zeros(na)
     pB = np.zeros(nb)
-    lib().orc_pair_far(na, _d(xa), _d(ya), _d(za), _d(ma), nb, _d(xb), _d(yb), _d(zb), _d(mb),
-                       variant, _d(gA), _d(pA), _d(gB), _d(pB))
+    lib().orc_pair_far_order(int(order), int(general), na, _d(xa), _d(ya), _d(za), _d(ma), nb, _d(xb), _d(yb), _d(zb), _d(mb),
+                             variant, _d(gA), _d(pA), _d(gB), _d(pB))
     return gA, pA, gB, pB
 
 

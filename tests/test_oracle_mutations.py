@@ -33,9 +33,17 @@ def pins_for(name):
         return LEARNED_PINS
     if name.startswith("soft_"):
         return ["tests/test_oracle_softening.py"]
+    if name.startswith("order_"):
+        return ["tests/test_oracle_order.py"]
     return CORE_PINS
 
 MUTATIONS = {
+    "order_correction_sign": ("    gp.Fc[k] = -s;", "    gp.Fc[k] = s;"),
+    "order_drop_quadrupole_pair": ("      if (n == 1 || P - n == 1) continue;",
+                                   "      if (n == 1 || P - n == 1 || (n > 0 && n < P)) continue;"),
+    "order_source_sign": ("      double sb = (nb % 2) ? -1.0 : 1.0;", "      double sb = 1.0;"),
+    "order_mirror_sign": ("    if (kMI.order[al] % 2) gp.Lb[al] = -gp.Lb[al];", ""),
+    "order_pairing_count": ("            ways /= power(2.0, b[i]);", "            ways /= 1.0;"),
     "correction_prefactor_half": ("pt.Fc[i] = -(1.0 / 6.0) * s;", "pt.Fc[i] = -(0.5) * s;"),
     "correction_sign": ("pt.Fc[i] = -(1.0 / 6.0) * s;", "pt.Fc[i] = (1.0 / 6.0) * s;"),
     "separation_sign": ("double R[3] = {A.Z[0] - B.Z[0], A.Z[1] - B.Z[1], A.Z[2] - B.Z[2]};",
