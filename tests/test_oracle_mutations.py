@@ -46,8 +46,10 @@ MUTATIONS = {
     "order_pairing_count": ("            ways /= power(2.0, b[i]);", "            ways /= 1.0;"),
     "correction_prefactor_half": ("pt.Fc[i] = -(1.0 / 6.0) * s;", "pt.Fc[i] = -(0.5) * s;"),
     "correction_sign": ("pt.Fc[i] = -(1.0 / 6.0) * s;", "pt.Fc[i] = (1.0 / 6.0) * s;"),
-    "separation_sign": ("double R[3] = {A.Z[0] - B.Z[0], A.Z[1] - B.Z[1], A.Z[2] - B.Z[2]};",
-                        "double R[3] = {B.Z[0] - A.Z[0], B.Z[1] - A.Z[1], B.Z[2] - A.Z[2]};"),
+    "separation_sign": ("double R[3] = {A.Z[0] - B.Z[0], A.Z[1] - B.Z[1], A.Z[2] - B.Z[2]};\n  if (eps2 > 0.0)",
+                        "double R[3] = {B.Z[0] - A.Z[0], B.Z[1] - A.Z[1], B.Z[2] - A.Z[2]};\n  if (eps2 > 0.0)"),
+    "order_separation_sign": ("double R[3] = {A.Z[0] - B.Z[0], A.Z[1] - B.Z[1], A.Z[2] - B.Z[2]};\n  std::vector<double> D;",
+                              "double R[3] = {B.Z[0] - A.Z[0], B.Z[1] - A.Z[1], B.Z[2] - A.Z[2]};\n  std::vector<double> D;"),
     "eq3_quadrupole_half_dropped": ("    c0 += 0.5 * q;", "    c0 += q;"),
     "eq4_cubic_sign": ("out[i] = -(c0 + c1 - 0.5 * c2);", "out[i] = -(c0 + c1 + 0.5 * c2);"),
     "d3_coefficient": ("(15.0 * R[i] * R[j] * R[k] -", "(5.0 * R[i] * R[j] * R[k] -"),
