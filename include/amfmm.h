@@ -101,13 +101,22 @@ typedef struct {
                          default) is the plain -1/R.  Pairs at r = 0 are skipped
                          either way.  The walk's criteria and the learned features and
                          labels do not depend on it. */
+  int32_t order;      /* expansion order P of the far field (appendix: the Green's
+                         function expanded to order P in both cells' offsets, with the
+                         corrective force of order P that cancels each pair's torque):
+                         3 (default) is eqs. 2-4 and 7/8 as printed; 4 adds the octupole
+                         to the field and the hexadecapole (and the quadrupole-quadrupole
+                         term) to the correction, FP64 only, UC or TC (eq. 8's tensor is
+                         printed for P = 3 only); other values are AMFMM_E_INVALID.  The
+                         walk's criteria are unchanged; amfmm_solve_gravity_noalloc takes
+                         order 3 only. */
 } amfmm_options;
 
 typedef struct amfmm_ctx amfmm_ctx;
 
 /* Fills *opt with n_crit = 25, TC, FP64, geometric, G = 1, error_tol = 1e-4,
  * theta_max = 1, max_bytes = 0, list_bytes = 0, learned_min_work = 262144,
- * softening = 0. */
+ * softening = 0, order = 3. */
 int amfmm_default_options(amfmm_options* opt);
 
 /* Creates a context bound to hip_stream (a hipStream_t; NULL = null stream)

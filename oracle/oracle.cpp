@@ -312,9 +312,9 @@ void greens_general(const double R[3], double eps2, int nmax, std::vector<double
   }
 }
 
-// x^alpha for every |alpha| <= n
-void monomials(const double x[3], int n, std::vector<double>& out) {
-  out.assign(kMI.count[n + 1], 0.0);
+// x^alpha for every |alpha| <= n (out holds kMI.count[n + 1] values)
+constexpr int kMaxMono = (kMaxOrder + 1) * (kMaxOrder + 2) * (kMaxOrder + 3) / 6;
+void monomials(const double x[3], int n, double* out) {
   for (int g = 0; g < kMI.count[n + 1]; ++g)
     out[g] = power(x[0], kMI.e[g][0]) * power(x[1], kMI.e[g][1]) * power(x[2], kMI.e[g][2]);
 }
@@ -322,11 +322,11 @@ void monomials(const double x[3], int n, std::vector<double>& out) {
 // M_alpha = sum mu x^alpha about Z, |alpha| <= P, of the particles [b, b+cnt)
 void moments_general(const orc_tree& t, int64_t b, int64_t cnt, int P, Moments& mo) {
   mo.mono.assign(kMI.count[P + 1], 0.0);
-  std::vector<double> xm;
+  double xm[kMaxMono];
   for (int64_t p = b; p < b + cnt; ++p) {
     double xv[3] = {t.x[p] - mo.Z[0], t.y[p] - mo.Z[1], t.z[p] - mo.Z[2]};
     monomials(xv, P, xm);
-    for (size_t g = 0; g < xm.size(); ++g) mo.mono[g] += t.m[p] * xm[g];
+    for (int g = 0; g < kMI.count[P + 1]; ++g) mo.mono[g] += t.m[p] * xm[g];
   }
 }
 
@@ -392,7 +392,7 @@ void general_pair(const Moments& A, const Moments& B, int variant, int P, double
 // acceleration (minus the gradient) and potential of a local expansion L of
 // order P at offset x
 void general_local_at(const std::vector<double>& L, int P, const double x[3], double g[3], double& phi) {
-  std::vector<double> xm;
+  double xm[kMaxMono];
   monomials(x, P, xm);
   phi = 0.0;
   for (int al = 0; al < kMI.count[P + 1]; ++al) phi += xm[al] / kMI.fact[al] * L[al];

@@ -28,7 +28,7 @@ class amfmm_options(C.Structure):
     _fields_ = [("n_crit", C.c_int32), ("variant", C.c_int32), ("precision", C.c_int32),
                 ("criterion", C.c_int32), ("G", C.c_double), ("error_tol", C.c_double),
                 ("theta_max", C.c_double), ("max_bytes", C.c_int64), ("list_bytes", C.c_int64),
-                ("learned_min_work", C.c_int64), ("softening", C.c_double)]
+                ("learned_min_work", C.c_int64), ("softening", C.c_double), ("order", C.c_int32)]
 
 
 _lib = None
@@ -135,7 +135,7 @@ class Solver:
 
     def __init__(self, n_crit=25, variant=TC, precision=FP64, criterion=GEOMETRIC, G=1.0,
                  error_tol=1e-4, theta_max=1.0, max_bytes=0, list_bytes=0, learned_min_work=1 << 18,
-                 stream=None, softening=0.0):
+                 stream=None, softening=0.0, order=3):
         L = lib()
         o = amfmm_options()
         L.amfmm_default_options(C.byref(o))
@@ -144,6 +144,7 @@ class Solver:
         o.list_bytes = list_bytes
         o.learned_min_work = learned_min_work
         o.softening = softening
+        o.order = order
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = C.c_void_p()
         st = L.amfmm_create(C.byref(o), C.c_void_p(self.stream.cuda_stream), C.byref(h))

@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libamfmm_hip.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["api.hip", "scan.hip", "sort.hip", "tree.hip", "moments.hip", "walk.hip", "eval.hip", "near.hip",
-           "direct.hip", "mlp.hip", "integrate.hip"]
+           "direct.hip", "mlp.hip", "integrate.hip", "order.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall",

@@ -150,7 +150,7 @@ static DevBuf* all_bufs(Ctx& c, int i) {
                  &c.c_begin, &c.c_count, &c.c_parent, &c.c_child0, &c.c_nchild, &c.leaves, &c.geo, &c.mom,
                  &c.msum, &c.loc, &c.far_start, &c.far_count, &c.far_src, &c.near_start, &c.near_count,
                  &c.near_src, &c.fx, &c.fy, &c.fx2, &c.fy2, &c.fcnt, &c.grp, &c.walkrec, &c.fsave, &c.gsave, &c.counters, &c.gqueue, &c.stage, &c.farrec, &c.gmin, &c.model, &c.mlp_tmp, &c.mlp_part,
-                 &c.mlp_grad};
+                 &c.mlp_grad, &c.mono, &c.locg};
   const int nv = (int)(sizeof(v) / sizeof(v[0]));
   return i < nv ? v[i] : nullptr;
 }
@@ -247,6 +247,7 @@ int amfmm_default_options(amfmm_options* o) {
   o->max_bytes = 0;
   o->list_bytes = 0;
   o->softening = 0.0;
+  o->order = 3;
   return AMFMM_OK;
 }
 
@@ -257,6 +258,8 @@ static int check_options(const amfmm_options* o) {
   if (o->criterion < AMFMM_GEOMETRIC || o->criterion > AMFMM_MULTIPOLE) return AMFMM_E_INVALID;
   if (!(o->G == o->G) || o->max_bytes < 0 || o->list_bytes < 0 || o->learned_min_work < 0) return AMFMM_E_INVALID;
   if (!(o->softening >= 0.0) || !std::isfinite(o->softening)) return AMFMM_E_INVALID;
+  if (o->order != 3 && (o->order != 4 || o->precision != AMFMM_FP64 || o->variant == AMFMM_TCO))
+    return AMFMM_E_INVALID;
   return AMFMM_OK;
 }
 
@@ -417,6 +420,7 @@ static int moments_impl(Ctx& c) {
   if (c.ev_used) --c.ev_used;  // continue the timeline of the tree build
   amfmm::mark(c, amfmm::kPhMoments);
   amfmm::upward_pass(c);
+  if (c.opt.order != 3) amfmm::order_upward(c);
   amfmm::far_prepare(c);
   amfmm::mark(c, amfmm::kPhEnd);
   return AMFMM_OK;
@@ -694,6 +698,7 @@ int amfmm_solve_gravity_noalloc(amfmm_ctx* ctx, int64_t n, const double* x, cons
     if (n > amfmm::kNoAllocMaxN)
       return fail(c, AMFMM_E_INVALID, "allocation-free solve: n exceeds its maximum of 2^18 particles");
     if (c.arena) return fail(c, AMFMM_E_STATE, "allocation-free solve already running on this context");
+    if (c.opt.order != 3) return fail(c, AMFMM_E_INVALID, "allocation-free solve: expansion order 3 only");
     struct Saved {
       Ctx& c;
       std::vector<amfmm::DevBuf> bufs;

@@ -300,6 +300,11 @@ void far_field(Ctx& c, int32_t c_lo, int32_t c_hi) {
   if (nc <= 0) return;
   double* loc = (double*)ensure_keep(c, c.loc, sizeof(double) * kLoc * (size_t)c.ncells,
                                      sizeof(double) * kLoc * (size_t)c.ncells);
+  if (c.opt.order != 3) {
+    ++c.far_launches;
+    order_far(c, c_lo, c_hi, loc);
+    return;
+  }
   dim3 grid(blocks_for(nc, kWaves));
   if (use_records(c)) {
     ++c.far_launches;
@@ -327,6 +332,10 @@ void far_field(Ctx& c, int32_t c_lo, int32_t c_hi) {
 void push_down(Ctx& c, int32_t c_lo, int32_t c_hi) {
   const int32_t nl = c_hi - c_lo;
   if (nl <= 0) return;
+  if (c.opt.order != 3) {  // the order-3 records hold zeros
+    order_push_down(c, c_lo, c_hi);
+    return;
+  }
   hipLaunchKernelGGL(k_l2l, dim3(blocks_for(nl, kBS)), dim3(kBS), 0, c.stream, c_lo, nl, as<int32_t>(c.c_parent),
                      (const double4*)c.geo.p, as<double>(c.loc));
   AMFMM_HIP(hipGetLastError());

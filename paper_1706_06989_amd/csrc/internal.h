@@ -16,6 +16,7 @@ constexpr int kMaxLevel = 21;  // Morton key resolution per coordinate
 constexpr int kGeo = 4;        // per cell: Zx, Zy, Zz, R_max
 constexpr int kMom = 18;       // per cell: M, M_ij (6), M_ijk (10), pad
 constexpr int kLoc = 24;       // per cell: C (1), C_k (3), C_kl (6), C_klm (10), g_c (3), pad
+constexpr int kLocGen = 40;    // expansion order 4: 35 local coefficients, g_c (3), pad
 
 // index of a symmetric pair / triple inside the packed arrays
 //   pairs   xx xy xz yy yz zz
@@ -73,6 +74,8 @@ struct Ctx {
   DevBuf mom;      // kMom doubles per cell
   DevBuf msum;     // double4 per cell: sum m*X (x,y,z), unused
   DevBuf loc;      // kLoc doubles per cell
+  DevBuf mono;     // expansion order 4: 35 moments per cell (sum mu x^alpha, |alpha| <= 4)
+  DevBuf locg;     // expansion order 4: kLocGen doubles per cell
   // directed interaction lists grouped by target cell
   int64_t n_far = 0, n_near = 0;
   DevBuf far_start, far_count, far_src;     // int32 (start as int64)
@@ -181,6 +184,12 @@ void group_arrays(Ctx& c, int64_t** gbeg, int32_t** gcnt);  // current level's g
 // field (after the moments)
 void far_prepare(Ctx& c);
 void far_field(Ctx& c, int32_t c_lo, int32_t c_hi);
+// expansion order 4 (order.hip): moments, far field, push-down, evaluation at the particles
+void order_upward(Ctx& c);
+void order_far(Ctx& c, int32_t c_lo, int32_t c_hi, double* loc);
+void order_push_down(Ctx& c, int32_t c_lo, int32_t c_hi);
+void order_l2p(Ctx& c, const int32_t* leaves, int32_t c_lo, int32_t count, double* ax, double* ay, double* az,
+               double* pot);
 void push_down(Ctx& c, int32_t c_lo, int32_t c_hi);  // cells of one level
 // leaves != nullptr: the first `count` leaves of that list; else the leaves
 // among cells [c_lo, c_lo + count)

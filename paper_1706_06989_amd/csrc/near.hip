@@ -379,6 +379,7 @@ void near_field(Ctx& c, const int32_t* leaves, int32_t c_lo, int32_t count, doub
                      (const int32_t*)c.near_count.p, (const int32_t*)c.near_src.p, as<int32_t>(c.perm), c.opt.G, ax,
                      ay, az, pot, (unsigned long long*)c.counters.p, c.opt.softening * c.opt.softening);
   AMFMM_HIP(hipGetLastError());
+  if (c.opt.order != 3) order_l2p(c, leaves, c_lo, count, ax, ay, az, pot);
 }
 
 }  // namespace amfmm

@@ -1,0 +1,81 @@
+"""The appendix's expansion order P = 4 on the GPU (FP64, UC and TC) through
+the C ABI, against the oracle's general form at P = 4: accelerations to
+1e-12 of gabs and potentials to 1e-12 relative, plain and softened; the
+balances at round-off (zero net torque with the correction at this order);
+the error against direct summation below the order-3 solve's; the option
+checks."""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_1706_06989_amd import amfmm
+from paper_1706_06989_amd import workloads as W
+from tests.gpu_util import dup_points, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "uniform4k": lambda: W.uniform_cube(4096, seed=1),
+    "plummer16k": lambda: W.plummer(16384, seed=2),
+    "twoplummer20k": lambda: W.two_plummer(20000, seed=3),
+    "duplicates": dup_points,
+}
+
+
+def host(o):
+    return np.stack([v.cpu().numpy() for v in o])
+
+
+@pytest.mark.parametrize("name,softening", [(n, 0.0) for n in sorted(CASES)] + [("plummer16k", 0.01)])
+def test_order4_matches_oracle(name, softening):
+    x, y, z, m = CASES[name]()
+    say("order 4", name, len(x), softening)
+    X, Y, Z, M = to_dev(x, y, z, m)
+    _, _, gabs = orc.direct(x, y, z, m, softening=softening)
+    for variant in (amfmm.UC, amfmm.TC):
+        oa, op = orc.solve(x, y, z, m, theta=0.5, variant=variant, softening=softening, order=4)
+        s = amfmm.Solver(variant=variant, softening=softening, order=4)
+        o = s.solve_gravity(X, Y, Z, M, 0.5)
+        a = host(o)
+        err = np.linalg.norm(a[:3] - oa, axis=0) / gabs
+        perr = np.abs(a[3] - op) / np.abs(op)
+        fb, tb = s.balance(X, Y, Z, M, o[0], o[1], o[2])
+        s.close()
+        say(f"  variant {variant}: max {err.max():.1e}, pot {perr.max():.1e}, balances {fb:.1e} {tb:.1e}")
+        assert err.max() <= 1e-12 and perr.max() <= 1e-12, (variant, err.max(), perr.max())
+        assert fb <= 1e-13
+        if variant == amfmm.TC:
+            assert tb <= 1e-13
+
+
+def test_order4_is_more_accurate_and_conserves():
+    x, y, z, m = W.plummer(65536, seed=7)
+    say("order 4 against order 3, plummer 65536")
+    X, Y, Z, M = to_dev(x, y, z, m)
+    idx = W.sample_targets(len(x), 2048, seed=99)
+    at, _, _ = orc.direct(x, y, z, m, idx)
+    p99 = {}
+    for order in (3, 4):
+        for variant in (amfmm.UC, amfmm.TC):
+            s = amfmm.Solver(variant=variant, order=order)
+            o = s.solve_gravity(X, Y, Z, M, 0.5, pot=False)
+            a = np.stack([o[k].cpu().numpy()[idx] for k in range(3)])
+            e = np.linalg.norm(a - at, axis=0) / np.linalg.norm(at, axis=0)
+            fb, tb = s.balance(X, Y, Z, M, o[0], o[1], o[2])
+            s.close()
+            p99[(order, variant)] = np.percentile(e, 99)
+            say(f"  order {order} variant {variant}: p99 {p99[(order, variant)]:.2e}, balances {fb:.1e} {tb:.1e}")
+            assert fb <= 1e-13
+            if variant == amfmm.TC:
+                assert tb <= 1e-13
+            else:
+                assert tb >= 1e-9
+    assert p99[(4, amfmm.TC)] <= 0.5 * p99[(3, amfmm.TC)]
+
+
+def test_order_option_checks():
+    for kw in ({"order": 5}, {"order": 2}, {"order": 4, "precision": amfmm.MIXED},
+               {"order": 4, "variant": amfmm.TCO}):
+        with pytest.raises(amfmm.AmfmmError) as e:
+            amfmm.Solver(**kw)
+        assert e.value.code == amfmm.E_INVALID
