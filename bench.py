@@ -27,8 +27,10 @@ angles; its time at the timed solve's own p99, interpolated log-log between
 the two angles that bracket it, and the speedup over it; also the speedup at
 the largest grid angle that meets p99 1e-4),
 `mixed_geometric` (the mixed-precision geometric solve at --theta against the
-FP64 one: times, errors, residuals) and the median of the per-step HIP-event
-totals.
+FP64 one: times, errors, residuals), `order4` (the same step at expansion
+order 4, the appendix's general order, with its own tolerance: time, error,
+balances; outside the timed region, the headline stays the quadrupole-order
+solve) and the median of the per-step HIP-event totals.
 """
 import argparse
 import hashlib
@@ -99,6 +101,10 @@ def parse():
     p.add_argument("--plain-thetas", default="0.5,0.1,0.095",
                    help="opening angles of the plain solve (FP64, geometric, same variant, no pilot) "
                         "timed after the benchmark for the matched-error speedup; empty = skip")
+    p.add_argument("--order4-eps", type=float, default=1.75e-5,
+                   help="error-estimate criterion: also time the same step at expansion order 4 with this "
+                        "tolerance, outside the timed region (0 = skip)")
+    p.add_argument("--order4-steps", type=int, default=5)
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain device copy of known size (scale for HBM byte counters)")
     return p.parse_args()
@@ -385,6 +391,47 @@ def main():
                 "mixed_force_balance": fb, "mixed_torque_balance": tb,
                 "fp64_force_balance": fb64, "fp64_torque_balance": tb64}
 
+    # The same step at expansion order 4 (the appendix's general order: the
+    # octupole in the field, the order-4 correction), outside the timed
+    # region: pilot + order-4 solve, its own warm-up and steps, its error at
+    # the same targets.
+    order4 = None
+    if field and a.order4_eps > 0 and a.order4_steps > 0:
+        s4 = amfmm.Solver(variant=variant, precision=prec, criterion=crit, error_tol=a.order4_eps,
+                          theta_max=a.theta_max, order=4)
+        o4 = s4._outputs(a.n, True)
+        s4.set_field_estimate(pout[0], pout[1], pout[2])
+
+        def step4():
+            pilot.solve_gravity(X, Y, Z, M, a.pilot_theta, out=pout)
+            s4.solve_gravity(X, Y, Z, M, a.theta, out=o4)
+
+        step4()
+        torch.cuda.synchronize()
+        ph4 = {}
+        t1 = time.perf_counter()
+        for i in range(a.order4_steps):
+            step4()
+            for k, v in s4.get_phase_times().items():
+                ph4[k] = ph4.get(k, 0.0) + v
+        torch.cuda.synchronize()
+        ms4 = (time.perf_counter() - t1) / a.order4_steps * 1e3
+        e4 = p_err(o4)
+        fb4, tb4 = s4.balance(X, Y, Z, M, o4[0], o4[1], o4[2])
+        c4 = s4.get_counts()
+        order4 = {"order": 4, "precision": a.precision + " near field; far field, push-down and evaluation FP64",
+                  "criterion": a.criterion, "eps": a.order4_eps, "theta_max": a.theta_max, "steps": a.order4_steps,
+                  "ms_per_step": round(ms4, 3), "value": a.n / (ms4 * 1e-3), "unit": "particles/s",
+                  "p99_rel_force_error": float(np.percentile(e4, 99)),
+                  "max_rel_force_error": float(e4.max()), "meets_1e-4_p99": bool(np.percentile(e4, 99) <= 1e-4),
+                  "force_balance": fb4, "torque_balance": tb4,
+                  "phase_ms": {k: round(v / a.order4_steps, 3) for k, v in ph4.items()},
+                  "counts": {k: c4[k] for k in ("far_evaluations", "near_interactions", "walk_candidates")},
+                  "speedup_over_order3": round(ms / ms4, 3)}
+        s4.close()
+        del o4
+        print(f"# order 4: {ms4:.1f} ms/step", file=sys.stderr, flush=True)
+
     plain = None
     mixed_geo = None
     thetas = [float(t) for t in a.plain_thetas.split(",") if t.strip()]
@@ -458,6 +505,7 @@ def main():
                    "force_balance": fbal, "torque_balance": tbal,
                    "phase_ms": {k: round(v, 3) for k, v in phases.items()}, "counts": counts},
         "roofline": roofline, "cpu_baseline": cpu, "plain_fp64": plain, "mixed_geometric": mixed_geo,
+        "order4": order4,
     }
     if a.copy_calibration:
         # 1 GiB read + 1 GiB written by one copy kernel per call

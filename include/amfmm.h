@@ -106,8 +106,10 @@ typedef struct {
                          corrective force of order P that cancels each pair's torque):
                          3 (default) is eqs. 2-4 and 7/8 as printed; 4 adds the octupole
                          to the field and the hexadecapole (and the quadrupole-quadrupole
-                         term) to the correction, FP64 only, UC or TC (eq. 8's tensor is
-                         printed for P = 3 only); other values are AMFMM_E_INVALID.  The
+                         term) to the correction, UC or TC (eq. 8's tensor is printed for
+                         P = 3 only); its far field, push-down and evaluation at the
+                         particles are FP64 at either precision (MIXED then makes the near
+                         field's pair terms FP32); other values are AMFMM_E_INVALID.  The
                          walk's criteria are unchanged; amfmm_solve_gravity_noalloc takes
                          order 3 only. */
 } amfmm_options;

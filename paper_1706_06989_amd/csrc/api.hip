@@ -258,7 +258,7 @@ static int check_options(const amfmm_options* o) {
   if (o->criterion < AMFMM_GEOMETRIC || o->criterion > AMFMM_MULTIPOLE) return AMFMM_E_INVALID;
   if (!(o->G == o->G) || o->max_bytes < 0 || o->list_bytes < 0 || o->learned_min_work < 0) return AMFMM_E_INVALID;
   if (!(o->softening >= 0.0) || !std::isfinite(o->softening)) return AMFMM_E_INVALID;
-  if (o->order != 3 && (o->order != 4 || o->precision != AMFMM_FP64 || o->variant == AMFMM_TCO))
+  if (o->order != 3 && (o->order != 4 || o->variant == AMFMM_TCO))
     return AMFMM_E_INVALID;
   return AMFMM_OK;
 }

@@ -284,7 +284,7 @@ void zero_u64(Ctx& c, unsigned long long* p, int n) {
 // the 128-byte records carry traceless octupoles, enough for the correction
 // of the plain -1/R only (mixed UC and TC)
 static bool use_records(const Ctx& c) {
-  return c.opt.precision == AMFMM_MIXED && c.opt.variant != AMFMM_TCO && c.opt.softening == 0.0;
+  return c.opt.precision == AMFMM_MIXED && c.opt.variant != AMFMM_TCO && c.opt.softening == 0.0 && c.opt.order == 3;
 }
 
 void far_prepare(Ctx& c) {

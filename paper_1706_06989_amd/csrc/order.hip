@@ -183,7 +183,37 @@ constexpr ShiftTerms make_shift() {
 constexpr ShiftTerms kShift = make_shift();
 static_assert(kNLocal == 135 && kNCorr == 66, "term counts at P = 4");
 
-// D_gamma(R), |gamma| <= P + 1
+// Derivative terms: D_gamma = sum over the pairings (p, q, r pairs among the
+// x, y and z indices of gamma) of f_(|gamma| - p - q - r) times the number of
+// such pairings times R^(gamma - 2 (p, q, r)).
+struct DerivTerm {
+  int g, f, e0, e1, e2;
+  double coef;
+};
+constexpr int count_deriv() {
+  int k = 0;
+  for (int g = 0; g < kND; ++g) k += (kMI.a[g] / 2 + 1) * (kMI.b[g] / 2 + 1) * (kMI.c[g] / 2 + 1);
+  return k;
+}
+constexpr int kNDeriv = count_deriv();
+struct DerivTerms {
+  DerivTerm t[kNDeriv];
+};
+constexpr DerivTerms make_deriv() {
+  DerivTerms r{};
+  int k = 0;
+  for (int g = 0; g < kND; ++g)
+    for (int p = 0; 2 * p <= kMI.a[g]; ++p)
+      for (int q = 0; 2 * q <= kMI.b[g]; ++q)
+        for (int u = 0; 2 * u <= kMI.c[g]; ++u)
+          r.t[k++] = {g, kMI.n[g] - p - q - u, kMI.a[g] - 2 * p, kMI.b[g] - 2 * q, kMI.c[g] - 2 * u,
+                      pair_ways(kMI.a[g], p) * pair_ways(kMI.b[g], q) * pair_ways(kMI.c[g], u)};
+  return r;
+}
+constexpr DerivTerms kDeriv = make_deriv();
+
+// D_gamma(R) for LO <= |gamma| <= HI (entries of other orders untouched)
+template <int LO, int HI>
 __device__ inline void derivatives(const double R[3], double eps2, double D[kND]) {
   const double s = ((R[0] * R[0] + R[1] * R[1]) + R[2] * R[2]) + eps2;
   double f[kP + 2];
@@ -198,22 +228,37 @@ __device__ inline void derivatives(const double R[3], double eps2, double D[kND]
     for (int k = 0; k <= kP; ++k) pw[i][k + 1] = pw[i][k] * R[i];
   }
 #pragma unroll
-  for (int g = 0; g < kND; ++g) {
-    const int a = kMI.a[g], b = kMI.b[g], c = kMI.c[g], n = kMI.n[g];
-    double sum = 0.0;
+  for (int g = num_mi(LO - 1); g < num_mi(HI); ++g) D[g] = 0.0;
 #pragma unroll
-    for (int p = 0; p <= (kP + 1) / 2; ++p)
-#pragma unroll
-      for (int q = 0; q <= (kP + 1) / 2; ++q)
-#pragma unroll
-        for (int r = 0; r <= (kP + 1) / 2; ++r) {
-          if (2 * p > a || 2 * q > b || 2 * r > c) continue;
-          sum += f[n - p - q - r] * ((pair_ways(a, p) * pair_ways(b, q) * pair_ways(c, r)) *
-                                     ((pw[0][a - 2 * p] * pw[1][b - 2 * q]) * pw[2][c - 2 * r]));
-        }
-    D[g] = sum;
+  for (int i = 0; i < kNDeriv; ++i) {
+    const DerivTerm& t = kDeriv.t[i];
+    if (kMI.n[t.g] < LO || kMI.n[t.g] > HI) continue;
+    D[t.g] += f[t.f] * (t.coef * ((pw[0][t.e0] * pw[1][t.e1]) * pw[2][t.e2]));
   }
 }
+
+// push-down shift: L'[al] += L[g] d^[ga] / ga!, g = al + ga, |al| + |ga| <= P
+constexpr int count_l2l() {
+  int k = 0;
+  for (int al = 0; al < kNL; ++al)
+    for (int ga = 0; ga < kNL; ++ga) k += kMI.n[al] + kMI.n[ga] <= kP;
+  return k;
+}
+constexpr int kNL2L = count_l2l();
+struct L2LTerms {
+  Term t[kNL2L];  // al: the child's coefficient, be: the power of d, g: the parent's coefficient
+};
+constexpr L2LTerms make_l2l() {
+  L2LTerms r{};
+  int k = 0;
+  for (int al = 0; al < kNL; ++al)
+    for (int ga = 0; ga < kNL; ++ga)
+      if (kMI.n[al] + kMI.n[ga] <= kP)
+        r.t[k++] = {al, ga, mi_id(kMI.a[al] + kMI.a[ga], kMI.b[al] + kMI.b[ga], kMI.c[al] + kMI.c[ga]),
+                    1.0 / kMI.fact[ga]};
+  return r;
+}
+constexpr L2LTerms kL2L = make_l2l();
 
 // x^alpha, |alpha| <= P
 __device__ inline void monomials(const double x[3], double X[kNL]) {
@@ -315,21 +360,34 @@ __global__ void __launch_bounds__(kBS) k_far_order(int32_t c_lo, int32_t nc, con
     const double4 gy = geo[Y];
     const double* my = mono + (int64_t)Y * kNL;
     const double R[3] = {gx.x - gy.x, gx.y - gy.y, gx.z - gy.z};
-    double D[kND];
-    derivatives(R, eps2, D);
+    // two phases, so that only part of the derivatives is live at a time:
+    // orders 0-4 for the coefficients of order <= P - 1, then orders P and
+    // P + 1 for those of order P and the correction
+    {
+      double D[kND];
+      derivatives<0, kP>(R, eps2, D);
 #pragma unroll
-    for (int i = 0; i < kNLocal; ++i) L[kLocal.t[i].al] += kLocal.t[i].coef * D[kLocal.t[i].g] * my[kLocal.t[i].be];
-    if (VARIANT != AMFMM_UC) {
-      double s[3] = {0.0, 0.0, 0.0};
+      for (int i = 0; i < kNLocal; ++i)
+        if (kMI.n[kLocal.t[i].al] < kP) L[kLocal.t[i].al] += kLocal.t[i].coef * D[kLocal.t[i].g] * my[kLocal.t[i].be];
+    }
+    {
+      double D[kND];
+      derivatives<kP, kP + 1>(R, eps2, D);
 #pragma unroll
-      for (int i = 0; i < kNCorr; ++i) {
-        const CorrTerm& t = kCorr.t[i];
-        const double w = t.coef * (mx[t.al] * my[t.be]);
+      for (int i = 0; i < kNLocal; ++i)
+        if (kMI.n[kLocal.t[i].al] == kP) L[kLocal.t[i].al] += kLocal.t[i].coef * D[kLocal.t[i].g] * my[kLocal.t[i].be];
+      if (VARIANT != AMFMM_UC) {
+        double s[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-        for (int k = 0; k < 3; ++k) s[k] += w * D[t.g[k]];
+        for (int i = 0; i < kNCorr; ++i) {
+          const CorrTerm& t = kCorr.t[i];
+          const double w = t.coef * (mx[t.al] * my[t.be]);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) s[k] += w * D[t.g[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) F[k] -= s[k];
       }
-#pragma unroll
-      for (int k = 0; k < 3; ++k) F[k] -= s[k];
     }
   }
 #pragma unroll
@@ -364,16 +422,16 @@ __global__ void __launch_bounds__(kBS) k_l2l_order(int32_t c0, int32_t nl, const
   monomials(d, Dm);
   const double* L = locg + (int64_t)P * kLocGen;
   double* o = locg + (int64_t)c * kLocGen;
+  double Lp[kNL], acc[kNL];
 #pragma unroll
-  for (int al = 0; al < kNL; ++al) {
-    double v = 0.0;
-#pragma unroll
-    for (int ga = 0; ga < kNL; ++ga) {
-      if (kMI.n[al] + kMI.n[ga] > kP) continue;
-      v += L[mi_id(kMI.a[al] + kMI.a[ga], kMI.b[al] + kMI.b[ga], kMI.c[al] + kMI.c[ga])] * Dm[ga] / kMI.fact[ga];
-    }
-    o[al] += v;
+  for (int g = 0; g < kNL; ++g) {
+    Lp[g] = L[g];
+    acc[g] = 0.0;
   }
+#pragma unroll
+  for (int i = 0; i < kNL2L; ++i) acc[kL2L.t[i].al] += Lp[kL2L.t[i].g] * (Dm[kL2L.t[i].be] * kL2L.t[i].coef);
+#pragma unroll
+  for (int g = 0; g < kNL; ++g) o[g] += acc[g];
 #pragma unroll
   for (int k = 0; k < 3; ++k) o[kNL + k] += L[kNL + k];
 }
