@@ -13,6 +13,8 @@
 // (TC) the acceleration g_c = F_c / M_X,
 //   F_c,k = -sum_n (-1)^n sum_{|alpha| = P-n, |beta| = n} M_X,alpha M_Y,beta
 //           D_(alpha+beta+e_k)(R) / (alpha! beta!)
+// (evaluated as -sum_gamma Q_gamma D_(gamma+e_k), Q_gamma the sum of the
+// moment products with alpha + beta = gamma)
 // (at P = 3 this is eq. 7; the mirrored pair gives -F_c, since D of odd order
 // changes sign with R).  The derivatives D_gamma of g(R) = -1/sqrt(R^2 +
 // eps^2) come from f_k = (1/R d/dR)^k g by pairing equal indices.  Push-down
@@ -108,11 +110,12 @@ constexpr int kNLocal = count_local();
 struct LocalTerms {
   Term t[kNLocal];
 };
+// (source moment outer: each is loaded once and used at once)
 constexpr LocalTerms make_local() {
   LocalTerms r{};
   int k = 0;
-  for (int al = 0; al < kNL; ++al)
-    for (int be = 0; be < kNL; ++be)
+  for (int be = 0; be < kNL; ++be)
+    for (int al = 0; al < kNL; ++al)
       if (local_term(al, be)) {
         const int sb = kMI.n[be] % 2 ? -1 : 1;
         r.t[k++] = {al, be, mi_id(kMI.a[al] + kMI.a[be], kMI.b[al] + kMI.b[be], kMI.c[al] + kMI.c[be]),
@@ -122,8 +125,10 @@ constexpr LocalTerms make_local() {
 }
 constexpr LocalTerms kLocal = make_local();
 
-// correction: s_k += coef M_target[al] M_source[be] D[g_k], coef =
-// (-1)^|be| / (al! be!), over |al| + |be| = P with neither a dipole
+// correction: the moment products gathered into one order-P tensor,
+// Q[g] += coef M_target[al] M_source[be] (g = al + be), coef = (-1)^|be| /
+// (al! be!), over |al| + |be| = P with neither a dipole; then s_k = sum_g
+// Q[g] D[g + e_k]
 constexpr bool corr_term(int al, int be) {
   return kMI.n[al] + kMI.n[be] == kP && kMI.n[al] != 1 && kMI.n[be] != 1;
 }
@@ -135,7 +140,7 @@ constexpr int count_corr() {
 }
 constexpr int kNCorr = count_corr();
 struct CorrTerm {
-  int al, be, g[3];
+  int al, be, q;
   double coef;
 };
 struct CorrTerms {
@@ -149,8 +154,7 @@ constexpr CorrTerms make_corr() {
       if (corr_term(al, be)) {
         const int a = kMI.a[al] + kMI.a[be], b = kMI.b[al] + kMI.b[be], c = kMI.c[al] + kMI.c[be];
         const int sb = kMI.n[be] % 2 ? -1 : 1;
-        r.t[k++] = {al, be, {mi_id(a + 1, b, c), mi_id(a, b + 1, c), mi_id(a, b, c + 1)},
-                    sb / (kMI.fact[al] * kMI.fact[be])};
+        r.t[k++] = {al, be, mi_id(a, b, c) - num_mi(kP - 1), sb / (kMI.fact[al] * kMI.fact[be])};
       }
   return r;
 }
@@ -336,10 +340,9 @@ __global__ void __launch_bounds__(kBS) k_mono_up(int32_t c0, int32_t nl, const i
 }
 
 // Far field of one target cell per wave: its local coefficients (locg: kNL
-// coefficients, then g_c) and, for the order-3 kernels that run after it,
-// zeros in its loc record (the evaluation at the particles adds this
-// expansion separately).
-template <int VARIANT>
+// coefficients, then g_c, zero here: k_corr_order sets it for TC) and, for
+// the order-3 kernels that run after it, zeros in its loc record (the
+// evaluation at the particles adds this expansion separately).
 __global__ void __launch_bounds__(kBS) k_far_order(int32_t c_lo, int32_t nc, const double4* __restrict__ geo,
                                                    const double* __restrict__ mono, const int64_t* __restrict__ fstart,
                                                    const int32_t* __restrict__ fcount, const int32_t* __restrict__ fsrc,
@@ -351,8 +354,7 @@ __global__ void __launch_bounds__(kBS) k_far_order(int32_t c_lo, int32_t nc, con
   const int32_t cnt = fcount[X];
   const int64_t st = fstart[X];
   const double4 gx = geo[X];
-  const double* mx = mono + (int64_t)X * kNL;
-  double L[kNL], F[3] = {0.0, 0.0, 0.0};
+  double L[kNL];
 #pragma unroll
   for (int g = 0; g < kNL; ++g) L[g] = 0.0;
   for (int64_t j = lane; j < cnt; j += 64) {
@@ -361,8 +363,8 @@ __global__ void __launch_bounds__(kBS) k_far_order(int32_t c_lo, int32_t nc, con
     const double* my = mono + (int64_t)Y * kNL;
     const double R[3] = {gx.x - gy.x, gx.y - gy.y, gx.z - gy.z};
     // two phases, so that only part of the derivatives is live at a time:
-    // orders 0-4 for the coefficients of order <= P - 1, then orders P and
-    // P + 1 for those of order P and the correction
+    // orders 0 to P for the coefficients of order < P, then order P for
+    // those of order P
     {
       double D[kND];
       derivatives<0, kP>(R, eps2, D);
@@ -372,38 +374,68 @@ __global__ void __launch_bounds__(kBS) k_far_order(int32_t c_lo, int32_t nc, con
     }
     {
       double D[kND];
-      derivatives<kP, kP + 1>(R, eps2, D);
+      derivatives<kP, kP>(R, eps2, D);
 #pragma unroll
       for (int i = 0; i < kNLocal; ++i)
         if (kMI.n[kLocal.t[i].al] == kP) L[kLocal.t[i].al] += kLocal.t[i].coef * D[kLocal.t[i].g] * my[kLocal.t[i].be];
-      if (VARIANT != AMFMM_UC) {
-        double s[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-        for (int i = 0; i < kNCorr; ++i) {
-          const CorrTerm& t = kCorr.t[i];
-          const double w = t.coef * (mx[t.al] * my[t.be]);
-#pragma unroll
-          for (int k = 0; k < 3; ++k) s[k] += w * D[t.g[k]];
-        }
-#pragma unroll
-        for (int k = 0; k < 3; ++k) F[k] -= s[k];
-      }
     }
   }
 #pragma unroll
   for (int g = 0; g < kNL; ++g) L[g] = wave_sum(L[g]);
-#pragma unroll
-  for (int k = 0; k < 3; ++k) F[k] = wave_sum(F[k]);
   if (lane == 0) {
     double* o = locg + (int64_t)X * kLocGen;
 #pragma unroll
     for (int g = 0; g < kNL; ++g) o[g] = L[g];
+    for (int u = kNL; u < kLocGen; ++u) o[u] = 0.0;
+    double* z = loc + (int64_t)X * kLoc;
+    for (int u = 0; u < kLoc; ++u) z[u] = 0.0;
+  }
+}
+
+// The correction (TC) of one target cell per wave over the same sources:
+// g_c = F_c / M_X into locg (after k_far_order).  Only the order-(P+1)
+// derivatives and the moments of orders 0, 2 and P enter.
+__global__ void __launch_bounds__(kBS) k_corr_order(int32_t c_lo, int32_t nc, const double4* __restrict__ geo,
+                                                    const double* __restrict__ mono, const int64_t* __restrict__ fstart,
+                                                    const int32_t* __restrict__ fcount, const int32_t* __restrict__ fsrc,
+                                                    double* __restrict__ locg, double eps2) {
+  constexpr int kNQ = num_mi(kP) - num_mi(kP - 1);  // order-P components
+  const int lane = threadIdx.x & 63;
+  const int32_t Xi = uniform((int32_t)(xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6)));
+  if (Xi >= nc) return;
+  const int32_t X = c_lo + Xi;
+  const int32_t cnt = fcount[X];
+  const int64_t st = fstart[X];
+  const double4 gx = geo[X];
+  const double* mx = mono + (int64_t)X * kNL;
+  double F[3] = {0.0, 0.0, 0.0};
+  for (int64_t j = lane; j < cnt; j += 64) {
+    const int32_t Y = fsrc[st + j];
+    const double4 gy = geo[Y];
+    const double* my = mono + (int64_t)Y * kNL;
+    const double R[3] = {gx.x - gy.x, gx.y - gy.y, gx.z - gy.z};
+    double Q[kNQ];
+#pragma unroll
+    for (int q = 0; q < kNQ; ++q) Q[q] = 0.0;
+#pragma unroll
+    for (int i = 0; i < kNCorr; ++i) Q[kCorr.t[i].q] += kCorr.t[i].coef * (mx[kCorr.t[i].al] * my[kCorr.t[i].be]);
+    double D[kND];
+    derivatives<kP + 1, kP + 1>(R, eps2, D);
+#pragma unroll
+    for (int q = 0; q < kNQ; ++q) {
+      const int g = num_mi(kP - 1) + q;
+      F[0] -= Q[q] * D[mi_id(kMI.a[g] + 1, kMI.b[g], kMI.c[g])];
+      F[1] -= Q[q] * D[mi_id(kMI.a[g], kMI.b[g] + 1, kMI.c[g])];
+      F[2] -= Q[q] * D[mi_id(kMI.a[g], kMI.b[g], kMI.c[g] + 1)];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) F[k] = wave_sum(F[k]);
+  if (lane == 0) {
+    double* o = locg + (int64_t)X * kLocGen;
     const double MX = mx[0];
 #pragma unroll
     for (int k = 0; k < 3; ++k) o[kNL + k] = F[k] / MX;
-    for (int u = kNL + 3; u < kLocGen; ++u) o[u] = 0.0;
-    double* z = loc + (int64_t)X * kLoc;
-    for (int u = 0; u < kLoc; ++u) z[u] = 0.0;
   }
 }
 
@@ -503,11 +535,18 @@ void order_far(Ctx& c, int32_t c_lo, int32_t c_hi, double* loc) {
   if (nc <= 0) return;
   double* locg = (double*)ensure_keep(c, c.locg, sizeof(double) * kLocGen * (size_t)c.ncells,
                                       sizeof(double) * kLocGen * (size_t)c.ncells);
-  auto kern = c.opt.variant == AMFMM_UC ? k_far_order<AMFMM_UC> : k_far_order<AMFMM_TC>;
-  hipLaunchKernelGGL(kern, dim3(blocks_for(nc, kWaves)), dim3(kBS), 0, c.stream, c_lo, nc, (const double4*)c.geo.p,
-                     (const double*)c.mono.p, (const int64_t*)c.far_start.p, (const int32_t*)c.far_count.p,
-                     (const int32_t*)c.far_src.p, locg, loc, c.opt.softening * c.opt.softening);
+  hipLaunchKernelGGL(k_far_order, dim3(blocks_for(nc, kWaves)), dim3(kBS), 0, c.stream, c_lo, nc,
+                     (const double4*)c.geo.p, (const double*)c.mono.p, (const int64_t*)c.far_start.p,
+                     (const int32_t*)c.far_count.p, (const int32_t*)c.far_src.p, locg, loc,
+                     c.opt.softening * c.opt.softening);
   AMFMM_HIP(hipGetLastError());
+  if (c.opt.variant != AMFMM_UC) {
+    hipLaunchKernelGGL(k_corr_order, dim3(blocks_for(nc, kWaves)), dim3(kBS), 0, c.stream, c_lo, nc,
+                       (const double4*)c.geo.p, (const double*)c.mono.p, (const int64_t*)c.far_start.p,
+                       (const int32_t*)c.far_count.p, (const int32_t*)c.far_src.p, locg,
+                       c.opt.softening * c.opt.softening);
+    AMFMM_HIP(hipGetLastError());
+  }
 }
 
 void order_push_down(Ctx& c, int32_t c_lo, int32_t c_hi) {
