@@ -100,3 +100,28 @@ def test_order_option_checks():
         with pytest.raises(amfmm.AmfmmError) as e:
             amfmm.Solver(**kw)
         assert e.value.code == amfmm.E_INVALID
+
+
+def test_order4_batched_matches_whole():
+    """At order 4 the batched solve (forced by a tiny list budget: the walk
+    and the evaluation cut into subtrees, the order-4 expansions of the top
+    levels kept across batches) selects the same pairs and gives the whole
+    solve's results up to summation order."""
+    x, y, z, m = W.plummer(1 << 17, seed=12)
+    say("order 4 batched", len(x))
+    X, Y, Z, M = to_dev(x, y, z, m)
+    whole = amfmm.Solver(order=4)
+    a1 = host(whole.solve_gravity(X, Y, Z, M, 0.5))
+    c1 = whole.get_counts()
+    part = amfmm.Solver(order=4, list_bytes=1 << 20)
+    a2 = host(part.solve_gravity(X, Y, Z, M, 0.5))
+    c2 = part.get_counts()
+    for k in ("near_interactions", "far_evaluations", "walk_candidates"):
+        assert c1[k] == c2[k] > 0, k
+    assert c2["walk_pass_launches"] > c1["walk_pass_launches"]
+    idx = W.sample_targets(len(x), 256, seed=99)
+    _, _, gabs = orc.direct(x, y, z, m, idx)
+    assert np.max(np.linalg.norm(a1[:3, idx] - a2[:3, idx], axis=0) / gabs) <= 1e-13
+    assert np.max(np.abs(a1[3] - a2[3]) / np.abs(a1[3])) <= 1e-13
+    whole.close()
+    part.close()
