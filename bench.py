@@ -3,9 +3,10 @@
 One step = the whole force solve on inputs already resident in HBM.  With an
 error-estimate criterion (default: the multipole estimate) a step is two
 amfmm_solve_gravity calls: a pilot solve with the geometric criterion
-(theta = 1.0) whose accelerations give every cell its field scale, then the
-solve whose pair selection keeps each pair's estimated error below eps times
-that scale.  Each solve covers validation, bounding cube, keys, sort, tree,
+(theta = 1.0, UC, leaves of up to 128 particles: its field magnitudes are
+within a few per cent, which is all the scale needs) whose accelerations give
+every cell its field scale, then the solve whose pair selection keeps each
+pair's estimated error below eps times that scale.  Each solve covers validation, bounding cube, keys, sort, tree,
 upward pass, walk, far field, push-down, near field, evaluation at the
 particles and the unsort.  Outputs one JSON line.  The error of the timed
 configuration is measured outside the timed region against direct summation
@@ -90,6 +91,8 @@ def parse():
                    help="opening angle (geometric criterion; also the pilot solve)")
     p.add_argument("--pilot-theta", type=float, default=1.0,
                    help="opening angle of the pilot solve that gives the field estimate")
+    p.add_argument("--pilot-ncrit", type=int, default=128,
+                   help="leaf size of the pilot solve's tree (UC variant, the timed solve's precision)")
     p.add_argument("--criterion", choices=["geometric", "estimate", "learned", "multipole"], default="multipole")
     p.add_argument("--eps", type=float, default=9e-8,
                    help="error-estimate criterion: accepted pair error relative to the field scale")
@@ -117,10 +120,11 @@ def source_hash(kernel):
     return h.hexdigest()[:16]
 
 
-def traffic(kernel, config, workload):
+def traffic(kernel, config, workload, launches):
     """HBM bytes per launch of a kernel from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE, scaled by the copy calibration), or None when
-    absent, taken on other sources of that kernel or on another configuration."""
+    absent, taken on other sources of that kernel, on another configuration
+    or with the step cut into other launches (bytes per launch follow the cut)."""
     try:
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
@@ -128,15 +132,15 @@ def traffic(kernel, config, workload):
     k = t.get("kernels", {}).get(kernel)
     if not k or k.get("source_hash") != source_hash(kernel) or t.get("config") != config:
         return None
-    if not str(t.get("workload", "")).startswith(workload + " "):
+    if not str(t.get("workload", "")).startswith(workload + " ") or k.get("launches") != launches:
         return None
     return k.get("bytes_per_launch")
 
 
-def counters(kernel, config, workload):
+def counters(kernel, config, workload, launches):
     """Instruction and L2 counters per launch of a kernel from the committed
-    summary, or None when absent, taken on other sources or another
-    configuration."""
+    summary, or None when absent, taken on other sources, another
+    configuration or another cut of the step into launches."""
     try:
         t = json.load(open(COUNTERS_FILE))
     except (OSError, ValueError):
@@ -144,14 +148,14 @@ def counters(kernel, config, workload):
     k = t.get("kernels", {}).get(kernel)
     if not k or k.get("source_hash") != source_hash(kernel) or t.get("config") != config:
         return None
-    if not str(t.get("workload", "")).startswith(workload + " "):
+    if not str(t.get("workload", "")).startswith(workload + " ") or k.get("launches") != launches:
         return None
     return {"valu_issue_frac": round(k["valu_issue_frac"], 3), "l2_hit": round(k["l2_hit"], 3),
             "fp64_tflops": round(k["fp64_tflops"], 3), "fp32_tflops": round(k["fp32_tflops"], 3),
             "avg_ms": round(k["avg_ms"], 3)}
 
 
-def cpu_baseline(workload, n, theta, criterion, eps, theta_max):
+def cpu_baseline(workload, n, theta, criterion, eps, theta_max, pilot_theta, pilot_ncrit):
     """The CPU oracle as it stands on a smaller sample of the same workload
     (generator and seed) and configuration: particles/s of its full solve
     (with an error-estimate criterion: its own pilot solve, then the solve).
@@ -167,14 +171,21 @@ def cpu_baseline(workload, n, theta, criterion, eps, theta_max):
     threads = orc.num_threads()
     x, y, z, m = W.make(workload, n=n)
     t0 = time.perf_counter()
+    if criterion != "geometric":
+        # the pilot as the GPU step runs it: its own tree, UC
+        tp = orc.Tree(x, y, z, m, n_crit=pilot_ncrit)
+        tp.compute_moments()
+        tp.walk(pilot_theta)
+        g, _ = tp.evaluate_targets(orc.UC)
+        del tp
     t = orc.Tree(x, y, z, m)
     t.compute_moments()
-    t.walk(theta)
-    a, _ = t.evaluate_targets(orc.TC)
     if criterion != "geometric":
         walk = t.walk_multipole if criterion == "multipole" else t.walk_field
-        walk(eps, theta_max, np.linalg.norm(a, axis=0))
-        t.evaluate_targets(orc.TC)
+        walk(eps, theta_max, np.linalg.norm(g, axis=0))
+    else:
+        t.walk(theta)
+    t.evaluate_targets(orc.TC)
     dt = time.perf_counter() - t0
     # the cost of the correction in the oracle: its evaluation (far field,
     # near field) of one geometric theta=0.5 walk of a 16384-particle sphere
@@ -192,7 +203,8 @@ def cpu_baseline(workload, n, theta, criterion, eps, theta_max):
             tv.evaluate(v)
             ts.append(time.perf_counter() - t1)
         best[name] = min(ts)
-    what = (f"pilot theta={theta} + {criterion} error-estimate solve eps={eps} theta_max={theta_max}"
+    what = (f"pilot (theta={pilot_theta}, UC, n_crit={pilot_ncrit}) + {criterion} error-estimate solve "
+            f"eps={eps} theta_max={theta_max}"
             if criterion != "geometric" else f"theta={theta}")
     model = None
     try:
@@ -246,7 +258,7 @@ def main():
     del x, y, z, m
     crit = {"geometric": amfmm.GEOMETRIC, "estimate": amfmm.ESTIMATE, "learned": amfmm.LEARNED,
             "multipole": amfmm.MULTIPOLE}[a.criterion]
-    pilot = amfmm.Solver(variant=variant, precision=prec)
+    pilot = amfmm.Solver(variant=amfmm.UC, precision=prec, n_crit=a.pilot_ncrit)
     solver = amfmm.Solver(variant=variant, precision=prec, criterion=crit, error_tol=a.eps,
                           theta_max=a.theta_max)
     if model is not None:
@@ -305,7 +317,8 @@ def main():
     pilot_info = None
     if field:
         pe = p_err(pout)
-        pilot_info = {"criterion": "geometric", "theta": a.pilot_theta, "ms": round(pphases["total"], 3),
+        pilot_info = {"criterion": "geometric", "theta": a.pilot_theta, "variant": "UC", "n_crit": a.pilot_ncrit,
+                      "ms": round(pphases["total"], 3),
                       "p99_rel_force_error": float(np.percentile(pe, 99))}
 
     # Roofline of the step's three large kernels; the one with the most time is
@@ -342,13 +355,13 @@ def main():
     def roof(name):
         k = kern[name]
         achieved = k["work"] / (k["ms"] * 1e-3)
-        tb = traffic(name, cfg_key, workload)
+        tb = traffic(name, cfg_key, workload, k["launches"])
         launches = max(1, k["launches"])
         r = {"kernel": k["kernel"], "bound": k["bound"], "achieved": round(achieved, 3), "peak": k["peak"],
              "unit": k["unit"], "frac": round(achieved / k["peak"], 4), "traffic": tb,
              "algorithmic": k["algorithmic"] + f" per step over {k['launches']} launches",
              "avg_launch_ms": round(k["ms"] / launches, 3), "step_ms": round(k["ms"], 3)}
-        cn = counters(name, cfg_key, workload)
+        cn = counters(name, cfg_key, workload, k["launches"])
         if cn is not None:
             # measured beside the model: HBM bytes per launch over its duration,
             # VALU issue (wave instructions x 4 cycles over the SIMD-cycles), L2 hits
@@ -483,8 +496,8 @@ def main():
 
     cpu = None
     if a.cpu_n > 0:
-        cpu = cpu_baseline(a.workload, a.cpu_n, a.pilot_theta if field else a.theta, a.criterion, a.eps,
-                           a.theta_max)
+        cpu = cpu_baseline(a.workload, a.cpu_n, a.theta, a.criterion, a.eps, a.theta_max, a.pilot_theta,
+                           a.pilot_ncrit)
 
     line = {
         "metric": METRIC if workload == "plummer16m" else f"particles/s full force solve, {workload}",

@@ -227,6 +227,67 @@ static std::vector<T> fetch(Ctx& c, const void* dev, size_t count) {
 
 static void build_near_pairs(Ctx& c);
 
+namespace {
+
+// Unordered near-field leaf pairs (x, o), x <= o, behind the near lists (the
+// pairs amfmm_get_lists returns): one thread per target cell x, a walk over
+// each entry's subtree by first child, next sibling and parent (no stack),
+// summed per wave and added to *total.
+__global__ void __launch_bounds__(256) k_count_near_pairs(int32_t nc, const int64_t* __restrict__ start,
+                                                           const int32_t* __restrict__ count,
+                                                           const int32_t* __restrict__ src,
+                                                           const int32_t* __restrict__ ch0,
+                                                           const int32_t* __restrict__ nch,
+                                                           const int32_t* __restrict__ par,
+                                                           unsigned long long* __restrict__ total) {
+  const int32_t x = blockIdx.x * 256 + threadIdx.x;
+  unsigned long long k = 0;
+  if (x < nc) {
+    for (int32_t j = 0; j < count[x]; ++j) {
+      const int32_t y = src[start[x] + j];
+      int32_t o = y;
+      for (;;) {
+        if (nch[o] > 0) {
+          o = ch0[o];
+          continue;
+        }
+        k += (x <= o) ? 1ull : 0ull;
+        // next leaf: the next sibling of o or of its nearest ancestor below y
+        while (o != y) {
+          const int32_t p = par[o];
+          if (o + 1 < ch0[p] + nch[p]) {
+            ++o;
+            break;
+          }
+          o = p;
+        }
+        if (o == y) break;
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) k += __shfl_down(k, off, 64);
+  if ((threadIdx.x & 63) == 0 && k) atomicAdd(total, k);
+}
+
+}  // namespace
+
+// the number of pairs build_near_pairs would list, counted on the device
+static int64_t count_near_pairs(Ctx& c) {
+  if (c.near_pairs_valid) return (int64_t)c.near_pairs_host.size();
+  unsigned long long* t = (unsigned long long*)amfmm::ensure(c, c.counters, 64) + 1;
+  amfmm::zero_u64(c, t, 1);
+  hipLaunchKernelGGL(k_count_near_pairs, dim3(amfmm::blocks_for(c.ncells, 256)), dim3(256), 0, c.stream,
+                     c.ncells, (const int64_t*)c.near_start.p, (const int32_t*)c.near_count.p,
+                     (const int32_t*)c.near_src.p, (const int32_t*)c.c_child0.p, (const int32_t*)c.c_nchild.p,
+                     (const int32_t*)c.c_parent.p, t);
+  AMFMM_HIP(hipGetLastError());
+  unsigned long long h = 0;
+  AMFMM_HIP(hipMemcpyAsync(&h, t, sizeof(h), hipMemcpyDeviceToHost, c.stream));
+  AMFMM_HIP(hipStreamSynchronize(c.stream));
+  return (int64_t)h;
+}
+
 static int fail(Ctx& c, int code, const char* msg) {
   c.last_error = msg;
   return code;
@@ -484,14 +545,27 @@ static double list_bytes_per_particle(double theta) {
   return 320.0 * r * r * r;
 }
 
+// List bytes a walk may take.  A list that grows is copied, so its old and
+// new blocks coexist for a moment, and each block carries a quarter of
+// headroom: lists within b bytes peak below 2.25 b.  Outside an arena the
+// lists and the staging room this context already holds are reused by the
+// next walk and count as free, and b is two fifths of that: the whole walk of a large problem fits
+// in one pass when the device has the memory (one evaluation launch per
+// phase instead of one per batch).  In an arena: a quarter of its largest
+// free block.
 static size_t list_budget(Ctx& c) {
   if (c.opt.list_bytes > 0) return (size_t)c.opt.list_bytes;
-  const size_t fr = amfmm::free_device_bytes(c);
-  // a quarter of the largest free arena block: a list that grows is copied,
-  // so its old and new blocks coexist for a moment
-  size_t b = std::min<size_t>(c.arena ? fr / 4 : fr / 3, size_t(48) << 30);
+  size_t fr = amfmm::free_device_bytes(c);
+  if (!c.arena) fr += c.far_src.cap + c.near_src.cap + c.fy.cap + c.fy2.cap + c.stage.cap;
+  size_t b = c.arena ? fr / 4 : fr / 5 * 2;
   if (c.opt.max_bytes > 0) b = std::min<size_t>(b, (size_t)c.opt.max_bytes / 2);
   return c.arena ? b : std::max<size_t>(b, size_t(64) << 20);
+}
+
+// a device allocation that failed outside an arena: the walk that needed it
+// can go batch by batch instead
+static bool out_of_device_memory(const Ctx& c, const amfmm::Error& e) {
+  return !c.arena && e.code == AMFMM_E_OOM && c.opt.max_bytes == 0;
 }
 
 // Walk and evaluation one batch of subtrees at a time, so that the lists of
@@ -590,11 +664,18 @@ static void solve_batched(Ctx& c, double theta, double* ax, double* ay, double* 
       bhi[l] = (int32_t)(std::lower_bound(first, last, pe) - hb.data());
     }
     int64_t bfb = 0, bnb = 0;
+    bool over = false;
     try {
       walk_levels(c, Ls, c.depth, blo, bhi, bfb, bnb);
     } catch (const BudgetExceeded&) {
-      // too many pairs for one batch: halve it (a single cell that does not
-      // fit is reported as out of memory)
+      over = true;
+    } catch (const Error& e) {
+      if (!out_of_device_memory(c, e)) throw;
+      over = true;
+    }
+    if (over) {
+      // too many pairs for one batch (or for the device): halve it (a single
+      // cell that does not fit is reported as out of memory)
       if (x1 - x0 == 1) throw Error(AMFMM_E_OOM, "one subtree's interaction lists exceed the list budget");
       c.batch_fail = c.batch_fail > 0 ? std::min(c.batch_fail, parts) : parts;
       plim = std::max<int64_t>(1, parts / 2);
@@ -644,6 +725,15 @@ static int solve_impl(Ctx& c, int64_t n, const double* x, const double* y, const
         amfmm::dual_walk(c, theta);
       } catch (const amfmm::BudgetExceeded&) {
         whole = false;  // the estimate was too low: walk batch by batch
+      } catch (const amfmm::Error& e) {
+        if (!out_of_device_memory(c, e)) throw;
+        // the lists did not fit the device after all: give back what the
+        // walk grew and go batch by batch within half the budget
+        release(c, c.far_src);
+        release(c, c.near_src);
+        release(c, c.stage);
+        c.batch_fail = std::max<int64_t>(1, n / 2);
+        whole = false;
       }
       c.walk_budget = 0;
     }
@@ -767,10 +857,7 @@ int amfmm_get_counts(amfmm_ctx* ctx, int64_t* counts) {
     counts[1] = c.have_tree ? c.depth : 0;
     counts[2] = c.have_lists ? c.n_far / 2 : c.far_evals / 2;
     counts[3] = 0;
-    if (c.have_lists) {
-      build_near_pairs(c);
-      counts[3] = (int64_t)c.near_pairs_host.size();
-    }
+    if (c.have_lists) counts[3] = count_near_pairs(c);
     counts[4] = c.have_tree ? c.nleaves : 0;
     counts[5] = c.have_tree ? c.n : 0;
     counts[6] = 0;
@@ -885,14 +972,18 @@ int amfmm_get_lists(amfmm_ctx* ctx, int32_t* far_ab, int32_t* near_ab) {
           if ((int32_t)x < o) v.emplace_back((int32_t)x, o);
         }
       std::sort(v.begin(), v.end());
+      // the caller sized far_ab from amfmm_get_counts: never write past it
+      if ((int64_t)v.size() != c.n_far / 2) return fail(c, AMFMM_E_STATE, "far lists are not symmetric");
       for (size_t i = 0; i < v.size(); ++i) {
         far_ab[2 * i] = v[i].first;
         far_ab[2 * i + 1] = v[i].second;
       }
     }
     if (near_ab) {
+      const int64_t want = count_near_pairs(c);  // what amfmm_get_counts reported
       build_near_pairs(c);
       const auto& v = c.near_pairs_host;
+      if ((int64_t)v.size() != want) return fail(c, AMFMM_E_STATE, "near pair count disagrees with the lists");
       for (size_t i = 0; i < v.size(); ++i) {
         near_ab[2 * i] = v[i].first;
         near_ab[2 * i + 1] = v[i].second;

@@ -7,7 +7,8 @@
 //    M_ijk to the parent's centre (exact for moments about a centre of mass);
 //  * R_max: exact largest distance to Z over the cell's particles; every
 //    particle visits its ancestors level by level, lanes holding the same
-//    ancestor reduce within the wave first, then one atomic max per run.
+//    ancestor reduce within the wave first, and a wave carries the run at
+//    the end of one 64-particle slab into the next before its atomic max.
 //
 // Compiled with -ffp-contract=off: the centres of mass and R_max must round
 // exactly as written (they decide the walk, which is reproduced bit for bit).
@@ -147,50 +148,85 @@ __global__ void __launch_bounds__(kBS) k_zero_u64(unsigned long long* p, int64_t
   if (i < n) p[i] = 0ull;
 }
 
+// 64-particle slabs one wave of k_rmax takes, in key order
+constexpr int kRmaxSlabs = 32;
+
 // R_max^2 of every ancestor of every particle, by atomic max on the bit
-// pattern (order-preserving for non-negative doubles)
+// pattern (order-preserving for non-negative doubles).  A wave takes
+// kRmaxSlabs consecutive slabs of 64 particles; on each level, lanes with
+// the same ancestor (contiguous, as cells are) reduce to the run's first
+// lane, and the run that reaches the slab's end stays pending in the wave
+// and joins the next slab's first run when that has the same cell.  A cell
+// of many particles so gets one atomic per wave that touches it rather than
+// one per slab (all waves otherwise meet on the same few top cells).
 __global__ void __launch_bounds__(kBS) k_rmax(const double4* __restrict__ pos, int64_t n,
                                               const int32_t* __restrict__ leafof, const int32_t* __restrict__ par,
                                               const int8_t* __restrict__ lev, const double4* __restrict__ geo,
                                               unsigned long long* __restrict__ r2max) {
-  int64_t p = (int64_t)blockIdx.x * kBS + threadIdx.x;
   const int lane = threadIdx.x & 63;
-  bool valid = p < n;
-  int32_t anc[kMaxLevel + 1];
-  double4 q = valid ? pos[p] : make_double4(0, 0, 0, 0);
-  {
-    int32_t a = valid ? leafof[p] : -1;
-    int L = valid ? (int)lev[a] : -1;
-#pragma unroll
-    for (int l = kMaxLevel; l >= 0; --l) {
-      if (l > L) {
-        anc[l] = -1;
-      } else {
-        anc[l] = a;
-        a = par[a];
-      }
-    }
-  }
+  const int64_t p0 = (((int64_t)blockIdx.x * kBS + threadIdx.x) >> 6) * (64 * kRmaxSlabs);
+  // per level, the pending run (wave-uniform): its cell (-1: none) and max
+  int32_t pend_id[kMaxLevel + 1];
+  double pend_r2[kMaxLevel + 1];
 #pragma unroll
   for (int l = 0; l <= kMaxLevel; ++l) {
-    int32_t id = anc[l];
-    if (!__any(id >= 0)) break;
-    double r2 = -1.0;
-    if (id >= 0) {
-      double4 g = geo[id];
-      double dx = q.x - g.x, dy = q.y - g.y, dz = q.z - g.z;
-      r2 = (dx * dx + dy * dy) + dz * dz;
-    }
-    // segmented max over contiguous lanes with the same ancestor
+    pend_id[l] = -1;
+    pend_r2[l] = -1.0;
+  }
+  for (int s = 0; s < kRmaxSlabs; ++s) {
+    const int64_t p = p0 + (int64_t)s * 64 + lane;
+    if (p0 + (int64_t)s * 64 >= n) break;  // wave-uniform
+    const bool valid = p < n;
+    int32_t anc[kMaxLevel + 1];
+    const double4 q = valid ? pos[p] : make_double4(0, 0, 0, 0);
+    {
+      int32_t a = valid ? leafof[p] : -1;
+      int L = valid ? (int)lev[a] : -1;
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      double o = __shfl_down(r2, off, 64);
-      int32_t oid = __shfl_down(id, off, 64);
-      if (lane + off < 64 && oid == id && o > r2) r2 = o;
+      for (int l = kMaxLevel; l >= 0; --l) {
+        if (l > L) {
+          anc[l] = -1;
+        } else {
+          anc[l] = a;
+          a = par[a];
+        }
+      }
     }
-    int32_t prev = __shfl_up(id, 1, 64);
-    bool head = lane == 0 || prev != id;
-    if (id >= 0 && head) atomicMax(&r2max[id], (unsigned long long)__double_as_longlong(r2));
+#pragma unroll
+    for (int l = 0; l <= kMaxLevel; ++l) {
+      const int32_t id = anc[l];
+      // no particle of the slab below this level: deeper runs stay pending
+      if (!__any(id >= 0)) break;
+      double r2 = -1.0;
+      if (id >= 0) {
+        const double4 g = geo[id];
+        const double dx = q.x - g.x, dy = q.y - g.y, dz = q.z - g.z;
+        r2 = (dx * dx + dy * dy) + dz * dz;
+      }
+      // segmented max over contiguous lanes with the same ancestor
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const double o = __shfl_down(r2, off, 64);
+        const int32_t oid = __shfl_down(id, off, 64);
+        if (lane + off < 64 && oid == id && o > r2) r2 = o;
+      }
+      const int32_t prev = __shfl_up(id, 1, 64);
+      const bool head = id >= 0 && (lane == 0 || prev != id);
+      const unsigned long long hm = __ballot(head);  // nonzero: some lane has an ancestor here
+      const int last = 63 - __clzll(hm);
+      const bool joins = __shfl(id, 0, 64) == pend_id[l];
+      if (lane == 0 && joins) r2 = fmax(r2, pend_r2[l]);
+      if (lane == 0 && !joins && pend_id[l] >= 0)
+        atomicMax(&r2max[pend_id[l]], (unsigned long long)__double_as_longlong(pend_r2[l]));
+      if (head && lane != last) atomicMax(&r2max[id], (unsigned long long)__double_as_longlong(r2));
+      pend_id[l] = __shfl(id, last, 64);
+      pend_r2[l] = __shfl(r2, last, 64);
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int l = 0; l <= kMaxLevel; ++l)
+      if (pend_id[l] >= 0) atomicMax(&r2max[pend_id[l]], (unsigned long long)__double_as_longlong(pend_r2[l]));
   }
 }
 
@@ -233,7 +269,8 @@ void upward_pass(Ctx& c) {
   hipLaunchKernelGGL(k_leaf_of, dim3(blocks_for(c.nleaves, kBS)), dim3(kBS), 0, c.stream,
                      as<int32_t>(c.leaves), c.nleaves, beg, cnt, leafof);
   hipLaunchKernelGGL(k_zero_u64, dim3(blocks_for(nc, kBS)), dim3(kBS), 0, c.stream, r2, (int64_t)nc);
-  hipLaunchKernelGGL(k_rmax, dim3(blocks_for(c.n, kBS)), dim3(kBS), 0, c.stream, (const double4*)c.pos4.p,
+  const int64_t rmax_waves = (c.n + 64 * kRmaxSlabs - 1) / (64 * kRmaxSlabs);
+  hipLaunchKernelGGL(k_rmax, dim3(blocks_for(rmax_waves * 64, kBS)), dim3(kBS), 0, c.stream, (const double4*)c.pos4.p,
                      c.n, (const int32_t*)leafof, as<int32_t>(c.c_parent), (const int8_t*)lev,
                      (const double4*)geo, r2);
   hipLaunchKernelGGL(k_rmax_final, dim3(blocks_for(nc, kBS)), dim3(kBS), 0, c.stream, nc,

@@ -33,12 +33,17 @@ def test_committed_profiles_match_sources_and_default_configuration():
         sys.argv = old
     cfg = {"n": 1 << 24, "criterion": a.criterion, "eps": a.eps, "theta": a.theta, "precision": a.precision,
            "variant": a.variant}
-    for kernel in ("walk", "far", "near"):
-        assert bench.traffic(kernel, cfg, a.workload) is not None, kernel
     lines = sorted(glob.glob(os.path.join(ROOT, "profiles", "bench_*.json")))
     assert len(lines) == 1, lines
     line = json.load(open(lines[0]))
     c = line["config"]
+    # the summary holds for the step as the line cut it into launches
+    launches = {"walk": c["counts"]["walk_pass_launches"], "far": c["counts"]["far_launches"],
+                "near": c["counts"]["near_launches"]}
+    for kernel in ("walk", "far", "near"):
+        assert bench.traffic(kernel, cfg, a.workload, launches[kernel]) is not None, kernel
+        assert bench.counters(kernel, cfg, a.workload, launches[kernel]) is not None, kernel
+    assert all(v["traffic"] is not None for v in line["roofline"]["others"].values())
     assert c["workload"] == a.workload and c["eps"] == a.eps and c["criterion"] == a.criterion
     assert line["steps"] == a.steps and line["warmup"] == a.warmup
     assert c["p99_rel_force_error"] <= 1e-4 and c["error_sample"] == a.error_sample
