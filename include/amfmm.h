@@ -87,9 +87,12 @@ typedef struct {
   double theta_max;   /* ESTIMATE / LEARNED / MULTIPOLE: pairs with (R_A+R_B)/d > theta_max always open */
   int64_t max_bytes;  /* cap on device scratch owned by the context (0 = no cap) */
   int64_t list_bytes; /* device bytes the interaction lists of one batch may take
-                         (0 = automatic); when the whole tree's lists would not
-                         fit, amfmm_solve_gravity walks and evaluates the tree
-                         in batches of subtrees, with identical results */
+                         (0 = automatic: two fifths of the free device memory
+                         plus the lists and staging room the context already
+                         holds); when the whole tree's lists would not fit, or
+                         a device allocation fails during the whole walk,
+                         amfmm_solve_gravity walks and evaluates the tree in
+                         batches of subtrees, with the same pairs */
   int64_t learned_min_work; /* LEARNED: the network decides pairs with N_A N_B >=
                                this (default 262144); smaller pairs, where a network
                                evaluation (about 9 kFLOP) costs more than the work
@@ -282,7 +285,9 @@ int amfmm_mlp_train(amfmm_ctx* ctx, int64_t n, const float* feats, const float* 
  * interactions (directed, i != j), far-field evaluations (directed cell
  * pairs), far-field kernel launches and near-field kernel launches of the
  * last evaluation, candidate pairs of the last walk (directed pairs it took a
- * decision on, self pairs included) and launches of the walk's pass kernel */
+ * decision on, self pairs included) and launches of the walk's pass kernel.
+ * The near-field pair count is taken on the device from the kept lists (one
+ * short kernel); it is 0 after a batched solve, which keeps no lists. */
 int amfmm_get_counts(amfmm_ctx* ctx, int64_t* counts12);
 /* sorted keys (n), permutation perm[s] = caller index of sorted particle s (n),
  * and per cell (in (level, first particle) order): level, begin, count,
@@ -292,7 +297,11 @@ int amfmm_get_tree(amfmm_ctx* ctx, uint64_t* keys, int64_t* perm, int32_t* level
 /* 21 doubles per cell: M, Zx, Zy, Zz, R_max, M_xx, M_xy, M_xz, M_yy, M_yz,
  * M_zz, M_xxx, M_xxy, M_xxz, M_xyy, M_xyz, M_xzz, M_yyy, M_yyz, M_yzz, M_zzz */
 int amfmm_get_moments(amfmm_ctx* ctx, double* out21);
-/* unordered pairs (2 int32 each), sorted: far field {a<b}, near field {a<=b} */
+/* unordered pairs (2 int32 each), sorted: far field {a<b}, near field {a<=b};
+ * far_ab holds counts[2] pairs and near_ab counts[3] of amfmm_get_counts
+ * (either may be NULL).  Expands the lists on the host: meant for checks at
+ * small sizes.  AMFMM_E_STATE without lists, or (writing nothing) when the
+ * lists do not hold the counted pairs. */
 int amfmm_get_lists(amfmm_ctx* ctx, int32_t* far_ab, int32_t* near_ab);
 /* milliseconds of the phases of the last solve: [0] validate+bbox, [1] keys+sort,
  * [2] tree levels, [3] moments, [4] walk, [5] far field, [6] push-down,

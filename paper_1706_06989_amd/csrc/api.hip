@@ -961,32 +961,35 @@ int amfmm_get_lists(amfmm_ctx* ctx, int32_t* far_ab, int32_t* near_ab) {
   return guarded(ctx, [&](Ctx& c) -> int {
     if (!c.have_lists) return fail(c, AMFMM_E_STATE, "no lists");
     const size_t nc = (size_t)c.ncells;
+    std::vector<std::pair<int32_t, int32_t>> v;
     if (far_ab) {
       auto s = fetch<int64_t>(c, c.far_start.p, nc);
       auto k = fetch<int32_t>(c, c.far_count.p, nc);
       auto y = fetch<int32_t>(c, c.far_src.p, (size_t)c.n_far);
-      std::vector<std::pair<int32_t, int32_t>> v;
       for (size_t x = 0; x < nc; ++x)
         for (int32_t j = 0; j < k[x]; ++j) {
           int32_t o = y[(size_t)s[x] + j];
           if ((int32_t)x < o) v.emplace_back((int32_t)x, o);
         }
       std::sort(v.begin(), v.end());
-      // the caller sized far_ab from amfmm_get_counts: never write past it
-      if ((int64_t)v.size() != c.n_far / 2) return fail(c, AMFMM_E_STATE, "far lists are not symmetric");
-      for (size_t i = 0; i < v.size(); ++i) {
-        far_ab[2 * i] = v[i].first;
-        far_ab[2 * i + 1] = v[i].second;
-      }
     }
     if (near_ab) {
       const int64_t want = count_near_pairs(c);  // what amfmm_get_counts reported
       build_near_pairs(c);
-      const auto& v = c.near_pairs_host;
-      if ((int64_t)v.size() != want) return fail(c, AMFMM_E_STATE, "near pair count disagrees with the lists");
-      for (size_t i = 0; i < v.size(); ++i) {
-        near_ab[2 * i] = v[i].first;
-        near_ab[2 * i + 1] = v[i].second;
+      if ((int64_t)c.near_pairs_host.size() != want)
+        return fail(c, AMFMM_E_STATE, "near pair count disagrees with the lists");
+    }
+    // the caller sized the arrays from amfmm_get_counts: check before writing
+    if (far_ab && (int64_t)v.size() != c.n_far / 2) return fail(c, AMFMM_E_STATE, "far lists are not symmetric");
+    for (size_t i = 0; far_ab && i < v.size(); ++i) {
+      far_ab[2 * i] = v[i].first;
+      far_ab[2 * i + 1] = v[i].second;
+    }
+    if (near_ab) {
+      const auto& w = c.near_pairs_host;
+      for (size_t i = 0; i < w.size(); ++i) {
+        near_ab[2 * i] = w[i].first;
+        near_ab[2 * i + 1] = w[i].second;
       }
     }
     return AMFMM_OK;

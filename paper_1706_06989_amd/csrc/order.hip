@@ -125,6 +125,23 @@ constexpr LocalTerms make_local() {
 }
 constexpr LocalTerms kLocal = make_local();
 
+// (-1)^|be| / be!: the factor of the source moment be in every term above
+struct MomentSigns {
+  double c[kNL];
+};
+constexpr MomentSigns make_signs() {
+  MomentSigns r{};
+  for (int be = 0; be < kNL; ++be) r.c[be] = (kMI.n[be] % 2 ? -1.0 : 1.0) / kMI.fact[be];
+  return r;
+}
+constexpr MomentSigns kSign = make_signs();
+constexpr bool local_coef_check() {
+  for (int i = 0; i < kNLocal; ++i)
+    if (kLocal.t[i].coef != kSign.c[kLocal.t[i].be]) return false;
+  return true;
+}
+static_assert(local_coef_check(), "local term coefficients are (-1)^|be| / be!");
+
 // correction: the moment products gathered into one order-P tensor,
 // Q[g] += coef M_target[al] M_source[be] (g = al + be), coef = (-1)^|be| /
 // (al! be!), over |al| + |be| = P with neither a dipole; then s_k = sum_g
@@ -146,11 +163,12 @@ struct CorrTerm {
 struct CorrTerms {
   CorrTerm t[kNCorr];
 };
+// (source moment outer, as for the local terms)
 constexpr CorrTerms make_corr() {
   CorrTerms r{};
   int k = 0;
-  for (int al = 0; al < kNL; ++al)
-    for (int be = 0; be < kNL; ++be)
+  for (int be = 0; be < kNL; ++be)
+    for (int al = 0; al < kNL; ++al)
       if (corr_term(al, be)) {
         const int a = kMI.a[al] + kMI.a[be], b = kMI.b[al] + kMI.b[be], c = kMI.c[al] + kMI.c[be];
         const int sb = kMI.n[be] % 2 ? -1 : 1;
@@ -216,28 +234,35 @@ constexpr DerivTerms make_deriv() {
 }
 constexpr DerivTerms kDeriv = make_deriv();
 
-// D_gamma(R) for LO <= |gamma| <= HI (entries of other orders untouched)
-template <int LO, int HI>
-__device__ inline void derivatives(const double R[3], double eps2, double D[kND]) {
+// The radial factors f_k = (1/R d/dR)^k g of g = -1/sqrt(R^2 + eps^2),
+// f_0 = -1/sqrt(s), f_(k+1) = -(2k+1) f_k / s (one division, then 1/s =
+// f_0^2), and the powers R_i^k, k <= P + 1
+__device__ inline void radial_and_powers(const double R[3], double eps2, double f[kP + 2], double pw[3][kP + 2]) {
   const double s = ((R[0] * R[0] + R[1] * R[1]) + R[2] * R[2]) + eps2;
-  double f[kP + 2];
   f[0] = -1.0 / sqrt(s);
+  const double is = f[0] * f[0];
 #pragma unroll
-  for (int k = 0; k <= kP; ++k) f[k + 1] = -(2.0 * k + 1.0) * f[k] / s;
-  double pw[3][kP + 2];
+  for (int k = 0; k <= kP; ++k) f[k + 1] = (-(2.0 * k + 1.0) * f[k]) * is;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     pw[i][0] = 1.0;
 #pragma unroll
     for (int k = 0; k <= kP; ++k) pw[i][k + 1] = pw[i][k] * R[i];
   }
+}
+
+// D_gamma(R) for LO <= |gamma| <= HI (entries of other orders untouched)
+template <int LO, int HI>
+__device__ inline void derivatives(const double R[3], double eps2, double D[kND]) {
+  double f[kP + 2], pw[3][kP + 2];
+  radial_and_powers(R, eps2, f, pw);
 #pragma unroll
   for (int g = num_mi(LO - 1); g < num_mi(HI); ++g) D[g] = 0.0;
 #pragma unroll
   for (int i = 0; i < kNDeriv; ++i) {
     const DerivTerm& t = kDeriv.t[i];
     if (kMI.n[t.g] < LO || kMI.n[t.g] > HI) continue;
-    D[t.g] += f[t.f] * (t.coef * ((pw[0][t.e0] * pw[1][t.e1]) * pw[2][t.e2]));
+    D[t.g] = fma(f[t.f], t.coef * ((pw[0][t.e0] * pw[1][t.e1]) * pw[2][t.e2]), D[t.g]);
   }
 }
 
@@ -362,23 +387,15 @@ __global__ void __launch_bounds__(kBS) k_far_order(int32_t c_lo, int32_t nc, con
     const double4 gy = geo[Y];
     const double* my = mono + (int64_t)Y * kNL;
     const double R[3] = {gx.x - gy.x, gx.y - gy.y, gx.z - gy.z};
-    // two phases, so that only part of the derivatives is live at a time:
-    // orders 0 to P for the coefficients of order < P, then order P for
-    // those of order P
-    {
-      double D[kND];
-      derivatives<0, kP>(R, eps2, D);
+    double D[kND];
+    derivatives<0, kP>(R, eps2, D);
+    // each source moment scaled once, then one fma per term
+    double cm[kNL];
 #pragma unroll
-      for (int i = 0; i < kNLocal; ++i)
-        if (kMI.n[kLocal.t[i].al] < kP) L[kLocal.t[i].al] += kLocal.t[i].coef * D[kLocal.t[i].g] * my[kLocal.t[i].be];
-    }
-    {
-      double D[kND];
-      derivatives<kP, kP>(R, eps2, D);
+    for (int be = 0; be < kNL; ++be) cm[be] = kSign.c[be] * my[be];
 #pragma unroll
-      for (int i = 0; i < kNLocal; ++i)
-        if (kMI.n[kLocal.t[i].al] == kP) L[kLocal.t[i].al] += kLocal.t[i].coef * D[kLocal.t[i].g] * my[kLocal.t[i].be];
-    }
+    for (int i = 0; i < kNLocal; ++i)
+      L[kLocal.t[i].al] = fma(D[kLocal.t[i].g], cm[kLocal.t[i].be], L[kLocal.t[i].al]);
   }
 #pragma unroll
   for (int g = 0; g < kNL; ++g) L[g] = wave_sum(L[g]);
@@ -417,16 +434,19 @@ __global__ void __launch_bounds__(kBS) k_corr_order(int32_t c_lo, int32_t nc, co
     double Q[kNQ];
 #pragma unroll
     for (int q = 0; q < kNQ; ++q) Q[q] = 0.0;
+    // the target's moments stay in scalar registers (wave-uniform loads); the
+    // constant goes with the source moment (products shared between terms)
 #pragma unroll
-    for (int i = 0; i < kNCorr; ++i) Q[kCorr.t[i].q] += kCorr.t[i].coef * (mx[kCorr.t[i].al] * my[kCorr.t[i].be]);
+    for (int i = 0; i < kNCorr; ++i)
+      Q[kCorr.t[i].q] = fma(mx[kCorr.t[i].al], kCorr.t[i].coef * my[kCorr.t[i].be], Q[kCorr.t[i].q]);
     double D[kND];
     derivatives<kP + 1, kP + 1>(R, eps2, D);
 #pragma unroll
     for (int q = 0; q < kNQ; ++q) {
       const int g = num_mi(kP - 1) + q;
-      F[0] -= Q[q] * D[mi_id(kMI.a[g] + 1, kMI.b[g], kMI.c[g])];
-      F[1] -= Q[q] * D[mi_id(kMI.a[g], kMI.b[g] + 1, kMI.c[g])];
-      F[2] -= Q[q] * D[mi_id(kMI.a[g], kMI.b[g], kMI.c[g] + 1)];
+      F[0] = fma(-Q[q], D[mi_id(kMI.a[g] + 1, kMI.b[g], kMI.c[g])], F[0]);
+      F[1] = fma(-Q[q], D[mi_id(kMI.a[g], kMI.b[g] + 1, kMI.c[g])], F[1]);
+      F[2] = fma(-Q[q], D[mi_id(kMI.a[g], kMI.b[g], kMI.c[g] + 1)], F[2]);
     }
   }
 #pragma unroll
