@@ -125,16 +125,26 @@ constexpr LocalTerms make_local() {
 }
 constexpr LocalTerms kLocal = make_local();
 
-// (-1)^|be| / be!: the factor of the source moment be in every term above
-struct MomentSigns {
+// one value per multi-index; kSign: (-1)^|be| / be!, the factor of the source
+// moment be in every term above
+struct PerIndex {
   double c[kNL];
 };
-constexpr MomentSigns make_signs() {
-  MomentSigns r{};
+constexpr PerIndex make_signs() {
+  PerIndex r{};
   for (int be = 0; be < kNL; ++be) r.c[be] = (kMI.n[be] % 2 ? -1.0 : 1.0) / kMI.fact[be];
   return r;
 }
-constexpr MomentSigns kSign = make_signs();
+constexpr PerIndex kSign = make_signs();
+// 1 / al!
+constexpr PerIndex make_inv_fact() {
+  PerIndex r{};
+  for (int al = 0; al < kNL; ++al) r.c[al] = 1.0 / kMI.fact[al];
+  return r;
+}
+constexpr PerIndex kInvFact = make_inv_fact();
+// lanes of the evaluation kernel per leaf
+constexpr int kL2PLanes = 8;
 constexpr bool local_coef_check() {
   for (int i = 0; i < kNLocal; ++i)
     if (kLocal.t[i].coef != kSign.c[kLocal.t[i].be]) return false;
@@ -490,7 +500,7 @@ __global__ void __launch_bounds__(kBS) k_l2l_order(int32_t c0, int32_t nl, const
 
 // At every particle of the target leaves: G times minus the gradient of the
 // leaf's expansion, plus g_c, added to the near field's outputs (caller
-// order); the potential likewise (one wave per leaf, lanes over particles).
+// order); the potential likewise (kL2PLanes lanes per leaf, over its particles).
 // leaves == nullptr: the leaves among cells [c_lo, c_lo + count).
 __global__ void __launch_bounds__(kBS) k_l2p_order(int32_t count, const int32_t* __restrict__ leaves, int32_t c_lo,
                                                    const int32_t* __restrict__ nch, const int32_t* __restrict__ beg,
@@ -499,21 +509,25 @@ __global__ void __launch_bounds__(kBS) k_l2p_order(int32_t count, const int32_t*
                                                    const int32_t* __restrict__ perm, double G,
                                                    double* __restrict__ ax, double* __restrict__ ay,
                                                    double* __restrict__ az, double* __restrict__ pot) {
-  const int lane = threadIdx.x & 63;
-  const int32_t li = uniform((int32_t)(blockIdx.x * kWaves + (threadIdx.x >> 6)));
+  // kL2PLanes lanes per leaf (leaves hold a few particles each)
+  const int64_t li = ((int64_t)blockIdx.x * kBS + threadIdx.x) / kL2PLanes;
+  const int sl = (int)(threadIdx.x % kL2PLanes);
   if (li >= count) return;
-  const int32_t X = leaves ? leaves[li] : c_lo + li;
+  const int32_t X = leaves ? leaves[li] : c_lo + (int32_t)li;
   if (!leaves && nch[X] != 0) return;
   const double4 z = geo[X];
   const double* L = locg + (int64_t)X * kLocGen;
-  for (int32_t p = beg[X] + lane; p < beg[X] + cnt[X]; p += 64) {
+  for (int32_t p = beg[X] + sl; p < beg[X] + cnt[X]; p += kL2PLanes) {
     const double4 q = pos[p];
     const double x[3] = {q.x - z.x, q.y - z.y, q.z - z.z};
     double Xm[kNL];
     monomials(x, Xm);
+    // x^al / al!, the reciprocal factorials as constants
+#pragma unroll
+    for (int al = 0; al < kNL; ++al) Xm[al] *= kInvFact.c[al];
     double phi = 0.0;
 #pragma unroll
-    for (int al = 0; al < kNL; ++al) phi += Xm[al] / kMI.fact[al] * L[al];
+    for (int al = 0; al < kNL; ++al) phi = fma(Xm[al], L[al], phi);
     double g[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -521,7 +535,7 @@ __global__ void __launch_bounds__(kBS) k_l2p_order(int32_t count, const int32_t*
 #pragma unroll
       for (int al = 0; al < kNL; ++al) {
         if (kMI.n[al] >= kP) continue;
-        s += Xm[al] / kMI.fact[al] * L[mi_id(kMI.a[al] + (k == 0), kMI.b[al] + (k == 1), kMI.c[al] + (k == 2))];
+        s = fma(Xm[al], L[mi_id(kMI.a[al] + (k == 0), kMI.b[al] + (k == 1), kMI.c[al] + (k == 2))], s);
       }
       g[k] = -s + L[kNL + k];
     }
@@ -580,7 +594,8 @@ void order_push_down(Ctx& c, int32_t c_lo, int32_t c_hi) {
 void order_l2p(Ctx& c, const int32_t* leaves, int32_t c_lo, int32_t count, double* ax, double* ay, double* az,
                double* pot) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_l2p_order, dim3(blocks_for(count, kWaves)), dim3(kBS), 0, c.stream, count, leaves, c_lo,
+  hipLaunchKernelGGL(k_l2p_order, dim3(blocks_for((int64_t)count * kL2PLanes, kBS)), dim3(kBS), 0, c.stream, count,
+                     leaves, c_lo,
                      as<int32_t>(c.c_nchild), as<int32_t>(c.c_begin), as<int32_t>(c.c_count),
                      (const double4*)c.pos4.p, (const double4*)c.geo.p, (const double*)c.locg.p, as<int32_t>(c.perm),
                      c.opt.G, ax, ay, az, pot);
