@@ -29,9 +29,10 @@ the two angles that bracket it, and the speedup over it; also the speedup at
 the largest grid angle that meets p99 1e-4),
 `mixed_geometric` (the mixed-precision geometric solve at --theta against the
 FP64 one: times, errors, residuals), `order4` (the same step at expansion
-order 4, the appendix's general order, with its own tolerance: time, error,
-balances; outside the timed region, the headline stays the quadrupole-order
-solve) and the median of the per-step HIP-event totals.
+order 4, the appendix's general order, with its own tolerance and leaf size:
+time, error, balances; outside the timed region, the headline stays the
+quadrupole-order solve with the configuration's n_crit = 25) and the median
+of the per-step HIP-event totals.
 """
 import argparse
 import hashlib
@@ -108,6 +109,9 @@ def parse():
                    help="error-estimate criterion: also time the same step at expansion order 4 with this "
                         "tolerance, outside the timed region (0 = skip)")
     p.add_argument("--order4-steps", type=int, default=5)
+    p.add_argument("--order4-ncrit", type=int, default=64,
+                   help="leaf size of the order-4 step (with the octupole in the expansion, larger leaves "
+                        "trade walk and far-field work for near-field work at the same error)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain device copy of known size (scale for HBM byte counters)")
     return p.parse_args()
@@ -411,7 +415,7 @@ def main():
     order4 = None
     if field and a.order4_eps > 0 and a.order4_steps > 0:
         s4 = amfmm.Solver(variant=variant, precision=prec, criterion=crit, error_tol=a.order4_eps,
-                          theta_max=a.theta_max, order=4)
+                          theta_max=a.theta_max, order=4, n_crit=a.order4_ncrit)
         o4 = s4._outputs(a.n, True)
         s4.set_field_estimate(pout[0], pout[1], pout[2])
 
@@ -433,7 +437,8 @@ def main():
         fb4, tb4 = s4.balance(X, Y, Z, M, o4[0], o4[1], o4[2])
         c4 = s4.get_counts()
         order4 = {"order": 4, "precision": a.precision + " near field; far field, push-down and evaluation FP64",
-                  "criterion": a.criterion, "eps": a.order4_eps, "theta_max": a.theta_max, "steps": a.order4_steps,
+                  "criterion": a.criterion, "eps": a.order4_eps, "theta_max": a.theta_max, "n_crit": a.order4_ncrit,
+                  "steps": a.order4_steps,
                   "ms_per_step": round(ms4, 3), "value": a.n / (ms4 * 1e-3), "unit": "particles/s",
                   "p99_rel_force_error": float(np.percentile(e4, 99)),
                   "max_rel_force_error": float(e4.max()), "meets_1e-4_p99": bool(np.percentile(e4, 99) <= 1e-4),

@@ -26,15 +26,18 @@ def host(o):
     return np.stack([v.cpu().numpy() for v in o])
 
 
-@pytest.mark.parametrize("name,softening", [(n, 0.0) for n in sorted(CASES)] + [("plummer16k", 0.01)])
-def test_order4_matches_oracle(name, softening):
+@pytest.mark.parametrize("name,softening,n_crit", [(n, 0.0, 25) for n in sorted(CASES)] +
+                         [("plummer16k", 0.01, 25), ("plummer16k", 0.0, 64), ("twoplummer20k", 0.0, 64)])
+def test_order4_matches_oracle(name, softening, n_crit):
+    """Plain and softened, with the configuration's leaves (25) and the
+    benchmark's order-4 leaves (64)."""
     x, y, z, m = CASES[name]()
-    say("order 4", name, len(x), softening)
+    say("order 4", name, len(x), softening, n_crit)
     X, Y, Z, M = to_dev(x, y, z, m)
     _, _, gabs = orc.direct(x, y, z, m, softening=softening)
     for variant in (amfmm.UC, amfmm.TC):
-        oa, op = orc.solve(x, y, z, m, theta=0.5, variant=variant, softening=softening, order=4)
-        s = amfmm.Solver(variant=variant, softening=softening, order=4)
+        oa, op = orc.solve(x, y, z, m, theta=0.5, n_crit=n_crit, variant=variant, softening=softening, order=4)
+        s = amfmm.Solver(variant=variant, softening=softening, order=4, n_crit=n_crit)
         o = s.solve_gravity(X, Y, Z, M, 0.5)
         a = host(o)
         err = np.linalg.norm(a[:3] - oa, axis=0) / gabs
