@@ -549,10 +549,10 @@ static double list_bytes_per_particle(double theta) {
 // new blocks coexist for a moment, and each block carries a quarter of
 // headroom: lists within b bytes peak below 2.25 b.  Outside an arena the
 // lists and the staging room this context already holds are reused by the
-// next walk and count as free, and b is two fifths of that: the whole walk of a large problem fits
-// in one pass when the device has the memory (one evaluation launch per
-// phase instead of one per batch).  In an arena: a quarter of its largest
-// free block.
+// next walk and count as free, and b is two fifths of that: the whole walk
+// of a large problem fits in one pass when the device has the memory (one
+// evaluation launch per phase instead of one per batch).  In an arena: a
+// quarter of its largest free block.
 static size_t list_budget(Ctx& c) {
   if (c.opt.list_bytes > 0) return (size_t)c.opt.list_bytes;
   size_t fr = amfmm::free_device_bytes(c);
@@ -728,7 +728,7 @@ static int solve_impl(Ctx& c, int64_t n, const double* x, const double* y, const
       } catch (const amfmm::Error& e) {
         if (!out_of_device_memory(c, e)) throw;
         // the lists did not fit the device after all: give back what the
-        // walk grew and go batch by batch within half the budget
+        // walk grew and go batch by batch, at most half the particles a batch
         release(c, c.far_src);
         release(c, c.near_src);
         release(c, c.stage);
