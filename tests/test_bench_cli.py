@@ -43,6 +43,10 @@ def test_committed_profiles_match_sources_and_default_configuration():
     for kernel in ("walk", "far", "near"):
         assert bench.traffic(kernel, cfg, a.workload, launches[kernel]) is not None, kernel
         assert bench.counters(kernel, cfg, a.workload, launches[kernel]) is not None, kernel
+        # a step cut into other launches (a batched walk) has other bytes per launch
+        assert bench.traffic(kernel, cfg, a.workload, launches[kernel] + 1) is None, kernel
+        assert bench.counters(kernel, cfg, a.workload, launches[kernel] + 1) is None, kernel
+        assert bench.traffic(kernel, dict(cfg, eps=2 * cfg["eps"]), a.workload, launches[kernel]) is None
     assert all(v["traffic"] is not None for v in line["roofline"]["others"].values())
     assert c["workload"] == a.workload and c["eps"] == a.eps and c["criterion"] == a.criterion
     assert line["steps"] == a.steps and line["warmup"] == a.warmup
